@@ -1,0 +1,191 @@
+// Internal data structures of libdogip (host side).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/dogip.h"
+
+namespace dogip {
+
+// Error carrying a status code; converted to the return value at the C boundary.
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define DOGIP_CHECK(cond, code, msg)                 \
+  do {                                               \
+    if (!(cond)) throw ::dogip::Error((code), (msg)); \
+  } while (0)
+
+void hip_check(hipError_t e, const char* what);
+#define HIPCHK(x) ::dogip::hip_check((x), #x)
+
+// Device buffer owned by RAII.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t n) { alloc(n); }
+  void alloc(size_t n);
+  void free();
+  ~DevBuf() { free(); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct Mesh {
+  int dim = 0;
+  int64_t nv = 0, nc = 0;
+  std::vector<double> xyz;     // [nv][dim]
+  std::vector<int32_t> cells;  // [nc][dim+1]
+};
+
+struct Space {
+  std::shared_ptr<const Mesh> mesh;
+  int dim = 0, k = 0, kind = 0, bc = 0;
+  int vt = 0, wt = 0, nsym = 0, nb = 0;
+  int64_t nc = 0, ndofs = 0;
+  std::vector<int32_t> cell_dofs;  // [nc][vt]
+  std::vector<double> dof_xyz;     // [ndofs][dim]
+  std::vector<int32_t> boundary;   // ascending
+  std::vector<uint8_t> is_bnd;     // [ndofs]
+  std::vector<double> bhat;        // [nb][wt][vt]
+  std::vector<double> what;        // [wt]
+  int64_t nnz_bhat = 0, nnz_pm1 = 0;
+};
+
+// Flags carried in the high bits of a tile dof entry.
+constexpr uint32_t TD_BND = 0x80000000u;     // Dirichlet dof: gathered as 0, written y = u
+constexpr uint32_t TD_SHARED = 0x40000000u;  // dof touched by more than one tile: atomic flush
+constexpr uint32_t TD_OWNER = 0x20000000u;   // the tile of lowest index touching this dof
+constexpr uint32_t TD_MASK = 0x1fffffffu;    // dof index (< 2^29)
+
+// Cell tiling: cells reordered along a Morton curve of their centroids and cut
+// into tiles of TE cells; each tile lists the distinct dofs it touches.
+struct TilePlan {
+  int te = 0;
+  int64_t ntiles = 0, nel_pad = 0;
+  std::vector<int32_t> perm;        // internal cell -> mesh cell
+  std::vector<int64_t> tile_off;    // [ntiles+1]
+  std::vector<uint32_t> tile_dofs;  // dof | flags
+  std::vector<uint16_t> lidx;       // AoSoA [nel_pad/64][nlc][64][8]: slot of each local node
+  std::vector<int32_t> shared;      // non-boundary dofs touched by several tiles
+  int nlc = 0;                      // 16-byte chunks of local indices per cell
+  int64_t max_tile_dofs = 0;
+};
+
+// D layout: AoSoA, cell e, flat value f = i*nsym + c at
+//   ((e/64) * nch + f/vec) * 64 * vec + (e%64) * vec + f%vec,  vec = 16 / sizeof(value).
+inline int64_t d_chunks(int wt, int nsym, int vec) { return (int64_t(wt) * nsym + vec - 1) / vec; }
+
+struct PcgWork;
+struct OpTimer;
+
+struct Op {
+  std::shared_ptr<const Space> space;
+  TilePlan plan;  // host copy (perm needed for outputs)
+  int variant = 0;
+  bool has32 = false;
+  int64_t nch64 = 0, nch32 = 0;
+  DevBuf d64, d32, lidx, tile_off, tile_dofs, shared, perm, cells, xyz, what, bhat64, bhat32, invdiag;
+  std::unique_ptr<PcgWork> pcg;
+  std::unique_ptr<OpTimer> timer;
+  ~Op();
+};
+
+// ---- host setup ----
+std::shared_ptr<Mesh> make_mesh(int dim, int64_t nv, const double* xyz, int64_t nc, const int32_t* cells);
+std::shared_ptr<Mesh> make_unit_mesh(int dim, int n);
+std::shared_ptr<Space> make_space(std::shared_ptr<const Mesh> mesh, int k, int kind, int bc);
+TilePlan make_tiles(const Space& s, int te);
+void reference_tables(int dim, int k, int kind, std::vector<double>& bhat, std::vector<double>& what,
+                      int64_t& nnz, int64_t& nnz_pm1);
+
+// ---- operator ----
+std::unique_ptr<Op> make_op(std::shared_ptr<const Space> s, int coef_kind, const double* coef, unsigned flags,
+                            int tile_waves, int variant, hipStream_t st);
+void op_set_coef(Op& op, int coef_kind, const double* coef, hipStream_t st);
+void op_apply(Op& op, const double* u, double* y, int prec, hipStream_t st, double* energy_partials = nullptr);
+void op_diag(Op& op, double* diag, hipStream_t st);
+void op_grad(Op& op, const double* u, const double* lam, double* g, hipStream_t st);
+void op_export_d(Op& op, double* out, hipStream_t st);
+dogip_op_info op_info(const Op& op);
+int op_pcg(Op& op, const double* b, double* x, const dogip_solve_opts& o, dogip_solve_stats& stats, hipStream_t st);
+void op_timer_enable(Op& op, bool on);
+void op_timer_read(Op& op, double* ms, int64_t* count);
+
+// ---- kernel launchers (defined in the .hip files) ----
+struct ApplyLaunch {
+  const void* D;
+  const uint16_t* lidx;
+  const int64_t* tile_off;
+  const uint32_t* tile_dofs;
+  const void* bhat;      // looped variant: [nb][wt][vt] in the compute precision
+  const double* u;
+  double* y;
+  double* energy;        // optional per-tile partial of u^T A u (nullptr: not computed)
+  int64_t nel;
+  int64_t ntiles;
+  int64_t nch;           // D chunks per cell
+  int nlc;               // local-index chunks per cell
+  int te;
+  int lds_slots;         // LDS slots per tile (>= max tile dofs)
+  int tile_base;         // first tile of this launch (batch uses 0)
+};
+
+bool launch_apply(int dim, int k, int kind, int prec, int variant, const ApplyLaunch& a, hipStream_t st);
+bool has_unrolled(int dim, int k, int kind);
+
+struct DiagLaunch {
+  const double* D;
+  const uint16_t* lidx;
+  const int64_t* tile_off;
+  const uint32_t* tile_dofs;
+  const double* bhat;
+  double* out;
+  int64_t nel, ntiles, nch;
+  int nlc, te, lds_slots;
+};
+void launch_diag(int dim, int k, int kind, const DiagLaunch& a, hipStream_t st);
+
+struct GradLaunch {
+  const double* D;
+  const uint16_t* lidx;
+  const int64_t* tile_off;
+  const uint32_t* tile_dofs;
+  const double* bhat;
+  const double* u;
+  const double* lam;
+  const int32_t* perm;
+  double* g;
+  int64_t nel, ntiles, nch;
+  int nlc, te, lds_slots;
+};
+void launch_grad(int dim, int k, int kind, const GradLaunch& a, hipStream_t st);
+
+struct BuildDLaunch {
+  const double* xyz;
+  const int32_t* cells;  // internal order [nel][dim+1]
+  const int32_t* perm;   // internal -> mesh cell
+  const double* what;    // [wt]
+  const double* coef;
+  double* d64;
+  float* d32;            // may be null
+  int64_t nel, nel_pad, nch64, nch32;
+  int dim, kind, coef_kind, wt, nsym;
+};
+void launch_build_d(const BuildDLaunch& a, hipStream_t st);
+void launch_export_d(const double* d64, const int32_t* perm, double* out, int64_t nel, int64_t nch64, int wt,
+                     int nsym, hipStream_t st);
+void launch_zero_indexed(double* y, const int32_t* idx, int64_t n, hipStream_t st);
+void launch_invert(const double* d, double* inv, int64_t n, hipStream_t st);
+
+}  // namespace dogip

@@ -1,0 +1,17 @@
+// Unrolled (compile-time sparse B^) apply kernels, 3D.
+#include "kern_apply.hpp"
+
+namespace dogip {
+bool launch_apply_unrolled_3d(int k, int kind, int prec, bool energy, const ApplyLaunch& a, hipStream_t st) {
+  constexpr int V = DOGIP_VARIANT_UNROLLED;
+  switch (kind * 16 + k) {
+    DOGIP_APPLY_CASE(3, 1, KIND_WP, V)
+    DOGIP_APPLY_CASE(3, 2, KIND_WP, V)
+    DOGIP_APPLY_CASE(3, 1, KIND_SE, V)
+    DOGIP_APPLY_CASE(3, 2, KIND_SE, V)
+    DOGIP_APPLY_CASE(3, 3, KIND_SE, V)
+    default:
+      return false;
+  }
+}
+}  // namespace dogip

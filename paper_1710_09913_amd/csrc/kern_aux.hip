@@ -1,0 +1,288 @@
+// Setup and auxiliary kernels: D construction (Theorems 2 and 4), D export,
+// Jacobi diagonal, adjoint contraction, small vector kernels.
+#include "kern_common.hpp"
+
+namespace dogip {
+namespace dev {
+
+// ---- D construction: one thread per cell (internal order) ----
+// Projection: D_T,i = w^_i |T| m_T.  Elliptic: D_T,i = w^_i |T| R_T^-1 M_T R_T^-T
+// (packed symmetric).  |T| = |det R_T| / d!, R_T columns X_r - X_0.
+__global__ __launch_bounds__(256) void k_build_d(BuildDLaunch a) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= a.nel) return;
+  const int dim = a.dim, d1 = dim + 1, ns = a.nsym, wt = a.wt;
+  const int64_t uc = a.perm[e];
+  auto store = [&](int f, double v) {
+    a.d64[((e >> 6) * a.nch64 + (f >> 1)) * 128 + (e & 63) * 2 + (f & 1)] = v;
+    if (a.d32) a.d32[((e >> 6) * a.nch32 + (f >> 2)) * 256 + (e & 63) * 4 + (f & 3)] = float(v);
+  };
+  if (a.coef_kind == DOGIP_COEF_RAW_D) {
+    const int nd = wt * ns;
+    for (int f = 0; f < nd; ++f) store(f, a.coef[uc * nd + f]);
+    return;
+  }
+  double X[4][3] = {};
+  for (int j = 0; j < d1; ++j) {
+    const int64_t v = a.cells[e * d1 + j];
+    for (int x = 0; x < dim; ++x) X[j][x] = a.xyz[v * dim + x];
+  }
+  double R[3][3] = {}, Ri[3][3] = {}, det;
+  for (int x = 0; x < dim; ++x)
+    for (int r = 0; r < dim; ++r) R[x][r] = X[r + 1][x] - X[0][x];
+  if (dim == 2) {
+    det = R[0][0] * R[1][1] - R[0][1] * R[1][0];
+    Ri[0][0] = R[1][1] / det;
+    Ri[0][1] = -R[0][1] / det;
+    Ri[1][0] = -R[1][0] / det;
+    Ri[1][1] = R[0][0] / det;
+  } else {
+    const double c00 = R[1][1] * R[2][2] - R[1][2] * R[2][1];
+    const double c01 = R[1][2] * R[2][0] - R[1][0] * R[2][2];
+    const double c02 = R[1][0] * R[2][1] - R[1][1] * R[2][0];
+    det = R[0][0] * c00 + R[0][1] * c01 + R[0][2] * c02;
+    Ri[0][0] = c00 / det;
+    Ri[1][0] = c01 / det;
+    Ri[2][0] = c02 / det;
+    Ri[0][1] = (R[0][2] * R[2][1] - R[0][1] * R[2][2]) / det;
+    Ri[1][1] = (R[0][0] * R[2][2] - R[0][2] * R[2][0]) / det;
+    Ri[2][1] = (R[0][1] * R[2][0] - R[0][0] * R[2][1]) / det;
+    Ri[0][2] = (R[0][1] * R[1][2] - R[0][2] * R[1][1]) / det;
+    Ri[1][2] = (R[0][2] * R[1][0] - R[0][0] * R[1][2]) / det;
+    Ri[2][2] = (R[0][0] * R[1][1] - R[0][1] * R[1][0]) / det;
+  }
+  const double vol = fabs(det) / (dim == 2 ? 2.0 : 6.0);
+  double K[6] = {};
+  if (a.kind == KIND_WP) {
+    const double c = a.coef[uc];
+    K[0] = a.coef_kind == DOGIP_COEF_LOGSCALAR ? exp(c) : c;
+  } else {
+    double M[3][3] = {};
+    if (a.coef_kind == DOGIP_COEF_SYM) {
+      int c = 0;
+      for (int r = 0; r < dim; ++r)
+        for (int s = r; s < dim; ++s) {
+          M[r][s] = M[s][r] = a.coef[uc * ns + c];
+          ++c;
+        }
+    } else {
+      const double c = a.coef[uc];
+      const double m = a.coef_kind == DOGIP_COEF_LOGSCALAR ? exp(c) : c;
+      for (int r = 0; r < dim; ++r) M[r][r] = m;
+    }
+    int c = 0;
+    for (int r = 0; r < dim; ++r)
+      for (int s = r; s < dim; ++s) {
+        double acc = 0.0;
+        for (int p = 0; p < dim; ++p)
+          for (int q = 0; q < dim; ++q) acc += Ri[r][p] * M[p][q] * Ri[s][q];
+        K[c++] = acc;
+      }
+  }
+  for (int i = 0; i < wt; ++i) {
+    const double wv = a.what[i] * vol;
+    for (int c = 0; c < ns; ++c) store(i * ns + c, wv * K[c]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_export_d(const double* __restrict__ d64, const int32_t* __restrict__ perm,
+                                                  double* __restrict__ out, int64_t nel, int64_t nch64, int nd) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nel * nd) return;
+  const int64_t e = i / nd;
+  const int f = int(i % nd);
+  out[int64_t(perm[e]) * nd + f] = d64[((e >> 6) * nch64 + (f >> 1)) * 128 + (e & 63) * 2 + (f & 1)];
+}
+
+__global__ __launch_bounds__(256) void k_zero_indexed(double* __restrict__ y, const int32_t* __restrict__ idx,
+                                                      int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    y[idx[i]] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_invert(const double* __restrict__ d, double* __restrict__ inv, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    inv[i] = 1.0 / d[i];
+}
+
+// ---- Jacobi diagonal: diag_l = sum_T sum_i b_il^T D_T,i b_il, b_il = (B^[r][i][l])_r ----
+template <int D, int K, int KIND>
+__global__ __launch_bounds__(512) void k_diag(DiagLaunch a) {
+  using TB = ref::BTable<D, K, KIND>;
+  constexpr int VT = TB::VT, WT = TB::WT, NB = TB::NB, S = KIND == KIND_SE ? n_sym(D) : 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* ys = reinterpret_cast<double*>(smem);
+  const int64_t t = blockIdx.x;
+  const int64_t o0 = a.tile_off[t], nd = a.tile_off[t + 1] - o0;
+  for (int64_t j = threadIdx.x; j < nd; j += blockDim.x) ys[j] = 0.0;
+  __syncthreads();
+  const int64_t e = t * a.te + threadIdx.x;
+  if (e < a.nel) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w = e >> 6;
+    int li[VT];
+    load_lidx<VT>(a.lidx, w, a.nlc, lane, li);
+    const double* dsc = a.D + (w * a.nch) * 128 + lane * 2;
+    const double* bt = ctab<D, K, KIND, double>.v;
+    double ye[VT];
+    sfor<VT>([&](auto L) { ye[L] = 0.0; });
+    for (int i = 0; i < WT; ++i) {
+      double dv[S];
+      sfor<S>([&](auto C) {
+        const int f = i * S + C;
+        dv[C] = dsc[(f >> 1) * 128 + (f & 1)];
+      });
+      sfor<VT>([&](auto L) {
+        double b[NB];
+        sfor<NB>([&](auto R) { b[R] = bt[(R * WT + i) * VT + L]; });
+        double h[NB];
+        dmul<NB, S>(dv, b, h);
+        double s = 0.0;
+        sfor<NB>([&](auto R) { s = fma_t(b[R], h[R], s); });
+        ye[L] += s;
+      });
+    }
+    sfor<VT>([&](auto L) { atomicAdd(&ys[li[L]], ye[L]); });
+  }
+  __syncthreads();
+  for (int64_t j = threadIdx.x; j < nd; j += blockDim.x) {
+    const uint32_t td = a.tile_dofs[o0 + j];
+    const uint32_t dof = td & TD_MASK;
+    if (td & TD_BND)
+      a.out[dof] = 1.0;
+    else if (td & TD_SHARED)
+      unsafeAtomicAdd(&a.out[dof], ys[j]);
+    else
+      a.out[dof] = ys[j];
+  }
+}
+
+// ---- adjoint contraction: g_T = -(B^ lam_T) . D_T (B^ u_T), boundary entries zero ----
+template <int D, int K, int KIND>
+__global__ __launch_bounds__(512) void k_grad(GradLaunch a) {
+  using TB = ref::BTable<D, K, KIND>;
+  constexpr int VT = TB::VT, WT = TB::WT, NB = TB::NB, S = KIND == KIND_SE ? n_sym(D) : 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* us = reinterpret_cast<double*>(smem);
+  double* ls = us + a.lds_slots;
+  const int64_t t = blockIdx.x;
+  const int64_t o0 = a.tile_off[t], nd = a.tile_off[t + 1] - o0;
+  for (int64_t j = threadIdx.x; j < nd; j += blockDim.x) {
+    const uint32_t td = a.tile_dofs[o0 + j];
+    const bool b = td & TD_BND;
+    us[j] = b ? 0.0 : a.u[td & TD_MASK];
+    ls[j] = b ? 0.0 : a.lam[td & TD_MASK];
+  }
+  __syncthreads();
+  const int64_t e = t * a.te + threadIdx.x;
+  if (e >= a.nel) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t w = e >> 6;
+  int li[VT];
+  load_lidx<VT>(a.lidx, w, a.nlc, lane, li);
+  double ue[VT], le[VT];
+  sfor<VT>([&](auto L) {
+    ue[L] = us[li[L]];
+    le[L] = ls[li[L]];
+  });
+  const double* dsc = a.D + (w * a.nch) * 128 + lane * 2;
+  const double* bt = ctab<D, K, KIND, double>.v;
+  double en = 0.0;
+  for (int i = 0; i < WT; ++i) {
+    double gu[NB], gl[NB];
+    sfor<NB>([&](auto R) {
+      double su = 0.0, sl = 0.0;
+      sfor<VT>([&](auto L) {
+        const double b = bt[(R * WT + i) * VT + L];
+        su = fma_t(b, ue[L], su);
+        sl = fma_t(b, le[L], sl);
+      });
+      gu[R] = su;
+      gl[R] = sl;
+    });
+    double dv[S];
+    sfor<S>([&](auto C) {
+      const int f = i * S + C;
+      dv[C] = dsc[(f >> 1) * 128 + (f & 1)];
+    });
+    double h[NB];
+    dmul<NB, S>(dv, gu, h);
+    sfor<NB>([&](auto R) { en = fma_t(gl[R], h[R], en); });
+  }
+  a.g[a.perm[e]] = -en;
+}
+
+template <int D, int K, int KIND>
+void diag_t(const DiagLaunch& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_diag<D, K, KIND>), dim3(unsigned(a.ntiles)), dim3(unsigned(a.te)),
+                     size_t(a.lds_slots) * sizeof(double), st, a);
+}
+template <int D, int K, int KIND>
+void grad_t(const GradLaunch& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_grad<D, K, KIND>), dim3(unsigned(a.ntiles)), dim3(unsigned(a.te)),
+                     size_t(2) * a.lds_slots * sizeof(double), st, a);
+}
+
+}  // namespace dev
+
+static unsigned grid_for(int64_t n, int block) {
+  int64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return unsigned(g);
+}
+
+void launch_build_d(const BuildDLaunch& a, hipStream_t st) {
+  if (a.nel <= 0) return;
+  hipLaunchKernelGGL(dev::k_build_d, dim3(unsigned((a.nel + 255) / 256)), dim3(256), 0, st, a);
+}
+
+void launch_export_d(const double* d64, const int32_t* perm, double* out, int64_t nel, int64_t nch64, int wt, int nsym,
+                     hipStream_t st) {
+  const int64_t n = nel * wt * nsym;
+  hipLaunchKernelGGL(dev::k_export_d, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, d64, perm, out, nel, nch64,
+                     wt * nsym);
+}
+
+void launch_zero_indexed(double* y, const int32_t* idx, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(dev::k_zero_indexed, dim3(grid_for(n, 256)), dim3(256), 0, st, y, idx, n);
+}
+
+void launch_invert(const double* d, double* inv, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_invert, dim3(grid_for(n, 256)), dim3(256), 0, st, d, inv, n);
+}
+
+#define DOGIP_DG_CASES(F)                                                                                          \
+  switch (dim * 1000 + kind * 16 + k) {                                                                            \
+    case 2000 + 1: F<2, 1, KIND_WP>(a, st); break;                                                                 \
+    case 2000 + 2: F<2, 2, KIND_WP>(a, st); break;                                                                 \
+    case 2000 + 3: F<2, 3, KIND_WP>(a, st); break;                                                                 \
+    case 2000 + 4: F<2, 4, KIND_WP>(a, st); break;                                                                 \
+    case 2000 + 5: F<2, 5, KIND_WP>(a, st); break;                                                                 \
+    case 2000 + 6: F<2, 6, KIND_WP>(a, st); break;                                                                 \
+    case 2000 + 7: F<2, 7, KIND_WP>(a, st); break;                                                                 \
+    case 2000 + 8: F<2, 8, KIND_WP>(a, st); break;                                                                 \
+    case 2016 + 1: F<2, 1, KIND_SE>(a, st); break;                                                                 \
+    case 2016 + 2: F<2, 2, KIND_SE>(a, st); break;                                                                 \
+    case 2016 + 3: F<2, 3, KIND_SE>(a, st); break;                                                                 \
+    case 2016 + 4: F<2, 4, KIND_SE>(a, st); break;                                                                 \
+    case 2016 + 5: F<2, 5, KIND_SE>(a, st); break;                                                                 \
+    case 2016 + 6: F<2, 6, KIND_SE>(a, st); break;                                                                 \
+    case 2016 + 7: F<2, 7, KIND_SE>(a, st); break;                                                                 \
+    case 2016 + 8: F<2, 8, KIND_SE>(a, st); break;                                                                 \
+    case 3000 + 1: F<3, 1, KIND_WP>(a, st); break;                                                                 \
+    case 3000 + 2: F<3, 2, KIND_WP>(a, st); break;                                                                 \
+    case 3000 + 3: F<3, 3, KIND_WP>(a, st); break;                                                                 \
+    case 3000 + 4: F<3, 4, KIND_WP>(a, st); break;                                                                 \
+    case 3016 + 1: F<3, 1, KIND_SE>(a, st); break;                                                                 \
+    case 3016 + 2: F<3, 2, KIND_SE>(a, st); break;                                                                 \
+    case 3016 + 3: F<3, 3, KIND_SE>(a, st); break;                                                                 \
+    case 3016 + 4: F<3, 4, KIND_SE>(a, st); break;                                                                 \
+    default: throw Error(DOGIP_E_RANGE, "no kernel for this (dim, k, kind)");                                     \
+  }
+
+void launch_diag(int dim, int k, int kind, const DiagLaunch& a, hipStream_t st) { DOGIP_DG_CASES(dev::diag_t) }
+void launch_grad(int dim, int k, int kind, const GradLaunch& a, hipStream_t st) { DOGIP_DG_CASES(dev::grad_t) }
+
+}  // namespace dogip

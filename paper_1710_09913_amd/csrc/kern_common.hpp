@@ -1,0 +1,194 @@
+// Device helpers shared by the libdogip kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+#include "internal.hpp"
+#include "reftab.hpp"
+
+namespace dogip {
+namespace dev {
+
+template <class F, int... Is>
+__device__ __forceinline__ void sfor_impl(F&& f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+// Compile-time loop: f(integral_constant<int, i>) for i = 0..N-1.
+template <int N, class F>
+__device__ __forceinline__ void sfor(F&& f) {
+  sfor_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; map them so that each
+// XCD (own L2) works on one contiguous range of tiles, which are neighbours in
+// the Morton order and share dofs.
+__device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t nblk) {
+  const int64_t x = bid & 7, pos = bid >> 3, q = nblk >> 3, r = nblk & 7;
+  return x * q + (x < r ? x : r) + pos;
+}
+
+template <typename T, int N>
+using vec_t = T __attribute__((ext_vector_type(N)));
+
+// Streaming load of one 16-byte chunk (D is read once per apply).
+template <typename V>
+__device__ __forceinline__ V ld_stream(const V* p) {
+  return __builtin_nontemporal_load(p);
+}
+
+template <typename T>
+__device__ __forceinline__ T fma_t(T a, T b, T c) {
+  return __builtin_fma(a, b, c);
+}
+template <>
+__device__ __forceinline__ float fma_t<float>(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
+
+// h = D g for one W node: scalar (projection) or packed symmetric d x d (elliptic).
+template <int NB, int S, typename T>
+__device__ __forceinline__ void dmul(const T (&dv)[S], const T (&g)[NB], T (&h)[NB]) {
+  if constexpr (S == 1) {
+    h[0] = dv[0] * g[0];
+  } else if constexpr (NB == 2) {
+    h[0] = fma_t(dv[1], g[1], dv[0] * g[0]);
+    h[1] = fma_t(dv[2], g[1], dv[1] * g[0]);
+  } else {
+    h[0] = fma_t(dv[2], g[2], fma_t(dv[1], g[1], dv[0] * g[0]));
+    h[1] = fma_t(dv[4], g[2], fma_t(dv[3], g[1], dv[1] * g[0]));
+    h[2] = fma_t(dv[5], g[2], fma_t(dv[4], g[1], dv[2] * g[0]));
+  }
+}
+
+// Compile-time reference table (exact rationals rounded once to double).
+template <int D, int K, int KIND>
+struct CT {
+  static constexpr ref::BTable<D, K, KIND> t{};
+};
+
+// The same table in device constant memory, in the compute precision, for the
+// looped element body (wave-uniform index -> scalar loads).
+template <int D, int K, int KIND, typename T>
+struct CArr {
+  using TB = ref::BTable<D, K, KIND>;
+  T v[TB::NB * TB::WT * TB::VT];
+  constexpr CArr() : v{} {
+    for (int r = 0; r < TB::NB; ++r)
+      for (int i = 0; i < TB::WT; ++i)
+        for (int l = 0; l < TB::VT; ++l) v[(r * TB::WT + i) * TB::VT + l] = T(CT<D, K, KIND>::t.v[r][i][l]);
+  }
+};
+template <int D, int K, int KIND, typename T>
+__constant__ CArr<D, K, KIND, T> ctab{};
+
+// Element body.  ue: local dof values; ye: local result (overwritten); dp: this
+// lane's first D chunk (chunk j of the cell at dp[j * 64]).  Returns the cell
+// energy u_T^T A_T u_T when ENERGY is set.
+template <int D, int K, int KIND, typename T, typename TD, int VARIANT, bool ENERGY>
+struct Elem {
+  using TB = ref::BTable<D, K, KIND>;
+  static constexpr int VT = TB::VT, WT = TB::WT, NB = TB::NB;
+  static constexpr int S = KIND == KIND_SE ? n_sym(D) : 1;
+  static constexpr int VEC = 16 / int(sizeof(TD));
+  using V = vec_t<TD, VEC>;
+
+  __device__ __forceinline__ static T run(const V* __restrict__ dp, const T (&ue)[VT], T (&ye)[VT]) {
+    T en = T(0);
+    sfor<VT>([&](auto L) { ye[L] = T(-0.0); });
+    if constexpr (VARIANT == DOGIP_VARIANT_UNROLLED) {
+      sfor<WT>([&](auto I) {
+        T g[NB];
+        sfor<NB>([&](auto R) {
+          T acc = T(-0.0);
+          sfor<VT>([&](auto L) {
+            constexpr double b = CT<D, K, KIND>::t.v[R][I][L];
+            if constexpr (b == 1.0)
+              acc = acc + ue[L];
+            else if constexpr (b == -1.0)
+              acc = acc - ue[L];
+            else if constexpr (b != 0.0)
+              acc = fma_t(T(b), ue[L], acc);
+          });
+          g[R] = acc;
+        });
+        T dv[S];
+        sfor<S>([&](auto C) {
+          constexpr int f = I * S + C;
+          const V ch = ld_stream(dp + (f / VEC) * 64);
+          dv[C] = T(ch[f % VEC]);
+        });
+        T h[NB];
+        dmul<NB, S>(dv, g, h);
+        if constexpr (ENERGY) sfor<NB>([&](auto R) { en = fma_t(g[R], h[R], en); });
+        sfor<NB>([&](auto R) {
+          sfor<VT>([&](auto L) {
+            constexpr double b = CT<D, K, KIND>::t.v[R][I][L];
+            if constexpr (b == 1.0)
+              ye[L] = ye[L] + h[R];
+            else if constexpr (b == -1.0)
+              ye[L] = ye[L] - h[R];
+            else if constexpr (b != 0.0)
+              ye[L] = fma_t(T(b), h[R], ye[L]);
+          });
+        });
+      });
+    } else {
+      const T* bt = ctab<D, K, KIND, T>.v;
+      const TD* dsc = reinterpret_cast<const TD*>(dp);
+      for (int i = 0; i < WT; ++i) {
+        T g[NB];
+        sfor<NB>([&](auto R) {
+          const T* br = bt + (R * WT + i) * VT;
+          T acc = T(-0.0);
+          sfor<VT>([&](auto L) { acc = fma_t(br[L], ue[L], acc); });
+          g[R] = acc;
+        });
+        T dv[S];
+        sfor<S>([&](auto C) {
+          const int f = i * S + C;
+          dv[C] = T(__builtin_nontemporal_load(dsc + (f / VEC) * 64 * VEC + (f % VEC)));
+        });
+        T h[NB];
+        dmul<NB, S>(dv, g, h);
+        if constexpr (ENERGY) sfor<NB>([&](auto R) { en = fma_t(g[R], h[R], en); });
+        sfor<NB>([&](auto R) {
+          const T* br = bt + (R * WT + i) * VT;
+          sfor<VT>([&](auto L) { ye[L] = fma_t(br[L], h[R], ye[L]); });
+        });
+      }
+    }
+    return en;
+  }
+};
+
+// Local indices of one cell: nlc 16-byte chunks of 8 uint16 slots, AoSoA by 64 cells.
+template <int VT>
+__device__ __forceinline__ void load_lidx(const uint16_t* __restrict__ lidx, int64_t w, int nlc, int lane,
+                                          int (&li)[VT]) {
+  const vec_t<uint32_t, 4>* p = reinterpret_cast<const vec_t<uint32_t, 4>*>(lidx) + (w * nlc) * 64 + lane;
+  sfor<(VT + 7) / 8>([&](auto C) {
+    const vec_t<uint32_t, 4> c = p[C * 64];
+    sfor<8>([&](auto J) {
+      constexpr int l = C * 8 + J;
+      if constexpr (l < VT) li[l] = int((c[J / 2] >> (16 * (J % 2))) & 0xffffu);
+    });
+  });
+}
+
+// Sum over the workgroup (any size that is a multiple of 64), result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < nw; ++i) s += red[i];
+  return s;
+}
+
+}  // namespace dev
+}  // namespace dogip

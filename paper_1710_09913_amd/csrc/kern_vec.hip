@@ -1,0 +1,211 @@
+// Vector kernels of the Jacobi-preconditioned CG (FP64 vectors and inner products).
+// Reductions are deterministic: a fixed grid of RED_BLOCKS x 256 threads writes
+// per-block partials, and a single 1024-thread block sums them in a fixed order.
+#include "kern_common.hpp"
+#include "solve.hpp"
+
+namespace dogip {
+namespace dev {
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Reduce up to 3 values over the block, thread 0 writes part[c * gridDim.x + blockIdx.x].
+__device__ __forceinline__ void block_partials(double* v, int nc, double* part) {
+  __shared__ double red[3][16];
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int c = 0; c < nc; ++c) {
+    const double s = wave_sum(v[c]);
+    if ((threadIdx.x & 63) == 0) red[c][w] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int c = 0; c < nc; ++c) {
+      double s = 0.0;
+      for (int i = 0; i < nw; ++i) s += red[c][i];
+      part[c * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// Sum n values (strided per thread, then tree) with one block; result in thread 0.
+__device__ __forceinline__ double block_total(const double* x, int64_t n) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += x[i];
+  s = wave_sum(s);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = s;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < nw; ++i) t += red[i];
+  __syncthreads();
+  return t;
+}
+
+#define GRID_STRIDE(i, n) \
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < (n); i += int64_t(gridDim.x) * blockDim.x)
+
+// r = b - y (y may be null: r = b), p = invd r; partials (r.z, r.r, b.b)
+__global__ __launch_bounds__(256) void k_pcg_init(const double* __restrict__ b, const double* __restrict__ y,
+                                                  const double* __restrict__ invd, double* __restrict__ r,
+                                                  double* __restrict__ p, int64_t n, double* __restrict__ part) {
+  double v[3] = {0.0, 0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    const double bi = b[i];
+    const double ri = y ? bi - y[i] : bi;
+    const double zi = invd[i] * ri;
+    r[i] = ri;
+    p[i] = zi;
+    v[0] += ri * zi;
+    v[1] += ri * ri;
+    v[2] += bi * bi;
+  }
+  block_partials(v, 3, part);
+}
+
+__global__ __launch_bounds__(1024) void k_fin_init(const double* __restrict__ part, int nparts, PcgScalars* s,
+                                                   double* hist) {
+  const double rz = block_total(part, nparts);
+  const double rr = block_total(part + nparts, nparts);
+  const double bb = block_total(part + 2 * nparts, nparts);
+  if (threadIdx.x == 0) {
+    s->rho = rz;
+    s->rr = rr;
+    s->bb = bb;
+    s->flags = (isfinite(rz) && isfinite(rr) && isfinite(bb)) ? 0 : PCG_NONFINITE;
+    hist[0] = rr;
+  }
+}
+
+// pq = sum of the apply's tile energies; alpha = rho / pq
+__global__ __launch_bounds__(1024) void k_fin_pq(const double* __restrict__ energy, int64_t ntiles, PcgScalars* s) {
+  const double pq = block_total(energy, ntiles);
+  if (threadIdx.x == 0) {
+    s->pq = pq;
+    if (!isfinite(pq))
+      s->flags |= PCG_NONFINITE;
+    else if (!(pq > 0.0))
+      s->flags |= PCG_BREAKDOWN;
+    s->alpha = (pq > 0.0 && s->flags == 0) ? s->rho / pq : 0.0;
+  }
+}
+
+// x += alpha p, r -= alpha q, z = invd r; partials (r.z, r.r)
+__global__ __launch_bounds__(256) void k_pcg_xr(double* __restrict__ x, double* __restrict__ r,
+                                                const double* __restrict__ p, const double* __restrict__ q,
+                                                const double* __restrict__ invd, const PcgScalars* __restrict__ s,
+                                                int64_t n, double* __restrict__ part) {
+  const double alpha = s->alpha;
+  double v[2] = {0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    x[i] = fma(alpha, p[i], x[i]);
+    const double ri = fma(-alpha, q[i], r[i]);
+    r[i] = ri;
+    v[0] += ri * (invd[i] * ri);
+    v[1] += ri * ri;
+  }
+  block_partials(v, 2, part);
+}
+
+__global__ __launch_bounds__(1024) void k_fin_rz(const double* __restrict__ part, int nparts, PcgScalars* s,
+                                                 double* hist, int it) {
+  const double rz = block_total(part, nparts);
+  const double rr = block_total(part + nparts, nparts);
+  if (threadIdx.x == 0) {
+    if (!isfinite(rz) || !isfinite(rr)) s->flags |= PCG_NONFINITE;
+    s->beta = (s->rho != 0.0 && s->flags == 0) ? rz / s->rho : 0.0;
+    s->rho = rz;
+    s->rr = rr;
+    hist[it] = s->flags ? -1.0 : rr;
+  }
+}
+
+// p = invd r + beta p
+__global__ __launch_bounds__(256) void k_pcg_p(double* __restrict__ p, const double* __restrict__ r,
+                                               const double* __restrict__ invd, const PcgScalars* __restrict__ s,
+                                               int64_t n) {
+  const double beta = s->beta;
+  GRID_STRIDE(i, n) p[i] = fma(beta, p[i], invd[i] * r[i]);
+}
+
+// r = b - y; partial r.r
+__global__ __launch_bounds__(256) void k_resid(const double* __restrict__ b, const double* __restrict__ y,
+                                               double* __restrict__ r, int64_t n, double* __restrict__ part) {
+  double v[1] = {0.0};
+  GRID_STRIDE(i, n) {
+    const double ri = b[i] - y[i];
+    r[i] = ri;
+    v[0] += ri * ri;
+  }
+  block_partials(v, 1, part);
+}
+
+// partial a.b
+__global__ __launch_bounds__(256) void k_dot(const double* __restrict__ a, const double* __restrict__ b, int64_t n,
+                                             double* __restrict__ part) {
+  double v[1] = {0.0};
+  GRID_STRIDE(i, n) v[0] += a[i] * b[i];
+  block_partials(v, 1, part);
+}
+
+__global__ __launch_bounds__(1024) void k_fin_sum(const double* __restrict__ part, int nparts, double* out) {
+  const double t = block_total(part, nparts);
+  if (threadIdx.x == 0) *out = t;
+}
+
+__global__ __launch_bounds__(256) void k_axpy1(double* __restrict__ x, const double* __restrict__ d, int64_t n) {
+  GRID_STRIDE(i, n) x[i] += d[i];
+}
+
+__global__ __launch_bounds__(256) void k_fill(double* __restrict__ x, double v, int64_t n) {
+  GRID_STRIDE(i, n) x[i] = v;
+}
+
+}  // namespace dev
+
+static unsigned red_grid(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g > RED_BLOCKS) g = RED_BLOCKS;
+  if (g < 1) g = 1;
+  return unsigned(g);
+}
+
+// The reduction kernels always run with RED_BLOCKS blocks so the partial layout is fixed.
+void vk_pcg_init(const double* b, const double* y, const double* invd, double* r, double* p, int64_t n, double* part,
+                 PcgScalars* s, double* hist, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_pcg_init, dim3(RED_BLOCKS), dim3(256), 0, st, b, y, invd, r, p, n, part);
+  hipLaunchKernelGGL(dev::k_fin_init, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, s, hist);
+}
+void vk_fin_pq(const double* energy, int64_t ntiles, PcgScalars* s, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_fin_pq, dim3(1), dim3(1024), 0, st, energy, ntiles, s);
+}
+void vk_pcg_xr(double* x, double* r, const double* p, const double* q, const double* invd, const PcgScalars* s,
+               int64_t n, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_pcg_xr, dim3(RED_BLOCKS), dim3(256), 0, st, x, r, p, q, invd, s, n, part);
+}
+void vk_fin_rz(const double* part, PcgScalars* s, double* hist, int it, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_fin_rz, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, s, hist, it);
+}
+void vk_pcg_p(double* p, const double* r, const double* invd, const PcgScalars* s, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_pcg_p, dim3(red_grid(n) * 4), dim3(256), 0, st, p, r, invd, s, n);
+}
+void vk_resid(const double* b, const double* y, double* r, int64_t n, double* part, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_resid, dim3(RED_BLOCKS), dim3(256), 0, st, b, y, r, n, part);
+  hipLaunchKernelGGL(dev::k_fin_sum, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, out);
+}
+void vk_dot(const double* a, const double* b, int64_t n, double* part, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_dot, dim3(RED_BLOCKS), dim3(256), 0, st, a, b, n, part);
+  hipLaunchKernelGGL(dev::k_fin_sum, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, out);
+}
+void vk_axpy1(double* x, const double* d, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_axpy1, dim3(red_grid(n) * 4), dim3(256), 0, st, x, d, n);
+}
+void vk_fill(double* x, double v, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_fill, dim3(red_grid(n) * 4), dim3(256), 0, st, x, v, n);
+}
+
+}  // namespace dogip

@@ -1,0 +1,291 @@
+// Operator construction and the apply / diagonal / gradient entry points.
+#include <algorithm>
+#include <cstring>
+
+#include "internal.hpp"
+#include "reftab.hpp"
+#include "solve.hpp"
+
+namespace dogip {
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    const int code = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? DOGIP_E_NOMEM : DOGIP_E_HIP;
+    throw Error(code, std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+
+void DevBuf::alloc(size_t n) {
+  free();
+  if (n == 0) return;
+  HIPCHK(hipMalloc(&p, n));
+  bytes = n;
+}
+void DevBuf::free() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+struct OpTimer {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  ~OpTimer() {
+    for (auto& e : ev) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+  }
+};
+
+bool launch_apply_unrolled_2d(int k, int kind, int prec, bool energy, const ApplyLaunch& a, hipStream_t st);
+bool launch_apply_unrolled_3d(int k, int kind, int prec, bool energy, const ApplyLaunch& a, hipStream_t st);
+bool launch_apply_looped_2d(int k, int kind, int prec, bool energy, const ApplyLaunch& a, hipStream_t st);
+bool launch_apply_looped_3d(int k, int kind, int prec, bool energy, const ApplyLaunch& a, hipStream_t st);
+
+bool has_unrolled(int dim, int k, int kind) {
+  if (dim == 2) return k <= 5;
+  return kind == KIND_SE ? k <= 3 : k <= 2;
+}
+
+bool launch_apply(int dim, int k, int kind, int prec, int variant, const ApplyLaunch& a, hipStream_t st) {
+  const bool en = a.energy != nullptr;
+  if (variant == DOGIP_VARIANT_UNROLLED)
+    return dim == 2 ? launch_apply_unrolled_2d(k, kind, prec, en, a, st)
+                    : launch_apply_unrolled_3d(k, kind, prec, en, a, st);
+  return dim == 2 ? launch_apply_looped_2d(k, kind, prec, en, a, st) : launch_apply_looped_3d(k, kind, prec, en, a, st);
+}
+
+Op::~Op() = default;
+
+template <class T>
+static void upload(DevBuf& b, const std::vector<T>& v) {
+  b.alloc(v.size() * sizeof(T));
+  if (!v.empty()) HIPCHK(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+static void check_coef(const Space& s, int coef_kind) {
+  DOGIP_CHECK(coef_kind >= DOGIP_COEF_SCALAR && coef_kind <= DOGIP_COEF_RAW_D, DOGIP_E_RANGE, "unknown coefficient form");
+  DOGIP_CHECK(!(coef_kind == DOGIP_COEF_SYM && s.kind == DOGIP_WP), DOGIP_E_RANGE,
+              "a tensor coefficient needs the elliptic problem");
+}
+
+static void build_d(Op& op, int coef_kind, const double* coef, hipStream_t st) {
+  const Space& s = *op.space;
+  BuildDLaunch b{};
+  b.xyz = op.xyz.as<double>();
+  b.cells = op.cells.as<int32_t>();
+  b.perm = op.perm.as<int32_t>();
+  b.what = op.what.as<double>();
+  b.coef = coef;
+  b.d64 = op.d64.as<double>();
+  b.d32 = op.has32 ? op.d32.as<float>() : nullptr;
+  b.nel = s.nc;
+  b.nel_pad = op.plan.nel_pad;
+  b.nch64 = op.nch64;
+  b.nch32 = op.nch32;
+  b.dim = s.dim;
+  b.kind = s.kind;
+  b.coef_kind = coef_kind;
+  b.wt = s.wt;
+  b.nsym = s.nsym;
+  launch_build_d(b, st);
+  HIPCHK(hipGetLastError());
+  // Jacobi diagonal -> inverse
+  DevBuf tmp(size_t(s.ndofs) * sizeof(double));
+  op_diag(op, tmp.as<double>(), st);
+  launch_invert(tmp.as<double>(), op.invdiag.as<double>(), s.ndofs, st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+std::unique_ptr<Op> make_op(std::shared_ptr<const Space> sp, int coef_kind, const double* coef, unsigned flags,
+                            int tile_waves, int variant, hipStream_t st) {
+  const Space& s = *sp;
+  check_coef(s, coef_kind);
+  DOGIP_CHECK(coef != nullptr, DOGIP_E_NULL, "null coefficient pointer");
+  DOGIP_CHECK(tile_waves >= 0 && tile_waves <= 8, DOGIP_E_RANGE, "tile_waves must be 0..8");
+  DOGIP_CHECK(variant >= DOGIP_VARIANT_AUTO && variant <= DOGIP_VARIANT_LOOPED, DOGIP_E_RANGE, "unknown variant");
+  auto op = std::make_unique<Op>();
+  op->space = sp;
+  op->has32 = (flags & DOGIP_OP_FP32) != 0;
+  if (variant == DOGIP_VARIANT_AUTO) variant = has_unrolled(s.dim, s.k, s.kind) ? DOGIP_VARIANT_UNROLLED : DOGIP_VARIANT_LOOPED;
+  DOGIP_CHECK(variant == DOGIP_VARIANT_LOOPED || has_unrolled(s.dim, s.k, s.kind), DOGIP_E_RANGE,
+              "no unrolled kernel for this (dim, k, kind)");
+  op->variant = variant;
+  // tile size: requested (default 4 waves), halved until the LDS arrays fit in 64 KB
+  int te = 64 * (tile_waves ? tile_waves : 4);
+  for (;;) {
+    op->plan = make_tiles(s, te);
+    if (op->plan.max_tile_dofs * 16 <= 65536 || te == 64) break;
+    te /= 2;
+  }
+  DOGIP_CHECK(op->plan.max_tile_dofs * 16 <= 65536, DOGIP_E_RANGE, "tile dofs exceed the LDS budget");
+  const TilePlan& p = op->plan;
+  op->nch64 = d_chunks(s.wt, s.nsym, 2);
+  op->nch32 = d_chunks(s.wt, s.nsym, 4);
+  const size_t ngrp = size_t(p.nel_pad / 64);
+  op->d64.alloc(ngrp * op->nch64 * 64 * 2 * sizeof(double));
+  HIPCHK(hipMemset(op->d64.p, 0, op->d64.bytes));
+  if (op->has32) {
+    op->d32.alloc(ngrp * op->nch32 * 64 * 4 * sizeof(float));
+    HIPCHK(hipMemset(op->d32.p, 0, op->d32.bytes));
+  }
+  upload(op->lidx, p.lidx);
+  upload(op->tile_off, p.tile_off);
+  upload(op->tile_dofs, p.tile_dofs);
+  upload(op->shared, p.shared);
+  upload(op->perm, p.perm);
+  const Mesh& m = *s.mesh;
+  std::vector<int32_t> cint(size_t(s.nc) * (s.dim + 1));
+  for (int64_t e = 0; e < s.nc; ++e)
+    std::memcpy(&cint[e * (s.dim + 1)], &m.cells[int64_t(p.perm[e]) * (s.dim + 1)], sizeof(int32_t) * (s.dim + 1));
+  upload(op->cells, cint);
+  upload(op->xyz, m.xyz);
+  upload(op->what, s.what);
+  op->invdiag.alloc(size_t(s.ndofs) * sizeof(double));
+  op->timer = std::make_unique<OpTimer>();
+  build_d(*op, coef_kind, coef, st);
+  return op;
+}
+
+void op_set_coef(Op& op, int coef_kind, const double* coef, hipStream_t st) {
+  check_coef(*op.space, coef_kind);
+  DOGIP_CHECK(coef != nullptr, DOGIP_E_NULL, "null coefficient pointer");
+  build_d(op, coef_kind, coef, st);
+}
+
+static ApplyLaunch apply_args(const Op& op, int prec) {
+  const Space& s = *op.space;
+  ApplyLaunch a{};
+  a.D = prec == DOGIP_F64 ? op.d64.p : op.d32.p;
+  a.lidx = op.lidx.as<uint16_t>();
+  a.tile_off = op.tile_off.as<int64_t>();
+  a.tile_dofs = op.tile_dofs.as<uint32_t>();
+  a.nel = s.nc;
+  a.ntiles = op.plan.ntiles;
+  a.nch = prec == DOGIP_F64 ? op.nch64 : op.nch32;
+  a.nlc = op.plan.nlc;
+  a.te = op.plan.te;
+  a.lds_slots = int(op.plan.max_tile_dofs);
+  a.tile_base = 0;
+  return a;
+}
+
+void op_apply(Op& op, const double* u, double* y, int prec, hipStream_t st, double* energy) {
+  const Space& s = *op.space;
+  DOGIP_CHECK(u && y, DOGIP_E_NULL, "null vector");
+  DOGIP_CHECK(u != y, DOGIP_E_INVALID, "apply needs u != y");
+  DOGIP_CHECK(prec == DOGIP_F64 || prec == DOGIP_F32, DOGIP_E_RANGE, "prec must be DOGIP_F64 or DOGIP_F32");
+  DOGIP_CHECK(prec == DOGIP_F64 || op.has32, DOGIP_E_STATE, "FP32 apply needs an operator built with DOGIP_OP_FP32");
+  launch_zero_indexed(y, op.shared.as<int32_t>(), int64_t(op.plan.shared.size()), st);
+  ApplyLaunch a = apply_args(op, prec);
+  a.u = u;
+  a.y = y;
+  a.energy = energy;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (op.timer->on) {
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, st));
+  }
+  DOGIP_CHECK(launch_apply(s.dim, s.k, s.kind, prec, op.variant, a, st), DOGIP_E_RANGE,
+              "no apply kernel for this (dim, k, kind, variant)");
+  HIPCHK(hipGetLastError());
+  if (op.timer->on) {
+    HIPCHK(hipEventRecord(e1, st));
+    op.timer->ev.push_back({e0, e1});
+  }
+}
+
+void op_diag(Op& op, double* diag, hipStream_t st) {
+  const Space& s = *op.space;
+  DOGIP_CHECK(diag != nullptr, DOGIP_E_NULL, "null output");
+  launch_zero_indexed(diag, op.shared.as<int32_t>(), int64_t(op.plan.shared.size()), st);
+  DiagLaunch a{};
+  a.D = op.d64.as<double>();
+  a.lidx = op.lidx.as<uint16_t>();
+  a.tile_off = op.tile_off.as<int64_t>();
+  a.tile_dofs = op.tile_dofs.as<uint32_t>();
+  a.out = diag;
+  a.nel = s.nc;
+  a.ntiles = op.plan.ntiles;
+  a.nch = op.nch64;
+  a.nlc = op.plan.nlc;
+  a.te = op.plan.te;
+  a.lds_slots = int(op.plan.max_tile_dofs);
+  launch_diag(s.dim, s.k, s.kind, a, st);
+  HIPCHK(hipGetLastError());
+}
+
+void op_grad(Op& op, const double* u, const double* lam, double* g, hipStream_t st) {
+  const Space& s = *op.space;
+  DOGIP_CHECK(u && lam && g, DOGIP_E_NULL, "null vector");
+  GradLaunch a{};
+  a.D = op.d64.as<double>();
+  a.lidx = op.lidx.as<uint16_t>();
+  a.tile_off = op.tile_off.as<int64_t>();
+  a.tile_dofs = op.tile_dofs.as<uint32_t>();
+  a.u = u;
+  a.lam = lam;
+  a.perm = op.perm.as<int32_t>();
+  a.g = g;
+  a.nel = s.nc;
+  a.ntiles = op.plan.ntiles;
+  a.nch = op.nch64;
+  a.nlc = op.plan.nlc;
+  a.te = op.plan.te;
+  a.lds_slots = int(op.plan.max_tile_dofs);
+  launch_grad(s.dim, s.k, s.kind, a, st);
+  HIPCHK(hipGetLastError());
+}
+
+void op_export_d(Op& op, double* out, hipStream_t st) {
+  const Space& s = *op.space;
+  DOGIP_CHECK(out != nullptr, DOGIP_E_NULL, "null output");
+  launch_export_d(op.d64.as<double>(), op.perm.as<int32_t>(), out, s.nc, op.nch64, s.wt, s.nsym, st);
+  HIPCHK(hipGetLastError());
+}
+
+dogip_op_info op_info(const Op& op) {
+  const Space& s = *op.space;
+  dogip_op_info i{};
+  i.tile_cells = op.plan.te;
+  i.variant = op.variant;
+  i.has_fp32 = op.has32;
+  i.ntiles = op.plan.ntiles;
+  i.tile_dofs_total = int64_t(op.plan.tile_dofs.size());
+  i.nshared = int64_t(op.plan.shared.size());
+  i.max_tile_dofs = op.plan.max_tile_dofs;
+  i.bytes_d64 = int64_t(op.d64.bytes);
+  i.bytes_d32 = int64_t(op.d32.bytes);
+  i.bytes_index = int64_t(op.lidx.bytes + op.tile_off.bytes + op.tile_dofs.bytes + op.shared.bytes);
+  const double nd = double(s.wt) * s.nsym * s.nc, conn = 4.0 * s.vt * s.nc, vec = 2.0 * 8.0 * s.ndofs;
+  i.alg_bytes_f64 = 8.0 * nd + conn + vec;
+  i.alg_bytes_f32 = 4.0 * nd + conn + vec;
+  // multiplications per cell as counted in eq. comp_eff, two flops each
+  const double mults = 2.0 * double(s.nnz_bhat - s.nnz_pm1) + double(s.kind == DOGIP_SE ? s.dim * s.dim : 1) * s.wt;
+  i.alg_flops = 2.0 * mults * double(s.nc);
+  return i;
+}
+
+void op_timer_enable(Op& op, bool on) { op.timer->on = on; }
+
+void op_timer_read(Op& op, double* ms, int64_t* count) {
+  double sum = 0.0;
+  for (auto& e : op.timer->ev) {
+    HIPCHK(hipEventSynchronize(e.second));
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, e.first, e.second));
+    sum += t;
+  }
+  if (ms) *ms = sum;
+  if (count) *count = int64_t(op.timer->ev.size());
+  for (auto& e : op.timer->ev) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  op.timer->ev.clear();
+}
+
+}  // namespace dogip

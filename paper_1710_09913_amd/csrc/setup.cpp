@@ -1,0 +1,406 @@
+// Host setup: meshes, the dof map of C_{N,k}, boundary dofs, reference tables and
+// the cell tiling used by the device kernels.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "internal.hpp"
+#include "reftab.hpp"
+
+namespace dogip {
+
+// ---------------------------------------------------------------- meshes
+
+static double cell_det(int dim, const double* X) {
+  // X: (dim+1) vertices of dim coordinates; R columns X_r - X_0
+  if (dim == 2) {
+    double a = X[2] - X[0], b = X[4] - X[0], c = X[3] - X[1], d = X[5] - X[1];
+    return a * d - b * c;
+  }
+  double r[3][3];
+  for (int x = 0; x < 3; ++x)
+    for (int c = 0; c < 3; ++c) r[x][c] = X[(c + 1) * 3 + x] - X[x];
+  return r[0][0] * (r[1][1] * r[2][2] - r[1][2] * r[2][1]) - r[0][1] * (r[1][0] * r[2][2] - r[1][2] * r[2][0]) +
+         r[0][2] * (r[1][0] * r[2][1] - r[1][1] * r[2][0]);
+}
+
+std::shared_ptr<Mesh> make_mesh(int dim, int64_t nv, const double* xyz, int64_t nc, const int32_t* cells) {
+  DOGIP_CHECK(dim == 2 || dim == 3, DOGIP_E_RANGE, "dim must be 2 or 3");
+  DOGIP_CHECK(nv > 0 && nc > 0, DOGIP_E_INVALID, "empty mesh");
+  DOGIP_CHECK(xyz && cells, DOGIP_E_NULL, "null coordinate or cell array");
+  DOGIP_CHECK(nv < (int64_t(1) << 31), DOGIP_E_RANGE, "too many vertices");
+  auto m = std::make_shared<Mesh>();
+  m->dim = dim;
+  m->nv = nv;
+  m->nc = nc;
+  m->xyz.assign(xyz, xyz + nv * dim);
+  m->cells.assign(cells, cells + nc * (dim + 1));
+  std::vector<uint8_t> used(nv, 0);
+  double X[12];
+  for (int64_t c = 0; c < nc; ++c) {
+    double hmax = 0;
+    for (int j = 0; j <= dim; ++j) {
+      int32_t v = m->cells[c * (dim + 1) + j];
+      DOGIP_CHECK(v >= 0 && v < nv, DOGIP_E_INVALID, "cell " + std::to_string(c) + " has an out-of-range vertex");
+      used[v] = 1;
+      for (int x = 0; x < dim; ++x) X[j * dim + x] = m->xyz[int64_t(v) * dim + x];
+    }
+    for (int a = 0; a <= dim; ++a)
+      for (int b = a + 1; b <= dim; ++b) {
+        double s = 0;
+        for (int x = 0; x < dim; ++x) s += (X[a * dim + x] - X[b * dim + x]) * (X[a * dim + x] - X[b * dim + x]);
+        hmax = std::max(hmax, std::sqrt(s));
+      }
+    double det = cell_det(dim, X);
+    DOGIP_CHECK(std::isfinite(det) && std::fabs(det) > 1e-14 * std::pow(hmax, dim), DOGIP_E_INVALID,
+                "cell " + std::to_string(c) + " is degenerate (det R_T = 0)");
+  }
+  for (int64_t v = 0; v < nv; ++v)
+    DOGIP_CHECK(used[v], DOGIP_E_INVALID, "vertex " + std::to_string(v) + " belongs to no cell");
+  return m;
+}
+
+std::shared_ptr<Mesh> make_unit_mesh(int dim, int n) {
+  DOGIP_CHECK(dim == 2 || dim == 3, DOGIP_E_RANGE, "dim must be 2 or 3");
+  DOGIP_CHECK(n >= 1 && n <= (dim == 2 ? 16384 : 1024), DOGIP_E_RANGE, "n out of range");
+  const int64_t m = n + 1;
+  const int64_t nv = dim == 2 ? m * m : m * m * m;
+  std::vector<double> xyz(nv * dim);
+  for (int64_t v = 0; v < nv; ++v) {
+    int64_t i = v % m, j = (v / m) % m, l = v / (m * m);
+    xyz[v * dim + 0] = double(i) / n;
+    xyz[v * dim + 1] = double(j) / n;
+    if (dim == 3) xyz[v * dim + 2] = double(l) / n;
+  }
+  std::vector<int32_t> cells;
+  if (dim == 2) {
+    cells.resize(int64_t(2) * n * n * 3);
+    int64_t c = 0;
+    for (int64_t j = 0; j < n; ++j)
+      for (int64_t i = 0; i < n; ++i) {
+        int32_t v00 = int32_t(i + m * j), v10 = v00 + 1, v01 = int32_t(v00 + m), v11 = v01 + 1;
+        int32_t t[6] = {v00, v10, v11, v00, v11, v01};
+        std::memcpy(&cells[c * 3], t, sizeof t);
+        c += 2;
+      }
+  } else {
+    cells.resize(int64_t(6) * n * n * n * 4);
+    const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    int64_t c = 0;
+    for (int64_t l = 0; l < n; ++l)
+      for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < n; ++i)
+          for (int p = 0; p < 6; ++p) {
+            int64_t o[3] = {i, j, l};
+            cells[c * 4 + 0] = int32_t(o[0] + m * (o[1] + m * o[2]));
+            for (int s = 0; s < 3; ++s) {
+              o[perms[p][s]] += 1;
+              cells[c * 4 + 1 + s] = int32_t(o[0] + m * (o[1] + m * o[2]));
+            }
+            ++c;
+          }
+  }
+  return make_mesh(dim, nv, xyz.data(), int64_t(cells.size()) / (dim + 1), cells.data());
+}
+
+// ---------------------------------------------------------------- reference tables
+
+void reference_tables(int dim, int k, int kind, std::vector<double>& bhat, std::vector<double>& what, int64_t& nnz,
+                      int64_t& nnz_pm1) {
+  const int vt = dim_p(dim, k), q = w_order(k, kind), wt = dim_p(dim, q), nb = kind == KIND_SE ? dim : 1;
+  bhat.assign(size_t(nb) * wt * vt, 0.0);
+  what.assign(wt, 0.0);
+  nnz = nnz_pm1 = 0;
+  for (int r = 0; r < nb; ++r)
+    for (int i = 0; i < wt; ++i)
+      for (int l = 0; l < vt; ++l) {
+        ref::Q v = ref::bhat_entry(dim, k, kind, r, i, l);
+        bhat[(size_t(r) * wt + i) * vt + l] = ref::to_double(v);
+        if (!ref::is_zero(v)) ++nnz;
+        if (v.d == 1 && (v.n == 1 || v.n == -1)) ++nnz_pm1;
+      }
+  for (int i = 0; i < wt; ++i) what[i] = ref::to_double(ref::what_entry(dim, q, i));
+}
+
+// ---------------------------------------------------------------- dof map
+
+namespace {
+
+struct EntityIds {
+  std::vector<int32_t> cell_ent;  // [nc][n_local] entity id
+  std::vector<int32_t> count;     // cells per entity
+  int64_t n = 0;
+};
+
+// Number the distinct vertex tuples (sorted) taken from each cell: local tuples
+// are given by lists of local vertex indices.
+template <int NV>
+EntityIds number_entities(const Mesh& m, const std::vector<std::array<int, NV>>& loc) {
+  const int d1 = m.dim + 1, nl = int(loc.size());
+  struct Key {
+    std::array<int32_t, NV> v;
+    int64_t slot;
+  };
+  std::vector<Key> keys(size_t(m.nc) * nl);
+  for (int64_t c = 0; c < m.nc; ++c)
+    for (int e = 0; e < nl; ++e) {
+      Key& k = keys[size_t(c) * nl + e];
+      for (int t = 0; t < NV; ++t) k.v[t] = m.cells[c * d1 + loc[e][t]];
+      std::sort(k.v.begin(), k.v.end());
+      k.slot = c * nl + e;
+    }
+  std::sort(keys.begin(), keys.end(), [](const Key& a, const Key& b) { return a.v < b.v; });
+  EntityIds ids;
+  ids.cell_ent.assign(size_t(m.nc) * nl, -1);
+  int64_t id = -1;
+  for (size_t i = 0; i < keys.size(); ++i) {
+    if (i == 0 || keys[i].v != keys[i - 1].v) {
+      ++id;
+      ids.count.push_back(0);
+    }
+    ids.cell_ent[keys[i].slot] = int32_t(id);
+    ids.count[id]++;
+  }
+  ids.n = id + 1;
+  return ids;
+}
+
+int tri_index(int i, int j, int n) { return i * (n + 1) - i * (i - 1) / 2 + j; }
+
+}  // namespace
+
+std::shared_ptr<Space> make_space(std::shared_ptr<const Mesh> mesh, int k, int kind, int bc) {
+  const Mesh& m = *mesh;
+  const int d = m.dim, d1 = d + 1;
+  DOGIP_CHECK(kind == DOGIP_WP || kind == DOGIP_SE, DOGIP_E_RANGE, "kind must be DOGIP_WP or DOGIP_SE");
+  DOGIP_CHECK(bc == DOGIP_BC_NONE || bc == DOGIP_BC_DIRICHLET0, DOGIP_E_RANGE, "unknown boundary condition");
+  DOGIP_CHECK(k >= 1 && k <= (d == 2 ? 8 : 4), DOGIP_E_RANGE, "k must be in 1..8 (2D) or 1..4 (3D)");
+  auto s = std::make_shared<Space>();
+  s->mesh = mesh;
+  s->dim = d;
+  s->k = k;
+  s->kind = kind;
+  s->bc = bc;
+  s->nc = m.nc;
+  s->vt = dim_p(d, k);
+  s->wt = dim_p(d, w_order(k, kind));
+  s->nsym = kind == KIND_SE ? n_sym(d) : 1;
+  s->nb = kind == KIND_SE ? d : 1;
+  reference_tables(d, k, kind, s->bhat, s->what, s->nnz_bhat, s->nnz_pm1);
+
+  // local edges (pairs) and facets
+  std::vector<std::array<int, 2>> ledges;
+  for (int a = 0; a <= d; ++a)
+    for (int b = a + 1; b <= d; ++b) ledges.push_back({a, b});
+  EntityIds E = number_entities<2>(m, ledges);
+  EntityIds F;
+  std::vector<std::array<int, 3>> lfaces;  // face opposite local vertex j (3D)
+  if (d == 3) {
+    for (int j = 0; j < 4; ++j) {
+      std::array<int, 3> f{};
+      int t = 0;
+      for (int a = 0; a < 4; ++a)
+        if (a != j) f[t++] = a;
+      lfaces.push_back(f);
+    }
+    F = number_entities<3>(m, lfaces);
+  }
+  const int64_t ne1 = k - 1, nf1 = d == 3 ? int64_t(k - 1) * (k - 2) / 2 : 0;
+  const int64_t nint = d == 2 ? int64_t(k - 1) * (k - 2) / 2 : int64_t(k - 1) * (k - 2) * (k - 3) / 6;
+  const int64_t base_e = m.nv, base_f = base_e + E.n * ne1, base_c = base_f + (d == 3 ? F.n * nf1 : 0);
+  s->ndofs = base_c + m.nc * nint;
+  DOGIP_CHECK(s->ndofs <= int64_t(TD_MASK), DOGIP_E_RANGE, "too many dofs for the tile encoding");
+
+  // local node barycentric indices and interior ordinals
+  const int vt = s->vt;
+  std::vector<std::array<int, 4>> bv(vt);
+  std::vector<int> iord(vt, -1);
+  int cnt = 0;
+  for (int l = 0; l < vt; ++l) {
+    int b[4] = {0, 0, 0, 0};
+    ref::bary_index(d, k, l, b);
+    bool inner = true;
+    for (int j = 0; j < 4; ++j) bv[l][j] = b[j];
+    for (int j = 0; j <= d; ++j) inner = inner && b[j] > 0;
+    if (inner) iord[l] = cnt++;
+  }
+  auto edge_local = [&](int a, int b) {
+    for (size_t e = 0; e < ledges.size(); ++e)
+      if ((ledges[e][0] == a && ledges[e][1] == b) || (ledges[e][0] == b && ledges[e][1] == a)) return int(e);
+    return -1;
+  };
+
+  s->cell_dofs.assign(size_t(m.nc) * vt, -1);
+  s->dof_xyz.assign(size_t(s->ndofs) * d, 0.0);
+  s->is_bnd.assign(s->ndofs, 0);
+  const int nle = int(ledges.size());
+  for (int64_t c = 0; c < m.nc; ++c) {
+    const int32_t* cv = &m.cells[c * d1];
+    // boundary facets of this cell: facet opposite local vertex j
+    bool fb[4] = {false, false, false, false};
+    for (int j = 0; j <= d; ++j) {
+      if (d == 2) {
+        int a = (j + 1) % 3, b = (j + 2) % 3;
+        fb[j] = E.count[E.cell_ent[c * nle + edge_local(a, b)]] == 1;
+      } else {
+        fb[j] = F.count[F.cell_ent[c * 4 + j]] == 1;
+      }
+    }
+    for (int l = 0; l < vt; ++l) {
+      int sup[4], mult[4], ns = 0;
+      for (int j = 0; j <= d; ++j)
+        if (bv[l][j] > 0) {
+          sup[ns] = j;
+          mult[ns] = bv[l][j];
+          ++ns;
+        }
+      int64_t dof;
+      if (ns == 1) {
+        dof = cv[sup[0]];
+      } else if (ns == 2) {
+        int a = sup[0], b = sup[1];
+        int64_t eid = E.cell_ent[c * nle + edge_local(a, b)];
+        int mb = cv[a] < cv[b] ? mult[1] : mult[0];  // multiplicity at the larger vertex id
+        dof = base_e + eid * ne1 + (mb - 1);
+      } else if (ns == 3 && d == 3) {
+        int opp = 0;
+        for (int j = 0; j < 4; ++j)
+          if (bv[l][j] == 0) opp = j;
+        int64_t fid = F.cell_ent[c * 4 + opp];
+        // order the three (vertex, multiplicity) pairs by vertex id
+        std::array<std::pair<int32_t, int>, 3> vm = {
+            std::make_pair(cv[sup[0]], mult[0]), std::make_pair(cv[sup[1]], mult[1]),
+            std::make_pair(cv[sup[2]], mult[2])};
+        std::sort(vm.begin(), vm.end());
+        dof = base_f + fid * nf1 + tri_index(vm[1].second - 1, vm[2].second - 1, k - 3);
+      } else {
+        dof = base_c + c * nint + iord[l];
+      }
+      s->cell_dofs[c * vt + l] = int32_t(dof);
+      // coordinates, summed in ascending vertex-id order so every cell gives the same bits
+      std::array<std::pair<int32_t, int>, 4> vw;
+      for (int t = 0; t < ns; ++t) vw[t] = {cv[sup[t]], mult[t]};
+      std::sort(vw.begin(), vw.begin() + ns);
+      for (int x = 0; x < d; ++x) {
+        double acc = 0.0;
+        for (int t = 0; t < ns; ++t) acc += (double(vw[t].second) / k) * m.xyz[int64_t(vw[t].first) * d + x];
+        s->dof_xyz[dof * d + x] = acc;
+      }
+      for (int j = 0; j <= d; ++j)
+        if (bv[l][j] == 0 && fb[j]) s->is_bnd[dof] = 1;
+    }
+  }
+  if (bc == DOGIP_BC_DIRICHLET0) {
+    for (int64_t i = 0; i < s->ndofs; ++i)
+      if (s->is_bnd[i]) s->boundary.push_back(int32_t(i));
+  } else {
+    std::fill(s->is_bnd.begin(), s->is_bnd.end(), 0);
+  }
+  return s;
+}
+
+// ---------------------------------------------------------------- tiling
+
+static uint64_t spread3(uint64_t x) {  // 21 bits -> every third bit
+  x &= 0x1fffff;
+  x = (x | x << 32) & 0x1f00000000ffffULL;
+  x = (x | x << 16) & 0x1f0000ff0000ffULL;
+  x = (x | x << 8) & 0x100f00f00f00f00fULL;
+  x = (x | x << 4) & 0x10c30c30c30c30c3ULL;
+  x = (x | x << 2) & 0x1249249249249249ULL;
+  return x;
+}
+static uint64_t spread2(uint64_t x) {  // 32 bits -> every second bit
+  x &= 0xffffffffULL;
+  x = (x | x << 16) & 0x0000ffff0000ffffULL;
+  x = (x | x << 8) & 0x00ff00ff00ff00ffULL;
+  x = (x | x << 4) & 0x0f0f0f0f0f0f0f0fULL;
+  x = (x | x << 2) & 0x3333333333333333ULL;
+  x = (x | x << 1) & 0x5555555555555555ULL;
+  return x;
+}
+
+TilePlan make_tiles(const Space& s, int te) {
+  const Mesh& m = *s.mesh;
+  const int d = m.dim, d1 = d + 1, vt = s.vt;
+  TilePlan p;
+  p.te = te;
+  p.ntiles = (s.nc + te - 1) / te;
+  p.nel_pad = p.ntiles * te;
+  // Morton order of cell centroids
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t v = 0; v < m.nv; ++v)
+    for (int x = 0; x < d; ++x) {
+      lo[x] = std::min(lo[x], m.xyz[v * d + x]);
+      hi[x] = std::max(hi[x], m.xyz[v * d + x]);
+    }
+  const double bits = d == 3 ? 2097151.0 : 4294967295.0;
+  std::vector<std::pair<uint64_t, int32_t>> key(s.nc);
+  for (int64_t c = 0; c < s.nc; ++c) {
+    uint64_t code = 0;
+    for (int x = 0; x < d; ++x) {
+      double cx = 0;
+      for (int j = 0; j < d1; ++j) cx += m.xyz[int64_t(m.cells[c * d1 + j]) * d + x];
+      cx /= d1;
+      double t = hi[x] > lo[x] ? (cx - lo[x]) / (hi[x] - lo[x]) : 0.0;
+      uint64_t qv = uint64_t(std::min(std::max(t, 0.0), 1.0) * bits);
+      code |= (d == 3 ? spread3(qv) : spread2(qv)) << x;
+    }
+    key[c] = {code, int32_t(c)};
+  }
+  std::sort(key.begin(), key.end());
+  p.perm.resize(s.nc);
+  for (int64_t c = 0; c < s.nc; ++c) p.perm[c] = key[c].second;
+
+  p.nlc = (vt + 7) / 8;
+  p.lidx.assign(size_t(p.nel_pad / 64) * p.nlc * 64 * 8, 0);
+  p.tile_off.assign(p.ntiles + 1, 0);
+  std::vector<int32_t> ntile_of(s.ndofs, 0), first_tile(s.ndofs, -1), slot(s.ndofs, -1);
+  std::vector<int32_t> tmp;
+  std::vector<int32_t> all;  // concatenated tile lists (dof only)
+  all.reserve(size_t(s.nc) * vt / 2);
+  for (int64_t t = 0; t < p.ntiles; ++t) {
+    const int64_t e0 = t * te, e1 = std::min<int64_t>(s.nc, e0 + te);
+    tmp.clear();
+    for (int64_t e = e0; e < e1; ++e) {
+      const int32_t* cd = &s.cell_dofs[int64_t(p.perm[e]) * vt];
+      tmp.insert(tmp.end(), cd, cd + vt);
+    }
+    std::sort(tmp.begin(), tmp.end());
+    tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+    DOGIP_CHECK(tmp.size() <= 65535, DOGIP_E_RANGE, "tile touches too many dofs");
+    for (size_t j = 0; j < tmp.size(); ++j) {
+      int32_t dof = tmp[j];
+      slot[dof] = int32_t(j);
+      ntile_of[dof]++;
+      if (first_tile[dof] < 0) first_tile[dof] = int32_t(t);
+    }
+    for (int64_t e = e0; e < e1; ++e) {
+      const int32_t* cd = &s.cell_dofs[int64_t(p.perm[e]) * vt];
+      for (int l = 0; l < vt; ++l) {
+        size_t at = ((size_t(e >> 6) * p.nlc + l / 8) * 64 + (e & 63)) * 8 + (l % 8);
+        p.lidx[at] = uint16_t(slot[cd[l]]);
+      }
+    }
+    all.insert(all.end(), tmp.begin(), tmp.end());
+    p.tile_off[t + 1] = int64_t(all.size());
+    p.max_tile_dofs = std::max<int64_t>(p.max_tile_dofs, int64_t(tmp.size()));
+  }
+  p.tile_dofs.resize(all.size());
+  for (int64_t t = 0; t < p.ntiles; ++t)
+    for (int64_t j = p.tile_off[t]; j < p.tile_off[t + 1]; ++j) {
+      int32_t dof = all[j];
+      uint32_t v = uint32_t(dof);
+      if (s.is_bnd[dof]) v |= TD_BND;
+      if (ntile_of[dof] > 1) v |= TD_SHARED;
+      if (first_tile[dof] == t) v |= TD_OWNER;
+      p.tile_dofs[j] = v;
+    }
+  for (int64_t i = 0; i < s.ndofs; ++i)
+    if (ntile_of[i] > 1 && !s.is_bnd[i]) p.shared.push_back(int32_t(i));
+  return p;
+}
+
+}  // namespace dogip

@@ -1,0 +1,235 @@
+// Jacobi-preconditioned conjugate gradients and FP64 iterative refinement around
+// an FP32-apply inner CG.  The paper leaves the solver open (Section 1: a
+// suitable iterative solver); CG fits because A is symmetric positive definite.
+//
+// All scalars live on the device; the host only reads the residual history
+// every check_every iterations, so iterations are queued back to back.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "internal.hpp"
+#include "solve.hpp"
+
+namespace dogip {
+
+static PcgWork& work(Op& op, int maxit) {
+  const int64_t n = op.space->ndofs;
+  if (!op.pcg || op.pcg->maxit < maxit) {
+    auto w = std::make_unique<PcgWork>();
+    w->n = n;
+    w->maxit = maxit;
+    const size_t vb = size_t(n) * sizeof(double);
+    w->r.alloc(vb);
+    w->p.alloc(vb);
+    w->q.alloc(vb);
+    w->rout.alloc(vb);
+    w->dx.alloc(vb);
+    w->yout.alloc(vb);
+    w->part.alloc(size_t(3) * RED_BLOCKS * sizeof(double));
+    w->energy.alloc(size_t(op.plan.ntiles) * sizeof(double));
+    w->scal.alloc(sizeof(PcgScalars));
+    w->nrm.alloc(sizeof(double));
+    w->hist.alloc(size_t(maxit + 2) * sizeof(double));
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&w->hhist), size_t(maxit + 2) * sizeof(double), hipHostMallocDefault));
+    op.pcg = std::move(w);
+  }
+  return *op.pcg;
+}
+
+struct CgResult {
+  int status = DOGIP_OK;
+  int iters = 0;
+  double relres = 0.0;
+  double bnorm = 0.0;
+};
+
+// One Jacobi-PCG run on A x = b (x holds the initial guess when x0_given).
+// Stops when ||r|| <= tol ||b|| (recursive residual) or after maxit iterations.
+static CgResult cg_run(Op& op, const double* b, double* x, bool x0_given, double tol, int maxit, int prec,
+                       int check_every, hipStream_t st) {
+  PcgWork& w = work(op, std::max(maxit, 1));
+  const int64_t n = op.space->ndofs;
+  double* r = w.r.as<double>();
+  double* p = w.p.as<double>();
+  double* q = w.q.as<double>();
+  double* part = w.part.as<double>();
+  double* hist = w.hist.as<double>();
+  auto* sc = w.scal.as<PcgScalars>();
+  const double* invd = op.invdiag.as<double>();
+  if (x0_given) {
+    op_apply(op, x, q, DOGIP_F64, st);
+    vk_pcg_init(b, q, invd, r, p, n, part, sc, hist, st);
+  } else {
+    vk_fill(x, 0.0, n, st);
+    vk_pcg_init(b, nullptr, invd, r, p, n, part, sc, hist, st);
+  }
+  PcgScalars hs{};
+  HIPCHK(hipMemcpyAsync(&hs, sc, sizeof hs, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  CgResult res;
+  res.bnorm = std::sqrt(hs.bb);
+  if (hs.flags) {
+    res.status = DOGIP_E_NONFINITE;
+    return res;
+  }
+  if (hs.bb == 0.0) {
+    vk_fill(x, 0.0, n, st);
+    return res;
+  }
+  const double thr = tol * tol * hs.bb;
+  if (hs.rr <= thr) {
+    res.relres = std::sqrt(hs.rr / hs.bb);
+    return res;
+  }
+  int it = 0;
+  int step = std::max(1, check_every);
+  for (;;) {
+    const int todo = std::min(step, maxit - it);
+    for (int j = 0; j < todo; ++j) {
+      op_apply(op, p, q, prec, st, w.energy.as<double>());
+      vk_fin_pq(w.energy.as<double>(), op.plan.ntiles, sc, st);
+      vk_pcg_xr(x, r, p, q, invd, sc, n, part, st);
+      vk_fin_rz(part, sc, hist, it + j + 1, st);
+      vk_pcg_p(p, r, invd, sc, n, st);
+    }
+    HIPCHK(hipMemcpyAsync(w.hhist + it + 1, hist + it + 1, sizeof(double) * todo, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int conv = -1;
+    for (int j = 1; j <= todo; ++j) {
+      const double rr = w.hhist[it + j];
+      if (rr < 0.0 || !std::isfinite(rr)) {
+        HIPCHK(hipMemcpy(&hs, sc, sizeof hs, hipMemcpyDeviceToHost));
+        res.status = (hs.flags & PCG_BREAKDOWN) ? DOGIP_E_BREAKDOWN : DOGIP_E_NONFINITE;
+        res.iters = it + j;
+        return res;
+      }
+      if (rr <= thr) {
+        conv = j;
+        break;
+      }
+    }
+    it += todo;
+    const double last = w.hhist[it];
+    res.relres = std::sqrt(std::max(last, 0.0) / hs.bb);
+    if (conv > 0) {
+      res.iters = it;
+      return res;
+    }
+    if (it >= maxit) {
+      res.iters = it;
+      res.status = DOGIP_E_NOT_CONVERGED;
+      return res;
+    }
+    // predict the iterations still needed from the recent convergence rate
+    const double first = w.hhist[it - todo + 1] > 0 ? w.hhist[it - todo + 1] : last;
+    if (todo > 1 && last > 0 && first > last) {
+      const double rate = std::log(last / first) / (todo - 1);
+      const double need = std::log(thr / last) / rate;
+      step = int(std::min<double>(std::max<double>(need * 0.9, 1.0), double(std::max(8, check_every * 4))));
+    } else {
+      step = std::max(1, check_every);
+    }
+  }
+}
+
+// ||b - A x|| with the FP64 apply; writes the residual into r.
+static double true_residual(Op& op, const double* b, const double* x, double* r, hipStream_t st) {
+  PcgWork& w = *op.pcg;
+  op_apply(op, x, w.yout.as<double>(), DOGIP_F64, st);
+  vk_resid(b, w.yout.as<double>(), r, op.space->ndofs, w.part.as<double>(), w.nrm.as<double>(), st);
+  double rr = 0.0;
+  HIPCHK(hipMemcpyAsync(&rr, w.nrm.p, sizeof rr, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return std::sqrt(rr);
+}
+
+// ||a||^2 (deterministic reduction).
+static double norm2(Op& op, const double* a, hipStream_t st) {
+  PcgWork& w = *op.pcg;
+  vk_dot(a, a, op.space->ndofs, w.part.as<double>(), w.nrm.as<double>(), st);
+  double v = 0.0;
+  HIPCHK(hipMemcpyAsync(&v, w.nrm.p, sizeof v, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return v;
+}
+
+int op_pcg(Op& op, const double* b, double* x, const dogip_solve_opts& o, dogip_solve_stats& stats, hipStream_t st) {
+  DOGIP_CHECK(b && x, DOGIP_E_NULL, "null vector");
+  DOGIP_CHECK(b != x, DOGIP_E_INVALID, "b and x must differ");
+  DOGIP_CHECK(o.tol > 0.0 && o.maxit >= 1, DOGIP_E_RANGE, "tol must be > 0 and maxit >= 1");
+  DOGIP_CHECK(o.mode == DOGIP_SOLVE_F64 || o.mode == DOGIP_SOLVE_MIXED, DOGIP_E_RANGE, "unknown solve mode");
+  DOGIP_CHECK(o.mode == DOGIP_SOLVE_F64 || op.has32, DOGIP_E_STATE, "mixed mode needs DOGIP_OP_FP32");
+  const auto t0 = std::chrono::steady_clock::now();
+  std::memset(&stats, 0, sizeof stats);
+  const int check = o.check_every > 0 ? o.check_every : 16;
+  PcgWork& w = work(op, o.maxit);
+  int status = DOGIP_OK;
+  if (o.mode == DOGIP_SOLVE_F64) {
+    CgResult c = cg_run(op, b, x, o.x0_given != 0, o.tol, o.maxit, DOGIP_F64, check, st);
+    status = c.status;
+    stats.iters = c.iters;
+    stats.outer = 1;
+    stats.relres = c.relres;
+  } else {
+    // FP64 iterative refinement: r = b - A64 x; A32 d ~= r by inner PCG; x += d.
+    const int64_t n = op.space->ndofs;
+    double* rout = w.rout.as<double>();
+    double* dx = w.dx.as<double>();
+    const double bn = std::sqrt(norm2(op, b, st));
+    if (o.x0_given) {
+      stats.relres = bn > 0 ? true_residual(op, b, x, rout, st) / bn : 0.0;
+    } else {
+      vk_fill(x, 0.0, n, st);
+      HIPCHK(hipMemcpyAsync(rout, b, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, st));
+      stats.relres = bn > 0 ? 1.0 : 0.0;
+    }
+    const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-5;
+    const int max_outer = o.max_outer > 0 ? o.max_outer : 20;
+    int total = 0;
+    for (int outer = 0; outer < max_outer; ++outer) {
+      if (bn == 0.0 || stats.relres <= o.tol) break;
+      const double want = std::max(inner_tol, 0.3 * o.tol / stats.relres);
+      CgResult c = cg_run(op, rout, dx, false, want, std::max(1, o.maxit - total), DOGIP_F32, check, st);
+      total += c.iters;
+      stats.outer = outer + 1;
+      if (c.status == DOGIP_E_BREAKDOWN || c.status == DOGIP_E_NONFINITE) {
+        status = c.status;
+        break;
+      }
+      vk_axpy1(x, dx, n, st);
+      const double rn = true_residual(op, b, x, rout, st);
+      const double prev = stats.relres;
+      stats.relres = rn / bn;
+      if (!std::isfinite(stats.relres)) {
+        status = DOGIP_E_NONFINITE;
+        break;
+      }
+      if (total >= o.maxit && stats.relres > o.tol) {
+        status = DOGIP_E_NOT_CONVERGED;
+        break;
+      }
+      if (stats.relres > 0.9 * prev && stats.relres > o.tol) {
+        // stagnation of the refinement: finish with FP64 CG from the current x
+        CgResult f = cg_run(op, b, x, true, o.tol, std::max(1, o.maxit - total), DOGIP_F64, check, st);
+        total += f.iters;
+        status = f.status;
+        stats.relres = f.relres;
+        break;
+      }
+    }
+    stats.iters = total;
+    if (status == DOGIP_OK && stats.relres > o.tol) status = DOGIP_E_NOT_CONVERGED;
+  }
+  // verified residual with the FP64 apply
+  if (status == DOGIP_OK || status == DOGIP_E_NOT_CONVERGED) {
+    const double bn = std::sqrt(norm2(op, b, st));
+    stats.relres_true = bn > 0 ? true_residual(op, b, x, w.rout.as<double>(), st) / bn : 0.0;
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  stats.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  stats.status = status;
+  return status;
+}
+
+}  // namespace dogip

@@ -1,0 +1,48 @@
+// Device-side state of the CG solver and the vector kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include "internal.hpp"
+
+namespace dogip {
+
+constexpr int RED_BLOCKS = 1024;  // fixed reduction grid (deterministic partial sums)
+constexpr int PCG_BREAKDOWN = 1;
+constexpr int PCG_NONFINITE = 2;
+
+struct PcgScalars {
+  double rho;    // r . z
+  double rr;     // r . r
+  double bb;     // b . b
+  double pq;     // p . A p
+  double alpha, beta;
+  int flags;
+  int pad;
+};
+
+// Device workspace of the CG solver, owned by the operator.
+struct PcgWork {
+  int64_t n = 0;
+  int maxit = 0;
+  DevBuf r, p, q, part, energy, scal, hist, rout, dx, yout, nrm;
+  double* hhist = nullptr;  // pinned mirror of hist
+  ~PcgWork() {
+    if (hhist) (void)hipHostFree(hhist);
+  }
+};
+
+void vk_pcg_init(const double* b, const double* y, const double* invd, double* r, double* p, int64_t n, double* part,
+                 PcgScalars* s, double* hist, hipStream_t st);
+void vk_fin_pq(const double* energy, int64_t ntiles, PcgScalars* s, hipStream_t st);
+void vk_pcg_xr(double* x, double* r, const double* p, const double* q, const double* invd, const PcgScalars* s,
+               int64_t n, double* part, hipStream_t st);
+void vk_fin_rz(const double* part, PcgScalars* s, double* hist, int it, hipStream_t st);
+void vk_pcg_p(double* p, const double* r, const double* invd, const PcgScalars* s, int64_t n, hipStream_t st);
+void vk_resid(const double* b, const double* y, double* r, int64_t n, double* part, double* out, hipStream_t st);
+void vk_dot(const double* a, const double* b, int64_t n, double* part, double* out, hipStream_t st);
+void vk_axpy1(double* x, const double* d, int64_t n, hipStream_t st);
+void vk_fill(double* x, double v, int64_t n, hipStream_t st);
+
+}  // namespace dogip

@@ -1,0 +1,113 @@
+"""GPU solves (FP64 PCG, mixed refinement) and the adjoint gradient against the oracle."""
+
+import numpy as np
+import pytest
+
+from helpers import match_dofs, rel_err
+from oracle import adjoint, dogip as odg, fem, solve
+from workloads import coef_uniform, theta_normal, unit_mesh
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _gpu(v):
+    return torch.from_numpy(np.ascontiguousarray(v)).cuda()
+
+
+def _c1(jitter=0.0, seed=0):
+    """2D 16x16 P2 elliptic, a ~ U[1, 10], f = 1, zero Dirichlet."""
+    from paper_1710_09913_amd import Mesh, Operator, Space
+
+    coords, cells = unit_mesh(2, 16, jitter=jitter, seed=seed)
+    a = coef_uniform(len(cells), 1.0, 10.0, seed)
+    sp = Space(Mesh(coords, cells), 2, "se", "dirichlet")
+    op = Operator(sp, torch.from_numpy(a), "scalar", fp32=True)
+    osp = fem.make_space(coords, cells, 2)
+    perm = match_dofs(sp.dof_coords(), osp.dof_coords)
+    A = fem.assemble(osp, fem.element_matrices(osp, a, "se"))
+    b = fem.load_vector(osp, 1.0)
+    b[osp.boundary] = 0.0
+    return sp, op, osp, perm, A, b
+
+
+@pytest.mark.parametrize("jitter", [0.0, 0.12])
+def test_pcg_f64_matches_direct(jitter):
+    print(f"[pcg f64] jitter={jitter}", flush=True)
+    sp, op, osp, perm, A, b = _c1(jitter, seed=1)
+    x_lu = solve.direct_dirichlet(A, b, osp.boundary)
+    x, st = op.pcg(_gpu(b[perm]), tol=1e-10, maxit=5000)
+    assert st["status"] == 0
+    assert st["relres_true"] <= 1.05e-10
+    Ab = solve.dirichlet_matrix(A, osp.boundary).toarray()
+    ev = np.linalg.eigvalsh(Ab)
+    kappa = ev.max() / ev.min()
+    assert rel_err(x.cpu().numpy(), x_lu[perm]) <= 2 * kappa * 1e-10
+    # the oracle's CG on the oracle's operator takes a comparable number of steps
+    D = odg.build_d(osp, coef_uniform(len(osp.cells), 1.0, 10.0, 1), "se")
+    _, it_o, _ = solve.pcg(lambda v: odg.apply_dirichlet(osp, D, v, "se"), b,
+                           odg.diagonal(osp, D, "se", True), 1e-10)
+    assert abs(st["iters"] - it_o) <= max(5, 0.1 * it_o)
+
+
+def test_pcg_mixed_reaches_fp64_accuracy():
+    sp, op, osp, perm, A, b = _c1(0.1, seed=2)
+    x_lu = solve.direct_dirichlet(A, b, osp.boundary)
+    x, st = op.pcg(_gpu(b[perm]), tol=1e-10, maxit=5000, mode="mixed", inner_tol=1e-4)
+    print(st, flush=True)
+    assert st["status"] == 0
+    assert st["relres_true"] <= 1e-10
+    assert st["outer"] >= 2
+    Ab = solve.dirichlet_matrix(A, osp.boundary).toarray()
+    ev = np.linalg.eigvalsh(Ab)
+    assert rel_err(x.cpu().numpy(), x_lu[perm]) <= 2 * (ev.max() / ev.min()) * 1e-10
+
+
+def test_pcg_status_codes():
+    from paper_1710_09913_amd import Mesh, Operator, Space
+
+    sp, op, osp, perm, A, b = _c1()
+    _, st = op.pcg(_gpu(b[perm]), tol=1e-12, maxit=3, raise_on_error=False)
+    assert st["status"] == 6 and st["iters"] == 3  # not converged
+    bad = b[perm].copy()
+    bad[5] = np.nan
+    _, st = op.pcg(_gpu(bad), tol=1e-8, maxit=50, raise_on_error=False)
+    assert st["status"] == 8  # non-finite
+    # an indefinite D makes p^T A p <= 0 at some step: CG reports a breakdown
+    s2 = Space(Mesh.unit(2, 4), 2, "se", "dirichlet")
+    a = -np.ones(32)
+    op2 = Operator(s2, torch.from_numpy(a), "scalar", fp32=False)
+    rhs = torch.ones(s2.ndofs, dtype=torch.float64, device="cuda")
+    rhs[torch.from_numpy(s2.boundary().astype(np.int64)).cuda()] = 0.0
+    _, st = op2.pcg(rhs, tol=1e-12, maxit=200, raise_on_error=False)
+    assert st["status"] in (7,)
+    # zero right-hand side -> x = 0 immediately
+    x, st = op.pcg(torch.zeros(sp.ndofs, dtype=torch.float64, device="cuda"), tol=1e-8)
+    assert st["iters"] == 0 and float(x.abs().max()) == 0.0
+
+
+def test_adjoint_gradient_matches_oracle():
+    """2D P3 inverse problem on a small mesh: GPU forward/adjoint PCG + contraction equals the
+    oracle gradient (direct solves, quadrature cell matrices)."""
+    from paper_1710_09913_amd import Mesh, Operator, Space
+
+    n, k = 6, 3
+    coords, cells = unit_mesh(2, n, jitter=0.1, seed=3)
+    nel = len(cells)
+    osp = fem.make_space(coords, cells, k)
+    b = fem.load_vector(osp, 1.0)
+    b[osp.boundary] = 0.0
+    u_star, _, _ = adjoint.forward(osp, theta_normal(nel, 8), b)
+    u_obs = u_star + 0.01 * np.sqrt(np.mean(u_star ** 2)) * np.random.default_rng(0).standard_normal(osp.ndofs)
+    u_obs[osp.boundary] = 0.0
+    theta = theta_normal(nel, 1)
+    J, g_o, _, _ = adjoint.gradient(osp, theta, b, u_obs)
+    sp = Space(Mesh(coords, cells), k, "se", "dirichlet")
+    perm = match_dofs(sp.dof_coords(), osp.dof_coords)
+    op = Operator(sp, torch.from_numpy(theta), "logscalar", fp32=False)
+    u, _ = op.pcg(_gpu(b[perm]), tol=1e-13, maxit=10000)
+    r = u - _gpu(u_obs[perm])
+    lam, _ = op.pcg(r.contiguous(), tol=1e-13, maxit=10000)
+    g = op.grad_logcoef(u, lam).cpu().numpy()
+    assert rel_err(g, g_o) <= 1e-8
