@@ -30,8 +30,10 @@
  *   - Handles are opaque; destroy functions accept NULL.  A space keeps its
  *     mesh alive and an operator keeps its space alive, so handles may be
  *     destroyed in any order.
- *   - Dofs are numbered: vertices (by vertex id), then nodes inside edges,
- *     then inside faces (3D), then inside cells.  Local nodes of a cell follow
+ *   - Dofs (Lagrange nodes of C_{N,k}) are numbered along the Morton (Z-order)
+ *     curve of their coordinates in the mesh bounding box, ties in the order
+ *     vertices, edge nodes, face nodes, cell nodes; dogip_space_dof_coords and
+ *     dogip_space_cell_dofs expose the numbering.  Local nodes of a cell follow
  *     the lattice a/k, |a| <= k, in lexicographic order of (a_1, .., a_d) on the
  *     reference simplex conv{0, e_1, .., e_d}, vertex j of the cell mapped to
  *     the reference vertex j (0 -> origin).
@@ -205,7 +207,10 @@ int dogip_op_export_d(dogip_op op, double* d_out, dogip_stream stream);
 
 /* y <- A u (overwrite), with Dirichlet identity rows if the space has them.
  * u, y: device [ndofs] FP64, u != y.  prec: DOGIP_F64 or DOGIP_F32 (the latter
- * needs DOGIP_OP_FP32).  async; allocates nothing. */
+ * needs DOGIP_OP_FP32).  async; allocates nothing.  The result is bitwise
+ * reproducible (no floating-point atomics outside a workgroup's own cells).
+ * The operator owns a staging buffer used by every apply, diag, solve and
+ * gradient call: calls on one operator must be ordered (one stream). */
 int dogip_apply(dogip_op op, const double* u, double* y, int prec, dogip_stream stream);
 /* diag <- diagonal of A (1 on Dirichlet rows).  device [ndofs].  async. */
 int dogip_diag(dogip_op op, double* diag, dogip_stream stream);

@@ -10,7 +10,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libdogip.so")
+# DOGIP_LIBRARY selects another build of the same library (for instance a tuning variant)
+LIB_PATH = os.environ.get("DOGIP_LIBRARY") or os.path.join(HERE, "libdogip.so")
 
 # status codes and enums (include/dogip.h)
 DOGIP_OK = 0

@@ -64,7 +64,7 @@ struct Space {
 
 // Flags carried in the high bits of a tile dof entry.
 constexpr uint32_t TD_BND = 0x80000000u;     // Dirichlet dof: gathered as 0, written y = u
-constexpr uint32_t TD_SHARED = 0x40000000u;  // dof touched by more than one tile: atomic flush
+constexpr uint32_t TD_SHARED = 0x40000000u;  // non-Dirichlet dof touched by several tiles: partial sum staged
 constexpr uint32_t TD_OWNER = 0x20000000u;   // the tile of lowest index touching this dof
 constexpr uint32_t TD_MASK = 0x1fffffffu;    // dof index (< 2^29)
 
@@ -77,7 +77,10 @@ struct TilePlan {
   std::vector<int64_t> tile_off;    // [ntiles+1]
   std::vector<uint32_t> tile_dofs;  // dof | flags
   std::vector<uint16_t> lidx;       // AoSoA [nel_pad/64][nlc][64][8]: slot of each local node
-  std::vector<int32_t> shared;      // non-boundary dofs touched by several tiles
+  std::vector<int32_t> shared;      // non-boundary dofs touched by several tiles, ascending
+  std::vector<int64_t> stage_off;   // [ntiles+1] staging offsets of each tile's shared entries
+  std::vector<uint32_t> sh_rowptr;  // [nshared+1] staging slots of shared dof i: sh_slots[rowptr[i]..]
+  std::vector<uint32_t> sh_slots;   // grouped by shared dof, ascending tile order
   int nlc = 0;                      // 16-byte chunks of local indices per cell
   int64_t max_tile_dofs = 0;
 };
@@ -96,6 +99,7 @@ struct Op {
   bool has32 = false;
   int64_t nch64 = 0, nch32 = 0;
   DevBuf d64, d32, lidx, tile_off, tile_dofs, shared, perm, cells, xyz, what, bhat64, bhat32, invdiag;
+  DevBuf stage_off, sh_rowptr, sh_slots, stage, bnd;  // second pass: shared dofs, Dirichlet rows
   std::unique_ptr<PcgWork> pcg;
   std::unique_ptr<OpTimer> timer;
   ~Op();
@@ -113,6 +117,7 @@ void reference_tables(int dim, int k, int kind, std::vector<double>& bhat, std::
 std::unique_ptr<Op> make_op(std::shared_ptr<const Space> s, int coef_kind, const double* coef, unsigned flags,
                             int tile_waves, int variant, hipStream_t st);
 void op_set_coef(Op& op, int coef_kind, const double* coef, hipStream_t st);
+// energy (optional): [ntiles] tile partials of u . A u, followed by FINISH_BLOCKS boundary partials
 void op_apply(Op& op, const double* u, double* y, int prec, hipStream_t st, double* energy_partials = nullptr);
 void op_diag(Op& op, double* diag, hipStream_t st);
 void op_grad(Op& op, const double* u, const double* lam, double* g, hipStream_t st);
@@ -132,6 +137,8 @@ struct ApplyLaunch {
   const double* u;
   double* y;
   double* energy;        // optional per-tile partial of u^T A u (nullptr: not computed)
+  const int64_t* stage_off;  // [ntiles+1] staging offsets of the tiles' shared entries
+  double* stage;             // staging buffer of shared partial sums
   int64_t nel;
   int64_t ntiles;
   int64_t nch;           // D chunks per cell
@@ -186,6 +193,13 @@ void launch_build_d(const BuildDLaunch& a, hipStream_t st);
 void launch_export_d(const double* d64, const int32_t* perm, double* out, int64_t nel, int64_t nch64, int wt,
                      int nsym, hipStream_t st);
 void launch_zero_indexed(double* y, const int32_t* idx, int64_t n, hipStream_t st);
+// Second pass of an apply: y[shared[i]] = sum of stage[slots[rowptr[i] .. rowptr[i+1])]
+// (fixed order) and y[b] = u[b] on Dirichlet dofs; with benergy (FINISH_BLOCKS
+// partials), the per-block sums of u_b^2.
+constexpr int FINISH_BLOCKS = 1024;
+void launch_apply_finish(const double* stage, const uint32_t* rowptr, const uint32_t* slots, const int32_t* shared,
+                         int64_t nshared, const int32_t* bnd, int64_t nbnd, const double* u, double* y,
+                         double* benergy, hipStream_t st);
 void launch_invert(const double* d, double* inv, int64_t n, hipStream_t st);
 
 }  // namespace dogip

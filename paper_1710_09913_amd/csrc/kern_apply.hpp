@@ -16,19 +16,76 @@
 namespace dogip {
 namespace dev {
 
-template <int D, int K, int KIND, typename T, int VARIANT, bool ENERGY>
-__global__ __launch_bounds__(512) void k_apply(ApplyLaunch a) {
-  using E = Elem<D, K, KIND, T, T, VARIANT, ENERGY>;
+#ifndef DOGIP_PF64
+#define DOGIP_PF64 2
+#endif
+#ifndef DOGIP_PF32
+#define DOGIP_PF32 3
+#endif
+#ifndef DOGIP_WPE
+#define DOGIP_WPE 1
+#endif
+
+constexpr int GB = 8;  // tile dof entries handled per thread in one batch
+
+// Gather of one batch: entries j = j0 + g * blockDim.x; u -> LDS (0 for Dirichlet
+// dofs), accumulation slots zeroed.  The GB loads of a thread are in flight together.
+template <typename T>
+__device__ __forceinline__ void gather_batch(const uint32_t* __restrict__ td, int64_t nd, int64_t j0,
+                                             const double* __restrict__ u, T* us, double* ys, uint32_t (&e)[GB]) {
+  double v[GB];
+#pragma unroll
+  for (int g = 0; g < GB; ++g) {
+    const int64_t j = j0 + int64_t(g) * blockDim.x;
+    e[g] = j < nd ? td[j] : TD_BND;
+  }
+#pragma unroll
+  for (int g = 0; g < GB; ++g) v[g] = (e[g] & TD_BND) ? 0.0 : u[e[g] & TD_MASK];
+#pragma unroll
+  for (int g = 0; g < GB; ++g) {
+    const int64_t j = j0 + int64_t(g) * blockDim.x;
+    if (j < nd) {
+      us[j] = T(v[g]);
+      ys[j] = 0.0;
+    }
+  }
+}
+
+// Flush of one batch: shared entries -> staging (second pass sums them), exclusive
+// entries -> y; Dirichlet entries are written by the second pass.
+__device__ __forceinline__ void flush_batch(const uint32_t (&e)[GB], int64_t nd, int64_t j0, const double* ys,
+                                            double* __restrict__ stage, double* __restrict__ y) {
+#pragma unroll
+  for (int g = 0; g < GB; ++g) {
+    const int64_t j = j0 + int64_t(g) * blockDim.x;
+    if (j >= nd || (e[g] & TD_BND)) continue;
+    if (e[g] & TD_SHARED)
+      stage[j] = ys[j];
+    else
+      y[e[g] & TD_MASK] = ys[j];
+  }
+}
+
+// The tile kernel.  T is the element arithmetic precision (D is stored in T);
+// the per-tile accumulation in LDS is always FP64 (ds_add_f64).  When the tile
+// has at most GB * blockDim entries (the usual case) the entries loaded by the
+// gather stay in registers for the flush.
+template <int D, int K, int KIND, typename T, int VARIANT, bool ENERGY, int PF>
+__global__ __launch_bounds__(512, DOGIP_WPE) void k_apply(ApplyLaunch a) {
+  using E = Elem<D, K, KIND, T, T, VARIANT, ENERGY, PF>;
   constexpr int VT = E::VT;
   extern __shared__ __align__(16) unsigned char smem[];
-  T* us = reinterpret_cast<T*>(smem);
-  T* ys = us + a.lds_slots;
+  double* ys = reinterpret_cast<double*>(smem);
+  T* us = reinterpret_cast<T*>(ys + a.lds_slots);
   const int64_t t = a.tile_base + xcd_tile(blockIdx.x, gridDim.x);
   const int64_t o0 = a.tile_off[t], nd = a.tile_off[t + 1] - o0;
-  for (int64_t j = threadIdx.x; j < nd; j += blockDim.x) {
-    const uint32_t td = a.tile_dofs[o0 + j];
-    us[j] = (td & TD_BND) ? T(0) : T(a.u[td & TD_MASK]);
-    ys[j] = T(0);
+  const uint32_t* td = a.tile_dofs + o0;
+  const bool one = nd <= int64_t(GB) * blockDim.x;
+  uint32_t ent[GB];
+  if (one) {
+    gather_batch<T>(td, nd, threadIdx.x, a.u, us, ys, ent);
+  } else {
+    for (int64_t j0 = threadIdx.x; j0 < nd; j0 += int64_t(GB) * blockDim.x) gather_batch<T>(td, nd, j0, a.u, us, ys, ent);
   }
   __syncthreads();
   const int64_t e = t * a.te + threadIdx.x;
@@ -42,26 +99,25 @@ __global__ __launch_bounds__(512) void k_apply(ApplyLaunch a) {
     sfor<VT>([&](auto L) { ue[L] = us[li[L]]; });
     const typename E::V* dp = reinterpret_cast<const typename E::V*>(a.D) + (w * a.nch) * 64 + lane;
     en = E::run(dp, ue, ye);
-    sfor<VT>([&](auto L) { atomicAdd(&ys[li[L]], ye[L]); });
+    sfor<VT>([&](auto L) { atomicAdd(&ys[li[L]], double(ye[L])); });
   }
   __syncthreads();
-  double eb = 0.0;
-  for (int64_t j = threadIdx.x; j < nd; j += blockDim.x) {
-    const uint32_t td = a.tile_dofs[o0 + j];
-    const uint32_t dof = td & TD_MASK;
-    if (td & TD_BND) {
-      const double ub = a.u[dof];
-      a.y[dof] = ub;
-      if (ENERGY && (td & TD_OWNER)) eb += ub * ub;
-    } else if (td & TD_SHARED) {
-      unsafeAtomicAdd(&a.y[dof], double(ys[j]));
-    } else {
-      a.y[dof] = double(ys[j]);
+  double* stage = a.stage + a.stage_off[t];
+  if (one) {
+    flush_batch(ent, nd, threadIdx.x, ys, stage, a.y);
+  } else {
+    for (int64_t j0 = threadIdx.x; j0 < nd; j0 += int64_t(GB) * blockDim.x) {
+#pragma unroll
+      for (int g = 0; g < GB; ++g) {
+        const int64_t j = j0 + int64_t(g) * blockDim.x;
+        ent[g] = j < nd ? td[j] : TD_BND;
+      }
+      flush_batch(ent, nd, j0, ys, stage, a.y);
     }
   }
   if constexpr (ENERGY) {
     __shared__ double red[8];
-    const double s = block_sum(double(en) + eb, red);
+    const double s = block_sum(double(en), red);
     if (threadIdx.x == 0) a.energy[t] = s;
   }
 }
@@ -69,18 +125,20 @@ __global__ __launch_bounds__(512) void k_apply(ApplyLaunch a) {
 template <int D, int K, int KIND, int VARIANT>
 bool launch_apply_t(int prec, bool energy, const ApplyLaunch& a, hipStream_t st) {
   const dim3 grid(unsigned(a.ntiles)), block(unsigned(a.te));
+  constexpr int P64 = VARIANT == DOGIP_VARIANT_UNROLLED ? DOGIP_PF64 : 0;
+  constexpr int P32 = VARIANT == DOGIP_VARIANT_UNROLLED ? DOGIP_PF32 : 0;
   if (prec == DOGIP_F64) {
-    const size_t lds = size_t(2) * a.lds_slots * sizeof(double);
+    const size_t lds = size_t(a.lds_slots) * (sizeof(double) + sizeof(double));
     if (energy)
-      hipLaunchKernelGGL((k_apply<D, K, KIND, double, VARIANT, true>), grid, block, lds, st, a);
+      hipLaunchKernelGGL((k_apply<D, K, KIND, double, VARIANT, true, P64>), grid, block, lds, st, a);
     else
-      hipLaunchKernelGGL((k_apply<D, K, KIND, double, VARIANT, false>), grid, block, lds, st, a);
+      hipLaunchKernelGGL((k_apply<D, K, KIND, double, VARIANT, false, P64>), grid, block, lds, st, a);
   } else {
-    const size_t lds = size_t(2) * a.lds_slots * sizeof(float);
+    const size_t lds = size_t(a.lds_slots) * (sizeof(double) + sizeof(float));
     if (energy)
-      hipLaunchKernelGGL((k_apply<D, K, KIND, float, VARIANT, true>), grid, block, lds, st, a);
+      hipLaunchKernelGGL((k_apply<D, K, KIND, float, VARIANT, true, P32>), grid, block, lds, st, a);
     else
-      hipLaunchKernelGGL((k_apply<D, K, KIND, float, VARIANT, false>), grid, block, lds, st, a);
+      hipLaunchKernelGGL((k_apply<D, K, KIND, float, VARIANT, false, P32>), grid, block, lds, st, a);
   }
   return true;
 }

@@ -1,5 +1,7 @@
 // Setup and auxiliary kernels: D construction (Theorems 2 and 4), D export,
 // Jacobi diagonal, adjoint contraction, small vector kernels.
+#include <algorithm>
+
 #include "kern_common.hpp"
 
 namespace dogip {
@@ -98,6 +100,39 @@ __global__ __launch_bounds__(256) void k_zero_indexed(double* __restrict__ y, co
                                                       int64_t n) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
     y[idx[i]] = 0.0;
+}
+
+// Second pass of the apply.  i < nshared: y[shared[i]] = sum of its staged partials,
+// added in ascending tile order (deterministic).  nshared <= i < nshared + nbnd:
+// Dirichlet identity row y[b] = u[b]; with benergy, each block writes its share of
+// sum u_b^2 (the identity rows' part of u . A u) to benergy[blockIdx.x].
+__global__ __launch_bounds__(256) void k_apply_finish(const double* __restrict__ stage,
+                                                      const uint32_t* __restrict__ rowptr,
+                                                      const uint32_t* __restrict__ slots,
+                                                      const int32_t* __restrict__ shared, int64_t nshared,
+                                                      const int32_t* __restrict__ bnd, int64_t nbnd,
+                                                      const double* __restrict__ u, double* __restrict__ y,
+                                                      double* __restrict__ benergy) {
+  double eb = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nshared + nbnd;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    if (i < nshared) {
+      const uint32_t a = rowptr[i], b = rowptr[i + 1];
+      double s = 0.0;
+      for (uint32_t j = a; j < b; ++j) s += stage[slots[j]];
+      y[shared[i]] = s;
+    } else {
+      const int32_t d = bnd[i - nshared];
+      const double ub = u[d];
+      y[d] = ub;
+      eb += ub * ub;
+    }
+  }
+  if (benergy) {
+    __shared__ double red[8];
+    const double s = block_sum(eb, red);
+    if (threadIdx.x == 0) benergy[blockIdx.x] = s;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_invert(const double* __restrict__ d, double* __restrict__ inv, int64_t n) {
@@ -247,6 +282,17 @@ void launch_export_d(const double* d64, const int32_t* perm, double* out, int64_
 void launch_zero_indexed(double* y, const int32_t* idx, int64_t n, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(dev::k_zero_indexed, dim3(grid_for(n, 256)), dim3(256), 0, st, y, idx, n);
+}
+
+void launch_apply_finish(const double* stage, const uint32_t* rowptr, const uint32_t* slots, const int32_t* shared,
+                         int64_t nshared, const int32_t* bnd, int64_t nbnd, const double* u, double* y,
+                         double* benergy, hipStream_t st) {
+  const int64_t n = nshared + nbnd;
+  if (n <= 0 && !benergy) return;
+  // a fixed grid when the boundary energy partials are wanted (FINISH_BLOCKS of them)
+  const unsigned grid = benergy ? unsigned(FINISH_BLOCKS) : unsigned(std::max<int64_t>(1, (n + 255) / 256));
+  hipLaunchKernelGGL(dev::k_apply_finish, dim3(grid), dim3(256), 0, st, stage, rowptr, slots, shared, nshared, bnd,
+                     nbnd, u, y, benergy);
 }
 
 void launch_invert(const double* d, double* inv, int64_t n, hipStream_t st) {

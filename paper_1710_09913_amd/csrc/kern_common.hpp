@@ -20,6 +20,15 @@ template <int N, class F>
 __device__ __forceinline__ void sfor(F&& f) {
   sfor_impl(f, std::make_integer_sequence<int, N>{});
 }
+template <int A, class F, int... Is>
+__device__ __forceinline__ void sfor_from_impl(F&& f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, A + Is>{}), ...);
+}
+// Compile-time loop over A..B-1.
+template <int A, int B, class F>
+__device__ __forceinline__ void sfor_range(F&& f) {
+  if constexpr (B > A) sfor_from_impl<A>(f, std::make_integer_sequence<int, B - A>{});
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs; map them so that each
 // XCD (own L2) works on one contiguous range of tiles, which are neighbours in
@@ -85,20 +94,33 @@ __constant__ CArr<D, K, KIND, T> ctab{};
 
 // Element body.  ue: local dof values; ye: local result (overwritten); dp: this
 // lane's first D chunk (chunk j of the cell at dp[j * 64]).  Returns the cell
-// energy u_T^T A_T u_T when ENERGY is set.
-template <int D, int K, int KIND, typename T, typename TD, int VARIANT, bool ENERGY>
+// energy u_T^T A_T u_T when ENERGY is set.  In the unrolled body the D chunks of
+// W node i + PF are requested while node i is computed (prefetch distance PF).
+template <int D, int K, int KIND, typename T, typename TD, int VARIANT, bool ENERGY, int PF = 0>
 struct Elem {
   using TB = ref::BTable<D, K, KIND>;
   static constexpr int VT = TB::VT, WT = TB::WT, NB = TB::NB;
   static constexpr int S = KIND == KIND_SE ? n_sym(D) : 1;
   static constexpr int VEC = 16 / int(sizeof(TD));
+  static constexpr int NCH = (WT * S + VEC - 1) / VEC;
   using V = vec_t<TD, VEC>;
+
+  // node step at which chunk j is requested, and the first chunk requested at step i
+  static constexpr int issue_step(int j) { return (j * VEC) / S - PF < 0 ? 0 : (j * VEC) / S - PF; }
+  static constexpr int first_chunk(int i) {
+    int j = 0;
+    while (j < NCH && issue_step(j) < i) ++j;
+    return j;
+  }
 
   __device__ __forceinline__ static T run(const V* __restrict__ dp, const T (&ue)[VT], T (&ye)[VT]) {
     T en = T(0);
     sfor<VT>([&](auto L) { ye[L] = T(-0.0); });
     if constexpr (VARIANT == DOGIP_VARIANT_UNROLLED) {
+      V ch[NCH];
       sfor<WT>([&](auto I) {
+        sfor_range<first_chunk(I), (I + 1 < WT ? first_chunk(I + 1) : NCH)>(
+            [&](auto J) { ch[J] = ld_stream(dp + J * 64); });
         T g[NB];
         sfor<NB>([&](auto R) {
           T acc = T(-0.0);
@@ -116,8 +138,7 @@ struct Elem {
         T dv[S];
         sfor<S>([&](auto C) {
           constexpr int f = I * S + C;
-          const V ch = ld_stream(dp + (f / VEC) * 64);
-          dv[C] = T(ch[f % VEC]);
+          dv[C] = T(ch[f / VEC][f % VEC]);
         });
         T h[NB];
         dmul<NB, S>(dv, g, h);

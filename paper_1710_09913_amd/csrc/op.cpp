@@ -135,6 +135,11 @@ std::unique_ptr<Op> make_op(std::shared_ptr<const Space> sp, int coef_kind, cons
   upload(op->tile_off, p.tile_off);
   upload(op->tile_dofs, p.tile_dofs);
   upload(op->shared, p.shared);
+  upload(op->stage_off, p.stage_off);
+  upload(op->sh_rowptr, p.sh_rowptr);
+  upload(op->sh_slots, p.sh_slots);
+  upload(op->bnd, s.boundary);
+  op->stage.alloc(size_t(std::max<int64_t>(p.stage_off.back(), 1)) * sizeof(double));
   upload(op->perm, p.perm);
   const Mesh& m = *s.mesh;
   std::vector<int32_t> cint(size_t(s.nc) * (s.dim + 1));
@@ -169,6 +174,8 @@ static ApplyLaunch apply_args(const Op& op, int prec) {
   a.te = op.plan.te;
   a.lds_slots = int(op.plan.max_tile_dofs);
   a.tile_base = 0;
+  a.stage_off = op.stage_off.as<int64_t>();
+  a.stage = op.stage.as<double>();
   return a;
 }
 
@@ -178,7 +185,6 @@ void op_apply(Op& op, const double* u, double* y, int prec, hipStream_t st, doub
   DOGIP_CHECK(u != y, DOGIP_E_INVALID, "apply needs u != y");
   DOGIP_CHECK(prec == DOGIP_F64 || prec == DOGIP_F32, DOGIP_E_RANGE, "prec must be DOGIP_F64 or DOGIP_F32");
   DOGIP_CHECK(prec == DOGIP_F64 || op.has32, DOGIP_E_STATE, "FP32 apply needs an operator built with DOGIP_OP_FP32");
-  launch_zero_indexed(y, op.shared.as<int32_t>(), int64_t(op.plan.shared.size()), st);
   ApplyLaunch a = apply_args(op, prec);
   a.u = u;
   a.y = y;
@@ -191,6 +197,9 @@ void op_apply(Op& op, const double* u, double* y, int prec, hipStream_t st, doub
   }
   DOGIP_CHECK(launch_apply(s.dim, s.k, s.kind, prec, op.variant, a, st), DOGIP_E_RANGE,
               "no apply kernel for this (dim, k, kind, variant)");
+  launch_apply_finish(op.stage.as<double>(), op.sh_rowptr.as<uint32_t>(), op.sh_slots.as<uint32_t>(),
+                      op.shared.as<int32_t>(), int64_t(op.plan.shared.size()), op.bnd.as<int32_t>(),
+                      int64_t(s.boundary.size()), u, y, energy ? energy + op.plan.ntiles : nullptr, st);
   HIPCHK(hipGetLastError());
   if (op.timer->on) {
     HIPCHK(hipEventRecord(e1, st));
@@ -259,7 +268,8 @@ dogip_op_info op_info(const Op& op) {
   i.max_tile_dofs = op.plan.max_tile_dofs;
   i.bytes_d64 = int64_t(op.d64.bytes);
   i.bytes_d32 = int64_t(op.d32.bytes);
-  i.bytes_index = int64_t(op.lidx.bytes + op.tile_off.bytes + op.tile_dofs.bytes + op.shared.bytes);
+  i.bytes_index = int64_t(op.lidx.bytes + op.tile_off.bytes + op.tile_dofs.bytes + op.shared.bytes +
+                          op.stage_off.bytes + op.sh_rowptr.bytes + op.sh_slots.bytes + op.stage.bytes);
   const double nd = double(s.wt) * s.nsym * s.nc, conn = 4.0 * s.vt * s.nc, vec = 2.0 * 8.0 * s.ndofs;
   i.alg_bytes_f64 = 8.0 * nd + conn + vec;
   i.alg_bytes_f32 = 4.0 * nd + conn + vec;

@@ -124,6 +124,53 @@ void reference_tables(int dim, int k, int kind, std::vector<double>& bhat, std::
   for (int i = 0; i < wt; ++i) what[i] = ref::to_double(ref::what_entry(dim, q, i));
 }
 
+// ---------------------------------------------------------------- space-filling order
+
+static uint64_t spread3(uint64_t x) {  // 21 bits -> every third bit
+  x &= 0x1fffff;
+  x = (x | x << 32) & 0x1f00000000ffffULL;
+  x = (x | x << 16) & 0x1f0000ff0000ffULL;
+  x = (x | x << 8) & 0x100f00f00f00f00fULL;
+  x = (x | x << 4) & 0x10c30c30c30c30c3ULL;
+  x = (x | x << 2) & 0x1249249249249249ULL;
+  return x;
+}
+static uint64_t spread2(uint64_t x) {  // 32 bits -> every second bit
+  x &= 0xffffffffULL;
+  x = (x | x << 16) & 0x0000ffff0000ffffULL;
+  x = (x | x << 8) & 0x00ff00ff00ff00ffULL;
+  x = (x | x << 4) & 0x0f0f0f0f0f0f0f0fULL;
+  x = (x | x << 2) & 0x3333333333333333ULL;
+  x = (x | x << 1) & 0x5555555555555555ULL;
+  return x;
+}
+
+// Order of n points (coordinates [n][d]) along the Morton curve of their bounding
+// box; ties keep the input order.
+static std::vector<int64_t> morton_order(const double* xyz, int64_t n, int d) {
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t i = 0; i < n; ++i)
+    for (int x = 0; x < d; ++x) {
+      lo[x] = std::min(lo[x], xyz[i * d + x]);
+      hi[x] = std::max(hi[x], xyz[i * d + x]);
+    }
+  const double bits = d == 3 ? 2097151.0 : 4294967295.0;
+  std::vector<std::pair<uint64_t, int64_t>> key(n);
+  for (int64_t i = 0; i < n; ++i) {
+    uint64_t code = 0;
+    for (int x = 0; x < d; ++x) {
+      const double t = hi[x] > lo[x] ? (xyz[i * d + x] - lo[x]) / (hi[x] - lo[x]) : 0.0;
+      const uint64_t qv = uint64_t(std::min(std::max(t, 0.0), 1.0) * bits);
+      code |= (d == 3 ? spread3(qv) : spread2(qv)) << x;
+    }
+    key[i] = {code, i};
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<int64_t> order(n);
+  for (int64_t i = 0; i < n; ++i) order[i] = key[i].second;
+  return order;
+}
+
 // ---------------------------------------------------------------- dof map
 
 namespace {
@@ -292,6 +339,22 @@ std::shared_ptr<Space> make_space(std::shared_ptr<const Mesh> mesh, int k, int k
         if (bv[l][j] == 0 && fb[j]) s->is_bnd[dof] = 1;
     }
   }
+  // final numbering: dofs in the Morton order of their coordinates, so that the dofs
+  // of a compact group of cells occupy a compact index range
+  {
+    const std::vector<int64_t> order = morton_order(s->dof_xyz.data(), s->ndofs, d);
+    std::vector<int32_t> inv(s->ndofs);
+    for (int64_t i = 0; i < s->ndofs; ++i) inv[order[i]] = int32_t(i);
+    for (auto& v : s->cell_dofs) v = inv[v];
+    std::vector<double> xyz(s->dof_xyz.size());
+    std::vector<uint8_t> bnd(s->ndofs);
+    for (int64_t i = 0; i < s->ndofs; ++i) {
+      for (int x = 0; x < d; ++x) xyz[i * d + x] = s->dof_xyz[order[i] * d + x];
+      bnd[i] = s->is_bnd[order[i]];
+    }
+    s->dof_xyz.swap(xyz);
+    s->is_bnd.swap(bnd);
+  }
   if (bc == DOGIP_BC_DIRICHLET0) {
     for (int64_t i = 0; i < s->ndofs; ++i)
       if (s->is_bnd[i]) s->boundary.push_back(int32_t(i));
@@ -303,25 +366,6 @@ std::shared_ptr<Space> make_space(std::shared_ptr<const Mesh> mesh, int k, int k
 
 // ---------------------------------------------------------------- tiling
 
-static uint64_t spread3(uint64_t x) {  // 21 bits -> every third bit
-  x &= 0x1fffff;
-  x = (x | x << 32) & 0x1f00000000ffffULL;
-  x = (x | x << 16) & 0x1f0000ff0000ffULL;
-  x = (x | x << 8) & 0x100f00f00f00f00fULL;
-  x = (x | x << 4) & 0x10c30c30c30c30c3ULL;
-  x = (x | x << 2) & 0x1249249249249249ULL;
-  return x;
-}
-static uint64_t spread2(uint64_t x) {  // 32 bits -> every second bit
-  x &= 0xffffffffULL;
-  x = (x | x << 16) & 0x0000ffff0000ffffULL;
-  x = (x | x << 8) & 0x00ff00ff00ff00ffULL;
-  x = (x | x << 4) & 0x0f0f0f0f0f0f0f0fULL;
-  x = (x | x << 2) & 0x3333333333333333ULL;
-  x = (x | x << 1) & 0x5555555555555555ULL;
-  return x;
-}
-
 TilePlan make_tiles(const Space& s, int te) {
   const Mesh& m = *s.mesh;
   const int d = m.dim, d1 = d + 1, vt = s.vt;
@@ -330,36 +374,23 @@ TilePlan make_tiles(const Space& s, int te) {
   p.ntiles = (s.nc + te - 1) / te;
   p.nel_pad = p.ntiles * te;
   // Morton order of cell centroids
-  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-  for (int64_t v = 0; v < m.nv; ++v)
-    for (int x = 0; x < d; ++x) {
-      lo[x] = std::min(lo[x], m.xyz[v * d + x]);
-      hi[x] = std::max(hi[x], m.xyz[v * d + x]);
-    }
-  const double bits = d == 3 ? 2097151.0 : 4294967295.0;
-  std::vector<std::pair<uint64_t, int32_t>> key(s.nc);
-  for (int64_t c = 0; c < s.nc; ++c) {
-    uint64_t code = 0;
+  std::vector<double> cen(size_t(s.nc) * d, 0.0);
+  for (int64_t c = 0; c < s.nc; ++c)
     for (int x = 0; x < d; ++x) {
       double cx = 0;
       for (int j = 0; j < d1; ++j) cx += m.xyz[int64_t(m.cells[c * d1 + j]) * d + x];
-      cx /= d1;
-      double t = hi[x] > lo[x] ? (cx - lo[x]) / (hi[x] - lo[x]) : 0.0;
-      uint64_t qv = uint64_t(std::min(std::max(t, 0.0), 1.0) * bits);
-      code |= (d == 3 ? spread3(qv) : spread2(qv)) << x;
+      cen[c * d + x] = cx / d1;
     }
-    key[c] = {code, int32_t(c)};
-  }
-  std::sort(key.begin(), key.end());
+  const std::vector<int64_t> order = morton_order(cen.data(), s.nc, d);
   p.perm.resize(s.nc);
-  for (int64_t c = 0; c < s.nc; ++c) p.perm[c] = key[c].second;
+  for (int64_t c = 0; c < s.nc; ++c) p.perm[c] = int32_t(order[c]);
 
   p.nlc = (vt + 7) / 8;
   p.lidx.assign(size_t(p.nel_pad / 64) * p.nlc * 64 * 8, 0);
   p.tile_off.assign(p.ntiles + 1, 0);
+  // pass 1: distinct dofs of every tile, and how many tiles touch each dof
   std::vector<int32_t> ntile_of(s.ndofs, 0), first_tile(s.ndofs, -1), slot(s.ndofs, -1);
-  std::vector<int32_t> tmp;
-  std::vector<int32_t> all;  // concatenated tile lists (dof only)
+  std::vector<int32_t> tmp, all;
   all.reserve(size_t(s.nc) * vt / 2);
   for (int64_t t = 0; t < p.ntiles; ++t) {
     const int64_t e0 = t * te, e1 = std::min<int64_t>(s.nc, e0 + te);
@@ -371,12 +402,46 @@ TilePlan make_tiles(const Space& s, int te) {
     std::sort(tmp.begin(), tmp.end());
     tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
     DOGIP_CHECK(tmp.size() <= 65535, DOGIP_E_RANGE, "tile touches too many dofs");
-    for (size_t j = 0; j < tmp.size(); ++j) {
-      int32_t dof = tmp[j];
-      slot[dof] = int32_t(j);
+    for (int32_t dof : tmp) {
       ntile_of[dof]++;
       if (first_tile[dof] < 0) first_tile[dof] = int32_t(t);
     }
+    all.insert(all.end(), tmp.begin(), tmp.end());
+    p.tile_off[t + 1] = int64_t(all.size());
+    p.max_tile_dofs = std::max<int64_t>(p.max_tile_dofs, int64_t(tmp.size()));
+  }
+  // shared (non-Dirichlet) dofs, numbered in ascending dof order
+  std::vector<int32_t> sh_index(s.ndofs, -1);
+  for (int64_t i = 0; i < s.ndofs; ++i)
+    if (ntile_of[i] > 1 && !s.is_bnd[i]) {
+      sh_index[i] = int32_t(p.shared.size());
+      p.shared.push_back(int32_t(i));
+    }
+  // pass 2: order each tile's list as [shared | exclusive | Dirichlet] (ascending dof within
+  // each group); the shared group's partial sums go to stage[stage_off[t] + j]
+  p.tile_dofs.resize(all.size());
+  p.stage_off.assign(p.ntiles + 1, 0);
+  std::vector<uint32_t> cnt(p.shared.size() + 1, 0);
+  for (int64_t t = 0; t < p.ntiles; ++t) {
+    const int64_t o0 = p.tile_off[t], o1 = p.tile_off[t + 1];
+    int64_t w = o0;
+    for (int grp = 0; grp < 3; ++grp)
+      for (int64_t j = o0; j < o1; ++j) {
+        const int32_t dof = all[j];
+        const int g = s.is_bnd[dof] ? 2 : (sh_index[dof] >= 0 ? 0 : 1);
+        if (g != grp) continue;
+        uint32_t v = uint32_t(dof);
+        if (g == 2) v |= TD_BND;
+        if (g == 0) v |= TD_SHARED;
+        if (first_tile[dof] == t) v |= TD_OWNER;
+        slot[dof] = int32_t(w - o0);
+        p.tile_dofs[w++] = v;
+        if (g == 0) cnt[sh_index[dof] + 1]++;
+      }
+    int64_t nsh = 0;
+    for (int64_t j = o0; j < o1; ++j) nsh += (p.tile_dofs[j] & TD_SHARED) ? 1 : 0;
+    p.stage_off[t + 1] = p.stage_off[t] + nsh;
+    const int64_t e0 = t * te, e1 = std::min<int64_t>(s.nc, e0 + te);
     for (int64_t e = e0; e < e1; ++e) {
       const int32_t* cd = &s.cell_dofs[int64_t(p.perm[e]) * vt];
       for (int l = 0; l < vt; ++l) {
@@ -384,22 +449,20 @@ TilePlan make_tiles(const Space& s, int te) {
         p.lidx[at] = uint16_t(slot[cd[l]]);
       }
     }
-    all.insert(all.end(), tmp.begin(), tmp.end());
-    p.tile_off[t + 1] = int64_t(all.size());
-    p.max_tile_dofs = std::max<int64_t>(p.max_tile_dofs, int64_t(tmp.size()));
   }
-  p.tile_dofs.resize(all.size());
+  DOGIP_CHECK(p.stage_off[p.ntiles] < (int64_t(1) << 32), DOGIP_E_RANGE, "too many shared entries");
+  // reduction lists: for each shared dof, its staging slots in ascending tile order
+  for (size_t i = 1; i < cnt.size(); ++i) cnt[i] += cnt[i - 1];
+  p.sh_rowptr = cnt;
+  p.sh_slots.assign(p.stage_off[p.ntiles], 0);
+  std::vector<uint32_t> fill(cnt.begin(), cnt.end() - 1);
   for (int64_t t = 0; t < p.ntiles; ++t)
     for (int64_t j = p.tile_off[t]; j < p.tile_off[t + 1]; ++j) {
-      int32_t dof = all[j];
-      uint32_t v = uint32_t(dof);
-      if (s.is_bnd[dof]) v |= TD_BND;
-      if (ntile_of[dof] > 1) v |= TD_SHARED;
-      if (first_tile[dof] == t) v |= TD_OWNER;
-      p.tile_dofs[j] = v;
+      const uint32_t v = p.tile_dofs[j];
+      if (!(v & TD_SHARED)) break;  // shared entries come first
+      const int32_t si = sh_index[v & TD_MASK];
+      p.sh_slots[fill[si]++] = uint32_t(p.stage_off[t] + (j - p.tile_off[t]));
     }
-  for (int64_t i = 0; i < s.ndofs; ++i)
-    if (ntile_of[i] > 1 && !s.is_bnd[i]) p.shared.push_back(int32_t(i));
   return p;
 }
 

@@ -213,3 +213,14 @@ def test_apply_errors():
         op.apply(u, prec="f32")  # no FP32 copy
     with pytest.raises(DogipError):
         Operator(Space(Mesh.unit(2, 2), 2, "wp", "none"), torch.ones(8, 3, dtype=torch.float64), "sym")
+
+
+def test_apply_bitwise_reproducible():
+    """No floating-point atomics across workgroups: repeated applies agree bit for bit."""
+    c = Case(3, 3, 3, "se", seed=7, tile_waves=1)
+    u = _gpu(random_vector(c.space.ndofs, seed=8))
+    y1 = c.op.apply(u).cpu().numpy()
+    for _ in range(3):
+        np.testing.assert_array_equal(c.op.apply(u).cpu().numpy(), y1)
+    z1 = c.op.apply(u, prec="f32").cpu().numpy()
+    np.testing.assert_array_equal(c.op.apply(u, prec="f32").cpu().numpy(), z1)
