@@ -81,8 +81,16 @@ extern "C" {
                        vectors stay FP64 */
 
 /* ---- solve modes ---- */
-#define DOGIP_SOLVE_F64 0   /* Jacobi-PCG with the FP64 apply */
-#define DOGIP_SOLVE_MIXED 1 /* FP64 iterative refinement around Jacobi-PCG with the FP32 apply */
+#define DOGIP_SOLVE_F64 0 /* Jacobi-PCG with the FP64 apply */
+/* Jacobi-PCG with the FP32 apply, refined in FP64 by residual replacement: the
+ * recursive residual is replaced by b - A64 x (FP64 apply) each time it has
+ * dropped by the factor inner_tol (default 0.1) and at apparent convergence, the
+ * search direction being kept (no restart).  Vectors and inner products are FP64.
+ * If the true residual stops decreasing, the solve finishes with FP64 CG. */
+#define DOGIP_SOLVE_MIXED 1
+/* FP64 iterative refinement that restarts an FP32-apply Jacobi-PCG for every
+ * correction, each inner solve reducing its residual by inner_tol. */
+#define DOGIP_SOLVE_MIXED_RESTART 2
 
 /* ---- dogip_op_create flags ---- */
 #define DOGIP_OP_FP32 1u /* also build the FP32 copy of D (needed by DOGIP_F32 and MIXED) */
@@ -123,8 +131,8 @@ typedef struct {
 typedef struct {
   double tol;          /* stop when ||b - A x||_2 <= tol ||b||_2 */
   int32_t maxit;       /* CG iteration cap (all inner iterations in mixed mode) */
-  int32_t mode;        /* DOGIP_SOLVE_F64 or DOGIP_SOLVE_MIXED */
-  double inner_tol;    /* mixed: relative residual reduction asked of each inner solve */
+  int32_t mode;        /* DOGIP_SOLVE_F64, DOGIP_SOLVE_MIXED or DOGIP_SOLVE_MIXED_RESTART */
+  double inner_tol;    /* MIXED: replacement factor delta; MIXED_RESTART: reduction per inner solve */
   int32_t max_outer;   /* mixed: refinement steps cap */
   int32_t check_every; /* CG iterations between host-side convergence checks (>= 1) */
   int32_t x0_given;    /* nonzero: x holds the initial guess; else x0 = 0 */

@@ -36,6 +36,7 @@ DOGIP_F64 = 0
 DOGIP_F32 = 1
 DOGIP_SOLVE_F64 = 0
 DOGIP_SOLVE_MIXED = 1
+DOGIP_SOLVE_MIXED_RESTART = 2
 DOGIP_OP_FP32 = 1
 DOGIP_VARIANT_AUTO = 0
 DOGIP_VARIANT_UNROLLED = 1

@@ -144,6 +144,30 @@ __global__ __launch_bounds__(256) void k_resid(const double* __restrict__ b, con
   block_partials(v, 1, part);
 }
 
+// residual replacement: r = b - y (y = A64 x); partials (r.z, r.r) with z = invd r
+__global__ __launch_bounds__(256) void k_replace(const double* __restrict__ b, const double* __restrict__ y,
+                                                 const double* __restrict__ invd, double* __restrict__ r, int64_t n,
+                                                 double* __restrict__ part) {
+  double v[2] = {0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    const double ri = b[i] - y[i];
+    r[i] = ri;
+    v[0] += ri * (invd[i] * ri);
+    v[1] += ri * ri;
+  }
+  block_partials(v, 2, part);
+}
+
+__global__ __launch_bounds__(1024) void k_fin_replace(const double* __restrict__ part, int nparts, PcgScalars* s) {
+  const double rz = block_total(part, nparts);
+  const double rr = block_total(part + nparts, nparts);
+  if (threadIdx.x == 0) {
+    if (!isfinite(rz) || !isfinite(rr)) s->flags |= PCG_NONFINITE;
+    s->rho = rz;
+    s->rr = rr;
+  }
+}
+
 // partial a.b
 __global__ __launch_bounds__(256) void k_dot(const double* __restrict__ a, const double* __restrict__ b, int64_t n,
                                              double* __restrict__ part) {
@@ -196,6 +220,11 @@ void vk_pcg_p(double* p, const double* r, const double* invd, const PcgScalars* 
 void vk_resid(const double* b, const double* y, double* r, int64_t n, double* part, double* out, hipStream_t st) {
   hipLaunchKernelGGL(dev::k_resid, dim3(RED_BLOCKS), dim3(256), 0, st, b, y, r, n, part);
   hipLaunchKernelGGL(dev::k_fin_sum, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, out);
+}
+void vk_replace(const double* b, const double* y, const double* invd, double* r, int64_t n, double* part,
+                PcgScalars* s, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_replace, dim3(RED_BLOCKS), dim3(256), 0, st, b, y, invd, r, n, part);
+  hipLaunchKernelGGL(dev::k_fin_replace, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, s);
 }
 void vk_dot(const double* a, const double* b, int64_t n, double* part, double* out, hipStream_t st) {
   hipLaunchKernelGGL(dev::k_dot, dim3(RED_BLOCKS), dim3(256), 0, st, a, b, n, part);

@@ -42,13 +42,27 @@ struct CgResult {
   int iters = 0;
   double relres = 0.0;
   double bnorm = 0.0;
+  bool stalled = false;
 };
 
 // One Jacobi-PCG run on A x = b (x holds the initial guess when x0_given).
-// Stops when ||r|| <= tol ||b|| (recursive residual) or after maxit iterations.
-static CgResult cg_run(Op& op, const double* b, double* x, bool x0_given, double tol, int maxit, int prec,
-                       int check_every, hipStream_t st) {
-  PcgWork& w = work(op, std::max(maxit, 1));
+// prec selects the apply used for the search directions.  With reliable, the
+// recursive residual is replaced by the true FP64 residual b - A64 x whenever it
+// has fallen by the factor delta since the last replacement, and at apparent
+// convergence; the search direction is kept (residual replacement in the sense of
+// van der Vorst and Ye), so the iteration continues without a restart.
+// Stops when the tracked residual (true residual under reliable) is <= tol ||b||.
+struct CgParams {
+  double tol = 1e-8;
+  int maxit = 1000;
+  int prec = DOGIP_F64;
+  bool reliable = false;
+  double delta = 0.1;
+  int check_every = 16;
+};
+
+static CgResult cg_run(Op& op, const double* b, double* x, bool x0_given, const CgParams& cp, hipStream_t st) {
+  PcgWork& w = work(op, std::max(cp.maxit, 1));
   const int64_t n = op.space->ndofs;
   double* r = w.r.as<double>();
   double* p = w.p.as<double>();
@@ -77,17 +91,17 @@ static CgResult cg_run(Op& op, const double* b, double* x, bool x0_given, double
     vk_fill(x, 0.0, n, st);
     return res;
   }
-  const double thr = tol * tol * hs.bb;
-  if (hs.rr <= thr) {
-    res.relres = std::sqrt(hs.rr / hs.bb);
-    return res;
-  }
+  const double thr = cp.tol * cp.tol * hs.bb;
+  res.relres = std::sqrt(hs.rr / hs.bb);
+  if (hs.rr <= thr) return res;
+  double rr_true = hs.rr;  // residual norm^2 at the last exact (re)computation
+  int stalls = 0;
   int it = 0;
-  int step = std::max(1, check_every);
+  int step = std::max(1, cp.check_every);
   for (;;) {
-    const int todo = std::min(step, maxit - it);
+    const int todo = std::min(step, cp.maxit - it);
     for (int j = 0; j < todo; ++j) {
-      op_apply(op, p, q, prec, st, w.energy.as<double>());
+      op_apply(op, p, q, cp.prec, st, w.energy.as<double>());
       vk_fin_pq(w.energy.as<double>(), op.plan.ntiles + FINISH_BLOCKS, sc, st);
       vk_pcg_xr(x, r, p, q, invd, sc, n, part, st);
       vk_fin_rz(part, sc, hist, it + j + 1, st);
@@ -95,7 +109,7 @@ static CgResult cg_run(Op& op, const double* b, double* x, bool x0_given, double
     }
     HIPCHK(hipMemcpyAsync(w.hhist + it + 1, hist + it + 1, sizeof(double) * todo, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    int conv = -1;
+    bool conv = false;
     for (int j = 1; j <= todo; ++j) {
       const double rr = w.hhist[it + j];
       if (rr < 0.0 || !std::isfinite(rr)) {
@@ -105,30 +119,50 @@ static CgResult cg_run(Op& op, const double* b, double* x, bool x0_given, double
         return res;
       }
       if (rr <= thr) {
-        conv = j;
+        conv = true;
         break;
       }
     }
+    const double first = w.hhist[it + 1];
     it += todo;
-    const double last = w.hhist[it];
-    res.relres = std::sqrt(std::max(last, 0.0) / hs.bb);
-    if (conv > 0) {
-      res.iters = it;
-      return res;
+    double last = w.hhist[it];
+    res.iters = it;
+    if (cp.reliable && (conv || last <= cp.delta * cp.delta * rr_true)) {
+      // residual replacement with the FP64 operator
+      op_apply(op, x, q, DOGIP_F64, st);
+      vk_replace(b, q, invd, r, n, part, sc, st);
+      HIPCHK(hipMemcpyAsync(&hs, sc, sizeof hs, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (hs.flags || !std::isfinite(hs.rr)) {
+        res.status = DOGIP_E_NONFINITE;
+        return res;
+      }
+      stalls = hs.rr > 0.25 * rr_true ? stalls + 1 : 0;
+      rr_true = hs.rr;
+      last = hs.rr;
+      conv = hs.rr <= thr;
+      if (!conv && stalls >= 3) {  // the FP32 operator no longer reduces the true residual
+        res.relres = std::sqrt(hs.rr / hs.bb);
+        res.status = DOGIP_E_NOT_CONVERGED;
+        res.stalled = true;
+        return res;
+      }
     }
-    if (it >= maxit) {
-      res.iters = it;
+    res.relres = std::sqrt(std::max(last, 0.0) / hs.bb);
+    if (conv) return res;
+    if (it >= cp.maxit) {
       res.status = DOGIP_E_NOT_CONVERGED;
       return res;
     }
     // predict the iterations still needed from the recent convergence rate
-    const double first = w.hhist[it - todo + 1] > 0 ? w.hhist[it - todo + 1] : last;
     if (todo > 1 && last > 0 && first > last) {
       const double rate = std::log(last / first) / (todo - 1);
-      const double need = std::log(thr / last) / rate;
-      step = int(std::min<double>(std::max<double>(need * 0.9, 1.0), double(std::max(8, check_every * 4))));
+      double target = thr;
+      if (cp.reliable) target = std::max(thr, cp.delta * cp.delta * rr_true);
+      const double need = std::log(target / last) / rate;
+      step = int(std::min<double>(std::max<double>(need * 0.9, 1.0), double(std::max(8, cp.check_every * 4))));
     } else {
-      step = std::max(1, check_every);
+      step = std::max(1, cp.check_every);
     }
   }
 }
@@ -158,21 +192,43 @@ int op_pcg(Op& op, const double* b, double* x, const dogip_solve_opts& o, dogip_
   DOGIP_CHECK(b && x, DOGIP_E_NULL, "null vector");
   DOGIP_CHECK(b != x, DOGIP_E_INVALID, "b and x must differ");
   DOGIP_CHECK(o.tol > 0.0 && o.maxit >= 1, DOGIP_E_RANGE, "tol must be > 0 and maxit >= 1");
-  DOGIP_CHECK(o.mode == DOGIP_SOLVE_F64 || o.mode == DOGIP_SOLVE_MIXED, DOGIP_E_RANGE, "unknown solve mode");
+  DOGIP_CHECK(o.mode >= DOGIP_SOLVE_F64 && o.mode <= DOGIP_SOLVE_MIXED_RESTART, DOGIP_E_RANGE, "unknown solve mode");
   DOGIP_CHECK(o.mode == DOGIP_SOLVE_F64 || op.has32, DOGIP_E_STATE, "mixed mode needs DOGIP_OP_FP32");
   const auto t0 = std::chrono::steady_clock::now();
   std::memset(&stats, 0, sizeof stats);
   const int check = o.check_every > 0 ? o.check_every : 16;
   PcgWork& w = work(op, o.maxit);
   int status = DOGIP_OK;
-  if (o.mode == DOGIP_SOLVE_F64) {
-    CgResult c = cg_run(op, b, x, o.x0_given != 0, o.tol, o.maxit, DOGIP_F64, check, st);
+  CgParams cp;
+  cp.tol = o.tol;
+  cp.maxit = o.maxit;
+  cp.check_every = check;
+  if (o.mode == DOGIP_SOLVE_F64 || o.mode == DOGIP_SOLVE_MIXED) {
+    // FP64: plain Jacobi-PCG.  MIXED: the same iteration with the FP32 apply and FP64
+    // residual replacement (reliable updates); vectors and inner products stay FP64.
+    cp.prec = o.mode == DOGIP_SOLVE_F64 ? DOGIP_F64 : DOGIP_F32;
+    cp.reliable = o.mode == DOGIP_SOLVE_MIXED;
+    cp.delta = (o.inner_tol > 0 && o.inner_tol < 1) ? o.inner_tol : 0.1;
+    CgResult c = cg_run(op, b, x, o.x0_given != 0, cp, st);
     status = c.status;
     stats.iters = c.iters;
     stats.outer = 1;
     stats.relres = c.relres;
+    if (c.stalled && c.iters < o.maxit) {
+      // finish with the FP64 operator from the current iterate
+      CgParams f = cp;
+      f.prec = DOGIP_F64;
+      f.reliable = false;
+      f.maxit = o.maxit - c.iters;
+      CgResult g = cg_run(op, b, x, true, f, st);
+      status = g.status;
+      stats.iters += g.iters;
+      stats.outer = 2;
+      stats.relres = g.relres;
+    }
   } else {
-    // FP64 iterative refinement: r = b - A64 x; A32 d ~= r by inner PCG; x += d.
+    // MIXED_RESTART: FP64 iterative refinement r = b - A64 x; A32 d ~= r by a restarted
+    // inner PCG to inner_tol; x += d.
     const int64_t n = op.space->ndofs;
     double* rout = w.rout.as<double>();
     double* dx = w.dx.as<double>();
@@ -189,8 +245,11 @@ int op_pcg(Op& op, const double* b, double* x, const dogip_solve_opts& o, dogip_
     int total = 0;
     for (int outer = 0; outer < max_outer; ++outer) {
       if (bn == 0.0 || stats.relres <= o.tol) break;
-      const double want = std::max(inner_tol, 0.3 * o.tol / stats.relres);
-      CgResult c = cg_run(op, rout, dx, false, want, std::max(1, o.maxit - total), DOGIP_F32, check, st);
+      CgParams in = cp;
+      in.prec = DOGIP_F32;
+      in.tol = std::max(inner_tol, 0.3 * o.tol / stats.relres);
+      in.maxit = std::max(1, o.maxit - total);
+      CgResult c = cg_run(op, rout, dx, false, in, st);
       total += c.iters;
       stats.outer = outer + 1;
       if (c.status == DOGIP_E_BREAKDOWN || c.status == DOGIP_E_NONFINITE) {
@@ -211,10 +270,12 @@ int op_pcg(Op& op, const double* b, double* x, const dogip_solve_opts& o, dogip_
       }
       if (stats.relres > 0.9 * prev && stats.relres > o.tol) {
         // stagnation of the refinement: finish with FP64 CG from the current x
-        CgResult f = cg_run(op, b, x, true, o.tol, std::max(1, o.maxit - total), DOGIP_F64, check, st);
-        total += f.iters;
-        status = f.status;
-        stats.relres = f.relres;
+        CgParams f = cp;
+        f.maxit = std::max(1, o.maxit - total);
+        CgResult g = cg_run(op, b, x, true, f, st);
+        total += g.iters;
+        status = g.status;
+        stats.relres = g.relres;
         break;
       }
     }

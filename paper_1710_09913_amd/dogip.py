@@ -18,6 +18,7 @@ BC = {"none": capi.DOGIP_BC_NONE, "dirichlet": capi.DOGIP_BC_DIRICHLET0}
 COEF = {"scalar": capi.DOGIP_COEF_SCALAR, "sym": capi.DOGIP_COEF_SYM, "logscalar": capi.DOGIP_COEF_LOGSCALAR,
         "raw_d": capi.DOGIP_COEF_RAW_D}
 PREC = {"f64": capi.DOGIP_F64, "f32": capi.DOGIP_F32}
+SOLVE = {"f64": capi.DOGIP_SOLVE_F64, "mixed": capi.DOGIP_SOLVE_MIXED, "mixed_restart": capi.DOGIP_SOLVE_MIXED_RESTART}
 
 
 def stream_ptr(stream=None) -> int:
@@ -186,14 +187,14 @@ class Operator:
         check(lib().dogip_op_export_d(self.h, _dev_ptr(out), stream_ptr(stream)))
         return out
 
-    def pcg(self, b, x=None, tol=1e-8, maxit=20000, mode="f64", inner_tol=1e-5, max_outer=20, check_every=16,
+    def pcg(self, b, x=None, tol=1e-8, maxit=20000, mode="f64", inner_tol=0.0, max_outer=20, check_every=16,
             stream=None, raise_on_error=True):
         import torch
 
         x0 = x is not None
         if x is None:
             x = torch.zeros_like(b)
-        o = capi.SolveOpts(tol=tol, maxit=maxit, mode=capi.DOGIP_SOLVE_MIXED if mode == "mixed" else 0,
+        o = capi.SolveOpts(tol=tol, maxit=maxit, mode=SOLVE[mode],
                            inner_tol=inner_tol, max_outer=max_outer, check_every=check_every, x0_given=int(x0))
         st = capi.SolveStats()
         rc = lib().dogip_pcg(self.h, _dev_ptr(b, torch.float64, self.ndofs), _dev_ptr(x, torch.float64, self.ndofs),
@@ -250,14 +251,14 @@ class Batch:
                                       _dev_ptr(y, torch.float64, self.ndofs), PREC[prec], stream_ptr(stream)))
         return y
 
-    def pcg(self, b, x=None, tol=1e-8, maxit=20000, mode="f64", inner_tol=1e-5, max_outer=20, check_every=16,
+    def pcg(self, b, x=None, tol=1e-8, maxit=20000, mode="f64", inner_tol=0.0, max_outer=20, check_every=16,
             stream=None, raise_on_error=True):
         import torch
 
         x0 = x is not None
         if x is None:
             x = torch.zeros_like(b)
-        o = capi.SolveOpts(tol=tol, maxit=maxit, mode=capi.DOGIP_SOLVE_MIXED if mode == "mixed" else 0,
+        o = capi.SolveOpts(tol=tol, maxit=maxit, mode=SOLVE[mode],
                            inner_tol=inner_tol, max_outer=max_outer, check_every=check_every, x0_given=int(x0))
         st = (capi.SolveStats * len(self.ops))()
         rc = lib().dogip_batch_pcg(self.h, _dev_ptr(b, torch.float64, self.ndofs),
