@@ -1,23 +1,269 @@
-// Batched operators (persistent launch): placeholder until the batch kernels land.
+// Batched operators: one persistent launch per apply over all problems, and a
+// Jacobi-PCG per problem driven by segmented vector kernels (one CG each, with its
+// own scalars and stopping test, all problems advancing in the same launches).
 #include "batch.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
 
 namespace dogip {
 
-struct BatchWork {};
+struct BatchWork {
+  int maxit = 0;
+  DevBuf r, p, q, yout, part, energy, sc, rr_true, iters, need, stalls, active, res;
+};
+
 Batch::~Batch() = default;
 
-std::unique_ptr<Batch> make_batch(const std::vector<std::shared_ptr<Op>>& ops, hipStream_t) {
+template <class T>
+static void upload_vec(DevBuf& b, const std::vector<T>& v) {
+  b.alloc(std::max<size_t>(v.size(), 1) * sizeof(T));
+  if (!v.empty()) HIPCHK(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+std::unique_ptr<Batch> make_batch(const std::vector<std::shared_ptr<Op>>& ops, hipStream_t st) {
   auto b = std::make_unique<Batch>();
   b->ops = ops;
-  b->offsets.push_back(0);
-  for (auto& o : ops) b->offsets.push_back(b->offsets.back() + o->space->ndofs);
+  const Space& s0 = *ops[0]->space;
+  b->dim = s0.dim;
+  b->kind = s0.kind;
+  DOGIP_CHECK(b->dim == 2, DOGIP_E_RANGE, "batched launches are built for 2D problems");
+  const int np = int(ops.size());
+  std::vector<BatchDesc> desc(np);
+  std::vector<int64_t> voff(np + 1, 0), tile_base(np + 1, 0), bnd_off(np + 1, 0);
+  std::vector<int32_t> shared, bnd;
+  std::vector<uint32_t> rowptr(1, 0), slots;
+  std::vector<std::pair<double, uint64_t>> items;
+  int64_t stage_total = 0;
+  int64_t max32 = 0, max64 = 0;
+  bool all32 = true;
+  for (int p = 0; p < np; ++p) {
+    const Op& op = *ops[p];
+    const Space& s = *op.space;
+    DOGIP_CHECK(s.dim == b->dim && s.kind == b->kind, DOGIP_E_INVALID, "batch problems must share dim and kind");
+    DOGIP_CHECK(s.k >= 1 && s.k <= 4, DOGIP_E_RANGE, "batched launches cover k = 1..4");
+    DOGIP_CHECK(op.variant == DOGIP_VARIANT_UNROLLED, DOGIP_E_INVALID, "batch operators must use the unrolled kernels");
+    DOGIP_CHECK(op.plan.te <= 256, DOGIP_E_RANGE, "batch tiles must have at most 256 cells");
+    all32 = all32 && op.has32;
+    BatchDesc& d = desc[p];
+    d.D64 = op.d64.p;
+    d.D32 = op.d32.p;
+    d.lidx = op.lidx.as<uint16_t>();
+    d.tile_off = op.tile_off.as<int64_t>();
+    d.tile_dofs = op.tile_dofs.as<uint32_t>();
+    d.stage_off = op.stage_off.as<int64_t>();
+    d.nel = s.nc;
+    d.ntiles = op.plan.ntiles;
+    d.nch64 = op.nch64;
+    d.nch32 = op.nch32;
+    d.voff = voff[p];
+    d.stage_base = stage_total;
+    d.tile_base = tile_base[p];
+    d.nlc = op.plan.nlc;
+    d.te = op.plan.te;
+    d.lds_slots = int(op.plan.max_tile_dofs);
+    d.k = s.k;
+    max64 = std::max<int64_t>(max64, d.lds_slots);
+    max32 = std::max<int64_t>(max32, d.lds_slots);
+    voff[p + 1] = voff[p] + s.ndofs;
+    tile_base[p + 1] = tile_base[p] + op.plan.ntiles;
+    // work items: cost ~ D bytes of the tile's cells
+    for (int64_t t = 0; t < op.plan.ntiles; ++t) {
+      const int64_t cells = std::min<int64_t>(op.plan.te, s.nc - t * op.plan.te);
+      items.push_back({-double(cells) * double(op.nch64 + op.plan.nlc), (uint64_t(p) << 32) | uint64_t(t)});
+    }
+    // combined second-pass lists (indices into the concatenated vectors / staging buffer)
+    for (size_t i = 0; i < op.plan.shared.size(); ++i) {
+      shared.push_back(int32_t(voff[p] + op.plan.shared[i]));
+      for (uint32_t j = op.plan.sh_rowptr[i]; j < op.plan.sh_rowptr[i + 1]; ++j)
+        slots.push_back(uint32_t(stage_total + op.plan.sh_slots[j]));
+      rowptr.push_back(uint32_t(slots.size()));
+    }
+    for (int32_t v : s.boundary) bnd.push_back(int32_t(voff[p] + v));
+    bnd_off[p + 1] = int64_t(bnd.size());
+    stage_total += op.plan.stage_off.back();
+  }
+  DOGIP_CHECK(voff[np] < (int64_t(1) << 31) && stage_total < (int64_t(1) << 32), DOGIP_E_RANGE, "batch too large");
+  std::stable_sort(items.begin(), items.end(),
+                   [](const std::pair<double, uint64_t>& a, const std::pair<double, uint64_t>& c) { return a.first < c.first; });
+  std::vector<uint64_t> it(items.size());
+  for (size_t i = 0; i < items.size(); ++i) it[i] = items[i].second;
+  b->offsets = voff;
+  b->ntiles_total = tile_base[np];
+  b->nitems = int64_t(it.size());
+  b->nshared = int64_t(shared.size());
+  b->nbnd = int64_t(bnd.size());
+  upload_vec(b->desc, desc);
+  upload_vec(b->items, it);
+  upload_vec(b->voff, voff);
+  upload_vec(b->tile_base, tile_base);
+  upload_vec(b->shared, shared);
+  upload_vec(b->rowptr, rowptr);
+  upload_vec(b->slots, slots);
+  upload_vec(b->bnd, bnd);
+  upload_vec(b->bnd_off, bnd_off);
+  b->counter.alloc(sizeof(uint32_t));
+  b->stage.alloc(size_t(std::max<int64_t>(stage_total, 1)) * sizeof(double));
+  b->invd.alloc(size_t(voff[np]) * sizeof(double));
+  for (int p = 0; p < np; ++p)
+    HIPCHK(hipMemcpyAsync(b->invd.as<double>() + voff[p], ops[p]->invdiag.p, size_t(voff[p + 1] - voff[p]) * sizeof(double),
+                          hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  // persistent grid: as many workgroups as fit on the device at once
+  b->lds64 = size_t(max64) * (sizeof(double) + sizeof(double));
+  b->lds32 = size_t(max32) * (sizeof(double) + sizeof(float));
+  int dev = 0, ncu = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const int o64 = std::max(1, batch_blocks_per_cu(b->dim, b->kind, DOGIP_F64, b->lds64));
+  const int o32 = all32 ? std::max(1, batch_blocks_per_cu(b->dim, b->kind, DOGIP_F32, b->lds32)) : 1;
+  b->grid64 = unsigned(std::max(1, ncu * o64));
+  b->grid32 = unsigned(std::max(1, ncu * o32));
+  b->w = std::make_unique<BatchWork>();
   return b;
 }
-void batch_apply(Batch&, const double*, double*, int, hipStream_t) {
-  throw Error(DOGIP_E_STATE, "batched apply not available in this build");
+
+static BatchLaunch launch_args(Batch& b, const double* u, double* y, int prec) {
+  BatchLaunch bl{};
+  bl.desc = b.desc.as<BatchDesc>();
+  bl.items = b.items.as<uint64_t>();
+  bl.counter = b.counter.as<uint32_t>();
+  bl.nitems = b.nitems;
+  bl.u = u;
+  bl.y = y;
+  bl.stage = b.stage.as<double>();
+  bl.prec = prec;
+  return bl;
 }
-int batch_pcg(Batch&, const double*, double*, const dogip_solve_opts&, dogip_solve_stats*, hipStream_t) {
-  throw Error(DOGIP_E_STATE, "batched solve not available in this build");
+
+static void run_apply(Batch& b, const BatchLaunch& bl, bool energy, hipStream_t st) {
+  const bool f64 = bl.prec == DOGIP_F64;
+  launch_batch_apply(b.dim, b.kind, bl, f64 ? b.grid64 : b.grid32, f64 ? b.lds64 : b.lds32, energy, st);
+  launch_apply_finish(b.stage.as<double>(), b.rowptr.as<uint32_t>(), b.slots.as<uint32_t>(), b.shared.as<int32_t>(),
+                      b.nshared, b.bnd.as<int32_t>(), b.nbnd, bl.u, bl.y, nullptr, st);
+  HIPCHK(hipGetLastError());
+}
+
+void batch_apply(Batch& b, const double* u, double* y, int prec, hipStream_t st) {
+  DOGIP_CHECK(u && y, DOGIP_E_NULL, "null vector");
+  DOGIP_CHECK(u != y, DOGIP_E_INVALID, "apply needs u != y");
+  DOGIP_CHECK(prec == DOGIP_F64 || prec == DOGIP_F32, DOGIP_E_RANGE, "prec must be DOGIP_F64 or DOGIP_F32");
+  if (prec == DOGIP_F32)
+    for (auto& o : b.ops) DOGIP_CHECK(o->has32, DOGIP_E_STATE, "FP32 apply needs operators built with DOGIP_OP_FP32");
+  run_apply(b, launch_args(b, u, y, prec), false, st);
+}
+
+int batch_pcg(Batch& b, const double* rhs, double* x, const dogip_solve_opts& o, dogip_solve_stats* stats,
+              hipStream_t st) {
+  DOGIP_CHECK(rhs && x, DOGIP_E_NULL, "null vector");
+  DOGIP_CHECK(rhs != x, DOGIP_E_INVALID, "b and x must differ");
+  DOGIP_CHECK(o.tol > 0.0 && o.maxit >= 1, DOGIP_E_RANGE, "tol must be > 0 and maxit >= 1");
+  DOGIP_CHECK(o.mode == DOGIP_SOLVE_F64 || o.mode == DOGIP_SOLVE_MIXED, DOGIP_E_RANGE,
+              "batched solves support DOGIP_SOLVE_F64 and DOGIP_SOLVE_MIXED");
+  DOGIP_CHECK(!o.x0_given, DOGIP_E_RANGE, "batched solves start from x0 = 0");
+  const bool mixed = o.mode == DOGIP_SOLVE_MIXED;
+  if (mixed)
+    for (auto& op : b.ops) DOGIP_CHECK(op->has32, DOGIP_E_STATE, "mixed mode needs DOGIP_OP_FP32");
+  const auto t0 = std::chrono::steady_clock::now();
+  const int np = int(b.ops.size());
+  const int64_t n = b.offsets.back();
+  constexpr int GX = 32;
+  BatchWork& w = *b.w;
+  if (!w.r.p) {
+    const size_t vb = size_t(n) * sizeof(double);
+    w.r.alloc(vb);
+    w.p.alloc(vb);
+    w.q.alloc(vb);
+    w.yout.alloc(vb);
+    w.part.alloc(size_t(np) * GX * 3 * sizeof(double));
+    w.energy.alloc(size_t(b.ntiles_total) * sizeof(double));
+    w.sc.alloc(size_t(np) * sizeof(PcgScalars));
+    w.rr_true.alloc(size_t(np) * sizeof(double));
+    w.iters.alloc(size_t(np) * sizeof(int));
+    w.need.alloc(size_t(np) * sizeof(int));
+    w.stalls.alloc(size_t(np) * sizeof(int));
+    w.active.alloc(size_t(np) * sizeof(int));
+    w.res.alloc(size_t(np) * sizeof(double));
+  }
+  BatchVecArgs v{};
+  v.voff = b.voff.as<int64_t>();
+  v.invd = b.invd.as<double>();
+  v.r = w.r.as<double>();
+  v.p = w.p.as<double>();
+  v.part = w.part.as<double>();
+  v.s = {w.sc.as<PcgScalars>(), w.rr_true.as<double>(), w.iters.as<int>(), w.need.as<int>(), w.stalls.as<int>(),
+         w.active.as<int>()};
+  v.gx = GX;
+  v.np = np;
+  v.tol = o.tol;
+  const double delta = (o.inner_tol > 0 && o.inner_tol < 1) ? o.inner_tol : 0.1;
+  const int check = o.check_every > 0 ? o.check_every : 16;
+  bk_init(v, rhs, x, st);
+  std::vector<int> active(np), iters(np);
+  int done_it = 0;
+  for (;;) {
+    HIPCHK(hipMemcpyAsync(active.data(), w.active.p, sizeof(int) * np, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int nact = 0;
+    for (int a : active) nact += a;
+    if (nact == 0 || done_it >= o.maxit) break;
+    const int todo = std::min(check, o.maxit - done_it);
+    for (int j = 0; j < todo; ++j) {
+      BatchLaunch bl = launch_args(b, v.p, w.q.as<double>(), mixed ? DOGIP_F32 : DOGIP_F64);
+      bl.energy = w.energy.as<double>();
+      bl.active = w.active.as<int>();
+      run_apply(b, bl, true, st);
+      bk_fin_pq(v, w.energy.as<double>(), b.tile_base.as<int64_t>(), b.bnd.as<int32_t>(), b.bnd_off.as<int64_t>(), st);
+      bk_xr(v, x, w.q.as<double>(), st);
+      bk_fin_rz(v, delta, mixed ? 1 : 0, st);
+      bk_p(v, st);
+    }
+    done_it += todo;
+    if (mixed) {
+      // residual replacement r = b - A64 x for the problems that asked for it
+      BatchLaunch bl = launch_args(b, x, w.yout.as<double>(), DOGIP_F64);
+      bl.active = w.active.as<int>();
+      bl.mask = w.need.as<int>();
+      run_apply(b, bl, false, st);
+      bk_replace(v, rhs, w.yout.as<double>(), st);
+    }
+  }
+  // verified residuals with the FP64 operator
+  run_apply(b, launch_args(b, x, w.yout.as<double>(), DOGIP_F64), false, st);
+  bk_resid(v, rhs, w.yout.as<double>(), w.res.as<double>(), st);
+  std::vector<double> res(np);
+  std::vector<PcgScalars> sc(np);
+  HIPCHK(hipMemcpyAsync(res.data(), w.res.p, sizeof(double) * np, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(sc.data(), w.sc.p, sizeof(PcgScalars) * np, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(iters.data(), w.iters.p, sizeof(int) * np, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int worst = DOGIP_OK;
+  for (int p = 0; p < np; ++p) {
+    const double bn = std::sqrt(sc[p].bb);
+    const double rel = bn > 0 ? std::sqrt(res[p]) / bn : 0.0;
+    int status = DOGIP_OK;
+    if (sc[p].flags & PCG_BREAKDOWN)
+      status = DOGIP_E_BREAKDOWN;
+    else if ((sc[p].flags & PCG_NONFINITE) || !std::isfinite(rel))
+      status = DOGIP_E_NONFINITE;
+    else if (rel > o.tol)
+      status = DOGIP_E_NOT_CONVERGED;
+    if (status != DOGIP_OK && (worst == DOGIP_OK || status > worst)) worst = status;
+    if (stats) {
+      dogip_solve_stats& s = stats[p];
+      std::memset(&s, 0, sizeof s);
+      s.status = status;
+      s.iters = iters[p];
+      s.outer = 1;
+      s.relres = bn > 0 ? std::sqrt(std::max(sc[p].rr, 0.0)) / bn : 0.0;
+      s.relres_true = rel;
+      s.seconds = secs;
+    }
+  }
+  return worst;
 }
 
 }  // namespace dogip

@@ -66,18 +66,17 @@ __device__ __forceinline__ void flush_batch(const uint32_t (&e)[GB], int64_t nd,
   }
 }
 
-// The tile kernel.  T is the element arithmetic precision (D is stored in T);
-// the per-tile accumulation in LDS is always FP64 (ds_add_f64).  When the tile
-// has at most GB * blockDim entries (the usual case) the entries loaded by the
-// gather stay in registers for the flush.
+// Work of one tile (one workgroup).  T is the element arithmetic precision (D is
+// stored in T); the per-tile accumulation in LDS is always FP64 (ds_add_f64).
+// When the tile has at most GB * blockDim entries (the usual case) the entries
+// loaded by the gather stay in registers for the flush.  energy_out: where the
+// tile's sum_T u_T^T A_T u_T goes (ENERGY only).
 template <int D, int K, int KIND, typename T, int VARIANT, bool ENERGY, int PF>
-__global__ __launch_bounds__(512, DOGIP_WPE) void k_apply(ApplyLaunch a) {
+__device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsigned char* smem, double* energy_out) {
   using E = Elem<D, K, KIND, T, T, VARIANT, ENERGY, PF>;
   constexpr int VT = E::VT;
-  extern __shared__ __align__(16) unsigned char smem[];
   double* ys = reinterpret_cast<double*>(smem);
   T* us = reinterpret_cast<T*>(ys + a.lds_slots);
-  const int64_t t = a.tile_base + xcd_tile(blockIdx.x, gridDim.x);
   const int64_t o0 = a.tile_off[t], nd = a.tile_off[t + 1] - o0;
   const uint32_t* td = a.tile_dofs + o0;
   const bool one = nd <= int64_t(GB) * blockDim.x;
@@ -88,8 +87,11 @@ __global__ __launch_bounds__(512, DOGIP_WPE) void k_apply(ApplyLaunch a) {
     for (int64_t j0 = threadIdx.x; j0 < nd; j0 += int64_t(GB) * blockDim.x) gather_batch<T>(td, nd, j0, a.u, us, ys, ent);
   }
   __syncthreads();
-  const int64_t e = t * a.te + threadIdx.x;
+  int64_t e = t * a.te + threadIdx.x;
+  if (int(threadIdx.x) >= a.te) e = a.nel;  // lanes beyond a smaller tile do no cell work
   T en = T(0);
+  double yacc[VT];
+  int sl[VT];
   if (e < a.nel) {
     const int lane = threadIdx.x & 63;
     const int64_t w = t * (a.te >> 6) + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
@@ -99,9 +101,14 @@ __global__ __launch_bounds__(512, DOGIP_WPE) void k_apply(ApplyLaunch a) {
     sfor<VT>([&](auto L) { ue[L] = us[li[L]]; });
     const typename E::V* dp = reinterpret_cast<const typename E::V*>(a.D) + (w * a.nch) * 64 + lane;
     en = E::run(dp, ue, ye);
-    sfor<VT>([&](auto L) { atomicAdd(&ys[li[L]], double(ye[L])); });
+    sfor<VT>([&](auto L) { yacc[L] = double(ye[L]); sl[L] = li[L]; });
   }
-  __syncthreads();
+  // LDS accumulation one wave after the other, so the sums are bitwise reproducible
+  const int nw = (a.te + 63) >> 6, me = int(threadIdx.x >> 6);
+  for (int wv = 0; wv < nw; ++wv) {
+    if (me == wv && e < a.nel) sfor<VT>([&](auto L) { atomicAdd(&ys[sl[L]], yacc[L]); });
+    __syncthreads();
+  }
   double* stage = a.stage + a.stage_off[t];
   if (one) {
     flush_batch(ent, nd, threadIdx.x, ys, stage, a.y);
@@ -118,8 +125,16 @@ __global__ __launch_bounds__(512, DOGIP_WPE) void k_apply(ApplyLaunch a) {
   if constexpr (ENERGY) {
     __shared__ double red[8];
     const double s = block_sum(double(en), red);
-    if (threadIdx.x == 0) a.energy[t] = s;
+    if (threadIdx.x == 0) *energy_out = s;
   }
+}
+
+// One workgroup per tile; workgroup -> tile mapping keeps each XCD on a contiguous range.
+template <int D, int K, int KIND, typename T, int VARIANT, bool ENERGY, int PF>
+__global__ __launch_bounds__(512, DOGIP_WPE) void k_apply(ApplyLaunch a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t t = a.tile_base + xcd_tile(blockIdx.x, gridDim.x);
+  tile_body<D, K, KIND, T, VARIANT, ENERGY, PF>(a, t, smem, ENERGY ? a.energy + t : nullptr);
 }
 
 template <int D, int K, int KIND, int VARIANT>

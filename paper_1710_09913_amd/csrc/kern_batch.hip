@@ -1,0 +1,331 @@
+// Batched operators: one persistent launch applies many independent problems, and
+// segmented vector kernels run one CG per problem with per-problem scalars.
+#include "batch.hpp"
+#include "kern_apply.hpp"
+#include "solve.hpp"
+
+namespace dogip {
+namespace dev {
+
+// Persistent apply: every workgroup takes (problem, tile) items from a queue
+// (largest work first) until the queue is exhausted; problems whose flag in
+// `active` (or `mask`) is zero are skipped.
+template <int D, int KIND, typename T, bool ENERGY>
+__global__ __launch_bounds__(256) void k_batch_apply(BatchLaunch bl) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ uint32_t cur;
+  for (;;) {
+    if (threadIdx.x == 0) cur = atomicAdd(bl.counter, 1u);
+    __syncthreads();
+    const uint32_t it = cur;
+    __syncthreads();
+    if (it >= bl.nitems) break;
+    const uint64_t item = bl.items[it];
+    const int p = int(item >> 32);
+    const int64_t t = int64_t(item & 0xffffffffu);
+    if ((bl.active && !bl.active[p]) || (bl.mask && !bl.mask[p])) continue;
+    const BatchDesc& d = bl.desc[p];
+    ApplyLaunch a{};
+    a.D = bl.prec == DOGIP_F64 ? d.D64 : d.D32;
+    a.lidx = d.lidx;
+    a.tile_off = d.tile_off;
+    a.tile_dofs = d.tile_dofs;
+    a.u = bl.u + d.voff;
+    a.y = bl.y + d.voff;
+    a.stage_off = d.stage_off;
+    a.stage = bl.stage + d.stage_base;
+    a.nel = d.nel;
+    a.ntiles = d.ntiles;
+    a.nch = bl.prec == DOGIP_F64 ? d.nch64 : d.nch32;
+    a.nlc = d.nlc;
+    a.te = d.te;
+    a.lds_slots = d.lds_slots;
+    double* eo = ENERGY ? bl.energy + d.tile_base + t : nullptr;
+    constexpr int V = DOGIP_VARIANT_UNROLLED;
+    constexpr int PF = sizeof(T) == 8 ? DOGIP_PF64 : DOGIP_PF32;
+    switch (d.k) {
+      case 1: tile_body<D, 1, KIND, T, V, ENERGY, PF>(a, t, smem, eo); break;
+      case 2: tile_body<D, 2, KIND, T, V, ENERGY, PF>(a, t, smem, eo); break;
+      case 3: tile_body<D, 3, KIND, T, V, ENERGY, PF>(a, t, smem, eo); break;
+      default: tile_body<D, 4, KIND, T, V, ENERGY, PF>(a, t, smem, eo); break;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_reset_counter(uint32_t* c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0u;
+}
+
+__device__ __forceinline__ double bwave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block partials of up to 3 sums: part[(p * gridDim.x + blockIdx.x) * 3 + c].
+__device__ __forceinline__ void bpartials(const double* v, int nc, double* part, int p) {
+  __shared__ double red[3][4];
+  const int w = threadIdx.x >> 6;
+  for (int c = 0; c < nc; ++c) {
+    const double s = bwave_sum(v[c]);
+    if ((threadIdx.x & 63) == 0) red[c][w] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int c = 0; c < nc; ++c) part[(int64_t(p) * gridDim.x + blockIdx.x) * 3 + c] = red[c][0] + red[c][1] + red[c][2] + red[c][3];
+}
+
+// Sum of n values with one 256-thread block (fixed order); result in thread 0.
+__device__ __forceinline__ double bsum(const double* x, int64_t n, int64_t stride) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += x[i * stride];
+  s = bwave_sum(s);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  const double t = red[0] + red[1] + red[2] + red[3];
+  __syncthreads();
+  return t;
+}
+
+#define PROBLEM_RANGE(p, lo, hi)               \
+  const int p = blockIdx.y;                    \
+  const int64_t lo = voff[p], hi = voff[p + 1]; \
+  for (int64_t i = lo + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < hi; i += int64_t(gridDim.x) * blockDim.x)
+
+// r = b, z = invd r, p = z; partials (r.z, r.r, b.b)
+__global__ __launch_bounds__(256) void k_b_init(const int64_t* __restrict__ voff, const double* __restrict__ b,
+                                                const double* __restrict__ invd, double* __restrict__ r,
+                                                double* __restrict__ pv, double* __restrict__ x,
+                                                double* __restrict__ part) {
+  double v[3] = {0.0, 0.0, 0.0};
+  PROBLEM_RANGE(p, lo, hi) {
+    const double bi = b[i], zi = invd[i] * bi;
+    r[i] = bi;
+    pv[i] = zi;
+    x[i] = 0.0;
+    v[0] += bi * zi;
+    v[1] += bi * bi;
+    v[2] += bi * bi;
+  }
+  bpartials(v, 3, part, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void k_b_fin_init(const double* __restrict__ part, int gx, BatchPcgState s,
+                                                    double tol) {
+  const int p = blockIdx.x;
+  const double rz = bsum(part + int64_t(p) * gx * 3 + 0, gx, 3);
+  const double rr = bsum(part + int64_t(p) * gx * 3 + 1, gx, 3);
+  const double bb = bsum(part + int64_t(p) * gx * 3 + 2, gx, 3);
+  if (threadIdx.x == 0) {
+    PcgScalars& c = s.sc[p];
+    c.rho = rz;
+    c.rr = rr;
+    c.bb = bb;
+    c.flags = (isfinite(rz) && isfinite(rr) && isfinite(bb)) ? 0 : PCG_NONFINITE;
+    s.rr_true[p] = rr;
+    s.iters[p] = 0;
+    s.need[p] = 0;
+    s.stalls[p] = 0;
+    s.active[p] = (c.flags == 0 && rr > tol * tol * bb) ? 1 : 0;
+  }
+}
+
+// pq = sum of the problem's tile energies + p_b^2 over its Dirichlet dofs; alpha = rho / pq
+__global__ __launch_bounds__(256) void k_b_fin_pq(const double* __restrict__ energy, const int64_t* __restrict__ tile_base,
+                                                  const int32_t* __restrict__ bnd, const int64_t* __restrict__ bnd_off,
+                                                  const double* __restrict__ pv, BatchPcgState s) {
+  const int p = blockIdx.x;
+  if (!s.active[p]) return;
+  const double e = bsum(energy + tile_base[p], tile_base[p + 1] - tile_base[p], 1);
+  __shared__ double red[4];
+  double q = 0.0;
+  for (int64_t i = bnd_off[p] + threadIdx.x; i < bnd_off[p + 1]; i += blockDim.x) {
+    const double v = pv[bnd[i]];
+    q += v * v;
+  }
+  q = bwave_sum(q);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = q;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double pq = e + red[0] + red[1] + red[2] + red[3];
+    PcgScalars& c = s.sc[p];
+    c.pq = pq;
+    if (!isfinite(pq))
+      c.flags |= PCG_NONFINITE;
+    else if (!(pq > 0.0))
+      c.flags |= PCG_BREAKDOWN;
+    c.alpha = c.flags ? 0.0 : c.rho / pq;
+    if (c.flags) s.active[p] = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_b_xr(const int64_t* __restrict__ voff, double* __restrict__ x,
+                                              double* __restrict__ r, const double* __restrict__ pv,
+                                              const double* __restrict__ q, const double* __restrict__ invd,
+                                              BatchPcgState s, double* __restrict__ part) {
+  if (!s.active[blockIdx.y]) return;
+  const double alpha = s.sc[blockIdx.y].alpha;
+  double v[2] = {0.0, 0.0};
+  PROBLEM_RANGE(p, lo, hi) {
+    x[i] = fma(alpha, pv[i], x[i]);
+    const double ri = fma(-alpha, q[i], r[i]);
+    r[i] = ri;
+    v[0] += ri * (invd[i] * ri);
+    v[1] += ri * ri;
+  }
+  bpartials(v, 2, part, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void k_b_fin_rz(const double* __restrict__ part, int gx, BatchPcgState s, double tol,
+                                                  double delta, int reliable) {
+  const int p = blockIdx.x;
+  if (!s.active[p]) return;
+  const double rz = bsum(part + int64_t(p) * gx * 3 + 0, gx, 3);
+  const double rr = bsum(part + int64_t(p) * gx * 3 + 1, gx, 3);
+  if (threadIdx.x == 0) {
+    PcgScalars& c = s.sc[p];
+    if (!isfinite(rz) || !isfinite(rr)) c.flags |= PCG_NONFINITE;
+    c.beta = (c.rho != 0.0 && c.flags == 0) ? rz / c.rho : 0.0;
+    c.rho = rz;
+    c.rr = rr;
+    s.iters[p] += 1;
+    const double thr = tol * tol * c.bb;
+    if (c.flags) {
+      s.active[p] = 0;
+    } else if (reliable) {
+      if (rr <= thr || rr <= delta * delta * s.rr_true[p]) s.need[p] = 1;
+    } else if (rr <= thr) {
+      s.active[p] = 0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_b_p(const int64_t* __restrict__ voff, double* __restrict__ pv,
+                                             const double* __restrict__ r, const double* __restrict__ invd,
+                                             BatchPcgState s) {
+  if (!s.active[blockIdx.y]) return;
+  const double beta = s.sc[blockIdx.y].beta;
+  PROBLEM_RANGE(p, lo, hi) pv[i] = fma(beta, pv[i], invd[i] * r[i]);
+}
+
+// residual replacement for problems with need[p]: r = b - A64 x
+__global__ __launch_bounds__(256) void k_b_replace(const int64_t* __restrict__ voff, const double* __restrict__ b,
+                                                   const double* __restrict__ y, const double* __restrict__ invd,
+                                                   double* __restrict__ r, BatchPcgState s,
+                                                   double* __restrict__ part) {
+  if (!s.active[blockIdx.y] || !s.need[blockIdx.y]) return;
+  double v[2] = {0.0, 0.0};
+  PROBLEM_RANGE(p, lo, hi) {
+    const double ri = b[i] - y[i];
+    r[i] = ri;
+    v[0] += ri * (invd[i] * ri);
+    v[1] += ri * ri;
+  }
+  bpartials(v, 2, part, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void k_b_fin_replace(const double* __restrict__ part, int gx, BatchPcgState s,
+                                                       double tol) {
+  const int p = blockIdx.x;
+  if (!s.active[p] || !s.need[p]) return;
+  const double rz = bsum(part + int64_t(p) * gx * 3 + 0, gx, 3);
+  const double rr = bsum(part + int64_t(p) * gx * 3 + 1, gx, 3);
+  if (threadIdx.x == 0) {
+    PcgScalars& c = s.sc[p];
+    if (!isfinite(rz) || !isfinite(rr)) c.flags |= PCG_NONFINITE;
+    s.stalls[p] = rr > 0.25 * s.rr_true[p] ? s.stalls[p] + 1 : 0;
+    c.rho = rz;
+    c.rr = rr;
+    s.rr_true[p] = rr;
+    s.need[p] = 0;
+    if (c.flags || rr <= tol * tol * c.bb || s.stalls[p] >= 3) s.active[p] = 0;
+  }
+}
+
+// per-problem ||b - y||^2 (final check)
+__global__ __launch_bounds__(256) void k_b_resid(const int64_t* __restrict__ voff, const double* __restrict__ b,
+                                                 const double* __restrict__ y, double* __restrict__ part) {
+  double v[1] = {0.0};
+  PROBLEM_RANGE(p, lo, hi) {
+    const double d = b[i] - y[i];
+    v[0] += d * d;
+  }
+  bpartials(v, 1, part, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void k_b_fin_resid(const double* __restrict__ part, int gx, double* out) {
+  const double t = bsum(part + int64_t(blockIdx.x) * gx * 3, gx, 3);
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
+template <int D, int KIND>
+void batch_apply_t(const BatchLaunch& bl, unsigned grid, size_t lds, bool energy, hipStream_t st) {
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, bl.counter);
+  if (bl.prec == DOGIP_F64) {
+    if (energy)
+      hipLaunchKernelGGL((k_batch_apply<D, KIND, double, true>), dim3(grid), dim3(256), lds, st, bl);
+    else
+      hipLaunchKernelGGL((k_batch_apply<D, KIND, double, false>), dim3(grid), dim3(256), lds, st, bl);
+  } else {
+    if (energy)
+      hipLaunchKernelGGL((k_batch_apply<D, KIND, float, true>), dim3(grid), dim3(256), lds, st, bl);
+    else
+      hipLaunchKernelGGL((k_batch_apply<D, KIND, float, false>), dim3(grid), dim3(256), lds, st, bl);
+  }
+}
+
+template <int D, int KIND>
+int batch_occupancy(int prec, size_t lds) {
+  int n = 0;
+  if (prec == DOGIP_F64)
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_batch_apply<D, KIND, double, true>), 256, lds));
+  else
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_batch_apply<D, KIND, float, true>), 256, lds));
+  return n;
+}
+
+}  // namespace dev
+
+void launch_batch_apply(int dim, int kind, const BatchLaunch& bl, unsigned grid, size_t lds, bool energy,
+                        hipStream_t st) {
+  DOGIP_CHECK(dim == 2, DOGIP_E_RANGE, "batched launches are built for 2D problems");
+  if (kind == KIND_SE)
+    dev::batch_apply_t<2, KIND_SE>(bl, grid, lds, energy, st);
+  else
+    dev::batch_apply_t<2, KIND_WP>(bl, grid, lds, energy, st);
+}
+
+int batch_blocks_per_cu(int dim, int kind, int prec, size_t lds) {
+  DOGIP_CHECK(dim == 2, DOGIP_E_RANGE, "batched launches are built for 2D problems");
+  return kind == KIND_SE ? dev::batch_occupancy<2, KIND_SE>(prec, lds) : dev::batch_occupancy<2, KIND_WP>(prec, lds);
+}
+
+void bk_init(const BatchVecArgs& v, const double* b, double* x, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_b_init, dim3(v.gx, v.np), dim3(256), 0, st, v.voff, b, v.invd, v.r, v.p, x, v.part);
+  hipLaunchKernelGGL(dev::k_b_fin_init, dim3(v.np), dim3(256), 0, st, v.part, v.gx, v.s, v.tol);
+}
+void bk_fin_pq(const BatchVecArgs& v, const double* energy, const int64_t* tile_base, const int32_t* bnd,
+               const int64_t* bnd_off, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_b_fin_pq, dim3(v.np), dim3(256), 0, st, energy, tile_base, bnd, bnd_off, v.p, v.s);
+}
+void bk_xr(const BatchVecArgs& v, double* x, const double* q, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_b_xr, dim3(v.gx, v.np), dim3(256), 0, st, v.voff, x, v.r, v.p, q, v.invd, v.s, v.part);
+}
+void bk_fin_rz(const BatchVecArgs& v, double delta, int reliable, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_b_fin_rz, dim3(v.np), dim3(256), 0, st, v.part, v.gx, v.s, v.tol, delta, reliable);
+}
+void bk_p(const BatchVecArgs& v, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_b_p, dim3(v.gx, v.np), dim3(256), 0, st, v.voff, v.p, v.r, v.invd, v.s);
+}
+void bk_replace(const BatchVecArgs& v, const double* b, const double* y, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_b_replace, dim3(v.gx, v.np), dim3(256), 0, st, v.voff, b, y, v.invd, v.r, v.s, v.part);
+  hipLaunchKernelGGL(dev::k_b_fin_replace, dim3(v.np), dim3(256), 0, st, v.part, v.gx, v.s, v.tol);
+}
+void bk_resid(const BatchVecArgs& v, const double* b, const double* y, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_b_resid, dim3(v.gx, v.np), dim3(256), 0, st, v.voff, b, y, v.part);
+  hipLaunchKernelGGL(dev::k_b_fin_resid, dim3(v.np), dim3(256), 0, st, v.part, v.gx, out);
+}
+
+}  // namespace dogip
