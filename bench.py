@@ -113,6 +113,199 @@ def cpu_baseline(k, n_sample=20):
     }
 
 
+def _base(metric, unit, value, ms, a, config, dtype="f64", hib=True):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+            "ms_per_step": ms, "higher_is_better": hib, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": config}
+
+
+def _rhs_f1(space, mesh, k):
+    """b_i = int phi_i (f = 1) from the projection operator with m = 1; zero on Dirichlet dofs."""
+    import numpy as np
+    import torch
+
+    from paper_1710_09913_amd import Operator, Space
+
+    wp = Operator(Space(mesh, k, "wp", "none"), torch.ones(space.ncells, dtype=torch.float64), "scalar", fp32=False)
+    b = wp.apply(torch.ones(space.ndofs, dtype=torch.float64, device="cuda"))
+    if space.info["bc"]:
+        b[torch.from_numpy(space.boundary().astype(np.int64)).cuda()] = 0.0
+    return b
+
+
+def run_c2(a):
+    """2D unit square 512^2 x 2 triangles, P1..P5, projection (m ~ U[1,100]) and elliptic
+    (anisotropic SPD per cell): FP64 and FP32 apply, and for the elliptic problem FP64 vs
+    mixed PCG to 1e-8."""
+    import torch
+
+    from paper_1710_09913_amd import Mesh, Operator, Space
+    from workloads import coef_aniso_2d, coef_uniform, random_vector
+
+    n = 512
+    mesh = Mesh.unit(2, n)
+    rows = []
+    for kind in ("wp", "se"):
+        for k in (1, 2, 3, 4, 5):
+            sp = Space(mesh, k, kind, "dirichlet" if kind == "se" else "none")
+            if kind == "wp":
+                op = Operator(sp, torch.from_numpy(coef_uniform(sp.ncells, 1, 100, a.seed)), "scalar", fp32=True)
+            else:
+                op = Operator(sp, torch.from_numpy(coef_aniso_2d(sp.ncells, a.seed)), "sym", fp32=True)
+            u = torch.from_numpy(random_vector(sp.ndofs, a.seed)).cuda()
+            y = torch.empty_like(u)
+            row = {"kind": kind, "k": k, "ndofs": sp.ndofs}
+            for prec in ("f64", "f32"):
+                ms, kms = time_apply(op, u, y, prec, a.steps, a.warmup)
+                ab = op.info["alg_bytes_" + prec]
+                row[prec] = {"GDoF_s": round(sp.ndofs / (ms * 1e-3) / 1e9, 3), "ms": round(ms, 5),
+                             "frac": round(ab / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            if kind == "se" and not a.no_solve:
+                b = _rhs_f1(sp, mesh, k)
+                for mode in ("f64", "mixed"):
+                    op.pcg(b, tol=1e-8, maxit=50000, mode=mode)
+                    torch.cuda.synchronize()
+                    t0 = time.time()
+                    _, st = op.pcg(b, tol=1e-8, maxit=50000, mode=mode)
+                    dt = time.time() - t0
+                    row["pcg_" + mode] = {"seconds": round(dt, 4), "iters": st["iters"],
+                                          "relres_true": st["relres_true"]}
+            log(f"[c2] {row}")
+            rows.append(row)
+            del op
+    head = next(r for r in rows if r["kind"] == "se" and r["k"] == 5)
+    out = _base("DoGIP apply GDoF/s, 2D 512^2 P1..P5 (projection and elliptic)", "GDoF/s", head["f64"]["GDoF_s"],
+                head["f64"]["ms"], a, {"workload": "2D unit square 512^2 x 2 triangles, P1..P5, projection "
+                                                   "(m ~ U[1,100]) and elliptic (anisotropic SPD, eigenvalues ~ U[1,100])",
+                                       "value_row": "elliptic P5 FP64 apply"})
+    out["rows"] = rows
+    return out
+
+
+def run_c4(a):
+    """2D 256^2 P3 inverse problem: time of one gradient (forward PCG + adjoint PCG +
+    contraction) and a finite-difference spot check."""
+    import numpy as np
+    import torch
+
+    from paper_1710_09913_amd import Mesh, Operator, Space
+    from paper_1710_09913_amd.autograd import solve
+    from workloads import theta_normal
+
+    n, k = 256, 3
+    mesh = Mesh.unit(2, n)
+    sp = Space(mesh, k, "se", "dirichlet")
+    op = Operator(sp, torch.zeros(sp.ncells, dtype=torch.float64), "logscalar", fp32=True)
+    b = _rhs_f1(sp, mesh, k)
+    bnd = torch.from_numpy(sp.boundary().astype(np.int64)).cuda()
+    with torch.no_grad():
+        u_star = solve(torch.from_numpy(theta_normal(sp.ncells, 99)).cuda(), b, op, tol=1e-12)
+        rms = torch.sqrt(torch.mean(u_star ** 2))
+        u_obs = u_star + 0.01 * rms * torch.from_numpy(np.random.default_rng(5).standard_normal(sp.ndofs)).cuda()
+        u_obs[bnd] = 0.0
+    theta0 = torch.from_numpy(theta_normal(sp.ncells, 1)).cuda()
+    times = {}
+    for mode, tol in (("f64", 1e-10), ("mixed", 1e-10)):
+        for rep in range(2):
+            th = theta0.clone().requires_grad_(True)
+            torch.cuda.synchronize()
+            t0 = time.time()
+            u = solve(th, b, op, tol=tol, mode=mode)
+            J = 0.5 * ((u - u_obs) ** 2).sum()
+            J.backward()
+            torch.cuda.synchronize()
+            times[mode] = time.time() - t0
+        log(f"[c4] gradient ({mode}) {times[mode]:.3f}s J={J.item():.6e}")
+    g = th.grad.detach()
+    rng = np.random.default_rng(7)
+    errs = []
+    with torch.no_grad():
+        for _ in range(4):
+            v = torch.from_numpy(rng.standard_normal(sp.ncells)).cuda()
+            jp = 0.5 * ((solve(theta0 + 1e-6 * v, b, op, tol=1e-14) - u_obs) ** 2).sum()
+            jm = 0.5 * ((solve(theta0 - 1e-6 * v, b, op, tol=1e-14) - u_obs) ** 2).sum()
+            gv = torch.dot(g, v).item()
+            errs.append(abs((jp - jm).item() / 2e-6 - gv) / abs(gv))
+    out = _base("Adjoint gradient dJ/dtheta, 2D 256^2 P3 inverse problem: seconds per gradient", "s",
+                round(times["mixed"], 4), round(times["mixed"] * 1e3, 3), a,
+                {"workload": "2D 256^2 x 2 triangles, P3 elliptic, theta ~ N(0, 0.5^2), u_obs from hidden theta* + 1% noise",
+                 "ndofs": sp.ndofs, "ncells": sp.ncells}, hib=False)
+    out["gradient_seconds"] = {m: round(t, 4) for m, t in times.items()}
+    out["fd_rel_err_max_4dirs"] = max(errs)
+    return out
+
+
+def run_c5(a):
+    """256 independent 2D elliptic problems (N ~ logU[32,256], k ~ U{1..4}, a ~ U[1,10]):
+    tuned tiles, one persistent launch per apply, batched FP64 vs mixed PCG to 1e-8,
+    against solving the problems one after another."""
+    import numpy as np
+    import torch
+
+    from paper_1710_09913_amd import Batch, Mesh, Operator, Space, tune
+    from workloads import batch_spec, coef_uniform
+
+    for k in (1, 2, 3, 4):
+        if tune.tuned(2, k, "se", "f32") == (0, 0):
+            tune.tune(2, k, "se", "f32", max_tile_cells=256)
+    spec = batch_spec(256, a.seed)
+    ops, meshes = [], {}
+    t0 = time.time()
+    for n, k, sub in spec:
+        if n not in meshes:
+            meshes[n] = Mesh.unit(2, n)
+        sp = Space(meshes[n], k, "se", "dirichlet")
+        tw, var = tune.tuned(2, k, "se", "f32")
+        ops.append(Operator(sp, torch.from_numpy(coef_uniform(sp.ncells, 1, 10, a.seed, sub)), "scalar", fp32=True,
+                            tile_waves=tw, variant=1))
+    bt = Batch(ops)
+    log(f"[c5] {len(ops)} problems, {bt.ndofs} dofs, setup {time.time() - t0:.1f}s")
+    rhs = torch.ones(bt.ndofs, dtype=torch.float64, device="cuda")
+    for i, op in enumerate(ops):
+        rhs[torch.from_numpy(op.space.boundary().astype(np.int64) + int(bt.offsets[i])).cuda()] = 0.0
+    u = torch.ones(bt.ndofs, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(u)
+    apply_ms = {}
+    for prec in ("f64", "f32"):
+        for _ in range(a.warmup):
+            bt.apply(u, y, prec=prec)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(a.steps):
+            bt.apply(u, y, prec=prec)
+        e1.record()
+        torch.cuda.synchronize()
+        apply_ms[prec] = e0.elapsed_time(e1) / a.steps
+    solve_s = {}
+    for mode in ("f64", "mixed"):
+        bt.pcg(rhs, tol=1e-8, maxit=50000, mode=mode)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        _, stats = bt.pcg(rhs, tol=1e-8, maxit=50000, mode=mode)
+        torch.cuda.synchronize()
+        solve_s[mode] = time.time() - t0
+        bad = [s for s in stats if s["status"] != 0]
+        dof_it = sum(s["iters"] * (int(bt.offsets[i + 1]) - int(bt.offsets[i])) for i, s in enumerate(stats))
+        log(f"[c5] batched pcg {mode}: {solve_s[mode]:.3f}s, max iters {max(s['iters'] for s in stats)}, "
+            f"failures {len(bad)}, {dof_it / solve_s[mode] / 1e9:.2f} G dof-iterations/s")
+    t0 = time.time()
+    for i, op in enumerate(ops):
+        lo, hi = int(bt.offsets[i]), int(bt.offsets[i + 1])
+        op.pcg(rhs[lo:hi].contiguous(), tol=1e-8, maxit=50000, mode="mixed")
+    torch.cuda.synchronize()
+    seq = time.time() - t0
+    log(f"[c5] one problem after another (mixed): {seq:.3f}s")
+    out = _base("Batch of 256 uneven 2D elliptic problems: batched mixed PCG time-to-1e-8", "s",
+                round(solve_s["mixed"], 4), round(apply_ms["f32"], 5), a,
+                {"workload": "256 2D elliptic problems, N ~ round(logU[32,256]), k ~ U{1..4}, a ~ U[1,10]",
+                 "ndofs_total": bt.ndofs}, hib=False)
+    out["batch_apply_GDoF_s"] = {p: round(bt.ndofs / (ms * 1e-3) / 1e9, 3) for p, ms in apply_ms.items()}
+    out["batched_pcg_seconds"] = {m: round(t, 4) for m, t in solve_s.items()}
+    out["sequential_mixed_pcg_seconds"] = round(seq, 4)
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +316,9 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "c5"],
+                    help="c3: 3D 64^3 P3 (default, the headline); c2: 2D 512^2 P1..P5 sweep; "
+                         "c4: 2D 256^2 P3 adjoint gradient; c5: batch of 256 uneven 2D problems")
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the multi-GPU path (element partition with an interface-dof "
@@ -132,6 +328,10 @@ def main(argv=None):
     import torch
 
     torch.cuda.set_device(0)
+    if a.workload != "c3":
+        out = {"c2": run_c2, "c4": run_c4, "c5": run_c5}[a.workload](a)
+        print(json.dumps(out), flush=True)
+        return 0
     space, op, b = build_problem(a.n, a.k, a.seed)
     from workloads import random_vector
 

@@ -12,7 +12,14 @@ namespace dogip {
 
 struct BatchWork {
   int maxit = 0;
-  DevBuf r, p, q, yout, part, energy, sc, rr_true, iters, need, stalls, active, res;
+  DevBuf r, p, q, yout, part, energy, sc, rr_true, iters, need, stalls, active, res, state, use64;
+  DevBuf act, rep, items_a, items_b, items_r;  // compacted problem and work-item lists
+  int* h_lists = nullptr;                      // pinned: active, use64, need, act, rep
+  uint64_t* h_items = nullptr;                 // pinned: three item lists
+  ~BatchWork() {
+    if (h_lists) (void)hipHostFree(h_lists);
+    if (h_items) (void)hipHostFree(h_items);
+  }
 };
 
 Batch::~Batch() = default;
@@ -34,6 +41,7 @@ std::unique_ptr<Batch> make_batch(const std::vector<std::shared_ptr<Op>>& ops, h
   std::vector<BatchDesc> desc(np);
   std::vector<int64_t> voff(np + 1, 0), tile_base(np + 1, 0), bnd_off(np + 1, 0);
   std::vector<int32_t> shared, bnd;
+  std::vector<int64_t> sh_off(np + 1, 0);
   std::vector<uint32_t> rowptr(1, 0), slots;
   std::vector<std::pair<double, uint64_t>> items;
   int64_t stage_total = 0;
@@ -81,6 +89,7 @@ std::unique_ptr<Batch> make_batch(const std::vector<std::shared_ptr<Op>>& ops, h
         slots.push_back(uint32_t(stage_total + op.plan.sh_slots[j]));
       rowptr.push_back(uint32_t(slots.size()));
     }
+    sh_off[p + 1] = int64_t(shared.size());
     for (int32_t v : s.boundary) bnd.push_back(int32_t(voff[p] + v));
     bnd_off[p + 1] = int64_t(bnd.size());
     stage_total += op.plan.stage_off.back();
@@ -104,6 +113,8 @@ std::unique_ptr<Batch> make_batch(const std::vector<std::shared_ptr<Op>>& ops, h
   upload_vec(b->slots, slots);
   upload_vec(b->bnd, bnd);
   upload_vec(b->bnd_off, bnd_off);
+  upload_vec(b->sh_off, sh_off);
+  b->items_host = it;
   b->counter.alloc(sizeof(uint32_t));
   b->stage.alloc(size_t(std::max<int64_t>(stage_total, 1)) * sizeof(double));
   b->invd.alloc(size_t(voff[np]) * sizeof(double));
@@ -169,15 +180,16 @@ int batch_pcg(Batch& b, const double* rhs, double* x, const dogip_solve_opts& o,
   const auto t0 = std::chrono::steady_clock::now();
   const int np = int(b.ops.size());
   const int64_t n = b.offsets.back();
-  constexpr int GX = 32;
+  constexpr int GX_MAX = 1024;  // blocks per problem in the segmented vector kernels
   BatchWork& w = *b.w;
+  const size_t ni = b.items_host.size();
   if (!w.r.p) {
     const size_t vb = size_t(n) * sizeof(double);
     w.r.alloc(vb);
     w.p.alloc(vb);
     w.q.alloc(vb);
     w.yout.alloc(vb);
-    w.part.alloc(size_t(np) * GX * 3 * sizeof(double));
+    w.part.alloc(size_t(np) * GX_MAX * 3 * sizeof(double));
     w.energy.alloc(size_t(b.ntiles_total) * sizeof(double));
     w.sc.alloc(size_t(np) * sizeof(PcgScalars));
     w.rr_true.alloc(size_t(np) * sizeof(double));
@@ -186,6 +198,15 @@ int batch_pcg(Batch& b, const double* rhs, double* x, const dogip_solve_opts& o,
     w.stalls.alloc(size_t(np) * sizeof(int));
     w.active.alloc(size_t(np) * sizeof(int));
     w.res.alloc(size_t(np) * sizeof(double));
+    w.state.alloc(size_t(np) * sizeof(int));
+    w.use64.alloc(size_t(np) * sizeof(int));
+    w.act.alloc(size_t(np) * sizeof(int));
+    w.rep.alloc(size_t(np) * sizeof(int));
+    w.items_a.alloc(ni * sizeof(uint64_t));
+    w.items_b.alloc(ni * sizeof(uint64_t));
+    w.items_r.alloc(ni * sizeof(uint64_t));
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&w.h_lists), size_t(5) * np * sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&w.h_items), size_t(3) * ni * sizeof(uint64_t), hipHostMallocDefault));
   }
   BatchVecArgs v{};
   v.voff = b.voff.as<int64_t>();
@@ -194,41 +215,93 @@ int batch_pcg(Batch& b, const double* rhs, double* x, const dogip_solve_opts& o,
   v.p = w.p.as<double>();
   v.part = w.part.as<double>();
   v.s = {w.sc.as<PcgScalars>(), w.rr_true.as<double>(), w.iters.as<int>(), w.need.as<int>(), w.stalls.as<int>(),
-         w.active.as<int>()};
-  v.gx = GX;
+         w.active.as<int>(), w.state.as<int>(), w.use64.as<int>()};
+  v.gx = 32;
   v.np = np;
   v.tol = o.tol;
   const double delta = (o.inner_tol > 0 && o.inner_tol < 1) ? o.inner_tol : 0.1;
   const int check = o.check_every > 0 ? o.check_every : 16;
   bk_init(v, rhs, x, st);
-  std::vector<int> active(np), iters(np);
+  int* h_active = w.h_lists;
+  int* h_use64 = w.h_lists + np;
+  int* h_need = w.h_lists + 2 * np;
+  int* h_act = w.h_lists + 3 * np;
+  int* h_rep = w.h_lists + 4 * np;
+  uint64_t* h_ia = w.h_items;
+  uint64_t* h_ib = w.h_items + ni;
+  uint64_t* h_ir = w.h_items + 2 * ni;
+  // items of the problems selected by sel(p), in the stored (largest first) order
+  auto filter_items = [&](uint64_t* out, auto sel) {
+    int64_t c = 0;
+    for (uint64_t it : b.items_host)
+      if (sel(int(it >> 32))) out[c++] = it;
+    return c;
+  };
+  auto apply_list = [&](const double* u, double* y, int prec, const uint64_t* items, int64_t nitems, bool energy) {
+    if (nitems <= 0) return;
+    BatchLaunch bl = launch_args(b, u, y, prec);
+    bl.items = items;
+    bl.nitems = nitems;
+    bl.energy = energy ? w.energy.as<double>() : nullptr;
+    const bool f64 = prec == DOGIP_F64;
+    launch_batch_apply(b.dim, b.kind, bl, f64 ? b.grid64 : b.grid32, f64 ? b.lds64 : b.lds32, energy, st);
+  };
+  auto finish_list = [&](const int* act, int nact, const double* u, double* y) {
+    bk_finish(v, act, nact, b.stage.as<double>(), b.rowptr.as<uint32_t>(), b.slots.as<uint32_t>(),
+              b.shared.as<int32_t>(), b.sh_off.as<int64_t>(), b.bnd.as<int32_t>(), b.bnd_off.as<int64_t>(), u, y, st);
+  };
+  std::vector<int> iters(np), state(np), use64(np);
   int done_it = 0;
   for (;;) {
-    HIPCHK(hipMemcpyAsync(active.data(), w.active.p, sizeof(int) * np, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_active, w.active.p, sizeof(int) * np, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_use64, w.use64.p, sizeof(int) * np, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h_need, w.need.p, sizeof(int) * np, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    if (mixed) {
+      // residual replacement r = b - A64 x for the problems that asked for it
+      int nrep = 0;
+      for (int p = 0; p < np; ++p)
+        if (h_active[p] && h_need[p]) h_rep[nrep++] = p;
+      if (nrep > 0) {
+        const int64_t nir = filter_items(h_ir, [&](int p) { return h_active[p] && h_need[p]; });
+        HIPCHK(hipMemcpyAsync(w.rep.p, h_rep, sizeof(int) * nrep, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(w.items_r.p, h_ir, sizeof(uint64_t) * nir, hipMemcpyHostToDevice, st));
+        apply_list(x, w.yout.as<double>(), DOGIP_F64, w.items_r.as<uint64_t>(), nir, false);
+        finish_list(w.rep.as<int>(), nrep, x, w.yout.as<double>());
+        BatchVecArgs vr = v;
+        vr.act = w.rep.as<int>();
+        vr.nact = nrep;
+        bk_replace(vr, rhs, w.yout.as<double>(), st);
+        HIPCHK(hipMemcpyAsync(h_active, w.active.p, sizeof(int) * np, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(h_use64, w.use64.p, sizeof(int) * np, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+      }
+    }
     int nact = 0;
-    for (int a : active) nact += a;
+    for (int p = 0; p < np; ++p)
+      if (h_active[p]) h_act[nact++] = p;
     if (nact == 0 || done_it >= o.maxit) break;
+    const int64_t nia = filter_items(h_ia, [&](int p) { return h_active[p] && !(mixed && h_use64[p]); });
+    const int64_t nib = mixed ? filter_items(h_ib, [&](int p) { return h_active[p] && h_use64[p]; }) : 0;
+    HIPCHK(hipMemcpyAsync(w.act.p, h_act, sizeof(int) * nact, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(w.items_a.p, h_ia, sizeof(uint64_t) * std::max<int64_t>(nia, 1), hipMemcpyHostToDevice, st));
+    if (nib > 0) HIPCHK(hipMemcpyAsync(w.items_b.p, h_ib, sizeof(uint64_t) * nib, hipMemcpyHostToDevice, st));
+    v.act = w.act.as<int>();
+    v.nact = nact;
+    // spread the segmented vector kernels over the whole device whatever the number of problems left
+    v.gx = std::min(GX_MAX, std::max(16, 8192 / nact));
     const int todo = std::min(check, o.maxit - done_it);
     for (int j = 0; j < todo; ++j) {
-      BatchLaunch bl = launch_args(b, v.p, w.q.as<double>(), mixed ? DOGIP_F32 : DOGIP_F64);
-      bl.energy = w.energy.as<double>();
-      bl.active = w.active.as<int>();
-      run_apply(b, bl, true, st);
+      apply_list(v.p, w.q.as<double>(), mixed ? DOGIP_F32 : DOGIP_F64, w.items_a.as<uint64_t>(), nia, true);
+      apply_list(v.p, w.q.as<double>(), DOGIP_F64, w.items_b.as<uint64_t>(), nib, true);
+      finish_list(v.act, nact, v.p, w.q.as<double>());
+      HIPCHK(hipGetLastError());
       bk_fin_pq(v, w.energy.as<double>(), b.tile_base.as<int64_t>(), b.bnd.as<int32_t>(), b.bnd_off.as<int64_t>(), st);
       bk_xr(v, x, w.q.as<double>(), st);
       bk_fin_rz(v, delta, mixed ? 1 : 0, st);
       bk_p(v, st);
     }
     done_it += todo;
-    if (mixed) {
-      // residual replacement r = b - A64 x for the problems that asked for it
-      BatchLaunch bl = launch_args(b, x, w.yout.as<double>(), DOGIP_F64);
-      bl.active = w.active.as<int>();
-      bl.mask = w.need.as<int>();
-      run_apply(b, bl, false, st);
-      bk_replace(v, rhs, w.yout.as<double>(), st);
-    }
   }
   // verified residuals with the FP64 operator
   run_apply(b, launch_args(b, x, w.yout.as<double>(), DOGIP_F64), false, st);
@@ -238,6 +311,8 @@ int batch_pcg(Batch& b, const double* rhs, double* x, const dogip_solve_opts& o,
   HIPCHK(hipMemcpyAsync(res.data(), w.res.p, sizeof(double) * np, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(sc.data(), w.sc.p, sizeof(PcgScalars) * np, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(iters.data(), w.iters.p, sizeof(int) * np, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(state.data(), w.state.p, sizeof(int) * np, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(use64.data(), w.use64.p, sizeof(int) * np, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   int worst = DOGIP_OK;
@@ -249,7 +324,7 @@ int batch_pcg(Batch& b, const double* rhs, double* x, const dogip_solve_opts& o,
       status = DOGIP_E_BREAKDOWN;
     else if ((sc[p].flags & PCG_NONFINITE) || !std::isfinite(rel))
       status = DOGIP_E_NONFINITE;
-    else if (rel > o.tol)
+    else if (state[p] != 1)
       status = DOGIP_E_NOT_CONVERGED;
     if (status != DOGIP_OK && (worst == DOGIP_OK || status > worst)) worst = status;
     if (stats) {
@@ -257,7 +332,7 @@ int batch_pcg(Batch& b, const double* rhs, double* x, const dogip_solve_opts& o,
       std::memset(&s, 0, sizeof s);
       s.status = status;
       s.iters = iters[p];
-      s.outer = 1;
+      s.outer = use64[p] ? 2 : 1;
       s.relres = bn > 0 ? std::sqrt(std::max(sc[p].rr, 0.0)) / bn : 0.0;
       s.relres_true = rel;
       s.seconds = secs;

@@ -34,7 +34,8 @@ struct BatchLaunch {
   double* stage;
   double* energy;         // [total tiles] tile energies (ENERGY launches)
   const int* active;      // optional: skip problems with active[p] == 0
-  const int* mask;        // optional: skip problems with mask[p] == 0
+  const int* mask;        // optional: skip problems with mask[p] != mask_val
+  int mask_val;
   int prec;
 };
 
@@ -46,6 +47,8 @@ struct BatchPcgState {
   int* need;    // residual replacement requested
   int* stalls;
   int* active;
+  int* state;   // 0 running, 1 converged, 2 failed (breakdown or non-finite)
+  int* use64;   // mixed mode: the problem switched to the FP64 apply
 };
 
 struct BatchVecArgs {
@@ -55,6 +58,8 @@ struct BatchVecArgs {
   double* p;
   double* part;  // [np][gx][3]
   BatchPcgState s;
+  const int* act;  // problems the per-iteration kernels work on
+  int nact;
   int gx, np;
   double tol;
 };
@@ -68,7 +73,8 @@ struct Batch {
   int64_t ntiles_total = 0, nitems = 0, nshared = 0, nbnd = 0;
   size_t lds64 = 0, lds32 = 0;
   unsigned grid64 = 0, grid32 = 0;
-  DevBuf desc, items, counter, voff, stage, tile_base, shared, rowptr, slots, bnd, bnd_off, invd;
+  DevBuf desc, items, counter, voff, stage, tile_base, shared, rowptr, slots, bnd, bnd_off, invd, sh_off;
+  std::vector<uint64_t> items_host;  // work items, largest first
   std::unique_ptr<BatchWork> w;
   ~Batch();
 };
@@ -86,9 +92,12 @@ void bk_init(const BatchVecArgs& v, const double* b, double* x, hipStream_t st);
 void bk_fin_pq(const BatchVecArgs& v, const double* energy, const int64_t* tile_base, const int32_t* bnd,
                const int64_t* bnd_off, hipStream_t st);
 void bk_xr(const BatchVecArgs& v, double* x, const double* q, hipStream_t st);
-void bk_fin_rz(const BatchVecArgs& v, double delta, int reliable, hipStream_t st);
+void bk_fin_rz(const BatchVecArgs& v, double delta, int mixed, hipStream_t st);
 void bk_p(const BatchVecArgs& v, hipStream_t st);
 void bk_replace(const BatchVecArgs& v, const double* b, const double* y, hipStream_t st);
 void bk_resid(const BatchVecArgs& v, const double* b, const double* y, double* out, hipStream_t st);
+void bk_finish(const BatchVecArgs& v, const int* act, int nact, const double* stage, const uint32_t* rowptr,
+               const uint32_t* slots, const int32_t* shared, const int64_t* sh_off, const int32_t* bnd,
+               const int64_t* bnd_off, const double* u, double* y, hipStream_t st);
 
 }  // namespace dogip

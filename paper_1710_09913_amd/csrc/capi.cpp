@@ -347,7 +347,9 @@ int dogip_batch_pcg(dogip_batch b, const double* rhs, double* x, const dogip_sol
   return guard([&] {
     need(b);
     DOGIP_CHECK(opts, DOGIP_E_NULL, "null options");
-    return dogip::batch_pcg(*b->b, rhs, x, *opts, stats, S(stream));
+    const int status = dogip::batch_pcg(*b->b, rhs, x, *opts, stats, S(stream));
+    if (status != DOGIP_OK) g_err = "at least one problem of the batch did not converge (see its stats)";
+    return status;
   });
 }
 

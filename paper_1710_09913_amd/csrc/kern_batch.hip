@@ -23,7 +23,7 @@ __global__ __launch_bounds__(256) void k_batch_apply(BatchLaunch bl) {
     const uint64_t item = bl.items[it];
     const int p = int(item >> 32);
     const int64_t t = int64_t(item & 0xffffffffu);
-    if ((bl.active && !bl.active[p]) || (bl.mask && !bl.mask[p])) continue;
+    if ((bl.active && !bl.active[p]) || (bl.mask && bl.mask[p] != bl.mask_val)) continue;
     const BatchDesc& d = bl.desc[p];
     ApplyLaunch a{};
     a.D = bl.prec == DOGIP_F64 ? d.D64 : d.D32;
@@ -57,6 +57,8 @@ __global__ void k_reset_counter(uint32_t* c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0u;
 }
 
+__device__ __forceinline__ int p_of(const int* act) { return act ? act[blockIdx.y] : int(blockIdx.y); }
+
 __device__ __forceinline__ double bwave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
@@ -89,13 +91,14 @@ __device__ __forceinline__ double bsum(const double* x, int64_t n, int64_t strid
   return t;
 }
 
+// blockIdx.y indexes the list act of problems (all problems when act is null)
 #define PROBLEM_RANGE(p, lo, hi)               \
-  const int p = blockIdx.y;                    \
+  const int p = act ? act[blockIdx.y] : int(blockIdx.y); \
   const int64_t lo = voff[p], hi = voff[p + 1]; \
   for (int64_t i = lo + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < hi; i += int64_t(gridDim.x) * blockDim.x)
 
 // r = b, z = invd r, p = z; partials (r.z, r.r, b.b)
-__global__ __launch_bounds__(256) void k_b_init(const int64_t* __restrict__ voff, const double* __restrict__ b,
+__global__ __launch_bounds__(256) void k_b_init(const int* __restrict__ act, const int64_t* __restrict__ voff, const double* __restrict__ b,
                                                 const double* __restrict__ invd, double* __restrict__ r,
                                                 double* __restrict__ pv, double* __restrict__ x,
                                                 double* __restrict__ part) {
@@ -109,7 +112,7 @@ __global__ __launch_bounds__(256) void k_b_init(const int64_t* __restrict__ voff
     v[1] += bi * bi;
     v[2] += bi * bi;
   }
-  bpartials(v, 3, part, blockIdx.y);
+  bpartials(v, 3, part, p_of(act));
 }
 
 __global__ __launch_bounds__(256) void k_b_fin_init(const double* __restrict__ part, int gx, BatchPcgState s,
@@ -128,15 +131,18 @@ __global__ __launch_bounds__(256) void k_b_fin_init(const double* __restrict__ p
     s.iters[p] = 0;
     s.need[p] = 0;
     s.stalls[p] = 0;
+    s.use64[p] = 0;
     s.active[p] = (c.flags == 0 && rr > tol * tol * bb) ? 1 : 0;
+    s.state[p] = c.flags ? 2 : (s.active[p] ? 0 : 1);
   }
 }
 
 // pq = sum of the problem's tile energies + p_b^2 over its Dirichlet dofs; alpha = rho / pq
-__global__ __launch_bounds__(256) void k_b_fin_pq(const double* __restrict__ energy, const int64_t* __restrict__ tile_base,
-                                                  const int32_t* __restrict__ bnd, const int64_t* __restrict__ bnd_off,
-                                                  const double* __restrict__ pv, BatchPcgState s) {
-  const int p = blockIdx.x;
+__global__ __launch_bounds__(256) void k_b_fin_pq(const int* __restrict__ act, const double* __restrict__ energy,
+                                                  const int64_t* __restrict__ tile_base, const int32_t* __restrict__ bnd,
+                                                  const int64_t* __restrict__ bnd_off, const double* __restrict__ pv,
+                                                  BatchPcgState s) {
+  const int p = act[blockIdx.x];
   if (!s.active[p]) return;
   const double e = bsum(energy + tile_base[p], tile_base[p + 1] - tile_base[p], 1);
   __shared__ double red[4];
@@ -157,16 +163,20 @@ __global__ __launch_bounds__(256) void k_b_fin_pq(const double* __restrict__ ene
     else if (!(pq > 0.0))
       c.flags |= PCG_BREAKDOWN;
     c.alpha = c.flags ? 0.0 : c.rho / pq;
-    if (c.flags) s.active[p] = 0;
+    if (c.flags) {
+      s.active[p] = 0;
+      s.state[p] = 2;
+    }
   }
 }
 
-__global__ __launch_bounds__(256) void k_b_xr(const int64_t* __restrict__ voff, double* __restrict__ x,
-                                              double* __restrict__ r, const double* __restrict__ pv,
-                                              const double* __restrict__ q, const double* __restrict__ invd,
-                                              BatchPcgState s, double* __restrict__ part) {
-  if (!s.active[blockIdx.y]) return;
-  const double alpha = s.sc[blockIdx.y].alpha;
+__global__ __launch_bounds__(256) void k_b_xr(const int* __restrict__ act, const int64_t* __restrict__ voff,
+                                              double* __restrict__ x, double* __restrict__ r,
+                                              const double* __restrict__ pv, const double* __restrict__ q,
+                                              const double* __restrict__ invd, BatchPcgState s,
+                                              double* __restrict__ part) {
+  if (!s.active[p_of(act)]) return;
+  const double alpha = s.sc[p_of(act)].alpha;
   double v[2] = {0.0, 0.0};
   PROBLEM_RANGE(p, lo, hi) {
     x[i] = fma(alpha, pv[i], x[i]);
@@ -175,12 +185,12 @@ __global__ __launch_bounds__(256) void k_b_xr(const int64_t* __restrict__ voff, 
     v[0] += ri * (invd[i] * ri);
     v[1] += ri * ri;
   }
-  bpartials(v, 2, part, blockIdx.y);
+  bpartials(v, 2, part, p_of(act));
 }
 
-__global__ __launch_bounds__(256) void k_b_fin_rz(const double* __restrict__ part, int gx, BatchPcgState s, double tol,
-                                                  double delta, int reliable) {
-  const int p = blockIdx.x;
+__global__ __launch_bounds__(256) void k_b_fin_rz(const int* __restrict__ act, const double* __restrict__ part, int gx,
+                                                  BatchPcgState s, double tol, double delta, int mixed) {
+  const int p = act[blockIdx.x];
   if (!s.active[p]) return;
   const double rz = bsum(part + int64_t(p) * gx * 3 + 0, gx, 3);
   const double rr = bsum(part + int64_t(p) * gx * 3 + 1, gx, 3);
@@ -194,28 +204,32 @@ __global__ __launch_bounds__(256) void k_b_fin_rz(const double* __restrict__ par
     const double thr = tol * tol * c.bb;
     if (c.flags) {
       s.active[p] = 0;
-    } else if (reliable) {
+      s.state[p] = 2;
+    } else if (mixed && !s.use64[p]) {
+      // FP32 search directions: replace the residual when it has dropped by delta, and
+      // verify apparent convergence on the FP64 residual
       if (rr <= thr || rr <= delta * delta * s.rr_true[p]) s.need[p] = 1;
     } else if (rr <= thr) {
       s.active[p] = 0;
+      s.state[p] = 1;
     }
   }
 }
 
-__global__ __launch_bounds__(256) void k_b_p(const int64_t* __restrict__ voff, double* __restrict__ pv,
-                                             const double* __restrict__ r, const double* __restrict__ invd,
-                                             BatchPcgState s) {
-  if (!s.active[blockIdx.y]) return;
-  const double beta = s.sc[blockIdx.y].beta;
+__global__ __launch_bounds__(256) void k_b_p(const int* __restrict__ act, const int64_t* __restrict__ voff,
+                                             double* __restrict__ pv, const double* __restrict__ r,
+                                             const double* __restrict__ invd, BatchPcgState s) {
+  if (!s.active[p_of(act)]) return;
+  const double beta = s.sc[p_of(act)].beta;
   PROBLEM_RANGE(p, lo, hi) pv[i] = fma(beta, pv[i], invd[i] * r[i]);
 }
 
 // residual replacement for problems with need[p]: r = b - A64 x
-__global__ __launch_bounds__(256) void k_b_replace(const int64_t* __restrict__ voff, const double* __restrict__ b,
-                                                   const double* __restrict__ y, const double* __restrict__ invd,
-                                                   double* __restrict__ r, BatchPcgState s,
-                                                   double* __restrict__ part) {
-  if (!s.active[blockIdx.y] || !s.need[blockIdx.y]) return;
+__global__ __launch_bounds__(256) void k_b_replace(const int* __restrict__ act, const int64_t* __restrict__ voff,
+                                                   const double* __restrict__ b, const double* __restrict__ y,
+                                                   const double* __restrict__ invd, double* __restrict__ r,
+                                                   BatchPcgState s, double* __restrict__ part) {
+  if (!s.active[p_of(act)] || !s.need[p_of(act)]) return;
   double v[2] = {0.0, 0.0};
   PROBLEM_RANGE(p, lo, hi) {
     const double ri = b[i] - y[i];
@@ -223,12 +237,12 @@ __global__ __launch_bounds__(256) void k_b_replace(const int64_t* __restrict__ v
     v[0] += ri * (invd[i] * ri);
     v[1] += ri * ri;
   }
-  bpartials(v, 2, part, blockIdx.y);
+  bpartials(v, 2, part, p_of(act));
 }
 
-__global__ __launch_bounds__(256) void k_b_fin_replace(const double* __restrict__ part, int gx, BatchPcgState s,
-                                                       double tol) {
-  const int p = blockIdx.x;
+__global__ __launch_bounds__(256) void k_b_fin_replace(const int* __restrict__ act, const double* __restrict__ part,
+                                                       int gx, BatchPcgState s, double tol) {
+  const int p = act[blockIdx.x];
   if (!s.active[p] || !s.need[p]) return;
   const double rz = bsum(part + int64_t(p) * gx * 3 + 0, gx, 3);
   const double rr = bsum(part + int64_t(p) * gx * 3 + 1, gx, 3);
@@ -240,19 +254,52 @@ __global__ __launch_bounds__(256) void k_b_fin_replace(const double* __restrict_
     c.rr = rr;
     s.rr_true[p] = rr;
     s.need[p] = 0;
-    if (c.flags || rr <= tol * tol * c.bb || s.stalls[p] >= 3) s.active[p] = 0;
+    if (c.flags) {
+      s.active[p] = 0;
+      s.state[p] = 2;
+    } else if (rr <= tol * tol * c.bb) {
+      s.active[p] = 0;
+      s.state[p] = 1;
+    } else if (s.stalls[p] >= 3) {
+      s.use64[p] = 1;  // the FP32 operator stopped reducing the true residual: continue in FP64
+      s.stalls[p] = 0;
+    }
   }
 }
 
 // per-problem ||b - y||^2 (final check)
-__global__ __launch_bounds__(256) void k_b_resid(const int64_t* __restrict__ voff, const double* __restrict__ b,
-                                                 const double* __restrict__ y, double* __restrict__ part) {
+__global__ __launch_bounds__(256) void k_b_resid(const int* __restrict__ act, const int64_t* __restrict__ voff,
+                                                 const double* __restrict__ b, const double* __restrict__ y,
+                                                 double* __restrict__ part) {
   double v[1] = {0.0};
   PROBLEM_RANGE(p, lo, hi) {
     const double d = b[i] - y[i];
     v[0] += d * d;
   }
-  bpartials(v, 1, part, blockIdx.y);
+  bpartials(v, 1, part, p_of(act));
+}
+
+// Second pass of a batched apply restricted to the problems in act: shared-dof sums
+// and Dirichlet rows of each listed problem.
+__global__ __launch_bounds__(256) void k_b_finish(const int* __restrict__ act, const double* __restrict__ stage,
+                                                  const uint32_t* __restrict__ rowptr, const uint32_t* __restrict__ slots,
+                                                  const int32_t* __restrict__ shared, const int64_t* __restrict__ sh_off,
+                                                  const int32_t* __restrict__ bnd, const int64_t* __restrict__ bnd_off,
+                                                  const double* __restrict__ u, double* __restrict__ y) {
+  const int p = act[blockIdx.y];
+  const int64_t s0 = sh_off[p], s1 = sh_off[p + 1], b0 = bnd_off[p], b1 = bnd_off[p + 1];
+  const int64_t n = (s1 - s0) + (b1 - b0);
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += int64_t(gridDim.x) * blockDim.x) {
+    if (k < s1 - s0) {
+      const int64_t i = s0 + k;
+      double acc = 0.0;
+      for (uint32_t j = rowptr[i]; j < rowptr[i + 1]; ++j) acc += stage[slots[j]];
+      y[shared[i]] = acc;
+    } else {
+      const int32_t d = bnd[b0 + k - (s1 - s0)];
+      y[d] = u[d];
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void k_b_fin_resid(const double* __restrict__ part, int gx, double* out) {
@@ -303,29 +350,41 @@ int batch_blocks_per_cu(int dim, int kind, int prec, size_t lds) {
 }
 
 void bk_init(const BatchVecArgs& v, const double* b, double* x, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_b_init, dim3(v.gx, v.np), dim3(256), 0, st, v.voff, b, v.invd, v.r, v.p, x, v.part);
+  hipLaunchKernelGGL(dev::k_b_init, dim3(v.gx, v.np), dim3(256), 0, st, nullptr, v.voff, b, v.invd, v.r, v.p, x,
+                     v.part);
   hipLaunchKernelGGL(dev::k_b_fin_init, dim3(v.np), dim3(256), 0, st, v.part, v.gx, v.s, v.tol);
 }
 void bk_fin_pq(const BatchVecArgs& v, const double* energy, const int64_t* tile_base, const int32_t* bnd,
                const int64_t* bnd_off, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_b_fin_pq, dim3(v.np), dim3(256), 0, st, energy, tile_base, bnd, bnd_off, v.p, v.s);
+  hipLaunchKernelGGL(dev::k_b_fin_pq, dim3(v.nact), dim3(256), 0, st, v.act, energy, tile_base, bnd, bnd_off, v.p,
+                     v.s);
 }
 void bk_xr(const BatchVecArgs& v, double* x, const double* q, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_b_xr, dim3(v.gx, v.np), dim3(256), 0, st, v.voff, x, v.r, v.p, q, v.invd, v.s, v.part);
+  hipLaunchKernelGGL(dev::k_b_xr, dim3(v.gx, v.nact), dim3(256), 0, st, v.act, v.voff, x, v.r, v.p, q, v.invd, v.s,
+                     v.part);
 }
-void bk_fin_rz(const BatchVecArgs& v, double delta, int reliable, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_b_fin_rz, dim3(v.np), dim3(256), 0, st, v.part, v.gx, v.s, v.tol, delta, reliable);
+void bk_fin_rz(const BatchVecArgs& v, double delta, int mixed, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_b_fin_rz, dim3(v.nact), dim3(256), 0, st, v.act, v.part, v.gx, v.s, v.tol, delta, mixed);
 }
 void bk_p(const BatchVecArgs& v, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_b_p, dim3(v.gx, v.np), dim3(256), 0, st, v.voff, v.p, v.r, v.invd, v.s);
+  hipLaunchKernelGGL(dev::k_b_p, dim3(v.gx, v.nact), dim3(256), 0, st, v.act, v.voff, v.p, v.r, v.invd, v.s);
 }
 void bk_replace(const BatchVecArgs& v, const double* b, const double* y, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_b_replace, dim3(v.gx, v.np), dim3(256), 0, st, v.voff, b, y, v.invd, v.r, v.s, v.part);
-  hipLaunchKernelGGL(dev::k_b_fin_replace, dim3(v.np), dim3(256), 0, st, v.part, v.gx, v.s, v.tol);
+  hipLaunchKernelGGL(dev::k_b_replace, dim3(v.gx, v.nact), dim3(256), 0, st, v.act, v.voff, b, y, v.invd, v.r, v.s,
+                     v.part);
+  hipLaunchKernelGGL(dev::k_b_fin_replace, dim3(v.nact), dim3(256), 0, st, v.act, v.part, v.gx, v.s, v.tol);
 }
 void bk_resid(const BatchVecArgs& v, const double* b, const double* y, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_b_resid, dim3(v.gx, v.np), dim3(256), 0, st, v.voff, b, y, v.part);
+  hipLaunchKernelGGL(dev::k_b_resid, dim3(v.gx, v.np), dim3(256), 0, st, nullptr, v.voff, b, y, v.part);
   hipLaunchKernelGGL(dev::k_b_fin_resid, dim3(v.np), dim3(256), 0, st, v.part, v.gx, out);
+}
+
+void bk_finish(const BatchVecArgs& v, const int* act, int nact, const double* stage, const uint32_t* rowptr,
+               const uint32_t* slots, const int32_t* shared, const int64_t* sh_off, const int32_t* bnd,
+               const int64_t* bnd_off, const double* u, double* y, hipStream_t st) {
+  if (nact <= 0) return;
+  hipLaunchKernelGGL(dev::k_b_finish, dim3(v.gx, nact), dim3(256), 0, st, act, stage, rowptr, slots, shared, sh_off, bnd,
+                     bnd_off, u, y);
 }
 
 }  // namespace dogip

@@ -1,0 +1,121 @@
+"""Autotuner for the apply kernels: picks the tile size (cells per workgroup) and the
+element-kernel variant per (dim, k, kind, precision) by timing candidates on a
+representative structured mesh, and caches the choice as JSON.
+
+    python -m paper_1710_09913_amd.tune --dim 2 --kind se --k 1 2 3 4 --prec f64 f32
+
+Cache: $DOGIP_TUNE_CACHE, else ~/.cache/dogip/tune.json.  Operator creation uses the
+cached choice when tile_waves / variant are left at 0 (see ``tuned``).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+
+from . import capi
+
+TILE_WAVES = (1, 2, 4, 8)
+
+
+def cache_path() -> str:
+    return os.environ.get("DOGIP_TUNE_CACHE") or os.path.join(os.path.expanduser("~"), ".cache", "dogip", "tune.json")
+
+
+def _key(dim, k, kind, prec):
+    return f"d{dim}-k{k}-{kind}-{prec}"
+
+
+def load_cache() -> dict:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(c: dict) -> None:
+    p = cache_path()
+    os.makedirs(os.path.dirname(p), exist_ok=True)
+    tmp = p + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(c, f, indent=1, sort_keys=True)
+    os.replace(tmp, p)
+
+
+def tuned(dim, k, kind, prec="f64"):
+    """(tile_waves, variant) from the cache, or (0, 0) for the library defaults."""
+    e = load_cache().get(_key(dim, k, kind, prec))
+    return (e["tile_waves"], e["variant"]) if e else (0, 0)
+
+
+def _mesh_size(dim, k, cells_target):
+    per = 2 if dim == 2 else 6
+    return max(2, int(round((cells_target / per) ** (1.0 / dim))))
+
+
+def tune(dim, k, kind, prec="f64", cells_target=400_000, reps=20, tile_waves=TILE_WAVES, variants=None,
+         max_tile_cells=512, verbose=False) -> dict:
+    """Time every candidate on a unit mesh of about cells_target cells; store and return the best."""
+    import torch
+
+    from .dogip import Mesh, Operator, Space
+
+    n = _mesh_size(dim, k, cells_target)
+    space = Space(Mesh.unit(dim, n), k, kind, "dirichlet" if kind == "se" else "none")
+    coef = torch.ones(space.ncells, dtype=torch.float64)
+    u = torch.ones(space.ndofs, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(u)
+    has_unrolled = (dim == 2 and k <= 5) or (dim == 3 and (k <= 3 if kind == "se" else k <= 2))
+    if variants is None:
+        variants = (capi.DOGIP_VARIANT_UNROLLED, capi.DOGIP_VARIANT_LOOPED) if has_unrolled else (capi.DOGIP_VARIANT_LOOPED,)
+    rows = []
+    for var in variants:
+        for tw in tile_waves:
+            if 64 * tw > max_tile_cells:
+                continue
+            op = Operator(space, coef, "scalar", fp32=(prec == "f32"), tile_waves=tw, variant=var)
+            if op.info["tile_cells"] != 64 * tw:  # shrunk to fit the LDS budget: duplicate candidate
+                del op
+                continue
+            for _ in range(3):
+                op.apply(u, y, prec=prec)
+            torch.cuda.synchronize()
+            op.timer_enable(True)
+            op.timer_read()
+            for _ in range(reps):
+                op.apply(u, y, prec=prec)
+            ms, cnt = op.timer_read()
+            op.timer_enable(False)
+            rows.append({"tile_waves": tw, "variant": var, "ms": ms / cnt})
+            if verbose:
+                print(f"  {_key(dim, k, kind, prec)} tw={tw} var={var}: {ms / cnt:.4f} ms", flush=True)
+            del op
+    best = min(rows, key=lambda r: r["ms"])
+    entry = {"tile_waves": best["tile_waves"], "variant": best["variant"], "ms": best["ms"],
+             "mesh_n": n, "ndofs": space.ndofs, "candidates": rows}
+    c = load_cache()
+    c[_key(dim, k, kind, prec)] = entry
+    save_cache(c)
+    return entry
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--dim", type=int, default=2)
+    ap.add_argument("--kind", default="se")
+    ap.add_argument("--k", type=int, nargs="+", default=[1, 2, 3, 4])
+    ap.add_argument("--prec", nargs="+", default=["f64", "f32"])
+    ap.add_argument("--cells", type=int, default=400_000)
+    ap.add_argument("--max-tile-cells", type=int, default=512)
+    a = ap.parse_args(argv)
+    for k in a.k:
+        for prec in a.prec:
+            e = tune(a.dim, k, a.kind, prec, cells_target=a.cells, max_tile_cells=a.max_tile_cells, verbose=True)
+            print(json.dumps({_key(a.dim, k, a.kind, prec): {x: e[x] for x in ("tile_waves", "variant", "ms")}}),
+                  flush=True)
+
+
+if __name__ == "__main__":
+    main()
