@@ -12,7 +12,7 @@ namespace dogip {
 
 struct BatchWork {
   int maxit = 0;
-  DevBuf r, p, q, yout, part, energy, sc, rr_true, iters, need, stalls, active, res, state, use64;
+  DevBuf r, p, q, yout, part, energy, sc, rr_true, iters, need, stalls, active, res, state, use64, last_rep;
   DevBuf act, rep, items_a, items_b, items_r;  // compacted problem and work-item lists
   int* h_lists = nullptr;                      // pinned: active, use64, need, act, rep
   uint64_t* h_items = nullptr;                 // pinned: three item lists
@@ -200,6 +200,7 @@ int batch_pcg(Batch& b, const double* rhs, double* x, const dogip_solve_opts& o,
     w.res.alloc(size_t(np) * sizeof(double));
     w.state.alloc(size_t(np) * sizeof(int));
     w.use64.alloc(size_t(np) * sizeof(int));
+    w.last_rep.alloc(size_t(np) * sizeof(int));
     w.act.alloc(size_t(np) * sizeof(int));
     w.rep.alloc(size_t(np) * sizeof(int));
     w.items_a.alloc(ni * sizeof(uint64_t));
@@ -215,7 +216,7 @@ int batch_pcg(Batch& b, const double* rhs, double* x, const dogip_solve_opts& o,
   v.p = w.p.as<double>();
   v.part = w.part.as<double>();
   v.s = {w.sc.as<PcgScalars>(), w.rr_true.as<double>(), w.iters.as<int>(), w.need.as<int>(), w.stalls.as<int>(),
-         w.active.as<int>(), w.state.as<int>(), w.use64.as<int>()};
+         w.active.as<int>(), w.state.as<int>(), w.use64.as<int>(), w.last_rep.as<int>()};
   v.gx = 32;
   v.np = np;
   v.tol = o.tol;
@@ -257,8 +258,9 @@ int batch_pcg(Batch& b, const double* rhs, double* x, const dogip_solve_opts& o,
     HIPCHK(hipMemcpyAsync(h_use64, w.use64.p, sizeof(int) * np, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(h_need, w.need.p, sizeof(int) * np, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    if (mixed) {
-      // residual replacement r = b - A64 x for the problems that asked for it
+    {
+      // residual replacement r = b - A64 x for the problems that asked for it (at apparent
+      // convergence, and in mixed mode also after each reduction by delta)
       int nrep = 0;
       for (int p = 0; p < np; ++p)
         if (h_active[p] && h_need[p]) h_rep[nrep++] = p;
@@ -271,7 +273,7 @@ int batch_pcg(Batch& b, const double* rhs, double* x, const dogip_solve_opts& o,
         BatchVecArgs vr = v;
         vr.act = w.rep.as<int>();
         vr.nact = nrep;
-        bk_replace(vr, rhs, w.yout.as<double>(), st);
+        bk_replace(vr, rhs, w.yout.as<double>(), mixed ? 1 : 0, st);
         HIPCHK(hipMemcpyAsync(h_active, w.active.p, sizeof(int) * np, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(h_use64, w.use64.p, sizeof(int) * np, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));

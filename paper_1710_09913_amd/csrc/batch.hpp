@@ -47,8 +47,9 @@ struct BatchPcgState {
   int* need;    // residual replacement requested
   int* stalls;
   int* active;
-  int* state;   // 0 running, 1 converged, 2 failed (breakdown or non-finite)
-  int* use64;   // mixed mode: the problem switched to the FP64 apply
+  int* state;     // 0 running, 1 converged, 2 failed (breakdown or non-finite)
+  int* use64;     // mixed mode: the problem switched to the FP64 apply
+  int* last_rep;  // iteration count at the last replacement
 };
 
 struct BatchVecArgs {
@@ -94,7 +95,7 @@ void bk_fin_pq(const BatchVecArgs& v, const double* energy, const int64_t* tile_
 void bk_xr(const BatchVecArgs& v, double* x, const double* q, hipStream_t st);
 void bk_fin_rz(const BatchVecArgs& v, double delta, int mixed, hipStream_t st);
 void bk_p(const BatchVecArgs& v, hipStream_t st);
-void bk_replace(const BatchVecArgs& v, const double* b, const double* y, hipStream_t st);
+void bk_replace(const BatchVecArgs& v, const double* b, const double* y, int mixed, hipStream_t st);
 void bk_resid(const BatchVecArgs& v, const double* b, const double* y, double* out, hipStream_t st);
 void bk_finish(const BatchVecArgs& v, const int* act, int nact, const double* stage, const uint32_t* rowptr,
                const uint32_t* slots, const int32_t* shared, const int64_t* sh_off, const int32_t* bnd,

@@ -132,6 +132,7 @@ __global__ __launch_bounds__(256) void k_b_fin_init(const double* __restrict__ p
     s.need[p] = 0;
     s.stalls[p] = 0;
     s.use64[p] = 0;
+    s.last_rep[p] = 0;
     s.active[p] = (c.flags == 0 && rr > tol * tol * bb) ? 1 : 0;
     s.state[p] = c.flags ? 2 : (s.active[p] ? 0 : 1);
   }
@@ -205,13 +206,12 @@ __global__ __launch_bounds__(256) void k_b_fin_rz(const int* __restrict__ act, c
     if (c.flags) {
       s.active[p] = 0;
       s.state[p] = 2;
-    } else if (mixed && !s.use64[p]) {
-      // FP32 search directions: replace the residual when it has dropped by delta, and
-      // verify apparent convergence on the FP64 residual
-      if (rr <= thr || rr <= delta * delta * s.rr_true[p]) s.need[p] = 1;
     } else if (rr <= thr) {
-      s.active[p] = 0;
-      s.state[p] = 1;
+      s.need[p] = 2;  // apparent convergence: verify on the FP64 residual (and restart the direction)
+    } else if (mixed && !s.use64[p] && s.need[p] == 0 &&
+               (rr <= delta * delta * s.rr_true[p] || s.iters[p] - s.last_rep[p] >= 512)) {
+      s.need[p] = 1;  // FP32 directions: replace the residual (keep the direction) after a reduction
+                      // by delta, and at least every 512 iterations
     }
   }
 }
@@ -228,20 +228,24 @@ __global__ __launch_bounds__(256) void k_b_p(const int* __restrict__ act, const 
 __global__ __launch_bounds__(256) void k_b_replace(const int* __restrict__ act, const int64_t* __restrict__ voff,
                                                    const double* __restrict__ b, const double* __restrict__ y,
                                                    const double* __restrict__ invd, double* __restrict__ r,
-                                                   BatchPcgState s, double* __restrict__ part) {
+                                                   double* __restrict__ pv, BatchPcgState s,
+                                                   double* __restrict__ part) {
   if (!s.active[p_of(act)] || !s.need[p_of(act)]) return;
+  const bool restart = s.need[p_of(act)] == 2;
   double v[2] = {0.0, 0.0};
   PROBLEM_RANGE(p, lo, hi) {
     const double ri = b[i] - y[i];
+    const double zi = invd[i] * ri;
     r[i] = ri;
-    v[0] += ri * (invd[i] * ri);
+    if (restart) pv[i] = zi;
+    v[0] += ri * zi;
     v[1] += ri * ri;
   }
   bpartials(v, 2, part, p_of(act));
 }
 
 __global__ __launch_bounds__(256) void k_b_fin_replace(const int* __restrict__ act, const double* __restrict__ part,
-                                                       int gx, BatchPcgState s, double tol) {
+                                                       int gx, BatchPcgState s, double tol, int mixed) {
   const int p = act[blockIdx.x];
   if (!s.active[p] || !s.need[p]) return;
   const double rz = bsum(part + int64_t(p) * gx * 3 + 0, gx, 3);
@@ -250,19 +254,25 @@ __global__ __launch_bounds__(256) void k_b_fin_replace(const int* __restrict__ a
     PcgScalars& c = s.sc[p];
     if (!isfinite(rz) || !isfinite(rr)) c.flags |= PCG_NONFINITE;
     s.stalls[p] = rr > 0.25 * s.rr_true[p] ? s.stalls[p] + 1 : 0;
+    if (mixed && !s.use64[p] && rr > s.rr_true[p]) s.stalls[p] = 3;  // divergence under the FP32 operator
     c.rho = rz;
     c.rr = rr;
     s.rr_true[p] = rr;
     s.need[p] = 0;
+    s.last_rep[p] = s.iters[p];
     if (c.flags) {
       s.active[p] = 0;
       s.state[p] = 2;
     } else if (rr <= tol * tol * c.bb) {
       s.active[p] = 0;
       s.state[p] = 1;
-    } else if (s.stalls[p] >= 3) {
-      s.use64[p] = 1;  // the FP32 operator stopped reducing the true residual: continue in FP64
-      s.stalls[p] = 0;
+    } else if (mixed && !s.use64[p]) {
+      if (s.stalls[p] >= 3) {
+        s.use64[p] = 1;  // the FP32 operator stopped reducing the true residual: continue in FP64
+        s.stalls[p] = 0;
+      }
+    } else if (s.stalls[p] >= 2) {
+      s.active[p] = 0;  // below the attainable accuracy: stop, reported as not converged
     }
   }
 }
@@ -369,10 +379,10 @@ void bk_fin_rz(const BatchVecArgs& v, double delta, int mixed, hipStream_t st) {
 void bk_p(const BatchVecArgs& v, hipStream_t st) {
   hipLaunchKernelGGL(dev::k_b_p, dim3(v.gx, v.nact), dim3(256), 0, st, v.act, v.voff, v.p, v.r, v.invd, v.s);
 }
-void bk_replace(const BatchVecArgs& v, const double* b, const double* y, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_b_replace, dim3(v.gx, v.nact), dim3(256), 0, st, v.act, v.voff, b, y, v.invd, v.r, v.s,
-                     v.part);
-  hipLaunchKernelGGL(dev::k_b_fin_replace, dim3(v.nact), dim3(256), 0, st, v.act, v.part, v.gx, v.s, v.tol);
+void bk_replace(const BatchVecArgs& v, const double* b, const double* y, int mixed, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_b_replace, dim3(v.gx, v.nact), dim3(256), 0, st, v.act, v.voff, b, y, v.invd, v.r, v.p,
+                     v.s, v.part);
+  hipLaunchKernelGGL(dev::k_b_fin_replace, dim3(v.nact), dim3(256), 0, st, v.act, v.part, v.gx, v.s, v.tol, mixed);
 }
 void bk_resid(const BatchVecArgs& v, const double* b, const double* y, double* out, hipStream_t st) {
   hipLaunchKernelGGL(dev::k_b_resid, dim3(v.gx, v.np), dim3(256), 0, st, nullptr, v.voff, b, y, v.part);

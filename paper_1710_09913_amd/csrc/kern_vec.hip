@@ -144,15 +144,18 @@ __global__ __launch_bounds__(256) void k_resid(const double* __restrict__ b, con
   block_partials(v, 1, part);
 }
 
-// residual replacement: r = b - y (y = A64 x); partials (r.z, r.r) with z = invd r
+// residual replacement: r = b - y (y = A64 x); partials (r.z, r.r) with z = invd r;
+// with p, also restart the search direction p = z
 __global__ __launch_bounds__(256) void k_replace(const double* __restrict__ b, const double* __restrict__ y,
-                                                 const double* __restrict__ invd, double* __restrict__ r, int64_t n,
-                                                 double* __restrict__ part) {
+                                                 const double* __restrict__ invd, double* __restrict__ r,
+                                                 double* __restrict__ p, int64_t n, double* __restrict__ part) {
   double v[2] = {0.0, 0.0};
   GRID_STRIDE(i, n) {
     const double ri = b[i] - y[i];
+    const double zi = invd[i] * ri;
     r[i] = ri;
-    v[0] += ri * (invd[i] * ri);
+    if (p) p[i] = zi;
+    v[0] += ri * zi;
     v[1] += ri * ri;
   }
   block_partials(v, 2, part);
@@ -221,9 +224,9 @@ void vk_resid(const double* b, const double* y, double* r, int64_t n, double* pa
   hipLaunchKernelGGL(dev::k_resid, dim3(RED_BLOCKS), dim3(256), 0, st, b, y, r, n, part);
   hipLaunchKernelGGL(dev::k_fin_sum, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, out);
 }
-void vk_replace(const double* b, const double* y, const double* invd, double* r, int64_t n, double* part,
+void vk_replace(const double* b, const double* y, const double* invd, double* r, double* p, int64_t n, double* part,
                 PcgScalars* s, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_replace, dim3(RED_BLOCKS), dim3(256), 0, st, b, y, invd, r, n, part);
+  hipLaunchKernelGGL(dev::k_replace, dim3(RED_BLOCKS), dim3(256), 0, st, b, y, invd, r, p, n, part);
   hipLaunchKernelGGL(dev::k_fin_replace, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, s);
 }
 void vk_dot(const double* a, const double* b, int64_t n, double* part, double* out, hipStream_t st) {

@@ -96,6 +96,7 @@ static CgResult cg_run(Op& op, const double* b, double* x, bool x0_given, const 
   if (hs.rr <= thr) return res;
   double rr_true = hs.rr;  // residual norm^2 at the last exact (re)computation
   int stalls = 0;
+  int last_rep = 0;  // iteration of the last replacement
   int it = 0;
   int step = std::max(1, cp.check_every);
   for (;;) {
@@ -127,24 +128,32 @@ static CgResult cg_run(Op& op, const double* b, double* x, bool x0_given, const 
     it += todo;
     double last = w.hhist[it];
     res.iters = it;
-    if (cp.reliable && (conv || last <= cp.delta * cp.delta * rr_true)) {
+    const bool forced = cp.prec == DOGIP_F32 && it - last_rep >= 512;  // keep the true residual in view
+    if (cp.reliable && (conv || forced || last <= cp.delta * cp.delta * rr_true)) {
+      last_rep = it;
       // residual replacement with the FP64 operator
+      // at apparent convergence the direction restarts from the true residual; the
+      // replacements triggered by delta keep it
       op_apply(op, x, q, DOGIP_F64, st);
-      vk_replace(b, q, invd, r, n, part, sc, st);
+      vk_replace(b, q, invd, r, conv ? p : nullptr, n, part, sc, st);
       HIPCHK(hipMemcpyAsync(&hs, sc, sizeof hs, hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       if (hs.flags || !std::isfinite(hs.rr)) {
         res.status = DOGIP_E_NONFINITE;
         return res;
       }
+      const bool grew = hs.rr > rr_true;
       stalls = hs.rr > 0.25 * rr_true ? stalls + 1 : 0;
+      if (grew && cp.prec == DOGIP_F32) stalls = 3;  // divergence under the FP32 operator: hand over now
       rr_true = hs.rr;
       last = hs.rr;
       conv = hs.rr <= thr;
-      if (!conv && stalls >= 3) {  // the FP32 operator no longer reduces the true residual
+      if (!conv && stalls >= (cp.prec == DOGIP_F32 ? 3 : 2)) {
+        // the true residual stopped decreasing: with the FP32 operator the caller
+        // finishes in FP64; with FP64 the tolerance is below the attainable accuracy
         res.relres = std::sqrt(hs.rr / hs.bb);
         res.status = DOGIP_E_NOT_CONVERGED;
-        res.stalled = true;
+        res.stalled = cp.prec == DOGIP_F32;
         return res;
       }
     }
@@ -206,9 +215,11 @@ int op_pcg(Op& op, const double* b, double* x, const dogip_solve_opts& o, dogip_
   if (o.mode == DOGIP_SOLVE_F64 || o.mode == DOGIP_SOLVE_MIXED) {
     // FP64: plain Jacobi-PCG.  MIXED: the same iteration with the FP32 apply and FP64
     // residual replacement (reliable updates); vectors and inner products stay FP64.
+    // In both modes apparent convergence is verified on the true FP64 residual (a
+    // replacement); MIXED also replaces whenever the residual has dropped by delta.
     cp.prec = o.mode == DOGIP_SOLVE_F64 ? DOGIP_F64 : DOGIP_F32;
-    cp.reliable = o.mode == DOGIP_SOLVE_MIXED;
-    cp.delta = (o.inner_tol > 0 && o.inner_tol < 1) ? o.inner_tol : 0.1;
+    cp.reliable = true;
+    cp.delta = o.mode == DOGIP_SOLVE_F64 ? 0.0 : ((o.inner_tol > 0 && o.inner_tol < 1) ? o.inner_tol : 0.1);
     CgResult c = cg_run(op, b, x, o.x0_given != 0, cp, st);
     status = c.status;
     stats.iters = c.iters;
@@ -218,7 +229,8 @@ int op_pcg(Op& op, const double* b, double* x, const dogip_solve_opts& o, dogip_
       // finish with the FP64 operator from the current iterate
       CgParams f = cp;
       f.prec = DOGIP_F64;
-      f.reliable = false;
+      f.reliable = true;  // convergence still verified on the true residual
+      f.delta = 0.0;
       f.maxit = o.maxit - c.iters;
       CgResult g = cg_run(op, b, x, true, f, st);
       status = g.status;
@@ -271,6 +283,9 @@ int op_pcg(Op& op, const double* b, double* x, const dogip_solve_opts& o, dogip_
       if (stats.relres > 0.9 * prev && stats.relres > o.tol) {
         // stagnation of the refinement: finish with FP64 CG from the current x
         CgParams f = cp;
+        f.prec = DOGIP_F64;
+        f.reliable = true;
+        f.delta = 0.0;
         f.maxit = std::max(1, o.maxit - total);
         CgResult g = cg_run(op, b, x, true, f, st);
         total += g.iters;

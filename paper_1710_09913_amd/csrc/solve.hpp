@@ -41,7 +41,8 @@ void vk_pcg_xr(double* x, double* r, const double* p, const double* q, const dou
 void vk_fin_rz(const double* part, PcgScalars* s, double* hist, int it, hipStream_t st);
 void vk_pcg_p(double* p, const double* r, const double* invd, const PcgScalars* s, int64_t n, hipStream_t st);
 void vk_resid(const double* b, const double* y, double* r, int64_t n, double* part, double* out, hipStream_t st);
-void vk_replace(const double* b, const double* y, const double* invd, double* r, int64_t n, double* part,
+// r = b - y, and when p is given also p = invd r (restart); rho and rr refreshed
+void vk_replace(const double* b, const double* y, const double* invd, double* r, double* p, int64_t n, double* part,
                 PcgScalars* s, hipStream_t st);
 void vk_dot(const double* a, const double* b, int64_t n, double* part, double* out, hipStream_t st);
 void vk_axpy1(double* x, const double* d, int64_t n, hipStream_t st);
