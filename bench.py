@@ -7,8 +7,9 @@ Dirichlet boundary.  A step is one FP64 operator apply y = A u (Algorithm 1) wit
 D resident in HBM; value = dofs / (seconds per apply) in GDoF/s.
 
 The same line carries: the FP32 apply, FP64 and mixed-precision PCG time-to-1e-8,
-the roofline of the tile kernel (algorithmic bytes / measured kernel time, HBM peak
-8 TB/s) and the CPU oracle timed on a bounded sample.
+the roofline of the apply's two kernels (algorithmic bytes / their measured time, HBM
+peak 8 TB/s; traffic = HBM bytes from the committed counter summary of this build)
+and the CPU oracle timed on a bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 64] [--k 3] [--no-solve] [--no-cpu]
 """
@@ -76,9 +77,26 @@ def time_apply(op, u, y, prec, steps, warmup):
     e1.record(s)
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
-    kern_ms, cnt = op.timer_read()
+    tile_ms, fin_ms, cnt = op.timer_read()
     op.timer_enable(False)
-    return total_ms / steps, kern_ms / max(cnt, 1)
+    cnt = max(cnt, 1)
+    return total_ms / steps, tile_ms / cnt, fin_ms / cnt
+
+
+def measured_traffic(n, k):
+    """HBM bytes per apply from the committed rocprofv3 counter summary of this workload
+    (FETCH_SIZE and WRITE_SIZE, calibrated by a copy of known size), per precision; empty
+    when the summary is missing or was measured on a build of other sources."""
+    from paper_1710_09913_amd.build import source_hash
+
+    path = os.path.join(ROOT, "profiles", f"traffic_k_apply_3d{n}_p{k}_se.json")
+    if not os.path.exists(path):
+        return {}
+    with open(path) as fh:
+        doc = json.load(fh)
+    if doc.get("source_hash") != source_hash():
+        return {}
+    return {p: round(v["bytes_per_apply"]) for p, v in doc.get("traffic", {}).items()}
 
 
 def cpu_baseline(k, n_sample=20):
@@ -156,7 +174,8 @@ def run_c2(a):
             y = torch.empty_like(u)
             row = {"kind": kind, "k": k, "ndofs": sp.ndofs}
             for prec in ("f64", "f32"):
-                ms, kms = time_apply(op, u, y, prec, a.steps, a.warmup)
+                ms, kms, fms = time_apply(op, u, y, prec, a.steps, a.warmup)
+                kms += fms
                 ab = op.info["alg_bytes_" + prec]
                 row[prec] = {"GDoF_s": round(sp.ndofs / (ms * 1e-3) / 1e9, 3), "ms": round(ms, 5),
                              "frac": round(ab / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
@@ -337,13 +356,15 @@ def main(argv=None):
 
     u = torch.from_numpy(random_vector(space.ndofs, a.seed)).cuda()
     y = torch.empty_like(u)
-    ms64, kms64 = time_apply(op, u, y, "f64", a.steps, a.warmup)
-    log(f"[apply f64] {ms64:.4f} ms/apply (tile kernel {kms64:.4f} ms)")
-    ms32, kms32 = time_apply(op, u, y, "f32", a.steps, a.warmup)
-    log(f"[apply f32] {ms32:.4f} ms/apply (tile kernel {kms32:.4f} ms)")
+    ms64, tms64, fms64 = time_apply(op, u, y, "f64", a.steps, a.warmup)
+    log(f"[apply f64] {ms64:.4f} ms/apply (tile kernel {tms64:.4f} ms, finish {fms64:.4f} ms)")
+    ms32, tms32, fms32 = time_apply(op, u, y, "f32", a.steps, a.warmup)
+    log(f"[apply f32] {ms32:.4f} ms/apply (tile kernel {tms32:.4f} ms, finish {fms32:.4f} ms)")
+    kms64, kms32 = tms64 + fms64, tms32 + fms32
     info = op.info
     gdofs = space.ndofs / (ms64 * 1e-3) / 1e9
     achieved = info["alg_bytes_f64"] / (kms64 * 1e-3) / 1e9
+    traffic = measured_traffic(a.n, a.k)
     out = {
         "metric": METRIC,
         "value": round(gdofs, 4),
@@ -371,15 +392,19 @@ def main(argv=None):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
-            "kernel": "k_apply (tile kernel), FP64",
+            "traffic": traffic.get("f64"),
+            "kernel": "FP64 apply: k_apply tile kernel + k_apply_finish (shared dofs, Dirichlet rows)",
             "alg_bytes_per_launch": info["alg_bytes_f64"],
             "kernel_ms": round(kms64, 5),
+            "tile_ms": round(tms64, 5),
+            "finish_ms": round(fms64, 5),
         },
         "apply_f32": {
             "GDoF_s": round(space.ndofs / (ms32 * 1e-3) / 1e9, 4),
             "ms": round(ms32, 5),
             "kernel_ms": round(kms32, 5),
+            "tile_ms": round(tms32, 5),
+            "traffic": traffic.get("f32"),
             "achieved_GB_s": round(info["alg_bytes_f32"] / (kms32 * 1e-3) / 1e9, 1),
             "frac": round(info["alg_bytes_f32"] / (kms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         },

@@ -233,11 +233,14 @@ int dogip_pcg(dogip_op op, const double* b, double* x, const dogip_solve_opts* o
  * to theta_T when D scales with exp(theta_T) and A lam = dJ/du.  u, lam: device
  * [ndofs]; g: device [ncells].  async. */
 int dogip_grad_logcoef(dogip_op op, const double* u, const double* lam, double* g, dogip_stream stream);
-/* Kernel timer: when enabled, every apply records HIP events around its tile
- * kernel on the apply's stream; dogip_op_timer_read synchronizes on the last
- * event and returns the summed milliseconds and the count, then resets. */
+/* Kernel timer: when enabled, every apply records HIP events on the apply's
+ * stream before its tile kernel, between the tile kernel and the shared-dof
+ * finish kernel, and after the finish.  dogip_op_timer_read synchronizes on the
+ * last event and returns the summed milliseconds of the tile kernels and of
+ * the finish kernels and the number of applies recorded, then resets.  Any
+ * output pointer may be NULL. */
 int dogip_op_timer_enable(dogip_op op, int enable);
-int dogip_op_timer_read(dogip_op op, double* ms_sum, int64_t* count);
+int dogip_op_timer_read(dogip_op op, double* tile_ms_sum, double* finish_ms_sum, int64_t* count);
 void dogip_op_destroy(dogip_op op);
 
 /* ---- batch: many operators applied in one persistent launch ---- */

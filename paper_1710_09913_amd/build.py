@@ -54,6 +54,19 @@ def _headers_mtime():
     return max((os.path.getmtime(h) for h in hs), default=0.0)
 
 
+def source_hash() -> str:
+    """SHA-256 over the kernel and host sources and the public header (identifies a build)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(CSRC, "*")) + glob.glob(os.path.join(INCLUDE, "*.h")))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def _compile(src: str, force: bool, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     if not force and os.path.exists(obj):

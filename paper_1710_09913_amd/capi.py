@@ -99,7 +99,7 @@ SIGNATURES = {
     "dogip_pcg": (C.c_int, [H, P, P, C.POINTER(SolveOpts), C.POINTER(SolveStats), P]),
     "dogip_grad_logcoef": (C.c_int, [H, P, P, P, P]),
     "dogip_op_timer_enable": (C.c_int, [H, C.c_int]),
-    "dogip_op_timer_read": (C.c_int, [H, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "dogip_op_timer_read": (C.c_int, [H, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "dogip_op_destroy": (None, [H]),
     "dogip_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, P, PH]),
     "dogip_batch_offsets": (C.c_int, [H, C.POINTER(C.c_int64)]),

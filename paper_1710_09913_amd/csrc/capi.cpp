@@ -299,10 +299,10 @@ int dogip_op_timer_enable(dogip_op op, int enable) {
   });
 }
 
-int dogip_op_timer_read(dogip_op op, double* ms_sum, int64_t* count) {
+int dogip_op_timer_read(dogip_op op, double* tile_ms_sum, double* finish_ms_sum, int64_t* count) {
   return guard([&] {
     need(op);
-    dogip::op_timer_read(*op->op, ms_sum, count);
+    dogip::op_timer_read(*op->op, tile_ms_sum, finish_ms_sum, count);
     return DOGIP_OK;
   });
 }

@@ -125,7 +125,7 @@ void op_export_d(Op& op, double* out, hipStream_t st);
 dogip_op_info op_info(const Op& op);
 int op_pcg(Op& op, const double* b, double* x, const dogip_solve_opts& o, dogip_solve_stats& stats, hipStream_t st);
 void op_timer_enable(Op& op, bool on);
-void op_timer_read(Op& op, double* ms, int64_t* count);
+void op_timer_read(Op& op, double* tile_ms, double* finish_ms, int64_t* count);
 
 // ---- kernel launchers (defined in the .hip files) ----
 struct ApplyLaunch {

@@ -1,5 +1,6 @@
 // Operator construction and the apply / diagonal / gradient entry points.
 #include <algorithm>
+#include <array>
 #include <cstring>
 
 #include "internal.hpp"
@@ -27,15 +28,16 @@ void DevBuf::free() {
   bytes = 0;
 }
 
+// Events before the tile kernel, between it and the finish kernel, and after the finish.
 struct OpTimer {
   bool on = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
-  ~OpTimer() {
-    for (auto& e : ev) {
-      (void)hipEventDestroy(e.first);
-      (void)hipEventDestroy(e.second);
-    }
+  std::vector<std::array<hipEvent_t, 3>> ev;
+  void clear() {
+    for (auto& e : ev)
+      for (auto x : e) (void)hipEventDestroy(x);
+    ev.clear();
   }
+  ~OpTimer() { clear(); }
 };
 
 bool launch_apply_unrolled_2d(int k, int kind, int prec, bool energy, const ApplyLaunch& a, hipStream_t st);
@@ -189,22 +191,20 @@ void op_apply(Op& op, const double* u, double* y, int prec, hipStream_t st, doub
   a.u = u;
   a.y = y;
   a.energy = energy;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
+  std::array<hipEvent_t, 3> ev{};
   if (op.timer->on) {
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    HIPCHK(hipEventRecord(e0, st));
+    for (auto& x : ev) HIPCHK(hipEventCreate(&x));
+    op.timer->ev.push_back(ev);
+    HIPCHK(hipEventRecord(ev[0], st));
   }
   DOGIP_CHECK(launch_apply(s.dim, s.k, s.kind, prec, op.variant, a, st), DOGIP_E_RANGE,
               "no apply kernel for this (dim, k, kind, variant)");
+  if (op.timer->on) HIPCHK(hipEventRecord(ev[1], st));
   launch_apply_finish(op.stage.as<double>(), op.sh_rowptr.as<uint32_t>(), op.sh_slots.as<uint32_t>(),
                       op.shared.as<int32_t>(), int64_t(op.plan.shared.size()), op.bnd.as<int32_t>(),
                       int64_t(s.boundary.size()), u, y, energy ? energy + op.plan.ntiles : nullptr, st);
   HIPCHK(hipGetLastError());
-  if (op.timer->on) {
-    HIPCHK(hipEventRecord(e1, st));
-    op.timer->ev.push_back({e0, e1});
-  }
+  if (op.timer->on) HIPCHK(hipEventRecord(ev[2], st));
 }
 
 void op_diag(Op& op, double* diag, hipStream_t st) {
@@ -281,21 +281,20 @@ dogip_op_info op_info(const Op& op) {
 
 void op_timer_enable(Op& op, bool on) { op.timer->on = on; }
 
-void op_timer_read(Op& op, double* ms, int64_t* count) {
-  double sum = 0.0;
+void op_timer_read(Op& op, double* tile_ms, double* finish_ms, int64_t* count) {
+  double st = 0.0, sf = 0.0;
   for (auto& e : op.timer->ev) {
-    HIPCHK(hipEventSynchronize(e.second));
-    float t = 0.f;
-    HIPCHK(hipEventElapsedTime(&t, e.first, e.second));
-    sum += t;
+    HIPCHK(hipEventSynchronize(e[2]));
+    float t0 = 0.f, t1 = 0.f;
+    HIPCHK(hipEventElapsedTime(&t0, e[0], e[1]));
+    HIPCHK(hipEventElapsedTime(&t1, e[1], e[2]));
+    st += t0;
+    sf += t1;
   }
-  if (ms) *ms = sum;
+  if (tile_ms) *tile_ms = st;
+  if (finish_ms) *finish_ms = sf;
   if (count) *count = int64_t(op.timer->ev.size());
-  for (auto& e : op.timer->ev) {
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
-  }
-  op.timer->ev.clear();
+  op.timer->clear();
 }
 
 }  // namespace dogip

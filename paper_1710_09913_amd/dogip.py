@@ -218,9 +218,10 @@ class Operator:
         check(lib().dogip_op_timer_enable(self.h, int(on)))
 
     def timer_read(self):
-        ms, n = C.c_double(), C.c_int64()
-        check(lib().dogip_op_timer_read(self.h, C.byref(ms), C.byref(n)))
-        return ms.value, n.value
+        """(tile kernel ms, finish kernel ms, applies) summed since the last read."""
+        ms, fin, n = C.c_double(), C.c_double(), C.c_int64()
+        check(lib().dogip_op_timer_read(self.h, C.byref(ms), C.byref(fin), C.byref(n)))
+        return ms.value, fin.value, n.value
 
     def __del__(self):
         if getattr(self, "h", None) and capi._lib is not None:

@@ -86,7 +86,8 @@ def tune(dim, k, kind, prec="f64", cells_target=400_000, reps=20, tile_waves=TIL
             op.timer_read()
             for _ in range(reps):
                 op.apply(u, y, prec=prec)
-            ms, cnt = op.timer_read()
+            ms, fin, cnt = op.timer_read()
+            ms += fin
             op.timer_enable(False)
             rows.append({"tile_waves": tw, "variant": var, "ms": ms / cnt})
             if verbose:
