@@ -103,18 +103,39 @@ def _run_info(log):
     raise ValueError(f"no run line in {log}")
 
 
+def _durations(stats):
+    lines = ["| kernel | calls | avg us | min us | max us | total ms |", "|---|---|---|---|---|---|"]
+    for r in stats:
+        lines.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.1f} |")
+    return lines
+
+
+def _trace_only(a, stats):
+    lines = [f"# {a.name}: rocprofv3 kernel durations", ""]
+    if a.command:
+        lines += ["Command (from the repository root):", "", "```", a.command, "```", ""]
+    lines += ["## Kernel trace (--kernel-trace --stats)", ""] + _durations(stats)
+    os.makedirs(a.out, exist_ok=True)
+    with open(os.path.join(a.out, f"{a.name}.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def summarize(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
-    ap.add_argument("--log", required=True, help="stdout of one of the profiled runs (its JSON line)")
+    ap.add_argument("--fetch", help="FETCH_SIZE run (omit with --write for a trace-only summary)")
+    ap.add_argument("--write", help="WRITE_SIZE run")
+    ap.add_argument("--log", help="stdout of one of the profiled runs (its JSON line)")
     ap.add_argument("--name", required=True)
     ap.add_argument("--out", default="profiles")
     ap.add_argument("--command", default="", help="command line recorded in the summary")
     a = ap.parse_args(argv)
-    info = _run_info(a.log)
     stats = _csv(_find(a.trace, "kernel_stats.csv"))
+    if not (a.fetch and a.write and a.log):
+        return _trace_only(a, stats)
+    info = _run_info(a.log)
     fetch = _csv(_find(a.fetch, "counter_collection.csv"))
     write = _csv(_find(a.write, "counter_collection.csv"))
 
@@ -159,10 +180,6 @@ def summarize(argv=None):
         res[prec] = {"tile_read": tile_r, "tile_write": tile_w, "finish_read": fin_r, "finish_write": fin_w,
                      "bytes_per_apply": tile_r + tile_w + fin_r + fin_w,
                      "alg_bytes_per_apply": info["alg_bytes_" + prec]}
-    durations = []
-    for r in stats:
-        durations.append((_short(r["Name"]), int(r["Calls"]), float(r["AverageNs"]) / 1e3,
-                          float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3))
     os.makedirs(a.out, exist_ok=True)
     doc = {"name": a.name, "source_hash": info["source_hash"], "ndofs": info["ndofs"], "ncells": info["ncells"],
            "fetch_scale": fscale, "write_scale": wscale, "traffic": res}
@@ -172,10 +189,7 @@ def summarize(argv=None):
     if a.command:
         lines += ["Commands (from the repository root):", "", "```", a.command, "```", ""]
     lines += [f"Build source hash `{info['source_hash']}`; {info['ncells']} cells, {info['ndofs']} dofs.", "",
-              "## Kernel trace (--kernel-trace --stats)", "",
-              "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
-    for n, c, av, mn, mx in durations:
-        lines.append(f"| `{n}` | {c} | {av:.1f} | {mn:.1f} | {mx:.1f} |")
+              "## Kernel trace (--kernel-trace --stats)", ""] + _durations(stats)
     lines += ["", "## Traffic (--pmc FETCH_SIZE, then --pmc WRITE_SIZE)", "",
               f"Calibration: a 1 GiB device copy reads {copy_read} B and the counters report "
               f"FETCH {sum(copies_f) / len(copies_f):.0f} KiB, WRITE {sum(copies_w) / len(copies_w):.0f} KiB: "
