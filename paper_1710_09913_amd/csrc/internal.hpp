@@ -117,7 +117,8 @@ void reference_tables(int dim, int k, int kind, std::vector<double>& bhat, std::
 std::unique_ptr<Op> make_op(std::shared_ptr<const Space> s, int coef_kind, const double* coef, unsigned flags,
                             int tile_waves, int variant, hipStream_t st);
 void op_set_coef(Op& op, int coef_kind, const double* coef, hipStream_t st);
-// energy (optional): [ntiles] tile partials of u . A u, followed by FINISH_BLOCKS boundary partials
+// energy (optional): [ntiles] tile partials of u . A u, followed by op_finish_energy_count(op)
+// partials of the Dirichlet rows
 void op_apply(Op& op, const double* u, double* y, int prec, hipStream_t st, double* energy_partials = nullptr);
 void op_diag(Op& op, double* diag, hipStream_t st);
 void op_grad(Op& op, const double* u, const double* lam, double* g, hipStream_t st);
@@ -194,9 +195,21 @@ void launch_export_d(const double* d64, const int32_t* perm, double* out, int64_
                      int nsym, hipStream_t st);
 void launch_zero_indexed(double* y, const int32_t* idx, int64_t n, hipStream_t st);
 // Second pass of an apply: y[shared[i]] = sum of stage[slots[rowptr[i] .. rowptr[i+1])]
-// (fixed order) and y[b] = u[b] on Dirichlet dofs; with benergy (FINISH_BLOCKS
-// partials), the per-block sums of u_b^2.
-constexpr int FINISH_BLOCKS = 1024;
+// (fixed order) and y[b] = u[b] on Dirichlet dofs; with benergy, the sums of u_b^2
+// per block of the Dirichlet range (finish_energy_count of them).
+constexpr int FINISH_THREADS = 256;
+inline int64_t finish_blocks(int64_t nshared, int64_t nbnd) {
+  return std::max<int64_t>(1, (nshared + nbnd + FINISH_THREADS - 1) / FINISH_THREADS);
+}
+inline int64_t finish_first_energy_block(int64_t nshared, int64_t nbnd) {
+  return std::min(nshared / FINISH_THREADS, finish_blocks(nshared, nbnd) - 1);
+}
+inline int64_t finish_energy_count(int64_t nshared, int64_t nbnd) {
+  return finish_blocks(nshared, nbnd) - finish_first_energy_block(nshared, nbnd);
+}
+inline int64_t op_finish_energy_count(const Op& op) {
+  return finish_energy_count(int64_t(op.plan.shared.size()), int64_t(op.space->boundary.size()));
+}
 void launch_apply_finish(const double* stage, const uint32_t* rowptr, const uint32_t* slots, const int32_t* shared,
                          int64_t nshared, const int32_t* bnd, int64_t nbnd, const double* u, double* y,
                          double* benergy, hipStream_t st);

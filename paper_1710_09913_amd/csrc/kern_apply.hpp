@@ -4,11 +4,13 @@
 //   1. gather: the tile's distinct dofs u[dof] -> LDS (0 for Dirichlet dofs)
 //   2. per cell: local slots -> u_T from LDS; y_T = B^^T D_T B^ u_T streaming D_T
 //      (AoSoA, 16-byte chunks, non-temporal); y_T added into LDS (ds_add)
-//   3. flush: dofs only this tile touches are stored, dofs shared with other
-//      tiles are added with a device atomic (the caller zeroed them), Dirichlet
-//      dofs get y = u.
-// With ENERGY, the tile also writes sum_T u_T^T A_T u_T (+ u_B^2 once per
-// Dirichlet dof) = u . (A u), which CG needs as p^T A p.
+//   3. flush: dofs only this tile touches are stored to y, the tile's partial sums
+//      for dofs shared with other tiles go to a staging buffer that a second pass
+//      adds up in a fixed order; Dirichlet dofs are left to the second pass.
+// With ENERGY, the tile also writes sum_T u_T^T A_T u_T, which with u_B^2 once per
+// Dirichlet dof (second pass) is u . (A u), the p^T A p of CG.  It is taken at the
+// flush as sum over the tile's slots of u_slot * y_slot (both in LDS): the same sum
+// regrouped by dof, with no extra registers in the element loop.
 #pragma once
 
 #include "kern_common.hpp"
@@ -53,12 +55,15 @@ __device__ __forceinline__ void gather_batch(const uint32_t* __restrict__ td, in
 
 // Flush of one batch: shared entries -> staging (second pass sums them), exclusive
 // entries -> y; Dirichlet entries are written by the second pass.
+template <bool ENERGY, typename T>
 __device__ __forceinline__ void flush_batch(const uint32_t (&e)[GB], int64_t nd, int64_t j0, const double* ys,
-                                            double* __restrict__ stage, double* __restrict__ y) {
+                                            const T* us, double* __restrict__ stage, double* __restrict__ y,
+                                            double& en) {
 #pragma unroll
   for (int g = 0; g < GB; ++g) {
     const int64_t j = j0 + int64_t(g) * blockDim.x;
     if (j >= nd || (e[g] & TD_BND)) continue;
+    if constexpr (ENERGY) en = fma(double(us[j]), ys[j], en);
     if (e[g] & TD_SHARED)
       stage[j] = ys[j];
     else
@@ -73,7 +78,7 @@ __device__ __forceinline__ void flush_batch(const uint32_t (&e)[GB], int64_t nd,
 // tile's sum_T u_T^T A_T u_T goes (ENERGY only).
 template <int D, int K, int KIND, typename T, int VARIANT, bool ENERGY, int PF>
 __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsigned char* smem, double* energy_out) {
-  using E = Elem<D, K, KIND, T, T, VARIANT, ENERGY, PF>;
+  using E = Elem<D, K, KIND, T, T, VARIANT, false, PF>;
   constexpr int VT = E::VT;
   double* ys = reinterpret_cast<double*>(smem);
   T* us = reinterpret_cast<T*>(ys + a.lds_slots);
@@ -89,7 +94,6 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
   __syncthreads();
   int64_t e = t * a.te + threadIdx.x;
   if (int(threadIdx.x) >= a.te) e = a.nel;  // lanes beyond a smaller tile do no cell work
-  T en = T(0);
   double yacc[VT];
   int sl[VT];
   if (e < a.nel) {
@@ -100,7 +104,7 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
     T ue[VT], ye[VT];
     sfor<VT>([&](auto L) { ue[L] = us[li[L]]; });
     const typename E::V* dp = reinterpret_cast<const typename E::V*>(a.D) + (w * a.nch) * 64 + lane;
-    en = E::run(dp, ue, ye);
+    E::run(dp, ue, ye);
     sfor<VT>([&](auto L) { yacc[L] = double(ye[L]); sl[L] = li[L]; });
   }
   // LDS accumulation one wave after the other, so the sums are bitwise reproducible
@@ -110,8 +114,9 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
     __syncthreads();
   }
   double* stage = a.stage + a.stage_off[t];
+  double en = 0.0;
   if (one) {
-    flush_batch(ent, nd, threadIdx.x, ys, stage, a.y);
+    flush_batch<ENERGY>(ent, nd, threadIdx.x, ys, us, stage, a.y, en);
   } else {
     for (int64_t j0 = threadIdx.x; j0 < nd; j0 += int64_t(GB) * blockDim.x) {
 #pragma unroll
@@ -119,12 +124,12 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
         const int64_t j = j0 + int64_t(g) * blockDim.x;
         ent[g] = j < nd ? td[j] : TD_BND;
       }
-      flush_batch(ent, nd, j0, ys, stage, a.y);
+      flush_batch<ENERGY>(ent, nd, j0, ys, us, stage, a.y, en);
     }
   }
   if constexpr (ENERGY) {
     __shared__ double red[8];
-    const double s = block_sum(double(en), red);
+    const double s = block_sum(en, red);
     if (threadIdx.x == 0) *energy_out = s;
   }
 }

@@ -104,18 +104,19 @@ __global__ __launch_bounds__(256) void k_zero_indexed(double* __restrict__ y, co
 
 // Second pass of the apply.  i < nshared: y[shared[i]] = sum of its staged partials,
 // added in ascending tile order (deterministic).  nshared <= i < nshared + nbnd:
-// Dirichlet identity row y[b] = u[b]; with benergy, each block writes its share of
-// sum u_b^2 (the identity rows' part of u . A u) to benergy[blockIdx.x].
-__global__ __launch_bounds__(256) void k_apply_finish(const double* __restrict__ stage,
+// Dirichlet identity row y[b] = u[b]; with benergy, every block from e0 on writes its
+// share of sum u_b^2 (the identity rows' part of u . A u) to benergy[blockIdx.x - e0].
+// One entry per thread: the grid covers nshared + nbnd exactly.
+__global__ __launch_bounds__(FINISH_THREADS) void k_apply_finish(const double* __restrict__ stage,
                                                       const uint32_t* __restrict__ rowptr,
                                                       const uint32_t* __restrict__ slots,
                                                       const int32_t* __restrict__ shared, int64_t nshared,
                                                       const int32_t* __restrict__ bnd, int64_t nbnd,
                                                       const double* __restrict__ u, double* __restrict__ y,
-                                                      double* __restrict__ benergy) {
+                                                      double* __restrict__ benergy, int64_t e0) {
   double eb = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nshared + nbnd;
-       i += int64_t(gridDim.x) * blockDim.x) {
+  const int64_t i = int64_t(blockIdx.x) * FINISH_THREADS + threadIdx.x;
+  if (i < nshared + nbnd) {
     if (i < nshared) {
       const uint32_t a = rowptr[i], b = rowptr[i + 1];
       double s = 0.0;
@@ -128,10 +129,10 @@ __global__ __launch_bounds__(256) void k_apply_finish(const double* __restrict__
       eb += ub * ub;
     }
   }
-  if (benergy) {
+  if (benergy && int64_t(blockIdx.x) >= e0) {  // block-uniform
     __shared__ double red[8];
     const double s = block_sum(eb, red);
-    if (threadIdx.x == 0) benergy[blockIdx.x] = s;
+    if (threadIdx.x == 0) benergy[blockIdx.x - e0] = s;
   }
 }
 
@@ -287,12 +288,10 @@ void launch_zero_indexed(double* y, const int32_t* idx, int64_t n, hipStream_t s
 void launch_apply_finish(const double* stage, const uint32_t* rowptr, const uint32_t* slots, const int32_t* shared,
                          int64_t nshared, const int32_t* bnd, int64_t nbnd, const double* u, double* y,
                          double* benergy, hipStream_t st) {
-  const int64_t n = nshared + nbnd;
-  if (n <= 0 && !benergy) return;
-  // a fixed grid when the boundary energy partials are wanted (FINISH_BLOCKS of them)
-  const unsigned grid = benergy ? unsigned(FINISH_BLOCKS) : unsigned(std::max<int64_t>(1, (n + 255) / 256));
-  hipLaunchKernelGGL(dev::k_apply_finish, dim3(grid), dim3(256), 0, st, stage, rowptr, slots, shared, nshared, bnd,
-                     nbnd, u, y, benergy);
+  if (nshared + nbnd <= 0 && !benergy) return;
+  const unsigned grid = unsigned(finish_blocks(nshared, nbnd));
+  hipLaunchKernelGGL(dev::k_apply_finish, dim3(grid), dim3(FINISH_THREADS), 0, st, stage, rowptr, slots, shared,
+                     nshared, bnd, nbnd, u, y, benergy, finish_first_energy_block(nshared, nbnd));
 }
 
 void launch_invert(const double* d, double* inv, int64_t n, hipStream_t st) {

@@ -27,7 +27,7 @@ static PcgWork& work(Op& op, int maxit) {
     w->dx.alloc(vb);
     w->yout.alloc(vb);
     w->part.alloc(size_t(3) * RED_BLOCKS * sizeof(double));
-    w->energy.alloc(size_t(op.plan.ntiles + FINISH_BLOCKS) * sizeof(double));
+    w->energy.alloc(size_t(op.plan.ntiles + op_finish_energy_count(op)) * sizeof(double));
     w->scal.alloc(sizeof(PcgScalars));
     w->nrm.alloc(sizeof(double));
     w->hist.alloc(size_t(maxit + 2) * sizeof(double));
@@ -103,7 +103,7 @@ static CgResult cg_run(Op& op, const double* b, double* x, bool x0_given, const 
     const int todo = std::min(step, cp.maxit - it);
     for (int j = 0; j < todo; ++j) {
       op_apply(op, p, q, cp.prec, st, w.energy.as<double>());
-      vk_fin_pq(w.energy.as<double>(), op.plan.ntiles + FINISH_BLOCKS, sc, st);
+      vk_fin_pq(w.energy.as<double>(), op.plan.ntiles + op_finish_energy_count(op), sc, st);
       vk_pcg_xr(x, r, p, q, invd, sc, n, part, st);
       vk_fin_rz(part, sc, hist, it + j + 1, st);
       vk_pcg_p(p, r, invd, sc, n, st);

@@ -1,0 +1,136 @@
+"""Parity at the benchmark sizes, in the launch configuration the benchmark times
+(library default tile and element-kernel variant).
+
+The full operator is too large for the oracle, so each case checks
+  * sampled rows: the rows of A u at a seeded sample of dofs, computed by the
+    oracle's Algorithm 1 on the sub-mesh of every cell that touches a sampled
+    dof (a row of A only involves the cells around its dof), FP64 to 1e-12 of
+    |B^|^T|D||B^||u| and FP32 within 2 gamma_m of it;
+  * properties that hold at any size: symmetry v.(A u) = u.(A v), identity rows
+    on the Dirichlet dofs (bit-exact), bitwise-reproducible repeated applies.
+"""
+
+import numpy as np
+import pytest
+
+from helpers import match_dofs, rel_err
+from oracle import dogip as odg
+from oracle import fem
+from workloads import coef_aniso_2d, coef_lognormal, coef_uniform, random_vector, unit_mesh
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# (id, dim, n, k, kind): the 3D headline operator and the largest 2D sweep operators
+FULL = [("3d64_p3_se", 3, 64, 3, "se"), ("2d512_p5_se", 2, 512, 5, "se"), ("2d512_p5_wp", 2, 512, 5, "wp")]
+NSAMPLE = 160
+
+
+class FullCase:
+    def __init__(self, d, n, k, kind, seed=0):
+        from paper_1710_09913_amd import Mesh, Operator, Space
+
+        self.d, self.k, self.kind = d, k, kind
+        self.coords, self.cells = unit_mesh(d, n)
+        nel = len(self.cells)
+        if d == 3:
+            self.coef, ck = coef_lognormal(self.coords, self.cells, seed), "scalar"
+        elif kind == "se":
+            self.coef, ck = coef_aniso_2d(nel, seed), "sym"
+        else:
+            self.coef, ck = coef_uniform(nel, 1.0, 100.0, seed), "scalar"
+        self.coef_kind = ck
+        self.dirichlet = kind == "se"
+        self.space = Space(Mesh.unit(d, n), k, kind, "dirichlet" if self.dirichlet else "none")
+        self.op = Operator(self.space, torch.from_numpy(self.coef), ck, fp32=True)
+        self.u = random_vector(self.space.ndofs, seed)
+        self.ug = torch.from_numpy(self.u).cuda()
+        self.cd = self.space.cell_dofs()
+        self.bnd = self.space.boundary() if self.dirichlet else np.zeros(0, np.int32)
+
+    def sampled_rows(self, samples):
+        """Oracle rows of A u at the sampled dofs, and |B^|^T|D||B^||u| there."""
+        touch = np.isin(self.cd, samples).any(axis=1)
+        sub = np.nonzero(touch)[0]
+        verts, local = np.unique(self.cells[sub], return_inverse=True)
+        cells_sub = local.reshape(len(sub), -1).astype(self.cells.dtype)
+        osp = fem.make_space(self.coords[verts], cells_sub, self.k)
+        coef = self.coef[sub]
+        if self.coef_kind == "sym":
+            coef = fem.unpack_sym(coef, self.d)
+        D = odg.build_d(osp, coef, self.kind)
+        pid = np.unique(self.cd[sub])
+        perm = match_dofs(self.space.dof_coords()[pid], osp.dof_coords)
+        uo = np.zeros(osp.ndofs)
+        uo[perm] = self.u[pid]
+        if self.dirichlet:
+            uo[perm[np.isin(pid, self.bnd)]] = 0.0  # boundary columns drop out of interior rows
+        yo = odg.apply(osp, D, uo, self.kind)
+        ab = odg.apply_abs(osp, D, uo, self.kind, False)
+        at = perm[np.searchsorted(pid, samples)]
+        return yo[at], ab[at]
+
+    def n_incident_max(self):
+        return int(np.bincount(self.cd.reshape(-1)).max())
+
+
+@pytest.fixture(scope="module", params=FULL, ids=[f[0] for f in FULL])
+def full(request):
+    _, d, n, k, kind = request.param
+    print(f"[full] dim={d} n={n} k={k} kind={kind}", flush=True)
+    c = FullCase(d, n, k, kind)
+    yield c
+    del c.op
+    torch.cuda.empty_cache()
+
+
+def _samples(c, seed=1234):
+    rng = np.random.default_rng(seed)
+    s = rng.choice(c.space.ndofs, NSAMPLE, replace=False)
+    if c.dirichlet:
+        s = np.setdiff1d(s, c.bnd)
+    return np.sort(s)
+
+
+def test_fullsize_f64_sampled_rows(full):
+    c = full
+    y = c.op.apply(c.ug).cpu().numpy()
+    s = _samples(c)
+    yo, ab = c.sampled_rows(s)
+    assert np.all(np.abs(y[s] - yo) <= 1e-12 * ab + 1e-300)
+    assert rel_err(y[s], yo) <= 1e-11
+
+
+def test_fullsize_f32_sampled_rows(full):
+    c = full
+    y32 = c.op.apply(c.ug, prec="f32").cpu().numpy()
+    s = _samples(c, seed=99)
+    yo, ab = c.sampled_rows(s)
+    info = c.space.info
+    m = info["vt"] + info["nb"] * info["wt"] + info["nb"] + c.n_incident_max() + 3
+    gam = m * 2.0 ** -24 / (1 - m * 2.0 ** -24)
+    assert np.all(np.abs(y32[s] - yo) <= 2 * gam * ab + 1e-300)
+    print(f"fp32 sampled normwise relative error {rel_err(y32[s], yo):.3e}")
+
+
+def test_fullsize_symmetry_and_identity_rows(full):
+    c = full
+    v = torch.from_numpy(random_vector(c.space.ndofs, 7)).cuda()
+    au, av = c.op.apply(c.ug), c.op.apply(v)
+    lhs, rhs = float(torch.dot(v, au)), float(torch.dot(c.ug, av))
+    scale = float(torch.linalg.norm(v) * torch.linalg.norm(au))
+    assert abs(lhs - rhs) <= 1e-12 * scale
+    if c.dirichlet:
+        b = torch.from_numpy(c.bnd.astype(np.int64)).cuda()
+        assert torch.equal(au[b], c.ug[b])
+
+
+def test_fullsize_bitwise_reproducible(full):
+    c = full
+    y1 = c.op.apply(c.ug)
+    y2 = c.op.apply(c.ug)
+    assert torch.equal(y1, y2)
+    z1 = c.op.apply(c.ug, prec="f32")
+    z2 = c.op.apply(c.ug, prec="f32")
+    assert torch.equal(z1, z2)
