@@ -12,7 +12,7 @@ namespace dogip {
 
 struct BatchWork {
   int maxit = 0;
-  DevBuf r, p, q, yout, part, energy, sc, rr_true, iters, need, stalls, active, res, state, use64, last_rep;
+  DevBuf r, p, q, yout, part, energy, sc, rr_true, rr_min, iters, need, stalls, active, res, state, use64, last_rep;
   DevBuf act, rep, items_a, items_b, items_r;  // compacted problem and work-item lists
   int* h_lists = nullptr;                      // pinned: active, use64, need, act, rep
   uint64_t* h_items = nullptr;                 // pinned: three item lists
@@ -193,6 +193,7 @@ int batch_pcg(Batch& b, const double* rhs, double* x, const dogip_solve_opts& o,
     w.energy.alloc(size_t(b.ntiles_total) * sizeof(double));
     w.sc.alloc(size_t(np) * sizeof(PcgScalars));
     w.rr_true.alloc(size_t(np) * sizeof(double));
+    w.rr_min.alloc(size_t(np) * sizeof(double));
     w.iters.alloc(size_t(np) * sizeof(int));
     w.need.alloc(size_t(np) * sizeof(int));
     w.stalls.alloc(size_t(np) * sizeof(int));
@@ -216,7 +217,7 @@ int batch_pcg(Batch& b, const double* rhs, double* x, const dogip_solve_opts& o,
   v.p = w.p.as<double>();
   v.part = w.part.as<double>();
   v.s = {w.sc.as<PcgScalars>(), w.rr_true.as<double>(), w.iters.as<int>(), w.need.as<int>(), w.stalls.as<int>(),
-         w.active.as<int>(), w.state.as<int>(), w.use64.as<int>(), w.last_rep.as<int>()};
+         w.active.as<int>(), w.state.as<int>(), w.use64.as<int>(), w.last_rep.as<int>(), w.rr_min.as<double>()};
   v.gx = 32;
   v.np = np;
   v.tol = o.tol;

@@ -50,6 +50,7 @@ struct BatchPcgState {
   int* state;     // 0 running, 1 converged, 2 failed (breakdown or non-finite)
   int* use64;     // mixed mode: the problem switched to the FP64 apply
   int* last_rep;  // iteration count at the last replacement
+  double* rr_min; // smallest true residual norm^2 so far
 };
 
 struct BatchVecArgs {

@@ -105,6 +105,16 @@ struct Op {
   ~Op();
 };
 
+// Global numbering of the order-q Lagrange nodes of a mesh (see setup.cpp).
+struct LatticeDofs {
+  int nl = 0;                      // nodes per cell
+  int64_t ndofs = 0;
+  std::vector<int32_t> cell_dofs;  // [nc][nl], local nodes in lattice order
+  std::vector<double> xyz;         // [ndofs][dim] (when asked for)
+  std::vector<uint8_t> is_bnd;     // [ndofs] on a boundary facet (when asked for)
+};
+LatticeDofs number_lattice(const Mesh& m, int q, bool xyz);
+
 // ---- host setup ----
 std::shared_ptr<Mesh> make_mesh(int dim, int64_t nv, const double* xyz, int64_t nc, const int32_t* cells);
 std::shared_ptr<Mesh> make_unit_mesh(int dim, int n);

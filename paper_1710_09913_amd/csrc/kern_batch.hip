@@ -128,6 +128,7 @@ __global__ __launch_bounds__(256) void k_b_fin_init(const double* __restrict__ p
     c.bb = bb;
     c.flags = (isfinite(rz) && isfinite(rr) && isfinite(bb)) ? 0 : PCG_NONFINITE;
     s.rr_true[p] = rr;
+    s.rr_min[p] = rr;
     s.iters[p] = 0;
     s.need[p] = 0;
     s.stalls[p] = 0;
@@ -253,8 +254,16 @@ __global__ __launch_bounds__(256) void k_b_fin_replace(const int* __restrict__ a
   if (threadIdx.x == 0) {
     PcgScalars& c = s.sc[p];
     if (!isfinite(rz) || !isfinite(rr)) c.flags |= PCG_NONFINITE;
-    s.stalls[p] = rr > 0.25 * s.rr_true[p] ? s.stalls[p] + 1 : 0;
-    if (mixed && !s.use64[p] && rr > s.rr_true[p]) s.stalls[p] = 3;  // divergence under the FP32 operator
+    if (mixed && !s.use64[p]) {
+      // FP32 operator: a stall is a true residual well above the recursive one (the
+      // FP32 error dominates); a true residual far above its minimum is divergence
+      const bool diverged = rr > DIVERGE_RR * s.rr_min[p];
+      const bool gap = rr > GAP_RR * fmax(c.rr, 1e-300);
+      s.stalls[p] = diverged ? 3 : (gap ? s.stalls[p] + 1 : 0);
+    } else {
+      s.stalls[p] = rr > 0.25 * s.rr_true[p] ? s.stalls[p] + 1 : 0;
+    }
+    s.rr_min[p] = fmin(s.rr_min[p], rr);
     c.rho = rz;
     c.rr = rr;
     s.rr_true[p] = rr;

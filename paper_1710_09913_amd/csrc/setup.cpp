@@ -218,25 +218,16 @@ int tri_index(int i, int j, int n) { return i * (n + 1) - i * (i - 1) / 2 + j; }
 
 }  // namespace
 
-std::shared_ptr<Space> make_space(std::shared_ptr<const Mesh> mesh, int k, int kind, int bc) {
-  const Mesh& m = *mesh;
+// Lagrange nodes of order q on every cell of the mesh, numbered globally:
+// vertices, then the q-1 nodes of each edge, the (q-1)(q-2)/2 of each face (3D),
+// then the cell-interior nodes.  A node shared by several cells gets one number
+// whatever the cells' local vertex orders (edge and face nodes are keyed by
+// vertex ids and multiplicities).  With xyz, also the node coordinates and the
+// flag of nodes on boundary facets.
+LatticeDofs number_lattice(const Mesh& m, int q, bool xyz) {
   const int d = m.dim, d1 = d + 1;
-  DOGIP_CHECK(kind == DOGIP_WP || kind == DOGIP_SE, DOGIP_E_RANGE, "kind must be DOGIP_WP or DOGIP_SE");
-  DOGIP_CHECK(bc == DOGIP_BC_NONE || bc == DOGIP_BC_DIRICHLET0, DOGIP_E_RANGE, "unknown boundary condition");
-  DOGIP_CHECK(k >= 1 && k <= (d == 2 ? 8 : 4), DOGIP_E_RANGE, "k must be in 1..8 (2D) or 1..4 (3D)");
-  auto s = std::make_shared<Space>();
-  s->mesh = mesh;
-  s->dim = d;
-  s->k = k;
-  s->kind = kind;
-  s->bc = bc;
-  s->nc = m.nc;
-  s->vt = dim_p(d, k);
-  s->wt = dim_p(d, w_order(k, kind));
-  s->nsym = kind == KIND_SE ? n_sym(d) : 1;
-  s->nb = kind == KIND_SE ? d : 1;
-  reference_tables(d, k, kind, s->bhat, s->what, s->nnz_bhat, s->nnz_pm1);
-
+  LatticeDofs out;
+  out.nl = dim_p(d, q);
   // local edges (pairs) and facets
   std::vector<std::array<int, 2>> ledges;
   for (int a = 0; a <= d; ++a)
@@ -254,20 +245,20 @@ std::shared_ptr<Space> make_space(std::shared_ptr<const Mesh> mesh, int k, int k
     }
     F = number_entities<3>(m, lfaces);
   }
-  const int64_t ne1 = k - 1, nf1 = d == 3 ? int64_t(k - 1) * (k - 2) / 2 : 0;
-  const int64_t nint = d == 2 ? int64_t(k - 1) * (k - 2) / 2 : int64_t(k - 1) * (k - 2) * (k - 3) / 6;
+  const int64_t ne1 = q - 1, nf1 = d == 3 ? int64_t(q - 1) * (q - 2) / 2 : 0;
+  const int64_t nint = d == 2 ? int64_t(q - 1) * (q - 2) / 2 : int64_t(q - 1) * (q - 2) * (q - 3) / 6;
   const int64_t base_e = m.nv, base_f = base_e + E.n * ne1, base_c = base_f + (d == 3 ? F.n * nf1 : 0);
-  s->ndofs = base_c + m.nc * nint;
-  DOGIP_CHECK(s->ndofs <= int64_t(TD_MASK), DOGIP_E_RANGE, "too many dofs for the tile encoding");
+  out.ndofs = base_c + m.nc * nint;
+  DOGIP_CHECK(out.ndofs <= int64_t(TD_MASK), DOGIP_E_RANGE, "too many dofs for the tile encoding");
 
   // local node barycentric indices and interior ordinals
-  const int vt = s->vt;
+  const int vt = out.nl;
   std::vector<std::array<int, 4>> bv(vt);
   std::vector<int> iord(vt, -1);
   int cnt = 0;
   for (int l = 0; l < vt; ++l) {
     int b[4] = {0, 0, 0, 0};
-    ref::bary_index(d, k, l, b);
+    ref::bary_index(d, q, l, b);
     bool inner = true;
     for (int j = 0; j < 4; ++j) bv[l][j] = b[j];
     for (int j = 0; j <= d; ++j) inner = inner && b[j] > 0;
@@ -279,9 +270,11 @@ std::shared_ptr<Space> make_space(std::shared_ptr<const Mesh> mesh, int k, int k
     return -1;
   };
 
-  s->cell_dofs.assign(size_t(m.nc) * vt, -1);
-  s->dof_xyz.assign(size_t(s->ndofs) * d, 0.0);
-  s->is_bnd.assign(s->ndofs, 0);
+  out.cell_dofs.assign(size_t(m.nc) * vt, -1);
+  if (xyz) {
+    out.xyz.assign(size_t(out.ndofs) * d, 0.0);
+    out.is_bnd.assign(out.ndofs, 0);
+  }
   const int nle = int(ledges.size());
   for (int64_t c = 0; c < m.nc; ++c) {
     const int32_t* cv = &m.cells[c * d1];
@@ -321,23 +314,52 @@ std::shared_ptr<Space> make_space(std::shared_ptr<const Mesh> mesh, int k, int k
             std::make_pair(cv[sup[0]], mult[0]), std::make_pair(cv[sup[1]], mult[1]),
             std::make_pair(cv[sup[2]], mult[2])};
         std::sort(vm.begin(), vm.end());
-        dof = base_f + fid * nf1 + tri_index(vm[1].second - 1, vm[2].second - 1, k - 3);
+        dof = base_f + fid * nf1 + tri_index(vm[1].second - 1, vm[2].second - 1, q - 3);
       } else {
         dof = base_c + c * nint + iord[l];
       }
-      s->cell_dofs[c * vt + l] = int32_t(dof);
+      out.cell_dofs[c * vt + l] = int32_t(dof);
+      if (!xyz) continue;
       // coordinates, summed in ascending vertex-id order so every cell gives the same bits
       std::array<std::pair<int32_t, int>, 4> vw;
       for (int t = 0; t < ns; ++t) vw[t] = {cv[sup[t]], mult[t]};
       std::sort(vw.begin(), vw.begin() + ns);
       for (int x = 0; x < d; ++x) {
         double acc = 0.0;
-        for (int t = 0; t < ns; ++t) acc += (double(vw[t].second) / k) * m.xyz[int64_t(vw[t].first) * d + x];
-        s->dof_xyz[dof * d + x] = acc;
+        for (int t = 0; t < ns; ++t) acc += (double(vw[t].second) / q) * m.xyz[int64_t(vw[t].first) * d + x];
+        out.xyz[dof * d + x] = acc;
       }
       for (int j = 0; j <= d; ++j)
-        if (bv[l][j] == 0 && fb[j]) s->is_bnd[dof] = 1;
+        if (bv[l][j] == 0 && fb[j]) out.is_bnd[dof] = 1;
     }
+  }
+  return out;
+}
+
+std::shared_ptr<Space> make_space(std::shared_ptr<const Mesh> mesh, int k, int kind, int bc) {
+  const Mesh& m = *mesh;
+  const int d = m.dim;
+  DOGIP_CHECK(kind == DOGIP_WP || kind == DOGIP_SE, DOGIP_E_RANGE, "kind must be DOGIP_WP or DOGIP_SE");
+  DOGIP_CHECK(bc == DOGIP_BC_NONE || bc == DOGIP_BC_DIRICHLET0, DOGIP_E_RANGE, "unknown boundary condition");
+  DOGIP_CHECK(k >= 1 && k <= (d == 2 ? 8 : 4), DOGIP_E_RANGE, "k must be in 1..8 (2D) or 1..4 (3D)");
+  auto s = std::make_shared<Space>();
+  s->mesh = mesh;
+  s->dim = d;
+  s->k = k;
+  s->kind = kind;
+  s->bc = bc;
+  s->nc = m.nc;
+  s->vt = dim_p(d, k);
+  s->wt = dim_p(d, w_order(k, kind));
+  s->nsym = kind == KIND_SE ? n_sym(d) : 1;
+  s->nb = kind == KIND_SE ? d : 1;
+  reference_tables(d, k, kind, s->bhat, s->what, s->nnz_bhat, s->nnz_pm1);
+  {
+    LatticeDofs L = number_lattice(m, k, true);
+    s->ndofs = L.ndofs;
+    s->cell_dofs.swap(L.cell_dofs);
+    s->dof_xyz.swap(L.xyz);
+    s->is_bnd.swap(L.is_bnd);
   }
   // final numbering: dofs in the Morton order of their coordinates, so that the dofs
   // of a compact group of cells occupy a compact index range

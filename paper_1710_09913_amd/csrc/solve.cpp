@@ -95,6 +95,7 @@ static CgResult cg_run(Op& op, const double* b, double* x, bool x0_given, const 
   res.relres = std::sqrt(hs.rr / hs.bb);
   if (hs.rr <= thr) return res;
   double rr_true = hs.rr;  // residual norm^2 at the last exact (re)computation
+  double rr_min = hs.rr;   // smallest true residual norm^2 so far
   int stalls = 0;
   int last_rep = 0;  // iteration of the last replacement
   int it = 0;
@@ -142,9 +143,16 @@ static CgResult cg_run(Op& op, const double* b, double* x, bool x0_given, const 
         res.status = DOGIP_E_NONFINITE;
         return res;
       }
-      const bool grew = hs.rr > rr_true;
-      stalls = hs.rr > 0.25 * rr_true ? stalls + 1 : 0;
-      if (grew && cp.prec == DOGIP_F32) stalls = 3;  // divergence under the FP32 operator: hand over now
+      if (cp.prec == DOGIP_F32) {
+        // the FP32 error dominates when the true residual is well above the recursive
+        // one; far above its minimum, the iteration diverges: hand over at once
+        const bool diverged = hs.rr > DIVERGE_RR * rr_min;
+        const bool gap = hs.rr > GAP_RR * std::max(last, 1e-300);
+        stalls = diverged ? 3 : (gap ? stalls + 1 : 0);
+      } else {
+        stalls = hs.rr > 0.25 * rr_true ? stalls + 1 : 0;
+      }
+      rr_min = std::min(rr_min, hs.rr);
       rr_true = hs.rr;
       last = hs.rr;
       conv = hs.rr <= thr;

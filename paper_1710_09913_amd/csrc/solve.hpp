@@ -12,6 +12,13 @@ constexpr int RED_BLOCKS = 1024;  // fixed reduction grid (deterministic partial
 constexpr int PCG_BREAKDOWN = 1;
 constexpr int PCG_NONFINITE = 2;
 
+// Hand-over rules of the FP32-operator CG at a residual replacement (ratios of squared
+// norms): the true residual above GAP_RR times the recursive one counts as a stall
+// (three in a row hand over to FP64); above DIVERGE_RR times its minimum so far the
+// iteration is taken as diverging and handed over at once.
+constexpr double GAP_RR = 10.0;
+constexpr double DIVERGE_RR = 1e4;
+
 struct PcgScalars {
   double rho;    // r . z
   double rr;     // r . r
