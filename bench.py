@@ -154,7 +154,8 @@ def _rhs_f1(space, mesh, k):
 def run_c2(a):
     """2D unit square 512^2 x 2 triangles, P1..P5, projection (m ~ U[1,100]) and elliptic
     (anisotropic SPD per cell): FP64 and FP32 apply, and for the elliptic problem FP64 vs
-    mixed PCG to 1e-8."""
+    mixed PCG to 1e-8.  The projection rows also time the global form (Theorem 1: one D
+    value per dof of C_{N,2k}) beside the element-wise one (Theorem 2)."""
     import torch
 
     from paper_1710_09913_amd import Mesh, Operator, Space
@@ -172,13 +173,23 @@ def run_c2(a):
                 op = Operator(sp, torch.from_numpy(coef_aniso_2d(sp.ncells, a.seed)), "sym", fp32=True)
             u = torch.from_numpy(random_vector(sp.ndofs, a.seed)).cuda()
             y = torch.empty_like(u)
-            row = {"kind": kind, "k": k, "ndofs": sp.ndofs}
-            for prec in ("f64", "f32"):
-                ms, kms, fms = time_apply(op, u, y, prec, a.steps, a.warmup)
-                kms += fms
-                ab = op.info["alg_bytes_" + prec]
-                row[prec] = {"GDoF_s": round(sp.ndofs / (ms * 1e-3) / 1e9, 3), "ms": round(ms, 5),
-                             "frac": round(ab / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            row = {"kind": kind, "k": k, "ndofs": sp.ndofs, "d_bytes_f64": op.info["bytes_d64"]}
+
+            def timed(o, tag):
+                for prec in ("f64", "f32"):
+                    ms, kms, fms = time_apply(o, u, y, prec, a.steps, a.warmup)
+                    kms += fms
+                    ab = o.info["alg_bytes_" + prec]
+                    row[tag + prec] = {"GDoF_s": round(sp.ndofs / (ms * 1e-3) / 1e9, 3), "ms": round(ms, 5),
+                                       "frac": round(ab / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+            timed(op, "")
+            if kind == "wp":
+                og = Operator(sp, torch.from_numpy(coef_uniform(sp.ncells, 1, 100, a.seed)), "scalar", fp32=True,
+                              global_w=True)
+                timed(og, "global_")
+                row["global_d_bytes_f64"] = og.info["bytes_d64"]
+                del og
             if kind == "se" and not a.no_solve:
                 b = _rhs_f1(sp, mesh, k)
                 for mode in ("f64", "mixed"):

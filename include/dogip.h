@@ -94,6 +94,10 @@ extern "C" {
 
 /* ---- dogip_op_create flags ---- */
 #define DOGIP_OP_FP32 1u /* also build the FP32 copy of D (needed by DOGIP_F32 and MIXED) */
+/* Global form of the weighted projection (Theorem 1): A = B^T A^DoGIP B with one D
+ * value per dof of the continuous double-grid space C_{N,2k} (the element-wise
+ * form of Theorem 2 stores one per cell and node).  Projection spaces only. */
+#define DOGIP_OP_GLOBAL_W 2u
 
 /* ---- element kernel variants ---- */
 #define DOGIP_VARIANT_AUTO 0     /* tuned choice: unrolled where compiled, else looped */
@@ -126,6 +130,7 @@ typedef struct {
   double alg_bytes_f64; /* algorithmic bytes of one apply: D + int32 connectivity + u + y */
   double alg_bytes_f32;
   double alg_flops;     /* 2 [2 (nnz B^ - nnz_pm1 B^) + d^2 W_T] ncells (Section 3 count, x2 for FMA) */
+  int64_t ndofs_w;      /* DOGIP_OP_GLOBAL_W: dofs of C_{N,2k} (D values held); 0 otherwise */
 } dogip_op_info;
 
 typedef struct {
@@ -199,18 +204,22 @@ void dogip_space_destroy(dogip_space s);
 /* ---- operator: D in device memory, tiles, Jacobi diagonal ---- */
 
 /* Build the operator.  coef: device pointer in the form coef_kind (cells in mesh
- * order), read during the call only.  flags: DOGIP_OP_FP32 or 0.  tile_waves:
+ * order), read during the call only.  flags: DOGIP_OP_FP32, DOGIP_OP_GLOBAL_W or
+ * both.  tile_waves:
  * cells per tile / 64, 1..8, or 0 for the tuned default.  variant:
  * DOGIP_VARIANT_*.  D is built by the HIP kernels (Theorem 2: m_T |T| w^_i;
  * Theorem 4: w^_i |T| R_T^-1 M_T R_T^-T; or copied for RAW_D).  The call
  * synchronizes the stream before returning.  DOGIP_E_RANGE for a form that does
- * not fit the kind (SYM with the projection). */
+ * not fit the kind (SYM with the projection) and for DOGIP_OP_GLOBAL_W on an
+ * elliptic space.  With DOGIP_OP_GLOBAL_W, D_j = int m phi^W_j is summed over the
+ * cells holding W dof j (RAW_D: the cells' [ncells][wt] values are summed). */
 int dogip_op_create(dogip_space s, int coef_kind, const double* coef, unsigned flags, int tile_waves,
                     int variant, dogip_stream stream, dogip_op* out);
 /* Rebuild D (and the FP32 copy and the Jacobi diagonal) from a new coefficient.  async. */
 int dogip_op_set_coef(dogip_op op, int coef_kind, const double* coef, dogip_stream stream);
 int dogip_op_get_info(dogip_op op, dogip_op_info* info);
-/* Copy D to device memory [ncells][wt][nsym] in mesh cell order (FP64).  async. */
+/* Copy D to device memory [ncells][wt][nsym] in mesh cell order (FP64).  async.
+ * DOGIP_E_STATE for a DOGIP_OP_GLOBAL_W operator (its D is not per cell). */
 int dogip_op_export_d(dogip_op op, double* d_out, dogip_stream stream);
 
 /* y <- A u (overwrite), with Dirichlet identity rows if the space has them.
@@ -233,6 +242,7 @@ int dogip_pcg(dogip_op op, const double* b, double* x, const dogip_solve_opts* o
  * to theta_T when D scales with exp(theta_T) and A lam = dJ/du.  u, lam: device
  * [ndofs]; g: device [ncells].  async. */
 int dogip_grad_logcoef(dogip_op op, const double* u, const double* lam, double* g, dogip_stream stream);
+/* (DOGIP_E_STATE for a DOGIP_OP_GLOBAL_W operator.) */
 /* Kernel timer: when enabled, every apply records HIP events on the apply's
  * stream before its tile kernel, between the tile kernel and the shared-dof
  * finish kernel, and after the finish.  dogip_op_timer_read synchronizes on the

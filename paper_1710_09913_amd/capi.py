@@ -38,6 +38,7 @@ DOGIP_SOLVE_F64 = 0
 DOGIP_SOLVE_MIXED = 1
 DOGIP_SOLVE_MIXED_RESTART = 2
 DOGIP_OP_FP32 = 1
+DOGIP_OP_GLOBAL_W = 2
 DOGIP_VARIANT_AUTO = 0
 DOGIP_VARIANT_UNROLLED = 1
 DOGIP_VARIANT_LOOPED = 2
@@ -55,7 +56,7 @@ class OpInfo(C.Structure):
                 ("ntiles", C.c_int64), ("tile_dofs_total", C.c_int64), ("nshared", C.c_int64),
                 ("max_tile_dofs", C.c_int64), ("bytes_d64", C.c_int64), ("bytes_d32", C.c_int64),
                 ("bytes_index", C.c_int64), ("alg_bytes_f64", C.c_double), ("alg_bytes_f32", C.c_double),
-                ("alg_flops", C.c_double)]
+                ("alg_flops", C.c_double), ("ndofs_w", C.c_int64)]
 
 
 class SolveOpts(C.Structure):

@@ -89,6 +89,23 @@ struct TilePlan {
 //   ((e/64) * nch + f/vec) * 64 * vec + (e%64) * vec + f%vec,  vec = 16 / sizeof(value).
 inline int64_t d_chunks(int wt, int nsym, int vec) { return (int64_t(wt) * nsym + vec - 1) / vec; }
 
+// Global projection form (Theorem 1): one D value per global W dof (C_{N,2k}).  Each
+// W dof is owned by one cell (the first in tile order holding it); a tile stores
+// the D values of the W dofs its cells own, cell after cell, each cell's in its
+// local node order.  Per cell, rec = (mask of owned sub-simplices) | offset << GW_SHIFT,
+// the offset of its first owned value within the tile's range.
+constexpr uint32_t GW_SHIFT = 15;
+constexpr uint32_t GW_MASK = (1u << GW_SHIFT) - 1u;
+struct GlobalPlan {
+  int64_t nw = 0;                  // global W dofs
+  std::vector<uint32_t> rec;       // [nel_pad] per cell (internal order)
+  std::vector<int64_t> off;        // [ntiles+1] tile ranges of owned D values
+  std::vector<int64_t> inc_ptr;    // [nw+1] cells holding each owned W dof (by position)
+  std::vector<int64_t> inc;        // internal cell * W_T + local node, ascending
+  int64_t max_tile_w = 0;
+};
+GlobalPlan make_global_plan(const Space& s, const TilePlan& p);
+
 struct PcgWork;
 struct OpTimer;
 
@@ -100,6 +117,10 @@ struct Op {
   int64_t nch64 = 0, nch32 = 0;
   DevBuf d64, d32, lidx, tile_off, tile_dofs, shared, perm, cells, xyz, what, bhat64, bhat32, invdiag;
   DevBuf stage_off, sh_rowptr, sh_slots, stage, bnd;  // second pass: shared dofs, Dirichlet rows
+  bool global_w = false;                               // global projection form
+  bool gw_staged = false;                              // its tile D ranges fit in LDS
+  GlobalPlan gplan;
+  DevBuf gw_rec, gw_off, gw_inc_ptr, gw_inc, dg64, dg32;
   std::unique_ptr<PcgWork> pcg;
   std::unique_ptr<OpTimer> timer;
   ~Op();
@@ -157,9 +178,13 @@ struct ApplyLaunch {
   int te;
   int lds_slots;         // LDS slots per tile (>= max tile dofs)
   int tile_base;         // first tile of this launch (batch uses 0)
+  const uint32_t* gw_rec;  // global projection form: per-cell records (else null)
+  const int64_t* gw_off;   // [ntiles+1] tile ranges of D (D then holds one value per W dof)
+  int lds_w;               // LDS entries for the tile's D values (>= max owned per tile + 1), 0: not staged
 };
 
 bool launch_apply(int dim, int k, int kind, int prec, int variant, const ApplyLaunch& a, hipStream_t st);
+bool launch_apply_global(int dim, int k, int prec, int variant, const ApplyLaunch& a, hipStream_t st);
 bool has_unrolled(int dim, int k, int kind);
 
 struct DiagLaunch {
@@ -171,8 +196,11 @@ struct DiagLaunch {
   double* out;
   int64_t nel, ntiles, nch;
   int nlc, te, lds_slots;
+  const uint32_t* gw_rec;  // global projection form (D one value per W dof), else null
+  const int64_t* gw_off;
 };
 void launch_diag(int dim, int k, int kind, const DiagLaunch& a, hipStream_t st);
+void launch_diag_global(int dim, int k, const DiagLaunch& a, hipStream_t st);
 
 struct GradLaunch {
   const double* D;
@@ -201,6 +229,10 @@ struct BuildDLaunch {
   int dim, kind, coef_kind, wt, nsym;
 };
 void launch_build_d(const BuildDLaunch& a, hipStream_t st);
+// Global projection form: D at position j (tile layout) = sum over inc[inc_ptr[j] ..
+// inc_ptr[j+1]) (internal cell * wt + node) of the cell's integral of m phi^W_node.
+void launch_build_dg(const BuildDLaunch& a, const int64_t* inc_ptr, const int64_t* inc, int64_t nw, double* dg64,
+                     float* dg32, hipStream_t st);
 void launch_export_d(const double* d64, const int32_t* perm, double* out, int64_t nel, int64_t nch64, int wt,
                      int nsym, hipStream_t st);
 void launch_zero_indexed(double* y, const int32_t* idx, int64_t n, hipStream_t st);

@@ -141,6 +141,48 @@ __global__ __launch_bounds__(256) void k_invert(const double* __restrict__ d, do
     inv[i] = 1.0 / d[i];
 }
 
+// ---- global projection form: D_j = sum over the cells holding W dof j of m_T |T| w^_i ----
+// (raw D: the cells' values summed).  One thread per W dof in tile layout; the
+// incidences are in ascending cell order, so the sums are reproducible.
+__global__ __launch_bounds__(256) void k_build_dg(BuildDLaunch a, const int64_t* __restrict__ inc_ptr,
+                                                  const int64_t* __restrict__ inc, int64_t nw, double* __restrict__ dg64,
+                                                  float* __restrict__ dg32) {
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= nw) return;
+  const int dim = a.dim, d1 = dim + 1, wt = a.wt;
+  double acc = 0.0;
+  for (int64_t q = inc_ptr[j]; q < inc_ptr[j + 1]; ++q) {
+    const int64_t e = inc[q] / wt;
+    const int i = int(inc[q] - e * wt);
+    const int64_t uc = a.perm[e];
+    if (a.coef_kind == DOGIP_COEF_RAW_D) {
+      acc += a.coef[uc * wt + i];
+      continue;
+    }
+    double X[4][3] = {};
+    for (int v = 0; v < d1; ++v) {
+      const int64_t g = a.cells[e * d1 + v];
+      for (int x = 0; x < dim; ++x) X[v][x] = a.xyz[g * dim + x];
+    }
+    double det;
+    if (dim == 2) {
+      det = (X[1][0] - X[0][0]) * (X[2][1] - X[0][1]) - (X[2][0] - X[0][0]) * (X[1][1] - X[0][1]);
+    } else {
+      double R[3][3];
+      for (int x = 0; x < 3; ++x)
+        for (int r = 0; r < 3; ++r) R[x][r] = X[r + 1][x] - X[0][x];
+      det = R[0][0] * (R[1][1] * R[2][2] - R[1][2] * R[2][1]) - R[0][1] * (R[1][0] * R[2][2] - R[1][2] * R[2][0]) +
+            R[0][2] * (R[1][0] * R[2][1] - R[1][1] * R[2][0]);
+    }
+    const double vol = fabs(det) / (dim == 2 ? 2.0 : 6.0);
+    const double c = a.coef[uc];
+    const double m = a.coef_kind == DOGIP_COEF_LOGSCALAR ? exp(c) : c;
+    acc += a.what[i] * vol * m;
+  }
+  dg64[j] = acc;
+  if (dg32) dg32[j] = float(acc);
+}
+
 // ---- Jacobi diagonal: diag_l = sum_T sum_i b_il^T D_T,i b_il, b_il = (B^[r][i][l])_r ----
 template <int D, int K, int KIND>
 __global__ __launch_bounds__(512) void k_diag(DiagLaunch a) {
@@ -176,6 +218,53 @@ __global__ __launch_bounds__(512) void k_diag(DiagLaunch a) {
         double s = 0.0;
         sfor<NB>([&](auto R) { s = fma_t(b[R], h[R], s); });
         ye[L] += s;
+      });
+    }
+    sfor<VT>([&](auto L) { atomicAdd(&ys[li[L]], ye[L]); });
+  }
+  __syncthreads();
+  for (int64_t j = threadIdx.x; j < nd; j += blockDim.x) {
+    const uint32_t td = a.tile_dofs[o0 + j];
+    const uint32_t dof = td & TD_MASK;
+    if (td & TD_BND)
+      a.out[dof] = 1.0;
+    else if (td & TD_SHARED)
+      unsafeAtomicAdd(&a.out[dof], ys[j]);
+    else
+      a.out[dof] = ys[j];
+  }
+}
+
+// ---- Jacobi diagonal of the global projection form: diag_l = sum_j B_jl^2 D_j, each
+// W dof j taken by the cell that owns it ----
+template <int D, int K>
+__global__ __launch_bounds__(512) void k_diag_g(DiagLaunch a) {
+  using TB = ref::BTable<D, K, KIND_WP>;
+  constexpr int VT = TB::VT, WT = TB::WT;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* ys = reinterpret_cast<double*>(smem);
+  const int64_t t = blockIdx.x;
+  const int64_t o0 = a.tile_off[t], nd = a.tile_off[t + 1] - o0;
+  for (int64_t j = threadIdx.x; j < nd; j += blockDim.x) ys[j] = 0.0;
+  __syncthreads();
+  const int64_t e = t * a.te + threadIdx.x;
+  if (e < a.nel) {
+    const int lane = threadIdx.x & 63;
+    int li[VT];
+    load_lidx<VT>(a.lidx, e >> 6, a.nlc, lane, li);
+    const uint32_t rec = a.gw_rec[e], mask = rec & GW_MASK;
+    const double* dg = a.D + a.gw_off[t] + (rec >> GW_SHIFT);
+    const double* bt = ctab<D, K, KIND_WP, double>.v;
+    const uint8_t* et = cent<D, K>.v;
+    double ye[VT];
+    sfor<VT>([&](auto L) { ye[L] = 0.0; });
+    int pos = 0;
+    for (int i = 0; i < WT; ++i) {
+      if (!((mask >> et[i]) & 1u)) continue;
+      const double dv = dg[pos++];
+      sfor<VT>([&](auto L) {
+        const double b = bt[i * VT + L];
+        ye[L] = fma(b * b, dv, ye[L]);
       });
     }
     sfor<VT>([&](auto L) { atomicAdd(&ys[li[L]], ye[L]); });
@@ -271,6 +360,33 @@ static unsigned grid_for(int64_t n, int block) {
 void launch_build_d(const BuildDLaunch& a, hipStream_t st) {
   if (a.nel <= 0) return;
   hipLaunchKernelGGL(dev::k_build_d, dim3(unsigned((a.nel + 255) / 256)), dim3(256), 0, st, a);
+}
+
+void launch_build_dg(const BuildDLaunch& a, const int64_t* inc_ptr, const int64_t* inc, int64_t nw, double* dg64,
+                     float* dg32, hipStream_t st) {
+  if (nw <= 0) return;
+  hipLaunchKernelGGL(dev::k_build_dg, dim3(unsigned((nw + 255) / 256)), dim3(256), 0, st, a, inc_ptr, inc, nw, dg64,
+                     dg32);
+}
+
+void launch_diag_global(int dim, int k, const DiagLaunch& a, hipStream_t st) {
+  const dim3 grid(unsigned(a.ntiles)), block(unsigned(a.te));
+  const size_t lds = size_t(a.lds_slots) * sizeof(double);
+  switch (dim * 16 + k) {
+    case 32 + 1: hipLaunchKernelGGL((dev::k_diag_g<2, 1>), grid, block, lds, st, a); break;
+    case 32 + 2: hipLaunchKernelGGL((dev::k_diag_g<2, 2>), grid, block, lds, st, a); break;
+    case 32 + 3: hipLaunchKernelGGL((dev::k_diag_g<2, 3>), grid, block, lds, st, a); break;
+    case 32 + 4: hipLaunchKernelGGL((dev::k_diag_g<2, 4>), grid, block, lds, st, a); break;
+    case 32 + 5: hipLaunchKernelGGL((dev::k_diag_g<2, 5>), grid, block, lds, st, a); break;
+    case 32 + 6: hipLaunchKernelGGL((dev::k_diag_g<2, 6>), grid, block, lds, st, a); break;
+    case 32 + 7: hipLaunchKernelGGL((dev::k_diag_g<2, 7>), grid, block, lds, st, a); break;
+    case 32 + 8: hipLaunchKernelGGL((dev::k_diag_g<2, 8>), grid, block, lds, st, a); break;
+    case 48 + 1: hipLaunchKernelGGL((dev::k_diag_g<3, 1>), grid, block, lds, st, a); break;
+    case 48 + 2: hipLaunchKernelGGL((dev::k_diag_g<3, 2>), grid, block, lds, st, a); break;
+    case 48 + 3: hipLaunchKernelGGL((dev::k_diag_g<3, 3>), grid, block, lds, st, a); break;
+    case 48 + 4: hipLaunchKernelGGL((dev::k_diag_g<3, 4>), grid, block, lds, st, a); break;
+    default: throw Error(DOGIP_E_RANGE, "no kernel for this (dim, k)");
+  }
 }
 
 void launch_export_d(const double* d64, const int32_t* perm, double* out, int64_t nel, int64_t nch64, int wt, int nsym,

@@ -184,6 +184,75 @@ struct Elem {
   }
 };
 
+// Sub-simplex bit of every W node of the projection form (global variant), for the
+// looped body.
+template <int D, int K>
+struct CEnt {
+  static constexpr int WT = dim_p(D, 2 * K);
+  uint8_t v[WT];
+  constexpr CEnt() : v{} {
+    for (int i = 0; i < WT; ++i) v[i] = uint8_t(ref::node_entity(D, 2 * K, i));
+  }
+};
+template <int D, int K>
+__constant__ CEnt<D, K> cent{};
+
+// Element body of the global projection form (Theorem 1).  The cell applies D only
+// at the W nodes it owns (sub-simplex mask in rec), reading the values from the
+// tile's LDS copy dl, where its owned values start at rec >> GW_SHIFT in local node
+// order; the other nodes are applied by the cells that own them.
+template <int D, int K, typename T, int VARIANT>
+struct ElemG {
+  using TB = ref::BTable<D, K, KIND_WP>;
+  static constexpr int VT = TB::VT, WT = TB::WT;
+
+  __device__ __forceinline__ static void run(const T* __restrict__ dl, uint32_t rec, const T (&ue)[VT],
+                                             T (&ye)[VT]) {
+    const uint32_t mask = rec & GW_MASK;
+    int pos = int(rec >> GW_SHIFT);
+    sfor<VT>([&](auto L) { ye[L] = T(-0.0); });
+    if constexpr (VARIANT == DOGIP_VARIANT_UNROLLED) {
+      sfor<WT>([&](auto I) {
+        constexpr int ent = ref::node_entity(D, 2 * K, I);
+        const bool own = (mask >> ent) & 1u;
+        T acc = T(-0.0);
+        sfor<VT>([&](auto L) {
+          constexpr double b = CT<D, K, KIND_WP>::t.v[0][I][L];
+          if constexpr (b == 1.0)
+            acc = acc + ue[L];
+          else if constexpr (b == -1.0)
+            acc = acc - ue[L];
+          else if constexpr (b != 0.0)
+            acc = fma_t(T(b), ue[L], acc);
+        });
+        const T h = (own ? dl[pos] : T(0)) * acc;
+        pos += own ? 1 : 0;
+        sfor<VT>([&](auto L) {
+          constexpr double b = CT<D, K, KIND_WP>::t.v[0][I][L];
+          if constexpr (b == 1.0)
+            ye[L] = ye[L] + h;
+          else if constexpr (b == -1.0)
+            ye[L] = ye[L] - h;
+          else if constexpr (b != 0.0)
+            ye[L] = fma_t(T(b), h, ye[L]);
+        });
+      });
+    } else {
+      const T* bt = ctab<D, K, KIND_WP, T>.v;
+      const uint8_t* et = cent<D, K>.v;
+      for (int i = 0; i < WT; ++i) {
+        const bool own = (mask >> et[i]) & 1u;
+        const T* br = bt + i * VT;
+        T acc = T(-0.0);
+        sfor<VT>([&](auto L) { acc = fma_t(br[L], ue[L], acc); });
+        const T h = (own ? dl[pos] : T(0)) * acc;
+        pos += own ? 1 : 0;
+        sfor<VT>([&](auto L) { ye[L] = fma_t(br[L], h, ye[L]); });
+      }
+    }
+  }
+};
+
 // Local indices of one cell: nlc 16-byte chunks of 8 uint16 slots, AoSoA by 64 cells.
 template <int VT>
 __device__ __forceinline__ void load_lidx(const uint16_t* __restrict__ lidx, int64_t w, int nlc, int lane,

@@ -91,7 +91,11 @@ static void build_d(Op& op, int coef_kind, const double* coef, hipStream_t st) {
   b.coef_kind = coef_kind;
   b.wt = s.wt;
   b.nsym = s.nsym;
-  launch_build_d(b, st);
+  if (op.global_w)
+    launch_build_dg(b, op.gw_inc_ptr.as<int64_t>(), op.gw_inc.as<int64_t>(), op.gplan.nw, op.dg64.as<double>(),
+                    op.has32 ? op.dg32.as<float>() : nullptr, st);
+  else
+    launch_build_d(b, st);
   HIPCHK(hipGetLastError());
   // Jacobi diagonal -> inverse
   DevBuf tmp(size_t(s.ndofs) * sizeof(double));
@@ -108,30 +112,63 @@ std::unique_ptr<Op> make_op(std::shared_ptr<const Space> sp, int coef_kind, cons
   DOGIP_CHECK(coef != nullptr, DOGIP_E_NULL, "null coefficient pointer");
   DOGIP_CHECK(tile_waves >= 0 && tile_waves <= 8, DOGIP_E_RANGE, "tile_waves must be 0..8");
   DOGIP_CHECK(variant >= DOGIP_VARIANT_AUTO && variant <= DOGIP_VARIANT_LOOPED, DOGIP_E_RANGE, "unknown variant");
+  DOGIP_CHECK((flags & ~(DOGIP_OP_FP32 | DOGIP_OP_GLOBAL_W)) == 0, DOGIP_E_RANGE, "unknown operator flag");
   auto op = std::make_unique<Op>();
   op->space = sp;
   op->has32 = (flags & DOGIP_OP_FP32) != 0;
+  op->global_w = (flags & DOGIP_OP_GLOBAL_W) != 0;
+  DOGIP_CHECK(!op->global_w || s.kind == DOGIP_WP, DOGIP_E_RANGE,
+              "DOGIP_OP_GLOBAL_W needs a weighted-projection space");
   if (variant == DOGIP_VARIANT_AUTO) variant = has_unrolled(s.dim, s.k, s.kind) ? DOGIP_VARIANT_UNROLLED : DOGIP_VARIANT_LOOPED;
   DOGIP_CHECK(variant == DOGIP_VARIANT_LOOPED || has_unrolled(s.dim, s.k, s.kind), DOGIP_E_RANGE,
               "no unrolled kernel for this (dim, k, kind)");
   op->variant = variant;
   // tile size: requested (default 4 waves), halved until the LDS arrays fit in 64 KB
-  int te = 64 * (tile_waves ? tile_waves : 4);
-  for (;;) {
-    op->plan = make_tiles(s, te);
-    if (op->plan.max_tile_dofs * 16 <= 65536 || te == 64) break;
-    te /= 2;
+  // (global form: with the tile's D values if they fit at some tile size, else
+  // read from device memory)
+  const int te0 = 64 * (tile_waves ? tile_waves : 4);
+  auto fit = [&](bool with_w) {
+    int te = te0;
+    for (;;) {
+      op->plan = make_tiles(s, te);
+      int64_t bytes = op->plan.max_tile_dofs * 16;
+      if (with_w) {
+        op->gplan = make_global_plan(s, op->plan);
+        bytes += (op->gplan.max_tile_w + 1) * 8;
+      }
+      if (bytes <= 65536) return true;
+      if (te == 64) return false;
+      te /= 2;
+    }
+  };
+  if (op->global_w) {
+    op->gw_staged = fit(true);
+    if (!op->gw_staged) {
+      DOGIP_CHECK(fit(false), DOGIP_E_RANGE, "tile dofs exceed the LDS budget");
+      op->gplan = make_global_plan(s, op->plan);
+    }
+  } else {
+    DOGIP_CHECK(fit(false), DOGIP_E_RANGE, "tile dofs exceed the LDS budget");
   }
-  DOGIP_CHECK(op->plan.max_tile_dofs * 16 <= 65536, DOGIP_E_RANGE, "tile dofs exceed the LDS budget");
   const TilePlan& p = op->plan;
   op->nch64 = d_chunks(s.wt, s.nsym, 2);
   op->nch32 = d_chunks(s.wt, s.nsym, 4);
-  const size_t ngrp = size_t(p.nel_pad / 64);
-  op->d64.alloc(ngrp * op->nch64 * 64 * 2 * sizeof(double));
-  HIPCHK(hipMemset(op->d64.p, 0, op->d64.bytes));
-  if (op->has32) {
-    op->d32.alloc(ngrp * op->nch32 * 64 * 4 * sizeof(float));
-    HIPCHK(hipMemset(op->d32.p, 0, op->d32.bytes));
+  if (op->global_w) {
+    const GlobalPlan& g = op->gplan;
+    upload(op->gw_rec, g.rec);
+    upload(op->gw_off, g.off);
+    upload(op->gw_inc_ptr, g.inc_ptr);
+    upload(op->gw_inc, g.inc);
+    op->dg64.alloc(size_t(g.nw) * sizeof(double));
+    if (op->has32) op->dg32.alloc(size_t(g.nw) * sizeof(float));
+  } else {
+    const size_t ngrp = size_t(p.nel_pad / 64);
+    op->d64.alloc(ngrp * op->nch64 * 64 * 2 * sizeof(double));
+    HIPCHK(hipMemset(op->d64.p, 0, op->d64.bytes));
+    if (op->has32) {
+      op->d32.alloc(ngrp * op->nch32 * 64 * 4 * sizeof(float));
+      HIPCHK(hipMemset(op->d32.p, 0, op->d32.bytes));
+    }
   }
   upload(op->lidx, p.lidx);
   upload(op->tile_off, p.tile_off);
@@ -178,6 +215,12 @@ static ApplyLaunch apply_args(const Op& op, int prec) {
   a.tile_base = 0;
   a.stage_off = op.stage_off.as<int64_t>();
   a.stage = op.stage.as<double>();
+  if (op.global_w) {
+    a.D = prec == DOGIP_F64 ? op.dg64.p : op.dg32.p;
+    a.gw_rec = op.gw_rec.as<uint32_t>();
+    a.gw_off = op.gw_off.as<int64_t>();
+    a.lds_w = op.gw_staged ? int(op.gplan.max_tile_w + 1) : 0;
+  }
   return a;
 }
 
@@ -197,8 +240,9 @@ void op_apply(Op& op, const double* u, double* y, int prec, hipStream_t st, doub
     op.timer->ev.push_back(ev);
     HIPCHK(hipEventRecord(ev[0], st));
   }
-  DOGIP_CHECK(launch_apply(s.dim, s.k, s.kind, prec, op.variant, a, st), DOGIP_E_RANGE,
-              "no apply kernel for this (dim, k, kind, variant)");
+  const bool ok = op.global_w ? launch_apply_global(s.dim, s.k, prec, op.variant, a, st)
+                              : launch_apply(s.dim, s.k, s.kind, prec, op.variant, a, st);
+  DOGIP_CHECK(ok, DOGIP_E_RANGE, "no apply kernel for this (dim, k, kind, variant)");
   if (op.timer->on) HIPCHK(hipEventRecord(ev[1], st));
   launch_apply_finish(op.stage.as<double>(), op.sh_rowptr.as<uint32_t>(), op.sh_slots.as<uint32_t>(),
                       op.shared.as<int32_t>(), int64_t(op.plan.shared.size()), op.bnd.as<int32_t>(),
@@ -223,13 +267,21 @@ void op_diag(Op& op, double* diag, hipStream_t st) {
   a.nlc = op.plan.nlc;
   a.te = op.plan.te;
   a.lds_slots = int(op.plan.max_tile_dofs);
-  launch_diag(s.dim, s.k, s.kind, a, st);
+  if (op.global_w) {
+    a.D = op.dg64.as<double>();
+    a.gw_rec = op.gw_rec.as<uint32_t>();
+    a.gw_off = op.gw_off.as<int64_t>();
+    launch_diag_global(s.dim, s.k, a, st);
+  } else {
+    launch_diag(s.dim, s.k, s.kind, a, st);
+  }
   HIPCHK(hipGetLastError());
 }
 
 void op_grad(Op& op, const double* u, const double* lam, double* g, hipStream_t st) {
   const Space& s = *op.space;
   DOGIP_CHECK(u && lam && g, DOGIP_E_NULL, "null vector");
+  DOGIP_CHECK(!op.global_w, DOGIP_E_STATE, "the gradient contraction needs the element-wise D");
   GradLaunch a{};
   a.D = op.d64.as<double>();
   a.lidx = op.lidx.as<uint16_t>();
@@ -252,6 +304,7 @@ void op_grad(Op& op, const double* u, const double* lam, double* g, hipStream_t 
 void op_export_d(Op& op, double* out, hipStream_t st) {
   const Space& s = *op.space;
   DOGIP_CHECK(out != nullptr, DOGIP_E_NULL, "null output");
+  DOGIP_CHECK(!op.global_w, DOGIP_E_STATE, "a global-form operator holds no per-cell D");
   launch_export_d(op.d64.as<double>(), op.perm.as<int32_t>(), out, s.nc, op.nch64, s.wt, s.nsym, st);
   HIPCHK(hipGetLastError());
 }
@@ -266,11 +319,15 @@ dogip_op_info op_info(const Op& op) {
   i.tile_dofs_total = int64_t(op.plan.tile_dofs.size());
   i.nshared = int64_t(op.plan.shared.size());
   i.max_tile_dofs = op.plan.max_tile_dofs;
-  i.bytes_d64 = int64_t(op.d64.bytes);
-  i.bytes_d32 = int64_t(op.d32.bytes);
+  i.bytes_d64 = int64_t(op.d64.bytes + op.dg64.bytes);
+  i.bytes_d32 = int64_t(op.d32.bytes + op.dg32.bytes);
   i.bytes_index = int64_t(op.lidx.bytes + op.tile_off.bytes + op.tile_dofs.bytes + op.shared.bytes +
-                          op.stage_off.bytes + op.sh_rowptr.bytes + op.sh_slots.bytes + op.stage.bytes);
-  const double nd = double(s.wt) * s.nsym * s.nc, conn = 4.0 * s.vt * s.nc, vec = 2.0 * 8.0 * s.ndofs;
+                          op.stage_off.bytes + op.sh_rowptr.bytes + op.sh_slots.bytes + op.stage.bytes +
+                          op.gw_rec.bytes + op.gw_off.bytes + op.gw_inc_ptr.bytes + op.gw_inc.bytes);
+  i.ndofs_w = op.global_w ? op.gplan.nw : 0;
+  // D values read per apply: one per cell and W node, or one per global W dof
+  const double nd = op.global_w ? double(op.gplan.nw) : double(s.wt) * s.nsym * s.nc;
+  const double conn = 4.0 * s.vt * s.nc, vec = 2.0 * 8.0 * s.ndofs;
   i.alg_bytes_f64 = 8.0 * nd + conn + vec;
   i.alg_bytes_f32 = 4.0 * nd + conn + vec;
   // multiplications per cell as counted in eq. comp_eff, two flops each

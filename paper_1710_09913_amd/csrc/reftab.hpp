@@ -105,6 +105,30 @@ constexpr void bary_index(int d, int p, int t, int* b) {
   b[0] = p - s;
 }
 
+// Sub-simplex of the reference cell whose relative interior holds lattice node t of
+// P_p, as a bit index: 2D vertices 0-2, edges 3-5, interior 6; 3D vertices 0-3,
+// edges 4-9, faces 10-13 (face j opposite vertex j), interior 14.  Edges (a, b),
+// a < b, are numbered lexicographically.
+constexpr int node_entity(int d, int p, int t) {
+  int b[4] = {0, 0, 0, 0};
+  bary_index(d, p, t, b);
+  int sup[4] = {0, 0, 0, 0}, ns = 0, opp = 0;
+  for (int j = 0; j <= d; ++j) {
+    if (b[j] > 0)
+      sup[ns++] = j;
+    else
+      opp = j;
+  }
+  if (ns == 1) return sup[0];
+  if (ns == 2) {
+    int idx = 0;
+    for (int i = 0; i < sup[0]; ++i) idx += d - i;
+    return d + 1 + idx + (sup[1] - sup[0] - 1);
+  }
+  if (ns == 3 && d == 3) return 10 + opp;
+  return d == 2 ? 6 : 14;
+}
+
 // Barycentric coordinates (exact) of W node i for double-grid order q.
 constexpr void w_node_bary(int d, int q, int i, Q* lam) {
   if (q == 0) {

@@ -488,4 +488,69 @@ TilePlan make_tiles(const Space& s, int te) {
   return p;
 }
 
+// ---------------------------------------------------------------- global projection form
+
+GlobalPlan make_global_plan(const Space& s, const TilePlan& p) {
+  const Mesh& m = *s.mesh;
+  const int d = s.dim, q = 2 * s.k;
+  DOGIP_CHECK(s.kind == DOGIP_WP, DOGIP_E_RANGE, "the global form is defined for the weighted projection");
+  const LatticeDofs W = number_lattice(m, q, false);
+  const int wt = W.nl;
+  DOGIP_CHECK(wt == s.wt, DOGIP_E_INVALID, "W node count mismatch");
+  std::vector<int> ent(wt);
+  for (int i = 0; i < wt; ++i) ent[i] = ref::node_entity(d, q, i);
+  GlobalPlan g;
+  g.nw = W.ndofs;
+  // owner: the first cell in tile order holding the W dof
+  std::vector<int64_t> owner(g.nw, -1);
+  for (int64_t e = 0; e < s.nc; ++e) {
+    const int32_t* wd = &W.cell_dofs[int64_t(p.perm[e]) * wt];
+    for (int i = 0; i < wt; ++i)
+      if (owner[wd[i]] < 0) owner[wd[i]] = e;
+  }
+  for (int64_t j = 0; j < g.nw; ++j) DOGIP_CHECK(owner[j] >= 0, DOGIP_E_INVALID, "W dof held by no cell");
+  // tile ranges: each cell's owned values in local node order
+  std::vector<int64_t> pos(g.nw, -1);
+  g.rec.assign(p.nel_pad, 0u);
+  g.off.assign(p.ntiles + 1, 0);
+  int64_t count = 0;
+  for (int64_t t = 0; t < p.ntiles; ++t) {
+    g.off[t] = count;
+    const int64_t e0 = t * p.te, e1 = std::min<int64_t>(s.nc, e0 + p.te);
+    for (int64_t e = e0; e < e1; ++e) {
+      const int32_t* wd = &W.cell_dofs[int64_t(p.perm[e]) * wt];
+      const int64_t off = count - g.off[t];
+      DOGIP_CHECK(off < (int64_t(1) << (32 - GW_SHIFT)), DOGIP_E_RANGE, "tile too large for the global form");
+      uint32_t mask = 0;
+      for (int i = 0; i < wt; ++i)
+        if (owner[wd[i]] == e) {
+          mask |= 1u << ent[i];
+          pos[wd[i]] = count++;
+        }
+      // all nodes of an owned sub-simplex belong to this cell and no other node does
+      for (int i = 0; i < wt; ++i)
+        DOGIP_CHECK(((mask >> ent[i]) & 1u) == (owner[wd[i]] == e ? 1u : 0u), DOGIP_E_INVALID,
+                    "W dof ownership does not follow sub-simplices");
+      g.rec[e] = mask | uint32_t(off) << GW_SHIFT;
+    }
+    g.max_tile_w = std::max(g.max_tile_w, count - g.off[t]);
+  }
+  g.off[p.ntiles] = count;
+  DOGIP_CHECK(count == g.nw, DOGIP_E_INVALID, "W dofs not all owned");
+  // incidence lists by position: (internal cell, local node), ascending cell
+  g.inc_ptr.assign(g.nw + 1, 0);
+  for (int64_t e = 0; e < s.nc; ++e) {
+    const int32_t* wd = &W.cell_dofs[int64_t(p.perm[e]) * wt];
+    for (int i = 0; i < wt; ++i) g.inc_ptr[pos[wd[i]] + 1]++;
+  }
+  for (int64_t j = 0; j < g.nw; ++j) g.inc_ptr[j + 1] += g.inc_ptr[j];
+  g.inc.assign(g.inc_ptr[g.nw], 0);
+  std::vector<int64_t> fill(g.inc_ptr.begin(), g.inc_ptr.end() - 1);
+  for (int64_t e = 0; e < s.nc; ++e) {
+    const int32_t* wd = &W.cell_dofs[int64_t(p.perm[e]) * wt];
+    for (int i = 0; i < wt; ++i) g.inc[fill[pos[wd[i]]]++] = e * wt + i;
+  }
+  return g;
+}
+
 }  // namespace dogip

@@ -127,7 +127,9 @@ class Operator:
     """dogip_op: D on the device plus tiles and the Jacobi diagonal."""
 
     def __init__(self, space: Space, coef, coef_kind: str = "scalar", fp32: bool = True, tile_waves: int = 0,
-                 variant: int = 0, stream=None):
+                 variant: int = 0, stream=None, global_w: bool = False):
+        """global_w: the global projection form (Theorem 1), one D value per dof of
+        C_{N,2k} instead of one per cell and node (projection spaces only)."""
         import torch
 
         self.space = space
@@ -135,7 +137,7 @@ class Operator:
         coef = coef.to(device="cuda", dtype=torch.float64).contiguous()
         self._check_coef(coef, coef_kind)
         h = C.c_void_p()
-        flags = capi.DOGIP_OP_FP32 if fp32 else 0
+        flags = (capi.DOGIP_OP_FP32 if fp32 else 0) | (capi.DOGIP_OP_GLOBAL_W if global_w else 0)
         check(lib().dogip_op_create(space.h, COEF[coef_kind], _dev_ptr(coef), flags, tile_waves, variant,
                                     stream_ptr(stream), C.byref(h)))
         self.h = h

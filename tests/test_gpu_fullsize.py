@@ -22,13 +22,15 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-# (id, dim, n, k, kind): the 3D headline operator and the largest 2D sweep operators
-FULL = [("3d64_p3_se", 3, 64, 3, "se"), ("2d512_p5_se", 2, 512, 5, "se"), ("2d512_p5_wp", 2, 512, 5, "wp")]
+# (id, dim, n, k, kind, global form): the 3D headline operator, the largest 2D sweep
+# operators and the global projection form (Theorem 1 gives the same rows as Theorem 2)
+FULL = [("3d64_p3_se", 3, 64, 3, "se", False), ("2d512_p5_se", 2, 512, 5, "se", False),
+        ("2d512_p5_wp", 2, 512, 5, "wp", False), ("2d512_p2_wp_global", 2, 512, 2, "wp", True)]
 NSAMPLE = 160
 
 
 class FullCase:
-    def __init__(self, d, n, k, kind, seed=0):
+    def __init__(self, d, n, k, kind, seed=0, global_w=False):
         from paper_1710_09913_amd import Mesh, Operator, Space
 
         self.d, self.k, self.kind = d, k, kind
@@ -43,7 +45,7 @@ class FullCase:
         self.coef_kind = ck
         self.dirichlet = kind == "se"
         self.space = Space(Mesh.unit(d, n), k, kind, "dirichlet" if self.dirichlet else "none")
-        self.op = Operator(self.space, torch.from_numpy(self.coef), ck, fp32=True)
+        self.op = Operator(self.space, torch.from_numpy(self.coef), ck, fp32=True, global_w=global_w)
         self.u = random_vector(self.space.ndofs, seed)
         self.ug = torch.from_numpy(self.u).cuda()
         self.cd = self.space.cell_dofs()
@@ -77,9 +79,9 @@ class FullCase:
 
 @pytest.fixture(scope="module", params=FULL, ids=[f[0] for f in FULL])
 def full(request):
-    _, d, n, k, kind = request.param
-    print(f"[full] dim={d} n={n} k={k} kind={kind}", flush=True)
-    c = FullCase(d, n, k, kind)
+    _, d, n, k, kind, gw = request.param
+    print(f"[full] dim={d} n={n} k={k} kind={kind} global={gw}", flush=True)
+    c = FullCase(d, n, k, kind, global_w=gw)
     yield c
     del c.op
     torch.cuda.empty_cache()
