@@ -90,19 +90,21 @@ struct TilePlan {
 inline int64_t d_chunks(int wt, int nsym, int vec) { return (int64_t(wt) * nsym + vec - 1) / vec; }
 
 // Global projection form (Theorem 1): one D value per global W dof (C_{N,2k}).  Each
-// W dof is owned by one cell (the first in tile order holding it); a tile stores
-// the D values of the W dofs its cells own, cell after cell, each cell's in its
-// local node order.  Per cell, rec = (mask of owned sub-simplices) | offset << GW_SHIFT,
-// the offset of its first owned value within the tile's range.
-constexpr uint32_t GW_SHIFT = 15;
-constexpr uint32_t GW_MASK = (1u << GW_SHIFT) - 1u;
+// W dof is owned by one cell, the first in tile order holding it.  The W nodes inside
+// one sub-simplex of a cell share their cells, hence their owner, so what a cell owns
+// is a mask over its sub-simplex slots (ref::node_entity).  D is stored per wave of 64
+// cells: for each slot s in order, for each node j of the slot (lattice order), the
+// values of the lanes owning s, in lane order.  A lane finds node j of slot s at
+// base_s + j * count_s + rank_s, with count_s and rank_s from a wave ballot of its
+// ownership bit and base_s the running sum of (nodes of slot) * count over the slots
+// before s.  Every owned value is read once per apply, by coalesced loads.
+constexpr int gw_slots(int d) { return d == 2 ? 7 : 15; }
 struct GlobalPlan {
   int64_t nw = 0;                  // global W dofs
-  std::vector<uint32_t> rec;       // [nel_pad] per cell (internal order)
-  std::vector<int64_t> off;        // [ntiles+1] tile ranges of owned D values
-  std::vector<int64_t> inc_ptr;    // [nw+1] cells holding each owned W dof (by position)
+  std::vector<uint32_t> mask;      // [nel_pad] owned slots per cell (internal order)
+  std::vector<int64_t> woff;       // [nel_pad/64 + 1] wave ranges of D
+  std::vector<int64_t> inc_ptr;    // [nw+1] cells holding each W dof (by position)
   std::vector<int64_t> inc;        // internal cell * W_T + local node, ascending
-  int64_t max_tile_w = 0;
 };
 GlobalPlan make_global_plan(const Space& s, const TilePlan& p);
 
@@ -118,7 +120,6 @@ struct Op {
   DevBuf d64, d32, lidx, tile_off, tile_dofs, shared, perm, cells, xyz, what, bhat64, bhat32, invdiag;
   DevBuf stage_off, sh_rowptr, sh_slots, stage, bnd;  // second pass: shared dofs, Dirichlet rows
   bool global_w = false;                               // global projection form
-  bool gw_staged = false;                              // its tile D ranges fit in LDS
   GlobalPlan gplan;
   DevBuf gw_rec, gw_off, gw_inc_ptr, gw_inc, dg64, dg32;
   std::unique_ptr<PcgWork> pcg;
@@ -178,9 +179,8 @@ struct ApplyLaunch {
   int te;
   int lds_slots;         // LDS slots per tile (>= max tile dofs)
   int tile_base;         // first tile of this launch (batch uses 0)
-  const uint32_t* gw_rec;  // global projection form: per-cell records (else null)
-  const int64_t* gw_off;   // [ntiles+1] tile ranges of D (D then holds one value per W dof)
-  int lds_w;               // LDS entries for the tile's D values (>= max owned per tile + 1), 0: not staged
+  const uint32_t* gw_mask;  // global projection form: owned slots per cell (else null)
+  const int64_t* gw_woff;   // [waves+1] wave ranges of D (D then holds one value per W dof)
 };
 
 bool launch_apply(int dim, int k, int kind, int prec, int variant, const ApplyLaunch& a, hipStream_t st);
@@ -196,8 +196,8 @@ struct DiagLaunch {
   double* out;
   int64_t nel, ntiles, nch;
   int nlc, te, lds_slots;
-  const uint32_t* gw_rec;  // global projection form (D one value per W dof), else null
-  const int64_t* gw_off;
+  const uint32_t* gw_mask;  // global projection form (D one value per W dof), else null
+  const int64_t* gw_woff;
 };
 void launch_diag(int dim, int k, int kind, const DiagLaunch& a, hipStream_t st);
 void launch_diag_global(int dim, int k, const DiagLaunch& a, hipStream_t st);

@@ -76,15 +76,13 @@ __device__ __forceinline__ void flush_batch(const uint32_t (&e)[GB], int64_t nd,
 // When the tile has at most GB * blockDim entries (the usual case) the entries
 // loaded by the gather stay in registers for the flush.  energy_out: where the
 // tile's sum_T u_T^T A_T u_T goes (ENERGY only).  GW: global projection form, D holds
-// one value per W dof, read from the tile's range staged in LDS after u (GW == 1) or
-// straight from device memory when the tile's range does not fit (GW == 2).
-template <int D, int K, int KIND, typename T, int VARIANT, bool ENERGY, int PF, int GW = 0>
+// one value per W dof in the per-wave layout of GlobalPlan.
+template <int D, int K, int KIND, typename T, int VARIANT, bool ENERGY, int PF, bool GW = false>
 __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsigned char* smem, double* energy_out) {
   using E = Elem<D, K, KIND, T, T, VARIANT, false, PF>;
   constexpr int VT = E::VT;
   double* ys = reinterpret_cast<double*>(smem);
   T* us = reinterpret_cast<T*>(ys + a.lds_slots);
-  T* dl = us + a.lds_slots;
   const int64_t o0 = a.tile_off[t], nd = a.tile_off[t + 1] - o0;
   const uint32_t* td = a.tile_dofs + o0;
   const bool one = nd <= int64_t(GB) * blockDim.x;
@@ -93,11 +91,6 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
     gather_batch<T>(td, nd, threadIdx.x, a.u, us, ys, ent);
   } else {
     for (int64_t j0 = threadIdx.x; j0 < nd; j0 += int64_t(GB) * blockDim.x) gather_batch<T>(td, nd, j0, a.u, us, ys, ent);
-  }
-  if constexpr (GW == 1) {
-    const int64_t w0 = a.gw_off[t], nw = a.gw_off[t + 1] - w0;
-    const T* dg = static_cast<const T*>(a.D) + w0;
-    for (int64_t j = threadIdx.x; j < nw; j += blockDim.x) dl[j] = __builtin_nontemporal_load(dg + j);
   }
   __syncthreads();
   int64_t e = t * a.te + threadIdx.x;
@@ -111,10 +104,8 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
     load_lidx<VT>(a.lidx, w, a.nlc, lane, li);
     T ue[VT], ye[VT];
     sfor<VT>([&](auto L) { ue[L] = us[li[L]]; });
-    if constexpr (GW == 1) {
-      ElemG<D, K, T, VARIANT>::run(dl, a.gw_rec[e], ue, ye);
-    } else if constexpr (GW == 2) {
-      ElemG<D, K, T, VARIANT>::run(static_cast<const T*>(a.D) + a.gw_off[t], a.gw_rec[e], ue, ye);
+    if constexpr (GW) {
+      ElemG<D, K, T, VARIANT>::run(static_cast<const T*>(a.D) + a.gw_woff[e >> 6], a.gw_mask[e], ue, ye);
     } else {
       const typename E::V* dp = reinterpret_cast<const typename E::V*>(a.D) + (w * a.nch) * 64 + lane;
       E::run(dp, ue, ye);
@@ -156,38 +147,29 @@ __global__ __launch_bounds__(512, DOGIP_WPE) void k_apply(ApplyLaunch a) {
   tile_body<D, K, KIND, T, VARIANT, ENERGY, PF>(a, t, smem, ENERGY ? a.energy + t : nullptr);
 }
 
-template <int D, int K, typename T, int VARIANT, bool ENERGY, int GW>
+template <int D, int K, typename T, int VARIANT, bool ENERGY>
 __global__ __launch_bounds__(512, DOGIP_WPE) void k_apply_g(ApplyLaunch a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t t = a.tile_base + xcd_tile(blockIdx.x, gridDim.x);
-  tile_body<D, K, KIND_WP, T, VARIANT, ENERGY, 0, GW>(a, t, smem, ENERGY ? a.energy + t : nullptr);
+  tile_body<D, K, KIND_WP, T, VARIANT, ENERGY, 0, true>(a, t, smem, ENERGY ? a.energy + t : nullptr);
 }
 
-template <int D, int K, typename T, int VARIANT, int GW>
+template <int D, int K, typename T, int VARIANT>
 void launch_apply_g_p(bool energy, const ApplyLaunch& a, hipStream_t st) {
   const dim3 grid(unsigned(a.ntiles)), block(unsigned(a.te));
-  const size_t lds = size_t(a.lds_slots) * (sizeof(double) + sizeof(T)) + size_t(GW == 1 ? a.lds_w : 0) * sizeof(T);
+  const size_t lds = size_t(a.lds_slots) * (sizeof(double) + sizeof(T));
   if (energy)
-    hipLaunchKernelGGL((k_apply_g<D, K, T, VARIANT, true, GW>), grid, block, lds, st, a);
+    hipLaunchKernelGGL((k_apply_g<D, K, T, VARIANT, true>), grid, block, lds, st, a);
   else
-    hipLaunchKernelGGL((k_apply_g<D, K, T, VARIANT, false, GW>), grid, block, lds, st, a);
+    hipLaunchKernelGGL((k_apply_g<D, K, T, VARIANT, false>), grid, block, lds, st, a);
 }
 
-// a.lds_w > 0: the tiles' D ranges are staged in LDS.
 template <int D, int K, int VARIANT>
 bool launch_apply_g_t(int prec, bool energy, const ApplyLaunch& a, hipStream_t st) {
-  const bool staged = a.lds_w > 0;
-  if (prec == DOGIP_F64) {
-    if (staged)
-      launch_apply_g_p<D, K, double, VARIANT, 1>(energy, a, st);
-    else
-      launch_apply_g_p<D, K, double, VARIANT, 2>(energy, a, st);
-  } else {
-    if (staged)
-      launch_apply_g_p<D, K, float, VARIANT, 1>(energy, a, st);
-    else
-      launch_apply_g_p<D, K, float, VARIANT, 2>(energy, a, st);
-  }
+  if (prec == DOGIP_F64)
+    launch_apply_g_p<D, K, double, VARIANT>(energy, a, st);
+  else
+    launch_apply_g_p<D, K, float, VARIANT>(energy, a, st);
   return true;
 }
 

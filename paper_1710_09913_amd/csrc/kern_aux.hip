@@ -240,7 +240,7 @@ __global__ __launch_bounds__(512) void k_diag(DiagLaunch a) {
 template <int D, int K>
 __global__ __launch_bounds__(512) void k_diag_g(DiagLaunch a) {
   using TB = ref::BTable<D, K, KIND_WP>;
-  constexpr int VT = TB::VT, WT = TB::WT;
+  constexpr int VT = TB::VT;
   extern __shared__ __align__(16) unsigned char smem[];
   double* ys = reinterpret_cast<double*>(smem);
   const int64_t t = blockIdx.x;
@@ -252,21 +252,27 @@ __global__ __launch_bounds__(512) void k_diag_g(DiagLaunch a) {
     const int lane = threadIdx.x & 63;
     int li[VT];
     load_lidx<VT>(a.lidx, e >> 6, a.nlc, lane, li);
-    const uint32_t rec = a.gw_rec[e], mask = rec & GW_MASK;
-    const double* dg = a.D + a.gw_off[t] + (rec >> GW_SHIFT);
+    const uint32_t mask = a.gw_mask[e];
+    const WaveSlots<D, K> ws(mask);
+    const double* dw = a.D + a.gw_woff[e >> 6];
     const double* bt = ctab<D, K, KIND_WP, double>.v;
-    const uint8_t* et = cent<D, K>.v;
     double ye[VT];
     sfor<VT>([&](auto L) { ye[L] = 0.0; });
-    int pos = 0;
-    for (int i = 0; i < WT; ++i) {
-      if (!((mask >> et[i]) & 1u)) continue;
-      const double dv = dg[pos++];
-      sfor<VT>([&](auto L) {
-        const double b = bt[i * VT + L];
-        ye[L] = fma(b * b, dv, ye[L]);
-      });
-    }
+    sfor<gw_slots(D)>([&](auto E) {
+      constexpr int ne = ref::entity_nodes(D, 2 * K, E);
+      if constexpr (ne > 0) {
+        if ((mask >> E) & 1u) {
+          for (int j = 0; j < ne; ++j) {
+            const int i = cslots<D, K>.node[cslots<D, K>.first[E] + j];
+            const double dv = dw[ws.base[E] + j * ws.cnt[E] + ws.rank[E]];
+            sfor<VT>([&](auto L) {
+              const double b = bt[i * VT + L];
+              ye[L] = fma(b * b, dv, ye[L]);
+            });
+          }
+        }
+      }
+    });
     sfor<VT>([&](auto L) { atomicAdd(&ys[li[L]], ye[L]); });
   }
   __syncthreads();

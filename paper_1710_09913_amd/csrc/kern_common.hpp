@@ -184,37 +184,66 @@ struct Elem {
   }
 };
 
-// Sub-simplex bit of every W node of the projection form (global variant), for the
-// looped body.
+// W nodes of the projection form grouped by sub-simplex slot (global variant, looped
+// body): nodes of slot s are node[first[s] .. first[s+1]) in lattice order.
 template <int D, int K>
-struct CEnt {
-  static constexpr int WT = dim_p(D, 2 * K);
-  uint8_t v[WT];
-  constexpr CEnt() : v{} {
-    for (int i = 0; i < WT; ++i) v[i] = uint8_t(ref::node_entity(D, 2 * K, i));
+struct CSlots {
+  static constexpr int WT = dim_p(D, 2 * K), NS = gw_slots(D);
+  int first[NS + 1];
+  uint8_t node[WT];
+  constexpr CSlots() : first{}, node{} {
+    int c = 0;
+    for (int e = 0; e < NS; ++e) {
+      first[e] = c;
+      for (int i = 0; i < WT; ++i)
+        if (ref::node_entity(D, 2 * K, i) == e) node[c++] = uint8_t(i);
+    }
+    first[NS] = c;
   }
 };
 template <int D, int K>
-__constant__ CEnt<D, K> cent{};
+__constant__ CSlots<D, K> cslots{};
 
-// Element body of the global projection form (Theorem 1).  The cell applies D only
-// at the W nodes it owns (sub-simplex mask in rec), reading the values from the
-// tile's LDS copy dl, where its owned values start at rec >> GW_SHIFT in local node
-// order; the other nodes are applied by the cells that own them.
+// Where this lane's values of each owned slot sit in the wave's D range (see
+// GlobalPlan): count, rank and base per slot from a ballot of the ownership bits.
+template <int D, int K>
+struct WaveSlots {
+  static constexpr int NS = gw_slots(D);
+  int cnt[NS], rank[NS], base[NS];
+  __device__ __forceinline__ explicit WaveSlots(uint32_t mask) {
+    int acc = 0;
+    const uint32_t lane = __lane_id();
+    sfor<NS>([&](auto E) {
+      constexpr int ne = ref::entity_nodes(D, 2 * K, E);
+      if constexpr (ne > 0) {
+        const uint64_t b = __ballot((mask >> E) & 1u);
+        cnt[E] = __popcll(b);
+        rank[E] = __popcll(b & ((uint64_t(1) << lane) - 1));
+        base[E] = acc;
+        acc += ne * cnt[E];
+      } else {
+        cnt[E] = rank[E] = base[E] = 0;
+      }
+    });
+  }
+};
+
+// Element body of the global projection form (Theorem 1).  The cell applies D only at
+// the W nodes of the sub-simplex slots it owns (mask); the other nodes are applied by
+// the cells that own them.  dw: the wave's D range.  Nodes are visited slot by slot.
 template <int D, int K, typename T, int VARIANT>
 struct ElemG {
   using TB = ref::BTable<D, K, KIND_WP>;
-  static constexpr int VT = TB::VT, WT = TB::WT;
+  static constexpr int VT = TB::VT, WT = TB::WT, NS = gw_slots(D);
 
-  __device__ __forceinline__ static void run(const T* __restrict__ dl, uint32_t rec, const T (&ue)[VT],
+  __device__ __forceinline__ static void run(const T* __restrict__ dw, uint32_t mask, const T (&ue)[VT],
                                              T (&ye)[VT]) {
-    const uint32_t mask = rec & GW_MASK;
-    int pos = int(rec >> GW_SHIFT);
+    const WaveSlots<D, K> ws(mask);
     sfor<VT>([&](auto L) { ye[L] = T(-0.0); });
     if constexpr (VARIANT == DOGIP_VARIANT_UNROLLED) {
       sfor<WT>([&](auto I) {
-        constexpr int ent = ref::node_entity(D, 2 * K, I);
-        const bool own = (mask >> ent) & 1u;
+        constexpr int e = ref::node_entity(D, 2 * K, I), j = ref::entity_rank(D, 2 * K, I);
+        const bool own = (mask >> e) & 1u;
         T acc = T(-0.0);
         sfor<VT>([&](auto L) {
           constexpr double b = CT<D, K, KIND_WP>::t.v[0][I][L];
@@ -225,8 +254,9 @@ struct ElemG {
           else if constexpr (b != 0.0)
             acc = fma_t(T(b), ue[L], acc);
         });
-        const T h = (own ? dl[pos] : T(0)) * acc;
-        pos += own ? 1 : 0;
+        T dv = T(0);
+        if (own) dv = __builtin_nontemporal_load(dw + ws.base[e] + j * ws.cnt[e] + ws.rank[e]);
+        const T h = dv * acc;
         sfor<VT>([&](auto L) {
           constexpr double b = CT<D, K, KIND_WP>::t.v[0][I][L];
           if constexpr (b == 1.0)
@@ -239,16 +269,23 @@ struct ElemG {
       });
     } else {
       const T* bt = ctab<D, K, KIND_WP, T>.v;
-      const uint8_t* et = cent<D, K>.v;
-      for (int i = 0; i < WT; ++i) {
-        const bool own = (mask >> et[i]) & 1u;
-        const T* br = bt + i * VT;
-        T acc = T(-0.0);
-        sfor<VT>([&](auto L) { acc = fma_t(br[L], ue[L], acc); });
-        const T h = (own ? dl[pos] : T(0)) * acc;
-        pos += own ? 1 : 0;
-        sfor<VT>([&](auto L) { ye[L] = fma_t(br[L], h, ye[L]); });
-      }
+      sfor<NS>([&](auto E) {
+        constexpr int ne = ref::entity_nodes(D, 2 * K, E);
+        if constexpr (ne > 0) {
+          const bool own = (mask >> E) & 1u;
+          const T* dp = dw + ws.base[E] + ws.rank[E];
+          for (int j = 0; j < ne; ++j) {
+            const int i = cslots<D, K>.node[cslots<D, K>.first[E] + j];
+            const T* br = bt + i * VT;
+            T acc = T(-0.0);
+            sfor<VT>([&](auto L) { acc = fma_t(br[L], ue[L], acc); });
+            T dv = T(0);
+            if (own) dv = __builtin_nontemporal_load(dp + j * ws.cnt[E]);
+            const T h = dv * acc;
+            sfor<VT>([&](auto L) { ye[L] = fma_t(br[L], h, ye[L]); });
+          }
+        }
+      });
     }
   }
 };

@@ -124,39 +124,21 @@ std::unique_ptr<Op> make_op(std::shared_ptr<const Space> sp, int coef_kind, cons
               "no unrolled kernel for this (dim, k, kind)");
   op->variant = variant;
   // tile size: requested (default 4 waves), halved until the LDS arrays fit in 64 KB
-  // (global form: with the tile's D values if they fit at some tile size, else
-  // read from device memory)
-  const int te0 = 64 * (tile_waves ? tile_waves : 4);
-  auto fit = [&](bool with_w) {
-    int te = te0;
-    for (;;) {
-      op->plan = make_tiles(s, te);
-      int64_t bytes = op->plan.max_tile_dofs * 16;
-      if (with_w) {
-        op->gplan = make_global_plan(s, op->plan);
-        bytes += (op->gplan.max_tile_w + 1) * 8;
-      }
-      if (bytes <= 65536) return true;
-      if (te == 64) return false;
-      te /= 2;
-    }
-  };
-  if (op->global_w) {
-    op->gw_staged = fit(true);
-    if (!op->gw_staged) {
-      DOGIP_CHECK(fit(false), DOGIP_E_RANGE, "tile dofs exceed the LDS budget");
-      op->gplan = make_global_plan(s, op->plan);
-    }
-  } else {
-    DOGIP_CHECK(fit(false), DOGIP_E_RANGE, "tile dofs exceed the LDS budget");
+  int te = 64 * (tile_waves ? tile_waves : 4);
+  for (;;) {
+    op->plan = make_tiles(s, te);
+    if (op->plan.max_tile_dofs * 16 <= 65536 || te == 64) break;
+    te /= 2;
   }
+  DOGIP_CHECK(op->plan.max_tile_dofs * 16 <= 65536, DOGIP_E_RANGE, "tile dofs exceed the LDS budget");
+  if (op->global_w) op->gplan = make_global_plan(s, op->plan);
   const TilePlan& p = op->plan;
   op->nch64 = d_chunks(s.wt, s.nsym, 2);
   op->nch32 = d_chunks(s.wt, s.nsym, 4);
   if (op->global_w) {
     const GlobalPlan& g = op->gplan;
-    upload(op->gw_rec, g.rec);
-    upload(op->gw_off, g.off);
+    upload(op->gw_rec, g.mask);
+    upload(op->gw_off, g.woff);
     upload(op->gw_inc_ptr, g.inc_ptr);
     upload(op->gw_inc, g.inc);
     op->dg64.alloc(size_t(g.nw) * sizeof(double));
@@ -217,9 +199,8 @@ static ApplyLaunch apply_args(const Op& op, int prec) {
   a.stage = op.stage.as<double>();
   if (op.global_w) {
     a.D = prec == DOGIP_F64 ? op.dg64.p : op.dg32.p;
-    a.gw_rec = op.gw_rec.as<uint32_t>();
-    a.gw_off = op.gw_off.as<int64_t>();
-    a.lds_w = op.gw_staged ? int(op.gplan.max_tile_w + 1) : 0;
+    a.gw_mask = op.gw_rec.as<uint32_t>();
+    a.gw_woff = op.gw_off.as<int64_t>();
   }
   return a;
 }
@@ -269,8 +250,8 @@ void op_diag(Op& op, double* diag, hipStream_t st) {
   a.lds_slots = int(op.plan.max_tile_dofs);
   if (op.global_w) {
     a.D = op.dg64.as<double>();
-    a.gw_rec = op.gw_rec.as<uint32_t>();
-    a.gw_off = op.gw_off.as<int64_t>();
+    a.gw_mask = op.gw_rec.as<uint32_t>();
+    a.gw_woff = op.gw_off.as<int64_t>();
     launch_diag_global(s.dim, s.k, a, st);
   } else {
     launch_diag(s.dim, s.k, s.kind, a, st);

@@ -129,6 +129,20 @@ constexpr int node_entity(int d, int p, int t) {
   return d == 2 ? 6 : 14;
 }
 
+// Number of lattice nodes of P_p inside sub-simplex slot e, and the rank of node t
+// among the nodes of its slot (lattice order).
+constexpr int entity_nodes(int d, int p, int e) {
+  int n = 0;
+  for (int t = 0; t < dim_p(d, p); ++t) n += node_entity(d, p, t) == e ? 1 : 0;
+  return n;
+}
+constexpr int entity_rank(int d, int p, int t) {
+  int r = 0;
+  const int e = node_entity(d, p, t);
+  for (int s = 0; s < t; ++s) r += node_entity(d, p, s) == e ? 1 : 0;
+  return r;
+}
+
 // Barycentric coordinates (exact) of W node i for double-grid order q.
 constexpr void w_node_bary(int d, int q, int i, Q* lam) {
   if (q == 0) {

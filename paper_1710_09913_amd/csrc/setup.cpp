@@ -509,33 +509,38 @@ GlobalPlan make_global_plan(const Space& s, const TilePlan& p) {
       if (owner[wd[i]] < 0) owner[wd[i]] = e;
   }
   for (int64_t j = 0; j < g.nw; ++j) DOGIP_CHECK(owner[j] >= 0, DOGIP_E_INVALID, "W dof held by no cell");
-  // tile ranges: each cell's owned values in local node order
-  std::vector<int64_t> pos(g.nw, -1);
-  g.rec.assign(p.nel_pad, 0u);
-  g.off.assign(p.ntiles + 1, 0);
-  int64_t count = 0;
-  for (int64_t t = 0; t < p.ntiles; ++t) {
-    g.off[t] = count;
-    const int64_t e0 = t * p.te, e1 = std::min<int64_t>(s.nc, e0 + p.te);
-    for (int64_t e = e0; e < e1; ++e) {
-      const int32_t* wd = &W.cell_dofs[int64_t(p.perm[e]) * wt];
-      const int64_t off = count - g.off[t];
-      DOGIP_CHECK(off < (int64_t(1) << (32 - GW_SHIFT)), DOGIP_E_RANGE, "tile too large for the global form");
-      uint32_t mask = 0;
-      for (int i = 0; i < wt; ++i)
-        if (owner[wd[i]] == e) {
-          mask |= 1u << ent[i];
-          pos[wd[i]] = count++;
-        }
-      // all nodes of an owned sub-simplex belong to this cell and no other node does
-      for (int i = 0; i < wt; ++i)
-        DOGIP_CHECK(((mask >> ent[i]) & 1u) == (owner[wd[i]] == e ? 1u : 0u), DOGIP_E_INVALID,
-                    "W dof ownership does not follow sub-simplices");
-      g.rec[e] = mask | uint32_t(off) << GW_SHIFT;
-    }
-    g.max_tile_w = std::max(g.max_tile_w, count - g.off[t]);
+  // per-cell slot masks (all nodes of an owned slot belong to the cell, no other node does)
+  const int nslot = gw_slots(d);
+  g.mask.assign(p.nel_pad, 0u);
+  for (int64_t e = 0; e < s.nc; ++e) {
+    const int32_t* wd = &W.cell_dofs[int64_t(p.perm[e]) * wt];
+    uint32_t mask = 0;
+    for (int i = 0; i < wt; ++i)
+      if (owner[wd[i]] == e) mask |= 1u << ent[i];
+    for (int i = 0; i < wt; ++i)
+      DOGIP_CHECK(((mask >> ent[i]) & 1u) == (owner[wd[i]] == e ? 1u : 0u), DOGIP_E_INVALID,
+                  "W dof ownership does not follow sub-simplices");
+    g.mask[e] = mask;
   }
-  g.off[p.ntiles] = count;
+  // nodes of each slot in lattice order
+  std::vector<std::vector<int>> slot_nodes(nslot);
+  for (int i = 0; i < wt; ++i) slot_nodes[ent[i]].push_back(i);
+  // wave layout: slot by slot, node by node, owning lanes in lane order
+  const int64_t nwave = p.nel_pad / 64;
+  std::vector<int64_t> pos(g.nw, -1);
+  g.woff.assign(nwave + 1, 0);
+  int64_t count = 0;
+  for (int64_t w = 0; w < nwave; ++w) {
+    g.woff[w] = count;
+    for (int sl = 0; sl < nslot; ++sl)
+      for (int i : slot_nodes[sl])
+        for (int lane = 0; lane < 64; ++lane) {
+          const int64_t e = w * 64 + lane;
+          if (e >= s.nc || !((g.mask[e] >> sl) & 1u)) continue;
+          pos[W.cell_dofs[int64_t(p.perm[e]) * wt + i]] = count++;
+        }
+  }
+  g.woff[nwave] = count;
   DOGIP_CHECK(count == g.nw, DOGIP_E_INVALID, "W dofs not all owned");
   // incidence lists by position: (internal cell, local node), ascending cell
   g.inc_ptr.assign(g.nw + 1, 0);
