@@ -336,6 +336,65 @@ def run_c5(a):
     return out
 
 
+def run_qp(a):
+    """DoGIP against the conventional quadrature-point apply (the comparison of Section 3.3)
+    on the 3D 64^3 P3 elliptic operator: the quadrature-point operator with the collapsed
+    Gauss rule of n = 2..6 points per direction (n = 4 is the lowest exact for a per-cell
+    constant coefficient, degree 2k-2 = 4; n = 6 integrates degree 3k = 9), beside the
+    DoGIP apply (W_T = 35 nodes).  The per-point samples repeat the cell's lognormal
+    value (the timing does not depend on the values)."""
+    import torch
+
+    from paper_1710_09913_amd import Mesh, Operator, Space
+    from workloads import random_vector
+
+    coef = torch.from_numpy(_lognormal(a.n, a.seed))
+    space = Space(Mesh.unit(3, a.n), a.k, "se", "dirichlet")
+    op = Operator(space, coef, "scalar", fp32=True)
+    coef = coef.cuda()
+    u = torch.from_numpy(random_vector(space.ndofs, a.seed)).cuda()
+    y = torch.empty_like(u)
+    rows = []
+
+    def timed(o, label, extra):
+        row = {"method": label, **extra}
+        for prec in ("f64", "f32"):
+            ms, tms, fms = time_apply(o, u, y, prec, a.steps, a.warmup)
+            kms = tms + fms
+            ab, fl = o.info["alg_bytes_" + prec], o.info["alg_flops"]
+            row[prec] = {"ms": round(ms, 5), "GDoF_s": round(space.ndofs / (ms * 1e-3) / 1e9, 3),
+                         "alg_GB": round(ab / 1e9, 4), "hbm_frac": round(ab / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "TFLOP_s": round(fl / (kms * 1e-3) / 1e12, 2)}
+        log(f"[qp] {row}")
+        rows.append(row)
+
+    timed(op, "dogip", {"points": space.info["wt"]})
+    d = 3
+    for n in (2, 3, 4, 5, 6):
+        nq = n ** d
+        samples = coef[:, None].expand(space.ncells, nq).contiguous()
+        q = Operator.quadrature(space, n, samples)
+        del samples
+        timed(q, "quadrature", {"points": nq, "per_dir": n, "exact_degree": 2 * n - d})
+        del q
+        torch.cuda.empty_cache()
+    dog = rows[0]["f64"]["ms"]
+    cross = [r for r in rows[1:] if r["f64"]["ms"] > dog]
+    out = _base("DoGIP vs quadrature-point apply, 3D 64^3 P3 elliptic: ms per FP64 apply", "ms", dog, dog, a,
+                {"workload": f"3D unit cube {a.n}^3 x 6 Kuhn tets, P{a.k} elliptic, collapsed Gauss n = 2..6"},
+                hib=False)
+    out["rows"] = rows
+    out["quadrature_slower_than_dogip_from_points"] = cross[0]["points"] if cross else None
+    return out
+
+
+def _lognormal(n, seed):
+    from workloads import coef_lognormal, unit_mesh
+
+    coords, cells = unit_mesh(3, n)
+    return coef_lognormal(coords, cells, seed)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -346,9 +405,10 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "c5"],
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "c5", "qp"],
                     help="c3: 3D 64^3 P3 (default, the headline); c2: 2D 512^2 P1..P5 sweep; "
-                         "c4: 2D 256^2 P3 adjoint gradient; c5: batch of 256 uneven 2D problems")
+                         "c4: 2D 256^2 P3 adjoint gradient; c5: batch of 256 uneven 2D problems; "
+                         "qp: DoGIP vs the quadrature-point apply on the 3D operator")
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the multi-GPU path (element partition with an interface-dof "
@@ -359,7 +419,7 @@ def main(argv=None):
 
     torch.cuda.set_device(0)
     if a.workload != "c3":
-        out = {"c2": run_c2, "c4": run_c4, "c5": run_c5}[a.workload](a)
+        out = {"c2": run_c2, "c4": run_c4, "c5": run_c5, "qp": run_qp}[a.workload](a)
         print(json.dumps(out), flush=True)
         return 0
     space, op, b = build_problem(a.n, a.k, a.seed)

@@ -124,7 +124,7 @@ typedef struct {
   int32_t tile_cells;  /* cells per tile (one workgroup) */
   int32_t variant;     /* DOGIP_VARIANT_UNROLLED or _LOOPED actually used */
   int32_t has_fp32;
-  int32_t pad0;
+  int32_t nq;          /* quadrature-point operator: points per cell; 0 for DoGIP */
   int64_t ntiles, tile_dofs_total, nshared, max_tile_dofs;
   int64_t bytes_d64, bytes_d32, bytes_index; /* device bytes held */
   double alg_bytes_f64; /* algorithmic bytes of one apply: D + int32 connectivity + u + y */
@@ -215,6 +215,27 @@ void dogip_space_destroy(dogip_space s);
  * cells holding W dof j (RAW_D: the cells' [ncells][wt] values are summed). */
 int dogip_op_create(dogip_space s, int coef_kind, const double* coef, unsigned flags, int tile_waves,
                     int variant, dogip_stream stream, dogip_op* out);
+/* ---- conventional quadrature-point operator (the comparison of Section 3.3) ----
+ * The matrix-free evaluation over integration points that the paper sets against
+ * DoGIP: per cell, the trial function's values (projection) or gradients (elliptic)
+ * are interpolated to the quadrature points, multiplied by w_q |det R_T| a(x_q)
+ * (elliptic: and R_T^-1 R_T^-T), and projected back.  Its cost grows with the number
+ * of points, DoGIP's with W_T.
+ *
+ * dogip_quadrature: the reference rule, host output pts [n^dim][dim], wts [n^dim]:
+ * the collapsed (Duffy) Gauss-Legendre rule with n points per direction, n = 1..16,
+ * ordered with s outermost (x1 = s, x2 = t (1-s), x3 = v (1-s)(1-t)), exact for total
+ * degree <= 2n - dim (so its weights sum to |T^| when 2n >= dim).
+ * dogip_op_create_qp: coef is a device array [ncells][n^dim] (mesh cell order) of the
+ * scalar coefficient at the mapped points x_q = X_0 + R_T xhat_q, read during the
+ * call.  flags: DOGIP_OP_FP32 or 0.  The operator supports dogip_apply, dogip_diag,
+ * dogip_pcg and the timer; dogip_op_set_coef, dogip_op_export_d and
+ * dogip_grad_logcoef return DOGIP_E_STATE.  Orders: 2D k <= 5, 3D k <= 3
+ * (projection) or 4 (elliptic), else DOGIP_E_RANGE.  Synchronizes the stream. */
+int dogip_quadrature(int dim, int n, double* pts, double* wts);
+int dogip_op_create_qp(dogip_space s, int n, const double* coef, unsigned flags, int tile_waves,
+                       dogip_stream stream, dogip_op* out);
+
 /* Rebuild D (and the FP32 copy and the Jacobi diagonal) from a new coefficient.  async. */
 int dogip_op_set_coef(dogip_op op, int coef_kind, const double* coef, dogip_stream stream);
 int dogip_op_get_info(dogip_op op, dogip_op_info* info);

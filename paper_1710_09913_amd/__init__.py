@@ -6,6 +6,6 @@ handles that take device memory and streams from torch.
 """
 
 from .capi import DogipError, lib  # noqa: F401
-from .dogip import Batch, Mesh, Operator, Space, stream_ptr  # noqa: F401
+from .dogip import Batch, Mesh, Operator, Space, quadrature_rule, stream_ptr  # noqa: F401
 
-__all__ = ["Mesh", "Space", "Operator", "Batch", "DogipError", "lib", "stream_ptr"]
+__all__ = ["Mesh", "Space", "Operator", "Batch", "DogipError", "lib", "stream_ptr", "quadrature_rule"]

@@ -52,7 +52,7 @@ class SpaceInfo(C.Structure):
 
 
 class OpInfo(C.Structure):
-    _fields_ = [("tile_cells", C.c_int32), ("variant", C.c_int32), ("has_fp32", C.c_int32), ("pad0", C.c_int32),
+    _fields_ = [("tile_cells", C.c_int32), ("variant", C.c_int32), ("has_fp32", C.c_int32), ("nq", C.c_int32),
                 ("ntiles", C.c_int64), ("tile_dofs_total", C.c_int64), ("nshared", C.c_int64),
                 ("max_tile_dofs", C.c_int64), ("bytes_d64", C.c_int64), ("bytes_d32", C.c_int64),
                 ("bytes_index", C.c_int64), ("alg_bytes_f64", C.c_double), ("alg_bytes_f32", C.c_double),
@@ -92,6 +92,8 @@ SIGNATURES = {
     "dogip_space_bhat": (C.c_int, [H, P, P]),
     "dogip_space_destroy": (None, [H]),
     "dogip_op_create": (C.c_int, [H, C.c_int, P, C.c_uint, C.c_int, C.c_int, P, PH]),
+    "dogip_quadrature": (C.c_int, [C.c_int, C.c_int, P, P]),
+    "dogip_op_create_qp": (C.c_int, [H, C.c_int, P, C.c_uint, C.c_int, P, PH]),
     "dogip_op_set_coef": (C.c_int, [H, C.c_int, P, P]),
     "dogip_op_get_info": (C.c_int, [H, C.POINTER(OpInfo)]),
     "dogip_op_export_d": (C.c_int, [H, P, P]),

@@ -53,7 +53,7 @@ std::unique_ptr<Batch> make_batch(const std::vector<std::shared_ptr<Op>>& ops, h
     DOGIP_CHECK(s.dim == b->dim && s.kind == b->kind, DOGIP_E_INVALID, "batch problems must share dim and kind");
     DOGIP_CHECK(s.k >= 1 && s.k <= 4, DOGIP_E_RANGE, "batched launches cover k = 1..4");
     DOGIP_CHECK(op.variant == DOGIP_VARIANT_UNROLLED, DOGIP_E_INVALID, "batch operators must use the unrolled kernels");
-    DOGIP_CHECK(!op.global_w, DOGIP_E_INVALID, "batch operators must use the element-wise D");
+    DOGIP_CHECK(!op.global_w && op.nq == 0, DOGIP_E_INVALID, "batch operators must use the element-wise D");
     DOGIP_CHECK(op.plan.te <= 256, DOGIP_E_RANGE, "batch tiles must have at most 256 cells");
     all32 = all32 && op.has32;
     BatchDesc& d = desc[p];

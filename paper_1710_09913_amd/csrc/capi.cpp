@@ -1,4 +1,5 @@
 // C interface of libdogip: opaque handles, status codes, thread-local error text.
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -220,6 +221,30 @@ int dogip_op_create(dogip_space s, int coef_kind, const double* coef, unsigned f
     need(out);
     *out = nullptr;
     auto op = dogip::make_op(s->s, coef_kind, coef, flags, tile_waves, variant, S(stream));
+    *out = new dogip_op_s{std::shared_ptr<dogip::Op>(std::move(op))};
+    return DOGIP_OK;
+  });
+}
+
+int dogip_quadrature(int dim, int n, double* pts, double* wts) {
+  return guard([&] {
+    need(pts);
+    need(wts);
+    std::vector<double> p, w;
+    dogip::collapsed_rule(dim, n, p, w);
+    std::copy(p.begin(), p.end(), pts);
+    std::copy(w.begin(), w.end(), wts);
+    return DOGIP_OK;
+  });
+}
+
+int dogip_op_create_qp(dogip_space s, int n, const double* coef, unsigned flags, int tile_waves, dogip_stream stream,
+                       dogip_op* out) {
+  return guard([&] {
+    need(s);
+    need(out);
+    *out = nullptr;
+    auto op = dogip::make_op_qp(s->s, n, coef, flags, tile_waves, S(stream));
     *out = new dogip_op_s{std::shared_ptr<dogip::Op>(std::move(op))};
     return DOGIP_OK;
   });

@@ -121,6 +121,8 @@ struct Op {
   DevBuf stage_off, sh_rowptr, sh_slots, stage, bnd;  // second pass: shared dofs, Dirichlet rows
   bool global_w = false;                               // global projection form
   GlobalPlan gplan;
+  int nq = 0;                                          // quadrature-point operator: points per cell
+  DevBuf qtab64, qtab32, qs64, qs32, qk64, qk32, qw;
   DevBuf gw_rec, gw_off, gw_inc_ptr, gw_inc, dg64, dg32;
   std::unique_ptr<PcgWork> pcg;
   std::unique_ptr<OpTimer> timer;
@@ -136,6 +138,13 @@ struct LatticeDofs {
   std::vector<uint8_t> is_bnd;     // [ndofs] on a boundary facet (when asked for)
 };
 LatticeDofs number_lattice(const Mesh& m, int q, bool xyz);
+
+// Conventional quadrature-point apply: the collapsed (Duffy) Gauss-Legendre rule on the
+// reference simplex with n points per direction (s outermost: x1 = s, x2 = t (1-s),
+// x3 = v (1-s)(1-t)), exact for total degree <= 2n - d; and the V basis values (projection) or
+// reference gradients (elliptic) at the points, [nq][nb][vt].
+void collapsed_rule(int d, int n, std::vector<double>& pts, std::vector<double>& wts);
+void basis_table(int d, int k, int kind, const std::vector<double>& pts, std::vector<double>& tab);
 
 // ---- host setup ----
 std::shared_ptr<Mesh> make_mesh(int dim, int64_t nv, const double* xyz, int64_t nc, const int32_t* cells);
@@ -181,6 +190,12 @@ struct ApplyLaunch {
   int tile_base;         // first tile of this launch (batch uses 0)
   const uint32_t* gw_mask;  // global projection form: owned slots per cell (else null)
   const int64_t* gw_woff;   // [waves+1] wave ranges of D (D then holds one value per W dof)
+  // quadrature-point operator: basis table [nq][nb][vt], per-point factors
+  // w_q |det R_T| a(x_q) AoSoA [(e/64)][nq][64], per-cell R^-1 R^-T packed AoSoA [(e/64)][s][64]
+  const void* qtab;
+  const void* qs;
+  const void* qk;
+  int nq;
 };
 
 bool launch_apply(int dim, int k, int kind, int prec, int variant, const ApplyLaunch& a, hipStream_t st);
@@ -201,6 +216,26 @@ struct DiagLaunch {
 };
 void launch_diag(int dim, int k, int kind, const DiagLaunch& a, hipStream_t st);
 void launch_diag_global(int dim, int k, const DiagLaunch& a, hipStream_t st);
+
+// Quadrature-point operator: per-point factors and per-cell geometry from the samples.
+struct QpSetupLaunch {
+  const double* xyz;
+  const int32_t* cells;  // internal order
+  const int32_t* perm;
+  const double* coef;    // [ncells][nq] samples a(x_q), mesh order
+  const double* w;       // [nq] reference weights
+  double* qs64;
+  float* qs32;           // may be null
+  double* qk64;          // elliptic only
+  float* qk32;
+  int64_t nel;
+  int nq, dim, kind;
+};
+void launch_qp_setup(const QpSetupLaunch& a, hipStream_t st);
+bool launch_apply_qp(int dim, int k, int kind, int prec, const ApplyLaunch& a, hipStream_t st);
+void launch_diag_qp(int dim, int k, int kind, const ApplyLaunch& a, double* out, hipStream_t st);
+std::unique_ptr<Op> make_op_qp(std::shared_ptr<const Space> s, int n, const double* coef, unsigned flags,
+                               int tile_waves, hipStream_t st);
 
 struct GradLaunch {
   const double* D;

@@ -75,12 +75,13 @@ __device__ __forceinline__ void flush_batch(const uint32_t (&e)[GB], int64_t nd,
 // stored in T); the per-tile accumulation in LDS is always FP64 (ds_add_f64).
 // When the tile has at most GB * blockDim entries (the usual case) the entries
 // loaded by the gather stay in registers for the flush.  energy_out: where the
-// tile's sum_T u_T^T A_T u_T goes (ENERGY only).  GW: global projection form, D holds
-// one value per W dof in the per-wave layout of GlobalPlan.
-template <int D, int K, int KIND, typename T, int VARIANT, bool ENERGY, int PF, bool GW = false>
+// tile's sum_T u_T^T A_T u_T goes (ENERGY only).  MODE 1: global projection form, D
+// holds one value per W dof in the per-wave layout of GlobalPlan; MODE 2: the
+// conventional quadrature-point apply (ElemQ).
+template <int D, int K, int KIND, typename T, int VARIANT, bool ENERGY, int PF, int MODE = 0>
 __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsigned char* smem, double* energy_out) {
   using E = Elem<D, K, KIND, T, T, VARIANT, false, PF>;
-  constexpr int VT = E::VT;
+  constexpr int VT = dim_p(D, K);
   double* ys = reinterpret_cast<double*>(smem);
   T* us = reinterpret_cast<T*>(ys + a.lds_slots);
   const int64_t o0 = a.tile_off[t], nd = a.tile_off[t + 1] - o0;
@@ -104,8 +105,10 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
     load_lidx<VT>(a.lidx, w, a.nlc, lane, li);
     T ue[VT], ye[VT];
     sfor<VT>([&](auto L) { ue[L] = us[li[L]]; });
-    if constexpr (GW) {
+    if constexpr (MODE == 1) {
       ElemG<D, K, T, VARIANT>::run(static_cast<const T*>(a.D) + a.gw_woff[e >> 6], a.gw_mask[e], ue, ye);
+    } else if constexpr (MODE == 2) {
+      ElemQ<D, K, KIND, T>::run(a, w, lane, ue, ye);
     } else {
       const typename E::V* dp = reinterpret_cast<const typename E::V*>(a.D) + (w * a.nch) * 64 + lane;
       E::run(dp, ue, ye);
@@ -151,7 +154,7 @@ template <int D, int K, typename T, int VARIANT, bool ENERGY>
 __global__ __launch_bounds__(512, DOGIP_WPE) void k_apply_g(ApplyLaunch a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t t = a.tile_base + xcd_tile(blockIdx.x, gridDim.x);
-  tile_body<D, K, KIND_WP, T, VARIANT, ENERGY, 0, true>(a, t, smem, ENERGY ? a.energy + t : nullptr);
+  tile_body<D, K, KIND_WP, T, VARIANT, ENERGY, 0, 1>(a, t, smem, ENERGY ? a.energy + t : nullptr);
 }
 
 template <int D, int K, typename T, int VARIANT>

@@ -290,6 +290,45 @@ struct ElemG {
   }
 };
 
+// Element body of the conventional quadrature-point apply: for each point q,
+// g = G_q u_T (values, or reference gradients), h = s_q g (projection) or s_q K_T g
+// (elliptic, K_T = R^-1 R^-T), y_T += G_q^T h; s_q = w_q |det R_T| a(x_q).  The table
+// index is wave-uniform.
+template <int D, int K, int KIND, typename T>
+struct ElemQ {
+  static constexpr int VT = dim_p(D, K), NB = KIND == KIND_SE ? D : 1, S = KIND == KIND_SE ? n_sym(D) : 1;
+
+  __device__ __forceinline__ static void run(const ApplyLaunch& a, int64_t w, int lane, const T (&ue)[VT],
+                                             T (&ye)[VT]) {
+    const T* qs = static_cast<const T*>(a.qs) + (w * a.nq) * 64 + lane;
+    const T* G = static_cast<const T*>(a.qtab);
+    T kc[S];
+    if constexpr (KIND == KIND_SE) {
+      const T* qk = static_cast<const T*>(a.qk) + (w * S) * 64 + lane;
+      sfor<S>([&](auto C) { kc[C] = qk[C * 64]; });
+    }
+    sfor<VT>([&](auto L) { ye[L] = T(-0.0); });
+    for (int q = 0; q < a.nq; ++q) {
+      const T sq = __builtin_nontemporal_load(qs + q * 64);
+      const T* gq = G + q * NB * VT;
+      T g[NB];
+      sfor<NB>([&](auto R) {
+        T acc = T(-0.0);
+        sfor<VT>([&](auto L) { acc = fma_t(gq[R * VT + L], ue[L], acc); });
+        g[R] = acc;
+      });
+      T h[NB];
+      if constexpr (KIND == KIND_SE) {
+        dmul<NB, S>(kc, g, h);
+        sfor<NB>([&](auto R) { h[R] = sq * h[R]; });
+      } else {
+        h[0] = sq * g[0];
+      }
+      sfor<NB>([&](auto R) { sfor<VT>([&](auto L) { ye[L] = fma_t(gq[R * VT + L], h[R], ye[L]); }); });
+    }
+  }
+};
+
 // Local indices of one cell: nlc 16-byte chunks of 8 uint16 slots, AoSoA by 64 cells.
 template <int VT>
 __device__ __forceinline__ void load_lidx(const uint16_t* __restrict__ lidx, int64_t w, int nlc, int lane,

@@ -175,7 +175,93 @@ std::unique_ptr<Op> make_op(std::shared_ptr<const Space> sp, int coef_kind, cons
   return op;
 }
 
+std::unique_ptr<Op> make_op_qp(std::shared_ptr<const Space> sp, int n, const double* coef, unsigned flags,
+                               int tile_waves, hipStream_t st) {
+  const Space& s = *sp;
+  DOGIP_CHECK(coef != nullptr, DOGIP_E_NULL, "null coefficient pointer");
+  DOGIP_CHECK(tile_waves >= 0 && tile_waves <= 8, DOGIP_E_RANGE, "tile_waves must be 0..8");
+  DOGIP_CHECK((flags & ~DOGIP_OP_FP32) == 0, DOGIP_E_RANGE, "unknown operator flag");
+  DOGIP_CHECK(s.k <= (s.dim == 2 ? 5 : (s.kind == DOGIP_SE ? 4 : 3)), DOGIP_E_RANGE,
+              "no quadrature-point kernel for this (dim, k, kind)");
+  std::vector<double> pts, wts, tab;
+  collapsed_rule(s.dim, n, pts, wts);
+  basis_table(s.dim, s.k, s.kind, pts, tab);
+  auto op = std::make_unique<Op>();
+  op->space = sp;
+  op->has32 = (flags & DOGIP_OP_FP32) != 0;
+  op->variant = DOGIP_VARIANT_LOOPED;
+  op->nq = int(wts.size());
+  int te = 64 * (tile_waves ? tile_waves : 4);
+  for (;;) {
+    op->plan = make_tiles(s, te);
+    if (op->plan.max_tile_dofs * 16 <= 65536 || te == 64) break;
+    te /= 2;
+  }
+  DOGIP_CHECK(op->plan.max_tile_dofs * 16 <= 65536, DOGIP_E_RANGE, "tile dofs exceed the LDS budget");
+  const TilePlan& p = op->plan;
+  upload(op->lidx, p.lidx);
+  upload(op->tile_off, p.tile_off);
+  upload(op->tile_dofs, p.tile_dofs);
+  upload(op->shared, p.shared);
+  upload(op->stage_off, p.stage_off);
+  upload(op->sh_rowptr, p.sh_rowptr);
+  upload(op->sh_slots, p.sh_slots);
+  upload(op->bnd, s.boundary);
+  op->stage.alloc(size_t(std::max<int64_t>(p.stage_off.back(), 1)) * sizeof(double));
+  upload(op->perm, p.perm);
+  const Mesh& m = *s.mesh;
+  std::vector<int32_t> cint(size_t(s.nc) * (s.dim + 1));
+  for (int64_t e = 0; e < s.nc; ++e)
+    std::memcpy(&cint[e * (s.dim + 1)], &m.cells[int64_t(p.perm[e]) * (s.dim + 1)], sizeof(int32_t) * (s.dim + 1));
+  upload(op->cells, cint);
+  upload(op->xyz, m.xyz);
+  upload(op->qtab64, tab);
+  upload(op->qw, wts);
+  std::vector<float> tab32(tab.begin(), tab.end());
+  if (op->has32) upload(op->qtab32, tab32);
+  const size_t ngrp = size_t(p.nel_pad / 64);
+  op->qs64.alloc(ngrp * op->nq * 64 * sizeof(double));
+  HIPCHK(hipMemset(op->qs64.p, 0, op->qs64.bytes));
+  if (op->has32) {
+    op->qs32.alloc(ngrp * op->nq * 64 * sizeof(float));
+    HIPCHK(hipMemset(op->qs32.p, 0, op->qs32.bytes));
+  }
+  if (s.kind == DOGIP_SE) {
+    op->qk64.alloc(ngrp * s.nsym * 64 * sizeof(double));
+    HIPCHK(hipMemset(op->qk64.p, 0, op->qk64.bytes));
+    if (op->has32) {
+      op->qk32.alloc(ngrp * s.nsym * 64 * sizeof(float));
+      HIPCHK(hipMemset(op->qk32.p, 0, op->qk32.bytes));
+    }
+  }
+  op->invdiag.alloc(size_t(s.ndofs) * sizeof(double));
+  op->timer = std::make_unique<OpTimer>();
+  QpSetupLaunch q{};
+  q.xyz = op->xyz.as<double>();
+  q.cells = op->cells.as<int32_t>();
+  q.perm = op->perm.as<int32_t>();
+  q.coef = coef;
+  q.w = op->qw.as<double>();
+  q.qs64 = op->qs64.as<double>();
+  q.qs32 = op->has32 ? op->qs32.as<float>() : nullptr;
+  q.qk64 = op->qk64.as<double>();
+  q.qk32 = op->has32 ? op->qk32.as<float>() : nullptr;
+  q.nel = s.nc;
+  q.nq = op->nq;
+  q.dim = s.dim;
+  q.kind = s.kind;
+  launch_qp_setup(q, st);
+  HIPCHK(hipGetLastError());
+  DevBuf tmp(size_t(s.ndofs) * sizeof(double));
+  op_diag(*op, tmp.as<double>(), st);
+  launch_invert(tmp.as<double>(), op->invdiag.as<double>(), s.ndofs, st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  return op;
+}
+
 void op_set_coef(Op& op, int coef_kind, const double* coef, hipStream_t st) {
+  DOGIP_CHECK(op.nq == 0, DOGIP_E_STATE, "a quadrature-point operator takes its samples at creation");
   check_coef(*op.space, coef_kind);
   DOGIP_CHECK(coef != nullptr, DOGIP_E_NULL, "null coefficient pointer");
   build_d(op, coef_kind, coef, st);
@@ -197,6 +283,13 @@ static ApplyLaunch apply_args(const Op& op, int prec) {
   a.tile_base = 0;
   a.stage_off = op.stage_off.as<int64_t>();
   a.stage = op.stage.as<double>();
+  if (op.nq > 0) {
+    const bool f64 = prec == DOGIP_F64;
+    a.qtab = f64 ? op.qtab64.p : op.qtab32.p;
+    a.qs = f64 ? op.qs64.p : op.qs32.p;
+    a.qk = f64 ? op.qk64.p : op.qk32.p;
+    a.nq = op.nq;
+  }
   if (op.global_w) {
     a.D = prec == DOGIP_F64 ? op.dg64.p : op.dg32.p;
     a.gw_mask = op.gw_rec.as<uint32_t>();
@@ -221,8 +314,9 @@ void op_apply(Op& op, const double* u, double* y, int prec, hipStream_t st, doub
     op.timer->ev.push_back(ev);
     HIPCHK(hipEventRecord(ev[0], st));
   }
-  const bool ok = op.global_w ? launch_apply_global(s.dim, s.k, prec, op.variant, a, st)
-                              : launch_apply(s.dim, s.k, s.kind, prec, op.variant, a, st);
+  const bool ok = op.nq > 0     ? launch_apply_qp(s.dim, s.k, s.kind, prec, a, st)
+                  : op.global_w ? launch_apply_global(s.dim, s.k, prec, op.variant, a, st)
+                                : launch_apply(s.dim, s.k, s.kind, prec, op.variant, a, st);
   DOGIP_CHECK(ok, DOGIP_E_RANGE, "no apply kernel for this (dim, k, kind, variant)");
   if (op.timer->on) HIPCHK(hipEventRecord(ev[1], st));
   launch_apply_finish(op.stage.as<double>(), op.sh_rowptr.as<uint32_t>(), op.sh_slots.as<uint32_t>(),
@@ -236,6 +330,11 @@ void op_diag(Op& op, double* diag, hipStream_t st) {
   const Space& s = *op.space;
   DOGIP_CHECK(diag != nullptr, DOGIP_E_NULL, "null output");
   launch_zero_indexed(diag, op.shared.as<int32_t>(), int64_t(op.plan.shared.size()), st);
+  if (op.nq > 0) {
+    launch_diag_qp(s.dim, s.k, s.kind, apply_args(op, DOGIP_F64), diag, st);
+    HIPCHK(hipGetLastError());
+    return;
+  }
   DiagLaunch a{};
   a.D = op.d64.as<double>();
   a.lidx = op.lidx.as<uint16_t>();
@@ -262,7 +361,7 @@ void op_diag(Op& op, double* diag, hipStream_t st) {
 void op_grad(Op& op, const double* u, const double* lam, double* g, hipStream_t st) {
   const Space& s = *op.space;
   DOGIP_CHECK(u && lam && g, DOGIP_E_NULL, "null vector");
-  DOGIP_CHECK(!op.global_w, DOGIP_E_STATE, "the gradient contraction needs the element-wise D");
+  DOGIP_CHECK(!op.global_w && op.nq == 0, DOGIP_E_STATE, "the gradient contraction needs the element-wise D");
   GradLaunch a{};
   a.D = op.d64.as<double>();
   a.lidx = op.lidx.as<uint16_t>();
@@ -285,7 +384,7 @@ void op_grad(Op& op, const double* u, const double* lam, double* g, hipStream_t 
 void op_export_d(Op& op, double* out, hipStream_t st) {
   const Space& s = *op.space;
   DOGIP_CHECK(out != nullptr, DOGIP_E_NULL, "null output");
-  DOGIP_CHECK(!op.global_w, DOGIP_E_STATE, "a global-form operator holds no per-cell D");
+  DOGIP_CHECK(!op.global_w && op.nq == 0, DOGIP_E_STATE, "this operator holds no per-cell D");
   launch_export_d(op.d64.as<double>(), op.perm.as<int32_t>(), out, s.nc, op.nch64, s.wt, s.nsym, st);
   HIPCHK(hipGetLastError());
 }
@@ -300,20 +399,26 @@ dogip_op_info op_info(const Op& op) {
   i.tile_dofs_total = int64_t(op.plan.tile_dofs.size());
   i.nshared = int64_t(op.plan.shared.size());
   i.max_tile_dofs = op.plan.max_tile_dofs;
-  i.bytes_d64 = int64_t(op.d64.bytes + op.dg64.bytes);
-  i.bytes_d32 = int64_t(op.d32.bytes + op.dg32.bytes);
+  i.bytes_d64 = int64_t(op.d64.bytes + op.dg64.bytes + op.qs64.bytes + op.qk64.bytes);
+  i.bytes_d32 = int64_t(op.d32.bytes + op.dg32.bytes + op.qs32.bytes + op.qk32.bytes);
   i.bytes_index = int64_t(op.lidx.bytes + op.tile_off.bytes + op.tile_dofs.bytes + op.shared.bytes +
                           op.stage_off.bytes + op.sh_rowptr.bytes + op.sh_slots.bytes + op.stage.bytes +
                           op.gw_rec.bytes + op.gw_off.bytes + op.gw_inc_ptr.bytes + op.gw_inc.bytes);
   i.ndofs_w = op.global_w ? op.gplan.nw : 0;
-  // D values read per apply: one per cell and W node, or one per global W dof
-  const double nd = op.global_w ? double(op.gplan.nw) : double(s.wt) * s.nsym * s.nc;
+  i.nq = op.nq;
+  // values read per apply: D per cell and W node, D per global W dof, or (quadrature
+  // points) one factor per cell and point plus the cell's R^-1 R^-T
+  const double nd = op.nq > 0     ? (double(op.nq) + (s.kind == DOGIP_SE ? s.nsym : 0)) * s.nc
+                    : op.global_w ? double(op.gplan.nw)
+                                  : double(s.wt) * s.nsym * s.nc;
   const double conn = 4.0 * s.vt * s.nc, vec = 2.0 * 8.0 * s.ndofs;
   i.alg_bytes_f64 = 8.0 * nd + conn + vec;
   i.alg_bytes_f32 = 4.0 * nd + conn + vec;
   // multiplications per cell as counted in eq. comp_eff, two flops each
   const double mults = 2.0 * double(s.nnz_bhat - s.nnz_pm1) + double(s.kind == DOGIP_SE ? s.dim * s.dim : 1) * s.wt;
   i.alg_flops = 2.0 * mults * double(s.nc);
+  if (op.nq > 0)  // dense tables: interpolation and projection at every point, plus the point product
+    i.alg_flops = 2.0 * double(op.nq) * (2.0 * s.nb * s.vt + (s.kind == DOGIP_SE ? s.dim * s.dim : 1)) * s.nc;
   return i;
 }
 

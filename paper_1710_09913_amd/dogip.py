@@ -11,7 +11,7 @@ import numpy as np
 from . import capi
 from .capi import check, lib
 
-__all__ = ["Mesh", "Space", "Operator", "Batch", "stream_ptr", "KIND", "BC", "COEF"]
+__all__ = ["Mesh", "Space", "Operator", "Batch", "stream_ptr", "quadrature_rule", "KIND", "BC", "COEF"]
 
 KIND = {"wp": capi.DOGIP_WP, "se": capi.DOGIP_SE}
 BC = {"none": capi.DOGIP_BC_NONE, "dirichlet": capi.DOGIP_BC_DIRICHLET0}
@@ -44,6 +44,15 @@ def _dev_ptr(t, dtype=None, n=None) -> int:
 def _host(a, dtype):
     a = np.ascontiguousarray(a, dtype=dtype)
     return a, a.ctypes.data_as(C.c_void_p)
+
+
+def quadrature_rule(dim: int, n: int):
+    """Reference points [n^dim, dim] and weights [n^dim] of the quadrature-point operator
+    (collapsed Gauss-Legendre, n points per direction)."""
+    pts = np.empty((n ** dim, dim))
+    wts = np.empty(n ** dim)
+    check(lib().dogip_quadrature(dim, n, pts.ctypes.data_as(C.c_void_p), wts.ctypes.data_as(C.c_void_p)))
+    return pts, wts
 
 
 class Mesh:
@@ -142,6 +151,27 @@ class Operator:
                                     stream_ptr(stream), C.byref(h)))
         self.h = h
         self.refresh_info()
+
+    @classmethod
+    def quadrature(cls, space: "Space", n: int, samples, fp32: bool = True, tile_waves: int = 0, stream=None):
+        """The conventional quadrature-point operator (dogip_op_create_qp): samples
+        [ncells, n^dim] of the scalar coefficient at the mapped points of
+        ``quadrature_rule(dim, n)``."""
+        import torch
+
+        nq = n ** space.info["dim"]
+        samples = samples.to(device="cuda", dtype=torch.float64).contiguous()
+        if samples.numel() != nq * space.ncells:
+            raise ValueError(f"samples have {samples.numel()} values, expected {nq * space.ncells}")
+        self = cls.__new__(cls)
+        self.space = space
+        self.ndofs = space.ndofs
+        h = C.c_void_p()
+        check(lib().dogip_op_create_qp(space.h, n, _dev_ptr(samples), capi.DOGIP_OP_FP32 if fp32 else 0, tile_waves,
+                                       stream_ptr(stream), C.byref(h)))
+        self.h = h
+        self.refresh_info()
+        return self
 
     def _check_coef(self, coef, coef_kind):
         i = self.space.info

@@ -110,3 +110,33 @@ def test_error_paths(L):
     L.dogip_space_destroy(None)
     L.dogip_op_destroy(None)
     L.dogip_batch_destroy(None)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8])
+def test_quadrature_rule(L, d, n):
+    """The quadrature-point operator's reference rule: exact for every monomial of total
+    degree <= 2n - d (closed form prod a_j! / (|a| + d)!; so the weights sum to |T^|
+    when 2n >= d), and the same rule, point for point, as the oracle's collapsed
+    Gauss-Legendre."""
+    import math
+
+    from paper_1710_09913_amd import quadrature_rule
+
+    pts, wts = quadrature_rule(d, n)
+    for a in (ref.multi_indices(d, 2 * n - d) if 2 * n >= d else []):
+        exact = math.prod(math.factorial(x) for x in a) / math.factorial(sum(a) + d)
+        assert math.isclose(float(np.sum(wts * np.prod(pts ** np.array(a), axis=1))), exact, rel_tol=1e-12,
+                            abs_tol=1e-16)
+    opts, owts = ref.collapsed_gauss(d, n)
+    assert np.abs(pts - opts).max() <= 1e-15 and np.abs(wts - owts).max() <= 1e-16
+
+
+def test_quadrature_rule_errors(L):
+    from paper_1710_09913_amd import quadrature_rule
+    from paper_1710_09913_amd.capi import DogipError
+
+    with pytest.raises(DogipError):
+        quadrature_rule(2, 0)
+    with pytest.raises(DogipError):
+        quadrature_rule(4, 2)
