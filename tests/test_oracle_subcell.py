@@ -1,0 +1,86 @@
+"""Pins of the oracle's sub-cell quadrature D for a coefficient with jumps inside cells."""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import dogip, fem, subcell
+from oracle import reference as ref
+from workloads import unit_mesh
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_red_refinement_tiles_the_parent(d):
+    """The children of a red refinement have equal volumes summing to the parent's, and
+    their vertices are the parent's vertices and edge midpoints."""
+    rng = np.random.default_rng(0)
+    v = rng.uniform(-1, 1, size=(d + 1, d))
+    vol = lambda s: abs(np.linalg.det((s[1:] - s[0]).T)) / math.factorial(d)  # noqa: E731
+    ch = subcell.red_children(v)
+    assert len(ch) == 2 ** d
+    assert np.allclose([vol(c) for c in ch], vol(v) / 2 ** d, rtol=1e-12)
+    allowed = [v[i] for i in range(d + 1)] + [(v[i] + v[j]) / 2 for i in range(d + 1) for j in range(i + 1, d + 1)]
+    for c in ch:
+        for p in c:
+            assert min(np.abs(p - a).max() for a in allowed) < 1e-15
+
+
+@pytest.mark.parametrize("d,k,kind", [(2, 2, "se"), (2, 2, "wp"), (3, 2, "se"), (3, 1, "wp")])
+def test_uncut_cells_match_the_closed_form(d, k, kind):
+    """A ball covering the whole domain (a = a_in everywhere) and a ball far away
+    (a = a_out everywhere) give Theorem 4 / 2 with a constant coefficient."""
+    coords, cells = unit_mesh(d, 2, jitter=0.1, seed=3)
+    sp = fem.make_space(coords, cells, k)
+    nel = len(cells)
+    big = np.array([[0.5] * d + [10.0]])
+    far = np.array([[50.0] * d + [1.0]])
+    for balls, a in ((big, 7.0), (far, 3.0)):
+        D = subcell.build_d_subcell(sp, balls, 7.0, 3.0, kind, depth=2, ng=3)
+        D0 = dogip.build_d(sp, np.full(nel, a), kind)
+        assert np.abs(D - D0).max() <= 1e-13 * np.abs(D0).max()
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_total_integral_converges_to_the_ball_volume(d):
+    """sum_{T,i} int_T a phi^W_i = int_Omega a = a_out + (a_in - a_out) |B| for a ball
+    inside the unit domain; the error stays within |a_in - a_out| times the volume of
+    the cut leaves and shrinks with the depth."""
+    coords, cells = unit_mesh(d, 2 if d == 2 else 1, jitter=0.0)
+    sp = fem.make_space(coords, cells, 1)
+    c, r = np.array([0.45, 0.55, 0.5][:d]), 0.3
+    exact_ball = math.pi * r ** 2 if d == 2 else 4.0 / 3.0 * math.pi * r ** 3
+    a_in, a_out = 5.0, 1.0
+    errs = []
+    for depth in (1, 2, 3, 4) if d == 2 else (1, 2, 3):
+        D = subcell.build_d_subcell(sp, np.array([[*c, r]]), a_in, a_out, "wp", depth=depth, ng=2)
+        total = D.sum()
+        err = abs(total - (a_out * 1.0 + (a_in - a_out) * exact_ball))
+        # bound: cut leaves at this depth, each of volume |T| / 2^(d depth)
+        cut = 0.0
+        for e in range(len(cells)):
+            X = coords[cells[e]]
+            R = (X[1:] - X[0]).T
+            J = abs(np.linalg.det(R))
+
+            def count(v, level):
+                cls = subcell.classify(X[0] + v @ R.T, np.array([[*c, r]]))
+                if cls != 2:
+                    return 0.0
+                if level == depth:
+                    return J * abs(np.linalg.det((v[1:] - v[0]).T)) / math.factorial(d)
+                return sum(count(ch, level + 1) for ch in subcell.red_children(v))
+
+            cut += count(np.vstack([np.zeros(d), np.eye(d)]), 0)
+        assert err <= (a_in - a_out) * cut + 1e-12
+        errs.append(err)
+    assert errs[-1] < errs[0] / 3
+
+
+def test_leaf_rule_is_exact_for_the_w_basis_on_inside_cells():
+    """On a sub-simplex wholly inside a ball the mapped rule integrates phi^W exactly:
+    a ball containing the cell reproduces w^_i |T^| per node."""
+    d, q = 3, 4
+    X = np.vstack([np.zeros(d), np.eye(d)]) * 0.1
+    s, _ = subcell.subcell_integrals(X, np.array([[0.0, 0.0, 0.0, 5.0]]), q, depth=2, ng=(q + d + 2) // 2)
+    assert np.abs(s - ref.what(d, q) / math.factorial(d)).max() <= 1e-15
