@@ -388,6 +388,61 @@ def run_qp(a):
     return out
 
 
+def run_inclusions(a):
+    """A coefficient with jumps inside the cells (the case Sections 2 and 3.3 argue DoGIP
+    suits): 3D 64^3 P3 elliptic with a = 100 inside 64 random balls (radius 0.04..0.1) and
+    1 outside.  D comes from sub-cell quadrature (red refinement of cut sub-simplices, depth
+    3, collapsed Gauss 3^3 per leaf); reports its build time and quadrature points per
+    cell, the apply (unchanged), FP64 vs mixed PCG to 1e-8, and a quadrature-point apply
+    that would evaluate about as many points at every apply."""
+    import numpy as np
+    import torch
+
+    from paper_1710_09913_amd import Mesh, Operator, Space
+
+    rng = np.random.default_rng(a.seed + 11)
+    balls = np.hstack([rng.uniform(0.05, 0.95, size=(64, 3)), rng.uniform(0.04, 0.1, size=(64, 1))])
+    mesh = Mesh.unit(3, a.n)
+    space = Space(mesh, a.k, "se", "dirichlet")
+    op = Operator(space, torch.ones(space.ncells, dtype=torch.float64), "scalar", fp32=True)
+    op.set_inclusions(balls, 100.0, 1.0, depth=1, ng=2)  # warm-up (module load)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    mean_pts = op.set_inclusions(balls, 100.0, 1.0, depth=3, ng=3)
+    torch.cuda.synchronize()
+    t_build = time.time() - t0
+    log(f"[incl] D by sub-cell quadrature {t_build:.3f}s, {mean_pts:.1f} points per cell")
+    from workloads import random_vector
+
+    u = torch.from_numpy(random_vector(space.ndofs, a.seed)).cuda()
+    y = torch.empty_like(u)
+    res = {"d_build_seconds": round(t_build, 4), "points_per_cell": round(mean_pts, 2)}
+    for prec in ("f64", "f32"):
+        ms, tms, fms = time_apply(op, u, y, prec, a.steps, a.warmup)
+        res["apply_" + prec] = {"ms": round(ms, 5), "GDoF_s": round(space.ndofs / (ms * 1e-3) / 1e9, 3)}
+    b = _rhs_f1(space, mesh, a.k)
+    for mode in ("f64", "mixed"):
+        op.pcg(b, tol=1e-8, maxit=100000, mode=mode, raise_on_error=False)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        _, st = op.pcg(b, tol=1e-8, maxit=100000, mode=mode, raise_on_error=False)
+        res["pcg_" + mode] = {"seconds": round(time.time() - t0, 4), "iters": st["iters"], "status": st["status"],
+                              "relres_true": st["relres_true"]}
+        log(f"[incl] pcg {mode} {res['pcg_' + mode]}")
+    n_eq = max(2, int(round(mean_pts ** (1.0 / 3.0))))
+    q = Operator.quadrature(space, n_eq, torch.ones(space.ncells * n_eq ** 3, dtype=torch.float64))
+    ms, _, _ = time_apply(q, u, y, "f64", a.steps, a.warmup)
+    res["quadrature_apply_f64"] = {"points": n_eq ** 3, "ms": round(ms, 5)}
+    del q
+    log(f"[incl] {res}")
+    out = _base("DoGIP with sub-cell quadrature D, 3D 64^3 P3 elliptic with inclusions: FP64 apply GDoF/s",
+                "GDoF/s", res["apply_f64"]["GDoF_s"], res["apply_f64"]["ms"], a,
+                {"workload": f"3D unit cube {a.n}^3 x 6 Kuhn tets, P{a.k} elliptic, a = 100 in 64 balls, 1 outside, "
+                             "sub-cell quadrature depth 3, 3^3 points per leaf"})
+    out["inclusions"] = res
+    return out
+
+
 def _lognormal(n, seed):
     from workloads import coef_lognormal, unit_mesh
 
@@ -405,10 +460,11 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "c5", "qp"],
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "c5", "qp", "incl"],
                     help="c3: 3D 64^3 P3 (default, the headline); c2: 2D 512^2 P1..P5 sweep; "
                          "c4: 2D 256^2 P3 adjoint gradient; c5: batch of 256 uneven 2D problems; "
-                         "qp: DoGIP vs the quadrature-point apply on the 3D operator")
+                         "qp: DoGIP vs the quadrature-point apply on the 3D operator; "
+                         "incl: inclusions (jumps inside cells) with sub-cell quadrature D")
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the multi-GPU path (element partition with an interface-dof "
@@ -419,7 +475,7 @@ def main(argv=None):
 
     torch.cuda.set_device(0)
     if a.workload != "c3":
-        out = {"c2": run_c2, "c4": run_c4, "c5": run_c5, "qp": run_qp}[a.workload](a)
+        out = {"c2": run_c2, "c4": run_c4, "c5": run_c5, "qp": run_qp, "incl": run_inclusions}[a.workload](a)
         print(json.dumps(out), flush=True)
         return 0
     space, op, b = build_problem(a.n, a.k, a.seed)

@@ -215,6 +215,24 @@ void dogip_space_destroy(dogip_space s);
  * cells holding W dof j (RAW_D: the cells' [ncells][wt] values are summed). */
 int dogip_op_create(dogip_space s, int coef_kind, const double* coef, unsigned flags, int tile_waves,
                     int variant, dogip_stream stream, dogip_op* out);
+/* Coefficient with jumps inside the cells, the case Sections 2 and 3.3 argue DoGIP
+ * suits: a = a_in inside the union of nballs balls (host array [nballs][dim+1]:
+ * center, radius > 0), a_out elsewhere, isotropic (M = a I, or m = a).  Rebuilds the
+ * D of an element-wise operator (with its FP32 copy and the Jacobi diagonal) from
+ * int_T a phi^W_i = a_out |T| w^_i + (a_in - a_out) int_T 1_B phi^W_i, the last
+ * integral by sub-cell quadrature on the GPU: the reference cell is red-refined
+ * (2D: 4 children; 3D: 8, the inner octahedron cut along its m02-m13 diagonal) where
+ * a sub-simplex is cut by a ball boundary, down to `depth` levels (0..6).  A
+ * sub-simplex with all vertices in one ball is inside; one whose bounding sphere
+ * misses every ball is outside.  Inside sub-simplices and cut ones at the last level
+ * take the collapsed Gauss rule of ng points per direction (1..8, see
+ * dogip_quadrature) mapped onto them, the indicator evaluated at the points of cut
+ * ones.  mean_points (optional host output): quadrature points evaluated per cell,
+ * averaged.  The apply's cost does not change.  Synchronizes the stream.
+ * DOGIP_E_STATE for a DOGIP_OP_GLOBAL_W or quadrature-point operator. */
+int dogip_op_set_inclusions(dogip_op op, int nballs, const double* balls, double a_in, double a_out, int depth,
+                            int ng, double* mean_points, dogip_stream stream);
+
 /* ---- conventional quadrature-point operator (the comparison of Section 3.3) ----
  * The matrix-free evaluation over integration points that the paper sets against
  * DoGIP: per cell, the trial function's values (projection) or gradients (elliptic)

@@ -93,6 +93,8 @@ SIGNATURES = {
     "dogip_space_destroy": (None, [H]),
     "dogip_op_create": (C.c_int, [H, C.c_int, P, C.c_uint, C.c_int, C.c_int, P, PH]),
     "dogip_quadrature": (C.c_int, [C.c_int, C.c_int, P, P]),
+    "dogip_op_set_inclusions": (C.c_int, [H, C.c_int, P, C.c_double, C.c_double, C.c_int, C.c_int,
+                                          C.POINTER(C.c_double), P]),
     "dogip_op_create_qp": (C.c_int, [H, C.c_int, P, C.c_uint, C.c_int, P, PH]),
     "dogip_op_set_coef": (C.c_int, [H, C.c_int, P, P]),
     "dogip_op_get_info": (C.c_int, [H, C.POINTER(OpInfo)]),

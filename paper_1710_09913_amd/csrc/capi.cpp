@@ -250,6 +250,15 @@ int dogip_op_create_qp(dogip_space s, int n, const double* coef, unsigned flags,
   });
 }
 
+int dogip_op_set_inclusions(dogip_op op, int nballs, const double* balls, double a_in, double a_out, int depth, int ng,
+                            double* mean_points, dogip_stream stream) {
+  return guard([&] {
+    need(op);
+    dogip::op_set_inclusions(*op->op, nballs, balls, a_in, a_out, depth, ng, mean_points, S(stream));
+    return DOGIP_OK;
+  });
+}
+
 int dogip_op_set_coef(dogip_op op, int coef_kind, const double* coef, dogip_stream stream) {
   return guard([&] {
     need(op);

@@ -264,6 +264,25 @@ struct BuildDLaunch {
   int dim, kind, coef_kind, wt, nsym;
 };
 void launch_build_d(const BuildDLaunch& a, hipStream_t st);
+
+// D for an inclusion coefficient by sub-cell quadrature (kern_subcell.hip).
+struct SubLaunch {
+  const double* xyz;
+  const int32_t* cells;  // internal order
+  const double* balls;   // [nballs][dim+1]: center, radius
+  const double* gpts;    // [ng][dim] reference rule of the leaves
+  const double* gwts;    // [ng]
+  const double* what;    // [wt]
+  double* d64;
+  float* d32;            // may be null
+  double* npts;          // optional [nel]: points evaluated per cell
+  double a_in, a_out;
+  int64_t nel, nch64, nch32;
+  int nballs, ng, depth, kind;
+};
+void launch_build_d_sub(int dim, int q, const SubLaunch& a, hipStream_t st);
+void op_set_inclusions(Op& op, int nballs, const double* balls, double a_in, double a_out, int depth, int ng,
+                       double* mean_points, hipStream_t st);
 // Global projection form: D at position j (tile layout) = sum over inc[inc_ptr[j] ..
 // inc_ptr[j+1]) (internal cell * wt + node) of the cell's integral of m phi^W_node.
 void launch_build_dg(const BuildDLaunch& a, const int64_t* inc_ptr, const int64_t* inc, int64_t nw, double* dg64,

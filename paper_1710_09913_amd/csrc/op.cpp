@@ -1,6 +1,7 @@
 // Operator construction and the apply / diagonal / gradient entry points.
 #include <algorithm>
 #include <array>
+#include <cmath>
 #include <cstring>
 
 #include "internal.hpp"
@@ -265,6 +266,65 @@ void op_set_coef(Op& op, int coef_kind, const double* coef, hipStream_t st) {
   check_coef(*op.space, coef_kind);
   DOGIP_CHECK(coef != nullptr, DOGIP_E_NULL, "null coefficient pointer");
   build_d(op, coef_kind, coef, st);
+}
+
+void op_set_inclusions(Op& op, int nballs, const double* balls, double a_in, double a_out, int depth, int ng,
+                       double* mean_points, hipStream_t st) {
+  const Space& s = *op.space;
+  DOGIP_CHECK(!op.global_w && op.nq == 0, DOGIP_E_STATE, "sub-cell quadrature builds the element-wise D");
+  DOGIP_CHECK(balls != nullptr, DOGIP_E_NULL, "null ball array");
+  DOGIP_CHECK(nballs >= 1, DOGIP_E_RANGE, "need at least one ball");
+  DOGIP_CHECK(depth >= 0 && depth <= 6, DOGIP_E_RANGE, "depth must be 0..6");
+  DOGIP_CHECK(ng >= 1 && ng <= 8, DOGIP_E_RANGE, "points per direction must be 1..8");
+  DOGIP_CHECK(std::isfinite(a_in) && std::isfinite(a_out), DOGIP_E_INVALID, "non-finite coefficient");
+  for (int j = 0; j < nballs; ++j) {
+    DOGIP_CHECK(balls[j * (s.dim + 1) + s.dim] > 0.0, DOGIP_E_INVALID, "ball radius must be positive");
+    for (int x = 0; x <= s.dim; ++x)
+      DOGIP_CHECK(std::isfinite(balls[j * (s.dim + 1) + x]), DOGIP_E_INVALID, "non-finite ball");
+  }
+  std::vector<double> pts, wts;
+  collapsed_rule(s.dim, ng, pts, wts);
+  DevBuf db(size_t(nballs) * (s.dim + 1) * sizeof(double)), dp(pts.size() * sizeof(double)),
+      dw(wts.size() * sizeof(double));
+  HIPCHK(hipMemcpy(db.p, balls, db.bytes, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(dp.p, pts.data(), dp.bytes, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(dw.p, wts.data(), dw.bytes, hipMemcpyHostToDevice));
+  DevBuf cnt;
+  if (mean_points) cnt.alloc(size_t(std::max<int64_t>(s.nc, 1)) * sizeof(double));
+  SubLaunch a{};
+  a.xyz = op.xyz.as<double>();
+  a.cells = op.cells.as<int32_t>();
+  a.balls = db.as<double>();
+  a.gpts = dp.as<double>();
+  a.gwts = dw.as<double>();
+  a.what = op.what.as<double>();
+  a.d64 = op.d64.as<double>();
+  a.d32 = op.has32 ? op.d32.as<float>() : nullptr;
+  a.npts = mean_points ? cnt.as<double>() : nullptr;
+  a.a_in = a_in;
+  a.a_out = a_out;
+  a.nel = s.nc;
+  a.nch64 = op.nch64;
+  a.nch32 = op.nch32;
+  a.nballs = nballs;
+  a.ng = int(wts.size());
+  a.depth = depth;
+  a.kind = s.kind;
+  launch_build_d_sub(s.dim, w_order(s.k, s.kind), a, st);
+  HIPCHK(hipGetLastError());
+  DevBuf tmp(size_t(s.ndofs) * sizeof(double));
+  op_diag(op, tmp.as<double>(), st);
+  launch_invert(tmp.as<double>(), op.invdiag.as<double>(), s.ndofs, st);
+  HIPCHK(hipGetLastError());
+  if (mean_points) {
+    std::vector<double> h(s.nc);
+    HIPCHK(hipMemcpyAsync(h.data(), cnt.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double sum = 0.0;
+    for (double v : h) sum += v;
+    *mean_points = s.nc ? sum / double(s.nc) : 0.0;
+  }
+  HIPCHK(hipStreamSynchronize(st));
 }
 
 static ApplyLaunch apply_args(const Op& op, int prec) {

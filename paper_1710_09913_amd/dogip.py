@@ -186,6 +186,18 @@ class Operator:
         check(lib().dogip_op_get_info(self.h, C.byref(info)))
         self.info = {f: getattr(info, f) for f, _ in capi.OpInfo._fields_}
 
+    def set_inclusions(self, balls, a_in: float, a_out: float, depth: int = 3, ng: int = 3, stream=None):
+        """D for a = a_in inside the balls ([nballs, dim+1]: center, radius), a_out elsewhere,
+        by sub-cell quadrature (dogip_op_set_inclusions); returns the mean number of
+        quadrature points evaluated per cell."""
+        b = np.ascontiguousarray(balls, dtype=np.float64)
+        if b.ndim != 2 or b.shape[1] != self.space.info["dim"] + 1:
+            raise ValueError("balls must be [nballs, dim + 1]")
+        mp = C.c_double()
+        check(lib().dogip_op_set_inclusions(self.h, b.shape[0], b.ctypes.data_as(C.c_void_p), float(a_in),
+                                            float(a_out), depth, ng, C.byref(mp), stream_ptr(stream)))
+        return mp.value
+
     def set_coef(self, coef, coef_kind: str = "scalar", stream=None):
         import torch
 
