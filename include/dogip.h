@@ -229,7 +229,8 @@ int dogip_op_create(dogip_space s, int coef_kind, const double* coef, unsigned f
  * dogip_quadrature) mapped onto them, the indicator evaluated at the points of cut
  * ones.  mean_points (optional host output): quadrature points evaluated per cell,
  * averaged.  The apply's cost does not change.  Synchronizes the stream.
- * DOGIP_E_STATE for a DOGIP_OP_GLOBAL_W or quadrature-point operator. */
+ * DOGIP_E_STATE for a DOGIP_OP_GLOBAL_W or quadrature-point operator;
+ * DOGIP_E_RANGE for double-grid orders above 8 (2D) or 6 (3D). */
 int dogip_op_set_inclusions(dogip_op op, int nballs, const double* balls, double a_in, double a_out, int depth,
                             int ng, double* mean_points, dogip_stream stream);
 
