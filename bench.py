@@ -550,7 +550,8 @@ def main(argv=None):
                          "relres_true": st["relres_true"]}
             log(f"[pcg {mode}] {dt:.3f}s {st}")
         res["speedup_mixed_vs_f64"] = round(res["f64"]["seconds"] / res["mixed"]["seconds"], 3)
-        res["mixed"]["method"] = "FP32 apply, FP64 vectors, FP64 residual replacement (reliable updates)"
+        res["mixed"]["method"] = ("FP32 apply, r/p/q stored in FP32 (x and inner products FP64), FP64 residual "
+                                  "replacement (reliable updates)")
         res["mixed_restart"]["method"] = "FP64 iterative refinement around restarted FP32-apply PCG (inner 1e-4)"
         out["pcg_time_to_1e-8"] = res
     if not a.no_cpu:

@@ -84,9 +84,12 @@ extern "C" {
 #define DOGIP_SOLVE_F64 0 /* Jacobi-PCG with the FP64 apply */
 /* Jacobi-PCG with the FP32 apply, refined in FP64 by residual replacement: the
  * recursive residual is replaced by b - A64 x (FP64 apply) each time it has
- * dropped by the factor inner_tol (default 0.1) and at apparent convergence, the
- * search direction being kept (no restart).  Vectors and inner products are FP64.
- * If the true residual stops decreasing, the solve finishes with FP64 CG. */
+ * dropped by the factor inner_tol (default 0.1), at least every 512 iterations and
+ * at apparent convergence (where the direction restarts; elsewhere it is kept).
+ * x and the inner products are FP64; the residual, direction and A p are stored in
+ * FP32 (element-wise operators; FP64 for the global and quadrature-point forms).
+ * When the true residual stays well above the recursive one or diverges, the solve
+ * finishes with FP64 CG. */
 #define DOGIP_SOLVE_MIXED 1
 /* FP64 iterative refinement that restarts an FP32-apply Jacobi-PCG for every
  * correction, each inner solve reducing its residual by inner_tol. */

@@ -118,6 +118,7 @@ struct Op {
   bool has32 = false;
   int64_t nch64 = 0, nch32 = 0;
   DevBuf d64, d32, lidx, tile_off, tile_dofs, shared, perm, cells, xyz, what, bhat64, bhat32, invdiag;
+  DevBuf invdiag32;  // FP32 copy of the inverse diagonal (operators with DOGIP_OP_FP32)
   DevBuf stage_off, sh_rowptr, sh_slots, stage, bnd;  // second pass: shared dofs, Dirichlet rows
   bool global_w = false;                               // global projection form
   GlobalPlan gplan;
@@ -178,6 +179,8 @@ struct ApplyLaunch {
   const void* bhat;      // looped variant: [nb][wt][vt] in the compute precision
   const double* u;
   double* y;
+  const float* u32;      // FP32 vectors (mixed CG): used instead of u and y when set
+  float* y32;
   double* energy;        // optional per-tile partial of u^T A u (nullptr: not computed)
   const int64_t* stage_off;  // [ntiles+1] staging offsets of the tiles' shared entries
   double* stage;             // staging buffer of shared partial sums
@@ -310,5 +313,13 @@ void launch_apply_finish(const double* stage, const uint32_t* rowptr, const uint
                          int64_t nshared, const int32_t* bnd, int64_t nbnd, const double* u, double* y,
                          double* benergy, hipStream_t st);
 void launch_invert(const double* d, double* inv, int64_t n, hipStream_t st);
+void launch_to_f32(const double* x, float* y, int64_t n, hipStream_t st);
+// FP32 apply on FP32 vectors with the energy partials (the mixed CG iteration):
+// y32 = A32 u32, energy as op_apply.
+void op_apply_v32(Op& op, const float* u, float* y, hipStream_t st, double* energy_partials);
+bool op_has_v32(const Op& op);
+void launch_apply_finish32(const double* stage, const uint32_t* rowptr, const uint32_t* slots, const int32_t* shared,
+                           int64_t nshared, const int32_t* bnd, int64_t nbnd, const float* u, float* y,
+                           double* benergy, hipStream_t st);
 
 }  // namespace dogip

@@ -32,17 +32,17 @@ constexpr int GB = 8;  // tile dof entries handled per thread in one batch
 
 // Gather of one batch: entries j = j0 + g * blockDim.x; u -> LDS (0 for Dirichlet
 // dofs), accumulation slots zeroed.  The GB loads of a thread are in flight together.
-template <typename T>
+template <typename T, typename VU>
 __device__ __forceinline__ void gather_batch(const uint32_t* __restrict__ td, int64_t nd, int64_t j0,
-                                             const double* __restrict__ u, T* us, double* ys, uint32_t (&e)[GB]) {
-  double v[GB];
+                                             const VU* __restrict__ u, T* us, double* ys, uint32_t (&e)[GB]) {
+  VU v[GB];
 #pragma unroll
   for (int g = 0; g < GB; ++g) {
     const int64_t j = j0 + int64_t(g) * blockDim.x;
     e[g] = j < nd ? td[j] : TD_BND;
   }
 #pragma unroll
-  for (int g = 0; g < GB; ++g) v[g] = (e[g] & TD_BND) ? 0.0 : u[e[g] & TD_MASK];
+  for (int g = 0; g < GB; ++g) v[g] = (e[g] & TD_BND) ? VU(0) : u[e[g] & TD_MASK];
 #pragma unroll
   for (int g = 0; g < GB; ++g) {
     const int64_t j = j0 + int64_t(g) * blockDim.x;
@@ -55,9 +55,9 @@ __device__ __forceinline__ void gather_batch(const uint32_t* __restrict__ td, in
 
 // Flush of one batch: shared entries -> staging (second pass sums them), exclusive
 // entries -> y; Dirichlet entries are written by the second pass.
-template <bool ENERGY, typename T>
+template <bool ENERGY, typename T, typename VY>
 __device__ __forceinline__ void flush_batch(const uint32_t (&e)[GB], int64_t nd, int64_t j0, const double* ys,
-                                            const T* us, double* __restrict__ stage, double* __restrict__ y,
+                                            const T* us, double* __restrict__ stage, VY* __restrict__ y,
                                             double& en) {
 #pragma unroll
   for (int g = 0; g < GB; ++g) {
@@ -67,7 +67,7 @@ __device__ __forceinline__ void flush_batch(const uint32_t (&e)[GB], int64_t nd,
     if (e[g] & TD_SHARED)
       stage[j] = ys[j];
     else
-      y[e[g] & TD_MASK] = ys[j];
+      y[e[g] & TD_MASK] = VY(ys[j]);
   }
 }
 
@@ -78,7 +78,8 @@ __device__ __forceinline__ void flush_batch(const uint32_t (&e)[GB], int64_t nd,
 // tile's sum_T u_T^T A_T u_T goes (ENERGY only).  MODE 1: global projection form, D
 // holds one value per W dof in the per-wave layout of GlobalPlan; MODE 2: the
 // conventional quadrature-point apply (ElemQ).
-template <int D, int K, int KIND, typename T, int VARIANT, bool ENERGY, int PF, int MODE = 0>
+// V32: FP32 input and output vectors (a.u32, a.y32).
+template <int D, int K, int KIND, typename T, int VARIANT, bool ENERGY, int PF, int MODE = 0, bool V32 = false>
 __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsigned char* smem, double* energy_out) {
   using E = Elem<D, K, KIND, T, T, VARIANT, false, PF>;
   constexpr int VT = dim_p(D, K);
@@ -88,10 +89,22 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
   const uint32_t* td = a.tile_dofs + o0;
   const bool one = nd <= int64_t(GB) * blockDim.x;
   uint32_t ent[GB];
+  const auto* uin = [&] {
+    if constexpr (V32)
+      return a.u32;
+    else
+      return a.u;
+  }();
+  auto* yout = [&] {
+    if constexpr (V32)
+      return a.y32;
+    else
+      return a.y;
+  }();
   if (one) {
-    gather_batch<T>(td, nd, threadIdx.x, a.u, us, ys, ent);
+    gather_batch<T>(td, nd, threadIdx.x, uin, us, ys, ent);
   } else {
-    for (int64_t j0 = threadIdx.x; j0 < nd; j0 += int64_t(GB) * blockDim.x) gather_batch<T>(td, nd, j0, a.u, us, ys, ent);
+    for (int64_t j0 = threadIdx.x; j0 < nd; j0 += int64_t(GB) * blockDim.x) gather_batch<T>(td, nd, j0, uin, us, ys, ent);
   }
   __syncthreads();
   int64_t e = t * a.te + threadIdx.x;
@@ -124,7 +137,7 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
   double* stage = a.stage + a.stage_off[t];
   double en = 0.0;
   if (one) {
-    flush_batch<ENERGY>(ent, nd, threadIdx.x, ys, us, stage, a.y, en);
+    flush_batch<ENERGY>(ent, nd, threadIdx.x, ys, us, stage, yout, en);
   } else {
     for (int64_t j0 = threadIdx.x; j0 < nd; j0 += int64_t(GB) * blockDim.x) {
 #pragma unroll
@@ -132,7 +145,7 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
         const int64_t j = j0 + int64_t(g) * blockDim.x;
         ent[g] = j < nd ? td[j] : TD_BND;
       }
-      flush_batch<ENERGY>(ent, nd, j0, ys, us, stage, a.y, en);
+      flush_batch<ENERGY>(ent, nd, j0, ys, us, stage, yout, en);
     }
   }
   if constexpr (ENERGY) {
@@ -143,11 +156,11 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
 }
 
 // One workgroup per tile; workgroup -> tile mapping keeps each XCD on a contiguous range.
-template <int D, int K, int KIND, typename T, int VARIANT, bool ENERGY, int PF>
+template <int D, int K, int KIND, typename T, int VARIANT, bool ENERGY, int PF, bool V32 = false>
 __global__ __launch_bounds__(512, DOGIP_WPE) void k_apply(ApplyLaunch a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t t = a.tile_base + xcd_tile(blockIdx.x, gridDim.x);
-  tile_body<D, K, KIND, T, VARIANT, ENERGY, PF>(a, t, smem, ENERGY ? a.energy + t : nullptr);
+  tile_body<D, K, KIND, T, VARIANT, ENERGY, PF, 0, V32>(a, t, smem, ENERGY ? a.energy + t : nullptr);
 }
 
 template <int D, int K, typename T, int VARIANT, bool ENERGY>
@@ -189,10 +202,14 @@ bool launch_apply_t(int prec, bool energy, const ApplyLaunch& a, hipStream_t st)
       hipLaunchKernelGGL((k_apply<D, K, KIND, double, VARIANT, false, P64>), grid, block, lds, st, a);
   } else {
     const size_t lds = size_t(a.lds_slots) * (sizeof(double) + sizeof(float));
-    if (energy)
+    if (a.u32) {
+      if (!energy) return false;  // FP32 vectors: the CG iteration only
+      hipLaunchKernelGGL((k_apply<D, K, KIND, float, VARIANT, true, P32, true>), grid, block, lds, st, a);
+    } else if (energy) {
       hipLaunchKernelGGL((k_apply<D, K, KIND, float, VARIANT, true, P32>), grid, block, lds, st, a);
-    else
+    } else {
       hipLaunchKernelGGL((k_apply<D, K, KIND, float, VARIANT, false, P32>), grid, block, lds, st, a);
+    }
   }
   return true;
 }

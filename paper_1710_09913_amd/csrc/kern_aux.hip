@@ -136,6 +136,41 @@ __global__ __launch_bounds__(FINISH_THREADS) void k_apply_finish(const double* _
   }
 }
 
+// The second pass on FP32 vectors (mixed CG): partial sums added in FP64, stored in FP32.
+__global__ __launch_bounds__(FINISH_THREADS) void k_apply_finish32(const double* __restrict__ stage,
+                                                        const uint32_t* __restrict__ rowptr,
+                                                        const uint32_t* __restrict__ slots,
+                                                        const int32_t* __restrict__ shared, int64_t nshared,
+                                                        const int32_t* __restrict__ bnd, int64_t nbnd,
+                                                        const float* __restrict__ u, float* __restrict__ y,
+                                                        double* __restrict__ benergy, int64_t e0) {
+  double eb = 0.0;
+  const int64_t i = int64_t(blockIdx.x) * FINISH_THREADS + threadIdx.x;
+  if (i < nshared + nbnd) {
+    if (i < nshared) {
+      const uint32_t a = rowptr[i], b = rowptr[i + 1];
+      double s = 0.0;
+      for (uint32_t j = a; j < b; ++j) s += stage[slots[j]];
+      y[shared[i]] = float(s);
+    } else {
+      const int32_t d = bnd[i - nshared];
+      const float ub = u[d];
+      y[d] = ub;
+      eb += double(ub) * double(ub);
+    }
+  }
+  if (benergy && int64_t(blockIdx.x) >= e0) {  // block-uniform
+    __shared__ double red[8];
+    const double s = block_sum(eb, red);
+    if (threadIdx.x == 0) benergy[blockIdx.x - e0] = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_to_f32(const double* __restrict__ x, float* __restrict__ y, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    y[i] = float(x[i]);
+}
+
 __global__ __launch_bounds__(256) void k_invert(const double* __restrict__ d, double* __restrict__ inv, int64_t n) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
     inv[i] = 1.0 / d[i];
@@ -414,6 +449,20 @@ void launch_apply_finish(const double* stage, const uint32_t* rowptr, const uint
   const unsigned grid = unsigned(finish_blocks(nshared, nbnd));
   hipLaunchKernelGGL(dev::k_apply_finish, dim3(grid), dim3(FINISH_THREADS), 0, st, stage, rowptr, slots, shared,
                      nshared, bnd, nbnd, u, y, benergy, finish_first_energy_block(nshared, nbnd));
+}
+
+void launch_apply_finish32(const double* stage, const uint32_t* rowptr, const uint32_t* slots, const int32_t* shared,
+                           int64_t nshared, const int32_t* bnd, int64_t nbnd, const float* u, float* y,
+                           double* benergy, hipStream_t st) {
+  if (nshared + nbnd <= 0 && !benergy) return;
+  const unsigned grid = unsigned(finish_blocks(nshared, nbnd));
+  hipLaunchKernelGGL(dev::k_apply_finish32, dim3(grid), dim3(FINISH_THREADS), 0, st, stage, rowptr, slots, shared,
+                     nshared, bnd, nbnd, u, y, benergy, finish_first_energy_block(nshared, nbnd));
+}
+
+void launch_to_f32(const double* x, float* y, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(dev::k_to_f32, dim3(grid_for(n, 256)), dim3(256), 0, st, x, y, n);
 }
 
 void launch_invert(const double* d, double* inv, int64_t n, hipStream_t st) {

@@ -192,6 +192,70 @@ __global__ __launch_bounds__(256) void k_fill(double* __restrict__ x, double v, 
   GRID_STRIDE(i, n) x[i] = v;
 }
 
+// ---- the same iteration on FP32 vectors r, p, q (x stays FP64; arithmetic and inner
+// products in FP64, each stored vector rounded once) ----
+
+// r = b - y (y may be null), z = invd r; partials (r.z, r.r, b.b) of the stored values
+__global__ __launch_bounds__(256) void k_pcg_init32(const double* __restrict__ b, const double* __restrict__ y,
+                                                    const float* __restrict__ invd, float* __restrict__ r,
+                                                    float* __restrict__ p, int64_t n, double* __restrict__ part) {
+  double v[3] = {0.0, 0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    const double bi = b[i];
+    const float ri = float(y ? bi - y[i] : bi);
+    const double zi = double(invd[i]) * double(ri);
+    r[i] = ri;
+    p[i] = float(zi);
+    v[0] += double(ri) * zi;
+    v[1] += double(ri) * double(ri);
+    v[2] += bi * bi;
+  }
+  block_partials(v, 3, part);
+}
+
+// x += alpha p, r -= alpha q, z = invd r; partials (r.z, r.r)
+__global__ __launch_bounds__(256) void k_pcg_xr32(double* __restrict__ x, float* __restrict__ r,
+                                                  const float* __restrict__ p, const float* __restrict__ q,
+                                                  const float* __restrict__ invd, const PcgScalars* __restrict__ s,
+                                                  int64_t n, double* __restrict__ part) {
+  const double alpha = s->alpha;
+  double v[2] = {0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    x[i] = fma(alpha, double(p[i]), x[i]);
+    const float ri = float(fma(-alpha, double(q[i]), double(r[i])));
+    r[i] = ri;
+    v[0] += double(ri) * (double(invd[i]) * double(ri));
+    v[1] += double(ri) * double(ri);
+  }
+  block_partials(v, 2, part);
+}
+
+// p = invd r + beta p
+__global__ __launch_bounds__(256) void k_pcg_p32(float* __restrict__ p, const float* __restrict__ r,
+                                                 const float* __restrict__ invd, const PcgScalars* __restrict__ s,
+                                                 int64_t n) {
+  const double beta = s->beta;
+  GRID_STRIDE(i, n) p[i] = float(fma(beta, double(p[i]), double(invd[i]) * double(r[i])));
+}
+
+// residual replacement: r = b - y (y = A64 x): the true r.r from the unrounded FP64
+// residual, r stored in FP32, r.z from the stored r; with p, restart p = z
+__global__ __launch_bounds__(256) void k_replace32(const double* __restrict__ b, const double* __restrict__ y,
+                                                   const float* __restrict__ invd, float* __restrict__ r,
+                                                   float* __restrict__ p, int64_t n, double* __restrict__ part) {
+  double v[2] = {0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    const double rd = b[i] - y[i];
+    const float ri = float(rd);
+    const double zi = double(invd[i]) * double(ri);
+    r[i] = ri;
+    if (p) p[i] = float(zi);
+    v[0] += double(ri) * zi;
+    v[1] += rd * rd;
+  }
+  block_partials(v, 2, part);
+}
+
 }  // namespace dev
 
 static unsigned red_grid(int64_t n) {
@@ -236,6 +300,27 @@ void vk_dot(const double* a, const double* b, int64_t n, double* part, double* o
 void vk_axpy1(double* x, const double* d, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(dev::k_axpy1, dim3(red_grid(n) * 4), dim3(256), 0, st, x, d, n);
 }
+void vk_pcg_init32(const double* b, const double* y, const float* invd, float* r, float* p, int64_t n, double* part,
+                   PcgScalars* s, double* hist, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_pcg_init32, dim3(RED_BLOCKS), dim3(256), 0, st, b, y, invd, r, p, n, part);
+  hipLaunchKernelGGL(dev::k_fin_init, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, s, hist);
+}
+
+void vk_pcg_xr32(double* x, float* r, const float* p, const float* q, const float* invd, const PcgScalars* s,
+                 int64_t n, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_pcg_xr32, dim3(RED_BLOCKS), dim3(256), 0, st, x, r, p, q, invd, s, n, part);
+}
+
+void vk_pcg_p32(float* p, const float* r, const float* invd, const PcgScalars* s, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_pcg_p32, dim3(red_grid(n) * 4), dim3(256), 0, st, p, r, invd, s, n);
+}
+
+void vk_replace32(const double* b, const double* y, const float* invd, float* r, float* p, int64_t n, double* part,
+                  PcgScalars* s, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_replace32, dim3(RED_BLOCKS), dim3(256), 0, st, b, y, invd, r, p, n, part);
+  hipLaunchKernelGGL(dev::k_fin_replace, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, s);
+}
+
 void vk_fill(double* x, double v, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(dev::k_fill, dim3(red_grid(n) * 4), dim3(256), 0, st, x, v, n);
 }

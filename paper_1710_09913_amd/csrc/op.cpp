@@ -67,6 +67,16 @@ static void upload(DevBuf& b, const std::vector<T>& v) {
   if (!v.empty()) HIPCHK(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
 }
 
+// inverse of the Jacobi diagonal, and its FP32 copy for the mixed CG
+static void set_invdiag(Op& op, const double* diag, hipStream_t st) {
+  const int64_t n = op.space->ndofs;
+  launch_invert(diag, op.invdiag.as<double>(), n, st);
+  if (op.has32) {
+    if (!op.invdiag32.p) op.invdiag32.alloc(size_t(std::max<int64_t>(n, 1)) * sizeof(float));
+    launch_to_f32(op.invdiag.as<double>(), op.invdiag32.as<float>(), n, st);
+  }
+}
+
 static void check_coef(const Space& s, int coef_kind) {
   DOGIP_CHECK(coef_kind >= DOGIP_COEF_SCALAR && coef_kind <= DOGIP_COEF_RAW_D, DOGIP_E_RANGE, "unknown coefficient form");
   DOGIP_CHECK(!(coef_kind == DOGIP_COEF_SYM && s.kind == DOGIP_WP), DOGIP_E_RANGE,
@@ -101,7 +111,7 @@ static void build_d(Op& op, int coef_kind, const double* coef, hipStream_t st) {
   // Jacobi diagonal -> inverse
   DevBuf tmp(size_t(s.ndofs) * sizeof(double));
   op_diag(op, tmp.as<double>(), st);
-  launch_invert(tmp.as<double>(), op.invdiag.as<double>(), s.ndofs, st);
+  set_invdiag(op, tmp.as<double>(), st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
 }
@@ -255,7 +265,7 @@ std::unique_ptr<Op> make_op_qp(std::shared_ptr<const Space> sp, int n, const dou
   HIPCHK(hipGetLastError());
   DevBuf tmp(size_t(s.ndofs) * sizeof(double));
   op_diag(*op, tmp.as<double>(), st);
-  launch_invert(tmp.as<double>(), op->invdiag.as<double>(), s.ndofs, st);
+  set_invdiag(*op, tmp.as<double>(), st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
   return op;
@@ -314,7 +324,7 @@ void op_set_inclusions(Op& op, int nballs, const double* balls, double a_in, dou
   HIPCHK(hipGetLastError());
   DevBuf tmp(size_t(s.ndofs) * sizeof(double));
   op_diag(op, tmp.as<double>(), st);
-  launch_invert(tmp.as<double>(), op.invdiag.as<double>(), s.ndofs, st);
+  set_invdiag(op, tmp.as<double>(), st);
   HIPCHK(hipGetLastError());
   if (mean_points) {
     std::vector<double> h(s.nc);
@@ -384,6 +394,23 @@ void op_apply(Op& op, const double* u, double* y, int prec, hipStream_t st, doub
                       int64_t(s.boundary.size()), u, y, energy ? energy + op.plan.ntiles : nullptr, st);
   HIPCHK(hipGetLastError());
   if (op.timer->on) HIPCHK(hipEventRecord(ev[2], st));
+}
+
+bool op_has_v32(const Op& op) { return op.has32 && !op.global_w && op.nq == 0; }
+
+void op_apply_v32(Op& op, const float* u, float* y, hipStream_t st, double* energy) {
+  const Space& s = *op.space;
+  DOGIP_CHECK(op_has_v32(op) && u && y && energy, DOGIP_E_STATE, "FP32-vector apply unavailable");
+  ApplyLaunch a = apply_args(op, DOGIP_F32);
+  a.u32 = u;
+  a.y32 = y;
+  a.energy = energy;
+  DOGIP_CHECK(launch_apply(s.dim, s.k, s.kind, DOGIP_F32, op.variant, a, st), DOGIP_E_RANGE,
+              "no apply kernel for this (dim, k, kind, variant)");
+  launch_apply_finish32(op.stage.as<double>(), op.sh_rowptr.as<uint32_t>(), op.sh_slots.as<uint32_t>(),
+                        op.shared.as<int32_t>(), int64_t(op.plan.shared.size()), op.bnd.as<int32_t>(),
+                        int64_t(s.boundary.size()), u, y, energy + op.plan.ntiles, st);
+  HIPCHK(hipGetLastError());
 }
 
 void op_diag(Op& op, double* diag, hipStream_t st) {

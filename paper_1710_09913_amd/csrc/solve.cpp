@@ -59,6 +59,7 @@ struct CgParams {
   bool reliable = false;
   double delta = 0.1;
   int check_every = 16;
+  bool v32 = false;  // with the FP32 apply: r, p, q stored in FP32 (x and inner products FP64)
 };
 
 static CgResult cg_run(Op& op, const double* b, double* x, bool x0_given, const CgParams& cp, hipStream_t st) {
@@ -71,12 +72,28 @@ static CgResult cg_run(Op& op, const double* b, double* x, bool x0_given, const 
   double* hist = w.hist.as<double>();
   auto* sc = w.scal.as<PcgScalars>();
   const double* invd = op.invdiag.as<double>();
+  const bool v32 = cp.v32 && cp.prec == DOGIP_F32 && op_has_v32(op);
+  if (v32 && !w.r32.p) {
+    w.r32.alloc(size_t(std::max<int64_t>(n, 1)) * sizeof(float));
+    w.p32.alloc(size_t(std::max<int64_t>(n, 1)) * sizeof(float));
+    w.q32.alloc(size_t(std::max<int64_t>(n, 1)) * sizeof(float));
+  }
+  float* r32 = w.r32.as<float>();
+  float* p32 = w.p32.as<float>();
+  float* q32 = w.q32.as<float>();
+  const float* invd32 = op.invdiag32.as<float>();
   if (x0_given) {
     op_apply(op, x, q, DOGIP_F64, st);
-    vk_pcg_init(b, q, invd, r, p, n, part, sc, hist, st);
+    if (v32)
+      vk_pcg_init32(b, q, invd32, r32, p32, n, part, sc, hist, st);
+    else
+      vk_pcg_init(b, q, invd, r, p, n, part, sc, hist, st);
   } else {
     vk_fill(x, 0.0, n, st);
-    vk_pcg_init(b, nullptr, invd, r, p, n, part, sc, hist, st);
+    if (v32)
+      vk_pcg_init32(b, nullptr, invd32, r32, p32, n, part, sc, hist, st);
+    else
+      vk_pcg_init(b, nullptr, invd, r, p, n, part, sc, hist, st);
   }
   PcgScalars hs{};
   HIPCHK(hipMemcpyAsync(&hs, sc, sizeof hs, hipMemcpyDeviceToHost, st));
@@ -103,11 +120,19 @@ static CgResult cg_run(Op& op, const double* b, double* x, bool x0_given, const 
   for (;;) {
     const int todo = std::min(step, cp.maxit - it);
     for (int j = 0; j < todo; ++j) {
-      op_apply(op, p, q, cp.prec, st, w.energy.as<double>());
-      vk_fin_pq(w.energy.as<double>(), op.plan.ntiles + op_finish_energy_count(op), sc, st);
-      vk_pcg_xr(x, r, p, q, invd, sc, n, part, st);
-      vk_fin_rz(part, sc, hist, it + j + 1, st);
-      vk_pcg_p(p, r, invd, sc, n, st);
+      if (v32) {
+        op_apply_v32(op, p32, q32, st, w.energy.as<double>());
+        vk_fin_pq(w.energy.as<double>(), op.plan.ntiles + op_finish_energy_count(op), sc, st);
+        vk_pcg_xr32(x, r32, p32, q32, invd32, sc, n, part, st);
+        vk_fin_rz(part, sc, hist, it + j + 1, st);
+        vk_pcg_p32(p32, r32, invd32, sc, n, st);
+      } else {
+        op_apply(op, p, q, cp.prec, st, w.energy.as<double>());
+        vk_fin_pq(w.energy.as<double>(), op.plan.ntiles + op_finish_energy_count(op), sc, st);
+        vk_pcg_xr(x, r, p, q, invd, sc, n, part, st);
+        vk_fin_rz(part, sc, hist, it + j + 1, st);
+        vk_pcg_p(p, r, invd, sc, n, st);
+      }
     }
     HIPCHK(hipMemcpyAsync(w.hhist + it + 1, hist + it + 1, sizeof(double) * todo, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -136,7 +161,10 @@ static CgResult cg_run(Op& op, const double* b, double* x, bool x0_given, const 
       // at apparent convergence the direction restarts from the true residual; the
       // replacements triggered by delta keep it
       op_apply(op, x, q, DOGIP_F64, st);
-      vk_replace(b, q, invd, r, conv ? p : nullptr, n, part, sc, st);
+      if (v32)
+        vk_replace32(b, q, invd32, r32, conv ? p32 : nullptr, n, part, sc, st);
+      else
+        vk_replace(b, q, invd, r, conv ? p : nullptr, n, part, sc, st);
       HIPCHK(hipMemcpyAsync(&hs, sc, sizeof hs, hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       if (hs.flags || !std::isfinite(hs.rr)) {
@@ -221,13 +249,15 @@ int op_pcg(Op& op, const double* b, double* x, const dogip_solve_opts& o, dogip_
   cp.maxit = o.maxit;
   cp.check_every = check;
   if (o.mode == DOGIP_SOLVE_F64 || o.mode == DOGIP_SOLVE_MIXED) {
-    // FP64: plain Jacobi-PCG.  MIXED: the same iteration with the FP32 apply and FP64
-    // residual replacement (reliable updates); vectors and inner products stay FP64.
-    // In both modes apparent convergence is verified on the true FP64 residual (a
-    // replacement); MIXED also replaces whenever the residual has dropped by delta.
+    // FP64: plain Jacobi-PCG.  MIXED: the same iteration with the FP32 apply, the
+    // vectors r, p, q in FP32 (x and the inner products FP64), and FP64 residual
+    // replacement (reliable updates).  In both modes apparent convergence is verified
+    // on the true FP64 residual (a replacement); MIXED also replaces whenever the
+    // residual has dropped by delta, which re-rounds r from the FP64 residual.
     cp.prec = o.mode == DOGIP_SOLVE_F64 ? DOGIP_F64 : DOGIP_F32;
     cp.reliable = true;
     cp.delta = o.mode == DOGIP_SOLVE_F64 ? 0.0 : ((o.inner_tol > 0 && o.inner_tol < 1) ? o.inner_tol : 0.1);
+    cp.v32 = o.mode == DOGIP_SOLVE_MIXED;
     CgResult c = cg_run(op, b, x, o.x0_given != 0, cp, st);
     status = c.status;
     stats.iters = c.iters;
@@ -239,6 +269,7 @@ int op_pcg(Op& op, const double* b, double* x, const dogip_solve_opts& o, dogip_
       f.prec = DOGIP_F64;
       f.reliable = true;  // convergence still verified on the true residual
       f.delta = 0.0;
+      f.v32 = false;
       f.maxit = o.maxit - c.iters;
       CgResult g = cg_run(op, b, x, true, f, st);
       status = g.status;

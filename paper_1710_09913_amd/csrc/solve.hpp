@@ -34,6 +34,7 @@ struct PcgWork {
   int64_t n = 0;
   int maxit = 0;
   DevBuf r, p, q, part, energy, scal, hist, rout, dx, yout, nrm;
+  DevBuf r32, p32, q32;  // FP32 vectors of the mixed iteration (allocated on first use)
   double* hhist = nullptr;  // pinned mirror of hist
   ~PcgWork() {
     if (hhist) (void)hipHostFree(hhist);
@@ -54,5 +55,14 @@ void vk_replace(const double* b, const double* y, const double* invd, double* r,
 void vk_dot(const double* a, const double* b, int64_t n, double* part, double* out, hipStream_t st);
 void vk_axpy1(double* x, const double* d, int64_t n, hipStream_t st);
 void vk_fill(double* x, double v, int64_t n, hipStream_t st);
+// The iteration on FP32 vectors (x FP64): the counterparts of vk_pcg_init, vk_pcg_xr,
+// vk_pcg_p and vk_replace; the inner products stay FP64.
+void vk_pcg_init32(const double* b, const double* y, const float* invd, float* r, float* p, int64_t n, double* part,
+                   PcgScalars* s, double* hist, hipStream_t st);
+void vk_pcg_xr32(double* x, float* r, const float* p, const float* q, const float* invd, const PcgScalars* s,
+                 int64_t n, double* part, hipStream_t st);
+void vk_pcg_p32(float* p, const float* r, const float* invd, const PcgScalars* s, int64_t n, hipStream_t st);
+void vk_replace32(const double* b, const double* y, const float* invd, float* r, float* p, int64_t n, double* part,
+                  PcgScalars* s, hipStream_t st);
 
 }  // namespace dogip
