@@ -77,6 +77,11 @@ static void set_invdiag(Op& op, const double* diag, hipStream_t st) {
   }
 }
 
+// Default tile size (waves of 64 cells): 8 for 3D orders >= 3, where the larger tile
+// shares fewer dofs (3D 64^3 P3: apply 4% faster than 4 waves); 4 elsewhere, where
+// 8 waves measured equal or slower.
+static int default_tile_waves(const Space& s) { return (s.dim == 3 && s.k >= 3) ? 8 : 4; }
+
 static void check_coef(const Space& s, int coef_kind) {
   DOGIP_CHECK(coef_kind >= DOGIP_COEF_SCALAR && coef_kind <= DOGIP_COEF_RAW_D, DOGIP_E_RANGE, "unknown coefficient form");
   DOGIP_CHECK(!(coef_kind == DOGIP_COEF_SYM && s.kind == DOGIP_WP), DOGIP_E_RANGE,
@@ -135,7 +140,7 @@ std::unique_ptr<Op> make_op(std::shared_ptr<const Space> sp, int coef_kind, cons
               "no unrolled kernel for this (dim, k, kind)");
   op->variant = variant;
   // tile size: requested (default 4 waves), halved until the LDS arrays fit in 64 KB
-  int te = 64 * (tile_waves ? tile_waves : 4);
+  int te = 64 * (tile_waves ? tile_waves : default_tile_waves(s));
   for (;;) {
     op->plan = make_tiles(s, te);
     if (op->plan.max_tile_dofs * 16 <= 65536 || te == 64) break;
@@ -202,7 +207,7 @@ std::unique_ptr<Op> make_op_qp(std::shared_ptr<const Space> sp, int n, const dou
   op->has32 = (flags & DOGIP_OP_FP32) != 0;
   op->variant = DOGIP_VARIANT_LOOPED;
   op->nq = int(wts.size());
-  int te = 64 * (tile_waves ? tile_waves : 4);
+  int te = 64 * (tile_waves ? tile_waves : default_tile_waves(s));
   for (;;) {
     op->plan = make_tiles(s, te);
     if (op->plan.max_tile_dofs * 16 <= 65536 || te == 64) break;

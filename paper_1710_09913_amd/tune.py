@@ -4,8 +4,9 @@ representative structured mesh, and caches the choice as JSON.
 
     python -m paper_1710_09913_amd.tune --dim 2 --kind se --k 1 2 3 4 --prec f64 f32
 
-Cache: $DOGIP_TUNE_CACHE, else ~/.cache/dogip/tune.json.  Operator creation uses the
-cached choice when tile_waves / variant are left at 0 (see ``tuned``).
+Cache: $DOGIP_TUNE_CACHE, else ~/.cache/dogip/tune.json.  ``tuned`` returns the cached
+choice to pass to ``Operator(..., tile_waves=, variant=)``; with 0 the library's built-in
+defaults apply.
 """
 
 from __future__ import annotations
