@@ -12,6 +12,7 @@ namespace dogip {
 
 struct BatchWork {
   int maxit = 0;
+  DevBuf r32, p32, q32;  // FP32 vectors of the mixed iteration
   DevBuf r, p, q, yout, part, energy, sc, rr_true, rr_min, iters, need, stalls, active, res, state, use64, last_rep;
   DevBuf act, rep, items_a, items_b, items_r;  // compacted problem and work-item lists
   int* h_lists = nullptr;                      // pinned: active, use64, need, act, rep
@@ -122,6 +123,10 @@ std::unique_ptr<Batch> make_batch(const std::vector<std::shared_ptr<Op>>& ops, h
   for (int p = 0; p < np; ++p)
     HIPCHK(hipMemcpyAsync(b->invd.as<double>() + voff[p], ops[p]->invdiag.p, size_t(voff[p + 1] - voff[p]) * sizeof(double),
                           hipMemcpyDeviceToDevice, st));
+  if (all32) {
+    b->invd32.alloc(size_t(std::max<int64_t>(voff[np], 1)) * sizeof(float));
+    launch_to_f32(b->invd.as<double>(), b->invd32.as<float>(), voff[np], st);
+  }
   HIPCHK(hipStreamSynchronize(st));
   // persistent grid: as many workgroups as fit on the device at once
   b->lds64 = size_t(max64) * (sizeof(double) + sizeof(double));
@@ -184,6 +189,12 @@ int batch_pcg(Batch& b, const double* rhs, double* x, const dogip_solve_opts& o,
   constexpr int GX_MAX = 1024;  // blocks per problem in the segmented vector kernels
   BatchWork& w = *b.w;
   const size_t ni = b.items_host.size();
+  if (mixed && !w.r32.p) {
+    const size_t vf = size_t(std::max<int64_t>(n, 1)) * sizeof(float);
+    w.r32.alloc(vf);
+    w.p32.alloc(vf);
+    w.q32.alloc(vf);
+  }
   if (!w.r.p) {
     const size_t vb = size_t(n) * sizeof(double);
     w.r.alloc(vb);
@@ -216,6 +227,11 @@ int batch_pcg(Batch& b, const double* rhs, double* x, const dogip_solve_opts& o,
   v.invd = b.invd.as<double>();
   v.r = w.r.as<double>();
   v.p = w.p.as<double>();
+  // mixed: r, p and A p in FP32 (x and the inner products FP64)
+  v.v32 = mixed;
+  v.invd32 = b.invd32.as<float>();
+  v.r32 = w.r32.as<float>();
+  v.p32 = w.p32.as<float>();
   v.part = w.part.as<double>();
   v.s = {w.sc.as<PcgScalars>(), w.rr_true.as<double>(), w.iters.as<int>(), w.need.as<int>(), w.stalls.as<int>(),
          w.active.as<int>(), w.state.as<int>(), w.use64.as<int>(), w.last_rep.as<int>(), w.rr_min.as<double>()};
@@ -240,18 +256,26 @@ int batch_pcg(Batch& b, const double* rhs, double* x, const dogip_solve_opts& o,
       if (sel(int(it >> 32))) out[c++] = it;
     return c;
   };
-  auto apply_list = [&](const double* u, double* y, int prec, const uint64_t* items, int64_t nitems, bool energy) {
+  // u, y: double, or float (the FP32 vectors of the mixed iteration) when f32
+  auto apply_list = [&](const void* u, void* y, bool f32, int prec, const uint64_t* items, int64_t nitems,
+                        bool energy) {
     if (nitems <= 0) return;
-    BatchLaunch bl = launch_args(b, u, y, prec);
+    BatchLaunch bl = launch_args(b, f32 ? nullptr : static_cast<const double*>(u),
+                                 f32 ? nullptr : static_cast<double*>(y), prec);
+    if (f32) {
+      bl.u32 = static_cast<const float*>(u);
+      bl.y32 = static_cast<float*>(y);
+    }
     bl.items = items;
     bl.nitems = nitems;
     bl.energy = energy ? w.energy.as<double>() : nullptr;
     const bool f64 = prec == DOGIP_F64;
     launch_batch_apply(b.dim, b.kind, bl, f64 ? b.grid64 : b.grid32, f64 ? b.lds64 : b.lds32, energy, st);
   };
-  auto finish_list = [&](const int* act, int nact, const double* u, double* y) {
+  auto finish_list = [&](const int* act, int nact, const void* u, void* y, bool f32) {
     bk_finish(v, act, nact, b.stage.as<double>(), b.rowptr.as<uint32_t>(), b.slots.as<uint32_t>(),
-              b.shared.as<int32_t>(), b.sh_off.as<int64_t>(), b.bnd.as<int32_t>(), b.bnd_off.as<int64_t>(), u, y, st);
+              b.shared.as<int32_t>(), b.sh_off.as<int64_t>(), b.bnd.as<int32_t>(), b.bnd_off.as<int64_t>(), u, y, f32,
+              st);
   };
   std::vector<int> iters(np), state(np), use64(np);
   int done_it = 0;
@@ -270,8 +294,8 @@ int batch_pcg(Batch& b, const double* rhs, double* x, const dogip_solve_opts& o,
         const int64_t nir = filter_items(h_ir, [&](int p) { return h_active[p] && h_need[p]; });
         HIPCHK(hipMemcpyAsync(w.rep.p, h_rep, sizeof(int) * nrep, hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(w.items_r.p, h_ir, sizeof(uint64_t) * nir, hipMemcpyHostToDevice, st));
-        apply_list(x, w.yout.as<double>(), DOGIP_F64, w.items_r.as<uint64_t>(), nir, false);
-        finish_list(w.rep.as<int>(), nrep, x, w.yout.as<double>());
+        apply_list(x, w.yout.as<double>(), false, DOGIP_F64, w.items_r.as<uint64_t>(), nir, false);
+        finish_list(w.rep.as<int>(), nrep, x, w.yout.as<double>(), false);
         BatchVecArgs vr = v;
         vr.act = w.rep.as<int>();
         vr.nact = nrep;
@@ -296,12 +320,14 @@ int batch_pcg(Batch& b, const double* rhs, double* x, const dogip_solve_opts& o,
     v.gx = std::min(GX_MAX, std::max(16, 8192 / nact));
     const int todo = std::min(check, o.maxit - done_it);
     for (int j = 0; j < todo; ++j) {
-      apply_list(v.p, w.q.as<double>(), mixed ? DOGIP_F32 : DOGIP_F64, w.items_a.as<uint64_t>(), nia, true);
-      apply_list(v.p, w.q.as<double>(), DOGIP_F64, w.items_b.as<uint64_t>(), nib, true);
-      finish_list(v.act, nact, v.p, w.q.as<double>());
+      const void* pv = mixed ? static_cast<const void*>(v.p32) : static_cast<const void*>(v.p);
+      void* qv = mixed ? static_cast<void*>(w.q32.p) : static_cast<void*>(w.q.p);
+      apply_list(pv, qv, mixed, mixed ? DOGIP_F32 : DOGIP_F64, w.items_a.as<uint64_t>(), nia, true);
+      apply_list(pv, qv, mixed, DOGIP_F64, w.items_b.as<uint64_t>(), nib, true);
+      finish_list(v.act, nact, pv, qv, mixed);
       HIPCHK(hipGetLastError());
       bk_fin_pq(v, w.energy.as<double>(), b.tile_base.as<int64_t>(), b.bnd.as<int32_t>(), b.bnd_off.as<int64_t>(), st);
-      bk_xr(v, x, w.q.as<double>(), st);
+      bk_xr(v, x, qv, st);
       bk_fin_rz(v, delta, mixed ? 1 : 0, st);
       bk_p(v, st);
     }

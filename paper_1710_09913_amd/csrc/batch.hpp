@@ -31,6 +31,8 @@ struct BatchLaunch {
   int64_t nitems;
   const double* u;
   double* y;
+  const float* u32;       // FP32 vectors (mixed CG): used instead of u and y when set
+  float* y32;
   double* stage;
   double* energy;         // [total tiles] tile energies (ENERGY launches)
   const int* active;      // optional: skip problems with active[p] == 0
@@ -58,6 +60,10 @@ struct BatchVecArgs {
   const double* invd;
   double* r;
   double* p;
+  bool v32;             // mixed CG: r, p (and A p) stored in FP32
+  const float* invd32;
+  float* r32;
+  float* p32;
   double* part;  // [np][gx][3]
   BatchPcgState s;
   const int* act;  // problems the per-iteration kernels work on
@@ -76,6 +82,7 @@ struct Batch {
   size_t lds64 = 0, lds32 = 0;
   unsigned grid64 = 0, grid32 = 0;
   DevBuf desc, items, counter, voff, stage, tile_base, shared, rowptr, slots, bnd, bnd_off, invd, sh_off;
+  DevBuf invd32;  // FP32 copy of invd (all operators with DOGIP_OP_FP32)
   std::vector<uint64_t> items_host;  // work items, largest first
   std::unique_ptr<BatchWork> w;
   ~Batch();
@@ -93,13 +100,14 @@ int batch_blocks_per_cu(int dim, int kind, int prec, size_t lds);
 void bk_init(const BatchVecArgs& v, const double* b, double* x, hipStream_t st);
 void bk_fin_pq(const BatchVecArgs& v, const double* energy, const int64_t* tile_base, const int32_t* bnd,
                const int64_t* bnd_off, hipStream_t st);
-void bk_xr(const BatchVecArgs& v, double* x, const double* q, hipStream_t st);
+void bk_xr(const BatchVecArgs& v, double* x, const void* q, hipStream_t st);
 void bk_fin_rz(const BatchVecArgs& v, double delta, int mixed, hipStream_t st);
 void bk_p(const BatchVecArgs& v, hipStream_t st);
 void bk_replace(const BatchVecArgs& v, const double* b, const double* y, int mixed, hipStream_t st);
 void bk_resid(const BatchVecArgs& v, const double* b, const double* y, double* out, hipStream_t st);
+// u, y: double, or float when f32
 void bk_finish(const BatchVecArgs& v, const int* act, int nact, const double* stage, const uint32_t* rowptr,
                const uint32_t* slots, const int32_t* shared, const int64_t* sh_off, const int32_t* bnd,
-               const int64_t* bnd_off, const double* u, double* y, hipStream_t st);
+               const int64_t* bnd_off, const void* u, void* y, bool f32, hipStream_t st);
 
 }  // namespace dogip

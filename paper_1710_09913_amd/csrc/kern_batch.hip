@@ -10,7 +10,7 @@ namespace dev {
 // Persistent apply: every workgroup takes (problem, tile) items from a queue
 // (largest work first) until the queue is exhausted; problems whose flag in
 // `active` (or `mask`) is zero are skipped.
-template <int D, int KIND, typename T, bool ENERGY>
+template <int D, int KIND, typename T, bool ENERGY, bool V32 = false>
 __global__ __launch_bounds__(256) void k_batch_apply(BatchLaunch bl) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ uint32_t cur;
@@ -30,8 +30,13 @@ __global__ __launch_bounds__(256) void k_batch_apply(BatchLaunch bl) {
     a.lidx = d.lidx;
     a.tile_off = d.tile_off;
     a.tile_dofs = d.tile_dofs;
-    a.u = bl.u + d.voff;
-    a.y = bl.y + d.voff;
+    if constexpr (V32) {
+      a.u32 = bl.u32 + d.voff;
+      a.y32 = bl.y32 + d.voff;
+    } else {
+      a.u = bl.u + d.voff;
+      a.y = bl.y + d.voff;
+    }
     a.stage_off = d.stage_off;
     a.stage = bl.stage + d.stage_base;
     a.nel = d.nel;
@@ -44,10 +49,10 @@ __global__ __launch_bounds__(256) void k_batch_apply(BatchLaunch bl) {
     constexpr int V = DOGIP_VARIANT_UNROLLED;
     constexpr int PF = sizeof(T) == 8 ? DOGIP_PF64 : DOGIP_PF32;
     switch (d.k) {
-      case 1: tile_body<D, 1, KIND, T, V, ENERGY, PF>(a, t, smem, eo); break;
-      case 2: tile_body<D, 2, KIND, T, V, ENERGY, PF>(a, t, smem, eo); break;
-      case 3: tile_body<D, 3, KIND, T, V, ENERGY, PF>(a, t, smem, eo); break;
-      default: tile_body<D, 4, KIND, T, V, ENERGY, PF>(a, t, smem, eo); break;
+      case 1: tile_body<D, 1, KIND, T, V, ENERGY, PF, 0, V32>(a, t, smem, eo); break;
+      case 2: tile_body<D, 2, KIND, T, V, ENERGY, PF, 0, V32>(a, t, smem, eo); break;
+      case 3: tile_body<D, 3, KIND, T, V, ENERGY, PF, 0, V32>(a, t, smem, eo); break;
+      default: tile_body<D, 4, KIND, T, V, ENERGY, PF, 0, V32>(a, t, smem, eo); break;
     }
     __syncthreads();
   }
@@ -97,19 +102,23 @@ __device__ __forceinline__ double bsum(const double* x, int64_t n, int64_t strid
   const int64_t lo = voff[p], hi = voff[p + 1]; \
   for (int64_t i = lo + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < hi; i += int64_t(gridDim.x) * blockDim.x)
 
-// r = b, z = invd r, p = z; partials (r.z, r.r, b.b)
+// r = b, z = invd r, p = z; partials (r.z, r.r, b.b).  V: storage type of r, p and
+// invd (FP32 in the mixed CG; the arithmetic and sums stay FP64, each value rounded once).
+template <typename V>
 __global__ __launch_bounds__(256) void k_b_init(const int* __restrict__ act, const int64_t* __restrict__ voff, const double* __restrict__ b,
-                                                const double* __restrict__ invd, double* __restrict__ r,
-                                                double* __restrict__ pv, double* __restrict__ x,
+                                                const V* __restrict__ invd, V* __restrict__ r,
+                                                V* __restrict__ pv, double* __restrict__ x,
                                                 double* __restrict__ part) {
   double v[3] = {0.0, 0.0, 0.0};
   PROBLEM_RANGE(p, lo, hi) {
-    const double bi = b[i], zi = invd[i] * bi;
-    r[i] = bi;
-    pv[i] = zi;
+    const double bi = b[i];
+    const V ri = V(bi);
+    const double zi = double(invd[i]) * double(ri);
+    r[i] = ri;
+    pv[i] = V(zi);
     x[i] = 0.0;
-    v[0] += bi * zi;
-    v[1] += bi * bi;
+    v[0] += double(ri) * zi;
+    v[1] += double(ri) * double(ri);
     v[2] += bi * bi;
   }
   bpartials(v, 3, part, p_of(act));
@@ -140,9 +149,10 @@ __global__ __launch_bounds__(256) void k_b_fin_init(const double* __restrict__ p
 }
 
 // pq = sum of the problem's tile energies + p_b^2 over its Dirichlet dofs; alpha = rho / pq
+template <typename V>
 __global__ __launch_bounds__(256) void k_b_fin_pq(const int* __restrict__ act, const double* __restrict__ energy,
                                                   const int64_t* __restrict__ tile_base, const int32_t* __restrict__ bnd,
-                                                  const int64_t* __restrict__ bnd_off, const double* __restrict__ pv,
+                                                  const int64_t* __restrict__ bnd_off, const V* __restrict__ pv,
                                                   BatchPcgState s) {
   const int p = act[blockIdx.x];
   if (!s.active[p]) return;
@@ -150,7 +160,7 @@ __global__ __launch_bounds__(256) void k_b_fin_pq(const int* __restrict__ act, c
   __shared__ double red[4];
   double q = 0.0;
   for (int64_t i = bnd_off[p] + threadIdx.x; i < bnd_off[p + 1]; i += blockDim.x) {
-    const double v = pv[bnd[i]];
+    const double v = double(pv[bnd[i]]);
     q += v * v;
   }
   q = bwave_sum(q);
@@ -172,20 +182,21 @@ __global__ __launch_bounds__(256) void k_b_fin_pq(const int* __restrict__ act, c
   }
 }
 
+template <typename V>
 __global__ __launch_bounds__(256) void k_b_xr(const int* __restrict__ act, const int64_t* __restrict__ voff,
-                                              double* __restrict__ x, double* __restrict__ r,
-                                              const double* __restrict__ pv, const double* __restrict__ q,
-                                              const double* __restrict__ invd, BatchPcgState s,
+                                              double* __restrict__ x, V* __restrict__ r,
+                                              const V* __restrict__ pv, const V* __restrict__ q,
+                                              const V* __restrict__ invd, BatchPcgState s,
                                               double* __restrict__ part) {
   if (!s.active[p_of(act)]) return;
   const double alpha = s.sc[p_of(act)].alpha;
   double v[2] = {0.0, 0.0};
   PROBLEM_RANGE(p, lo, hi) {
-    x[i] = fma(alpha, pv[i], x[i]);
-    const double ri = fma(-alpha, q[i], r[i]);
+    x[i] = fma(alpha, double(pv[i]), x[i]);
+    const V ri = V(fma(-alpha, double(q[i]), double(r[i])));
     r[i] = ri;
-    v[0] += ri * (invd[i] * ri);
-    v[1] += ri * ri;
+    v[0] += double(ri) * (double(invd[i]) * double(ri));
+    v[1] += double(ri) * double(ri);
   }
   bpartials(v, 2, part, p_of(act));
 }
@@ -217,30 +228,34 @@ __global__ __launch_bounds__(256) void k_b_fin_rz(const int* __restrict__ act, c
   }
 }
 
+template <typename V>
 __global__ __launch_bounds__(256) void k_b_p(const int* __restrict__ act, const int64_t* __restrict__ voff,
-                                             double* __restrict__ pv, const double* __restrict__ r,
-                                             const double* __restrict__ invd, BatchPcgState s) {
+                                             V* __restrict__ pv, const V* __restrict__ r,
+                                             const V* __restrict__ invd, BatchPcgState s) {
   if (!s.active[p_of(act)]) return;
   const double beta = s.sc[p_of(act)].beta;
-  PROBLEM_RANGE(p, lo, hi) pv[i] = fma(beta, pv[i], invd[i] * r[i]);
+  PROBLEM_RANGE(p, lo, hi) pv[i] = V(fma(beta, double(pv[i]), double(invd[i]) * double(r[i])));
 }
 
-// residual replacement for problems with need[p]: r = b - A64 x
+// residual replacement for problems with need[p]: r = b - A64 x (the true r.r from the
+// unrounded FP64 residual)
+template <typename V>
 __global__ __launch_bounds__(256) void k_b_replace(const int* __restrict__ act, const int64_t* __restrict__ voff,
                                                    const double* __restrict__ b, const double* __restrict__ y,
-                                                   const double* __restrict__ invd, double* __restrict__ r,
-                                                   double* __restrict__ pv, BatchPcgState s,
+                                                   const V* __restrict__ invd, V* __restrict__ r,
+                                                   V* __restrict__ pv, BatchPcgState s,
                                                    double* __restrict__ part) {
   if (!s.active[p_of(act)] || !s.need[p_of(act)]) return;
   const bool restart = s.need[p_of(act)] == 2;
   double v[2] = {0.0, 0.0};
   PROBLEM_RANGE(p, lo, hi) {
-    const double ri = b[i] - y[i];
-    const double zi = invd[i] * ri;
+    const double rd = b[i] - y[i];
+    const V ri = V(rd);
+    const double zi = double(invd[i]) * double(ri);
     r[i] = ri;
-    if (restart) pv[i] = zi;
-    v[0] += ri * zi;
-    v[1] += ri * ri;
+    if (restart) pv[i] = V(zi);
+    v[0] += double(ri) * zi;
+    v[1] += rd * rd;
   }
   bpartials(v, 2, part, p_of(act));
 }
@@ -300,11 +315,12 @@ __global__ __launch_bounds__(256) void k_b_resid(const int* __restrict__ act, co
 
 // Second pass of a batched apply restricted to the problems in act: shared-dof sums
 // and Dirichlet rows of each listed problem.
+template <typename V>
 __global__ __launch_bounds__(256) void k_b_finish(const int* __restrict__ act, const double* __restrict__ stage,
                                                   const uint32_t* __restrict__ rowptr, const uint32_t* __restrict__ slots,
                                                   const int32_t* __restrict__ shared, const int64_t* __restrict__ sh_off,
                                                   const int32_t* __restrict__ bnd, const int64_t* __restrict__ bnd_off,
-                                                  const double* __restrict__ u, double* __restrict__ y) {
+                                                  const V* __restrict__ u, V* __restrict__ y) {
   const int p = act[blockIdx.y];
   const int64_t s0 = sh_off[p], s1 = sh_off[p + 1], b0 = bnd_off[p], b1 = bnd_off[p + 1];
   const int64_t n = (s1 - s0) + (b1 - b0);
@@ -313,7 +329,7 @@ __global__ __launch_bounds__(256) void k_b_finish(const int* __restrict__ act, c
       const int64_t i = s0 + k;
       double acc = 0.0;
       for (uint32_t j = rowptr[i]; j < rowptr[i + 1]; ++j) acc += stage[slots[j]];
-      y[shared[i]] = acc;
+      y[shared[i]] = V(acc);
     } else {
       const int32_t d = bnd[b0 + k - (s1 - s0)];
       y[d] = u[d];
@@ -329,6 +345,13 @@ __global__ __launch_bounds__(256) void k_b_fin_resid(const double* __restrict__ 
 template <int D, int KIND>
 void batch_apply_t(const BatchLaunch& bl, unsigned grid, size_t lds, bool energy, hipStream_t st) {
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, bl.counter);
+  if (bl.u32) {  // FP32 vectors: the CG iteration (energy partials always taken)
+    if (bl.prec == DOGIP_F64)
+      hipLaunchKernelGGL((k_batch_apply<D, KIND, double, true, true>), dim3(grid), dim3(256), lds, st, bl);
+    else
+      hipLaunchKernelGGL((k_batch_apply<D, KIND, float, true, true>), dim3(grid), dim3(256), lds, st, bl);
+    return;
+  }
   if (bl.prec == DOGIP_F64) {
     if (energy)
       hipLaunchKernelGGL((k_batch_apply<D, KIND, double, true>), dim3(grid), dim3(256), lds, st, bl);
@@ -369,28 +392,48 @@ int batch_blocks_per_cu(int dim, int kind, int prec, size_t lds) {
 }
 
 void bk_init(const BatchVecArgs& v, const double* b, double* x, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_b_init, dim3(v.gx, v.np), dim3(256), 0, st, nullptr, v.voff, b, v.invd, v.r, v.p, x,
-                     v.part);
+  if (v.v32)
+    hipLaunchKernelGGL(dev::k_b_init<float>, dim3(v.gx, v.np), dim3(256), 0, st, nullptr, v.voff, b, v.invd32, v.r32,
+                       v.p32, x, v.part);
+  else
+    hipLaunchKernelGGL(dev::k_b_init<double>, dim3(v.gx, v.np), dim3(256), 0, st, nullptr, v.voff, b, v.invd, v.r,
+                       v.p, x, v.part);
   hipLaunchKernelGGL(dev::k_b_fin_init, dim3(v.np), dim3(256), 0, st, v.part, v.gx, v.s, v.tol);
 }
 void bk_fin_pq(const BatchVecArgs& v, const double* energy, const int64_t* tile_base, const int32_t* bnd,
                const int64_t* bnd_off, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_b_fin_pq, dim3(v.nact), dim3(256), 0, st, v.act, energy, tile_base, bnd, bnd_off, v.p,
-                     v.s);
+  if (v.v32)
+    hipLaunchKernelGGL(dev::k_b_fin_pq<float>, dim3(v.nact), dim3(256), 0, st, v.act, energy, tile_base, bnd, bnd_off,
+                       v.p32, v.s);
+  else
+    hipLaunchKernelGGL(dev::k_b_fin_pq<double>, dim3(v.nact), dim3(256), 0, st, v.act, energy, tile_base, bnd, bnd_off,
+                       v.p, v.s);
 }
-void bk_xr(const BatchVecArgs& v, double* x, const double* q, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_b_xr, dim3(v.gx, v.nact), dim3(256), 0, st, v.act, v.voff, x, v.r, v.p, q, v.invd, v.s,
-                     v.part);
+void bk_xr(const BatchVecArgs& v, double* x, const void* q, hipStream_t st) {
+  if (v.v32)
+    hipLaunchKernelGGL(dev::k_b_xr<float>, dim3(v.gx, v.nact), dim3(256), 0, st, v.act, v.voff, x, v.r32, v.p32,
+                       static_cast<const float*>(q), v.invd32, v.s, v.part);
+  else
+    hipLaunchKernelGGL(dev::k_b_xr<double>, dim3(v.gx, v.nact), dim3(256), 0, st, v.act, v.voff, x, v.r, v.p,
+                       static_cast<const double*>(q), v.invd, v.s, v.part);
 }
 void bk_fin_rz(const BatchVecArgs& v, double delta, int mixed, hipStream_t st) {
   hipLaunchKernelGGL(dev::k_b_fin_rz, dim3(v.nact), dim3(256), 0, st, v.act, v.part, v.gx, v.s, v.tol, delta, mixed);
 }
 void bk_p(const BatchVecArgs& v, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_b_p, dim3(v.gx, v.nact), dim3(256), 0, st, v.act, v.voff, v.p, v.r, v.invd, v.s);
+  if (v.v32)
+    hipLaunchKernelGGL(dev::k_b_p<float>, dim3(v.gx, v.nact), dim3(256), 0, st, v.act, v.voff, v.p32, v.r32, v.invd32,
+                       v.s);
+  else
+    hipLaunchKernelGGL(dev::k_b_p<double>, dim3(v.gx, v.nact), dim3(256), 0, st, v.act, v.voff, v.p, v.r, v.invd, v.s);
 }
 void bk_replace(const BatchVecArgs& v, const double* b, const double* y, int mixed, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_b_replace, dim3(v.gx, v.nact), dim3(256), 0, st, v.act, v.voff, b, y, v.invd, v.r, v.p,
-                     v.s, v.part);
+  if (v.v32)
+    hipLaunchKernelGGL(dev::k_b_replace<float>, dim3(v.gx, v.nact), dim3(256), 0, st, v.act, v.voff, b, y, v.invd32,
+                       v.r32, v.p32, v.s, v.part);
+  else
+    hipLaunchKernelGGL(dev::k_b_replace<double>, dim3(v.gx, v.nact), dim3(256), 0, st, v.act, v.voff, b, y, v.invd,
+                       v.r, v.p, v.s, v.part);
   hipLaunchKernelGGL(dev::k_b_fin_replace, dim3(v.nact), dim3(256), 0, st, v.act, v.part, v.gx, v.s, v.tol, mixed);
 }
 void bk_resid(const BatchVecArgs& v, const double* b, const double* y, double* out, hipStream_t st) {
@@ -400,10 +443,14 @@ void bk_resid(const BatchVecArgs& v, const double* b, const double* y, double* o
 
 void bk_finish(const BatchVecArgs& v, const int* act, int nact, const double* stage, const uint32_t* rowptr,
                const uint32_t* slots, const int32_t* shared, const int64_t* sh_off, const int32_t* bnd,
-               const int64_t* bnd_off, const double* u, double* y, hipStream_t st) {
+               const int64_t* bnd_off, const void* u, void* y, bool f32, hipStream_t st) {
   if (nact <= 0) return;
-  hipLaunchKernelGGL(dev::k_b_finish, dim3(v.gx, nact), dim3(256), 0, st, act, stage, rowptr, slots, shared, sh_off, bnd,
-                     bnd_off, u, y);
+  if (f32)
+    hipLaunchKernelGGL(dev::k_b_finish<float>, dim3(v.gx, nact), dim3(256), 0, st, act, stage, rowptr, slots, shared,
+                       sh_off, bnd, bnd_off, static_cast<const float*>(u), static_cast<float*>(y));
+  else
+    hipLaunchKernelGGL(dev::k_b_finish<double>, dim3(v.gx, nact), dim3(256), 0, st, act, stage, rowptr, slots, shared,
+                       sh_off, bnd, bnd_off, static_cast<const double*>(u), static_cast<double*>(y));
 }
 
 }  // namespace dogip
