@@ -94,6 +94,20 @@ extern "C" {
 /* FP64 iterative refinement that restarts an FP32-apply Jacobi-PCG for every
  * correction, each inner solve reducing its residual by inner_tol. */
 #define DOGIP_SOLVE_MIXED_RESTART 2
+/* Flexible CG preconditioned by a p-multigrid V-cycle (multigrid that fits the DoGIP
+ * structure, which Section 4 leaves to future work): the orders k, k-1, ..., 1 on the
+ * same mesh, each a DoGIP operator rebuilt from the operator's coefficient; the
+ * prolongation embeds P_{j-1} in P_j (nodal values), the restriction is its transpose;
+ * Chebyshev smoothing in D^-1 A (degree 2 on [lmax/30, 1.1 lmax], lmax by power
+ * iteration) before and after the coarse correction; the P_1 level solved by
+ * Jacobi-PCG to a relative residual of 0.1.  The hierarchy is built at the first such
+ * solve and kept until the coefficient changes.  Needs an element-wise operator built
+ * from a SCALAR, SYM or LOGSCALAR coefficient (else DOGIP_E_STATE).  iters counts outer
+ * iterations; convergence is verified on the true FP64 residual. */
+#define DOGIP_SOLVE_PMG 3
+/* The same with the V-cycle's applies (smoothing, coarse solve) in FP32; the outer CG
+ * and its residuals stay FP64.  Needs DOGIP_OP_FP32. */
+#define DOGIP_SOLVE_PMG_MIXED 4
 
 /* ---- dogip_op_create flags ---- */
 #define DOGIP_OP_FP32 1u /* also build the FP32 copy of D (needed by DOGIP_F32 and MIXED) */

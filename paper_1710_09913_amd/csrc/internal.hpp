@@ -110,6 +110,7 @@ GlobalPlan make_global_plan(const Space& s, const TilePlan& p);
 
 struct PcgWork;
 struct OpTimer;
+struct Pmg;
 
 struct Op {
   std::shared_ptr<const Space> space;
@@ -127,6 +128,11 @@ struct Op {
   DevBuf gw_rec, gw_off, gw_inc_ptr, gw_inc, dg64, dg32;
   std::unique_ptr<PcgWork> pcg;
   std::unique_ptr<OpTimer> timer;
+  // the coefficient the D was built from (for the coarser operators of the p-multigrid
+  // preconditioner); coef_kind_copy < 0 when D did not come from a coefficient form
+  int coef_kind_copy = -1;
+  DevBuf coef_copy;
+  std::unique_ptr<Pmg> pmg;  // p-multigrid hierarchy, built at the first multigrid solve
   ~Op();
 };
 
@@ -146,6 +152,9 @@ LatticeDofs number_lattice(const Mesh& m, int q, bool xyz);
 // reference gradients (elliptic) at the points, [nq][nb][vt].
 void collapsed_rule(int d, int n, std::vector<double>& pts, std::vector<double>& wts);
 void basis_table(int d, int k, int kind, const std::vector<double>& pts, std::vector<double>& tab);
+// Values of the order kf-1 basis at the order kf lattice nodes, [V_T(kf)][V_T(kf-1)]: the
+// embedding of P_{kf-1} in P_kf on the reference cell (p-multigrid prolongation).
+void coarse_basis_at_nodes(int d, int kf, std::vector<double>& tab);
 
 // ---- host setup ----
 std::shared_ptr<Mesh> make_mesh(int dim, int64_t nv, const double* xyz, int64_t nc, const int32_t* cells);

@@ -192,6 +192,58 @@ __global__ __launch_bounds__(256) void k_fill(double* __restrict__ x, double v, 
   GRID_STRIDE(i, n) x[i] = v;
 }
 
+// ---- p-multigrid pieces ----
+
+// y = M x for a CSR matrix (rows ascending; the sums in column order, deterministic)
+__global__ __launch_bounds__(256) void k_csr(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                             const double* __restrict__ val, const double* __restrict__ x,
+                                             double* __restrict__ y, int64_t nrows) {
+  GRID_STRIDE(i, nrows) {
+    double s = 0.0;
+    for (int64_t j = rowptr[i]; j < rowptr[i + 1]; ++j) s = fma(val[j], x[col[j]], s);
+    y[i] = s;
+  }
+}
+
+// d = s D^-1 r
+__global__ __launch_bounds__(256) void k_cheb_init(const double* __restrict__ r, const double* __restrict__ invd,
+                                                   double* __restrict__ d, double s, int64_t n) {
+  GRID_STRIDE(i, n) d[i] = s * invd[i] * r[i];
+}
+
+// one Chebyshev step after t = A d: x += d, r -= t, d = c1 d + c2 D^-1 r
+__global__ __launch_bounds__(256) void k_cheb_step(double* __restrict__ x, double* __restrict__ r,
+                                                   double* __restrict__ d, const double* __restrict__ t,
+                                                   const double* __restrict__ invd, double c1, double c2, int64_t n) {
+  GRID_STRIDE(i, n) {
+    const double di = d[i];
+    x[i] += di;
+    const double ri = r[i] - t[i];
+    r[i] = ri;
+    d[i] = fma(c1, di, c2 * invd[i] * ri);
+  }
+}
+
+// y = a x + b y
+__global__ __launch_bounds__(256) void k_axpby(double a, const double* x, double b, double* y,
+                                               int64_t n) {
+  GRID_STRIDE(i, n) y[i] = fma(a, x[i], b * y[i]);
+}
+
+// r = b - t
+__global__ __launch_bounds__(256) void k_sub(const double* __restrict__ b, const double* __restrict__ t,
+                                             double* __restrict__ r, int64_t n) {
+  GRID_STRIDE(i, n) r[i] = b[i] - t[i];
+}
+
+// deterministic start vector in [-1, 1): a multiplicative hash of the index
+__global__ __launch_bounds__(256) void k_hash_fill(double* __restrict__ v, int64_t n) {
+  GRID_STRIDE(i, n) {
+    const uint32_t h = uint32_t(uint64_t(i) * 2654435761ull) ^ uint32_t(uint64_t(i) >> 16);
+    v[i] = double(h) * (1.0 / 2147483648.0) - 1.0;
+  }
+}
+
 // ---- the same iteration on FP32 vectors r, p, q (x stays FP64; arithmetic and inner
 // products in FP64, each stored vector rounded once) ----
 
@@ -319,6 +371,28 @@ void vk_replace32(const double* b, const double* y, const float* invd, float* r,
                   PcgScalars* s, hipStream_t st) {
   hipLaunchKernelGGL(dev::k_replace32, dim3(RED_BLOCKS), dim3(256), 0, st, b, y, invd, r, p, n, part);
   hipLaunchKernelGGL(dev::k_fin_replace, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, s);
+}
+
+void vk_csr(const int64_t* rowptr, const int32_t* col, const double* val, const double* x, double* y, int64_t nrows,
+            hipStream_t st) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL(dev::k_csr, dim3(red_grid(nrows) * 4), dim3(256), 0, st, rowptr, col, val, x, y, nrows);
+}
+void vk_cheb_init(const double* r, const double* invd, double* d, double s, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_cheb_init, dim3(red_grid(n) * 4), dim3(256), 0, st, r, invd, d, s, n);
+}
+void vk_cheb_step(double* x, double* r, double* d, const double* t, const double* invd, double c1, double c2, int64_t n,
+                  hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_cheb_step, dim3(red_grid(n) * 4), dim3(256), 0, st, x, r, d, t, invd, c1, c2, n);
+}
+void vk_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_axpby, dim3(red_grid(n) * 4), dim3(256), 0, st, a, x, b, y, n);
+}
+void vk_sub(const double* b, const double* t, double* r, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_sub, dim3(red_grid(n) * 4), dim3(256), 0, st, b, t, r, n);
+}
+void vk_hash_fill(double* v, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_hash_fill, dim3(red_grid(n) * 4), dim3(256), 0, st, v, n);
 }
 
 void vk_fill(double* x, double v, int64_t n, hipStream_t st) {

@@ -6,6 +6,7 @@
 
 #include "internal.hpp"
 #include "reftab.hpp"
+#include "pmg.hpp"
 #include "solve.hpp"
 
 namespace dogip {
@@ -90,6 +91,17 @@ static void check_coef(const Space& s, int coef_kind) {
 
 static void build_d(Op& op, int coef_kind, const double* coef, hipStream_t st) {
   const Space& s = *op.space;
+  op.pmg.reset();
+  if (coef_kind == DOGIP_COEF_RAW_D || op.global_w) {
+    op.coef_kind_copy = -1;
+  } else {
+    const size_t per = coef_kind == DOGIP_COEF_SYM ? size_t(s.nsym) : 1;
+    const size_t bytes = std::max<size_t>(per * size_t(s.nc), 1) * sizeof(double);
+    if (op.coef_copy.bytes != bytes) op.coef_copy.alloc(bytes);
+    if (s.nc > 0) HIPCHK(hipMemcpyAsync(op.coef_copy.p, coef, per * size_t(s.nc) * sizeof(double),
+                                        hipMemcpyDeviceToDevice, st));
+    op.coef_kind_copy = coef_kind;
+  }
   BuildDLaunch b{};
   b.xyz = op.xyz.as<double>();
   b.cells = op.cells.as<int32_t>();
@@ -297,6 +309,8 @@ void op_set_inclusions(Op& op, int nballs, const double* balls, double a_in, dou
     for (int x = 0; x <= s.dim; ++x)
       DOGIP_CHECK(std::isfinite(balls[j * (s.dim + 1) + x]), DOGIP_E_INVALID, "non-finite ball");
   }
+  op.pmg.reset();
+  op.coef_kind_copy = -1;
   std::vector<double> pts, wts;
   collapsed_rule(s.dim, ng, pts, wts);
   DevBuf db(size_t(nballs) * (s.dim + 1) * sizeof(double)), dp(pts.size() * sizeof(double)),

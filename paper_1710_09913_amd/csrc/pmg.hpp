@@ -1,0 +1,36 @@
+// p-multigrid preconditioner: the spaces P_k, P_{k-1}, ..., P_1 on one mesh, their DoGIP
+// operators rebuilt from the fine operator's coefficient, and the transfers between them.
+#pragma once
+
+#include <memory>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace dogip {
+
+struct PmgLevel {
+  Op* op = nullptr;            // level 0: the fine operator itself
+  std::unique_ptr<Op> own;     // coarser levels
+  std::shared_ptr<Space> space;
+  // prolongation to the next finer level (this level's vector -> the finer one), and
+  // restriction (its transpose), both CSR with rows in ascending order
+  DevBuf prow, pcol, pval, rrow, rcol, rval;
+  int64_t n = 0, nfine = 0;
+  double lmax = 0.0;           // largest eigenvalue of D^-1 A (power iteration)
+  DevBuf x, b, r, d, t;        // V-cycle work vectors
+};
+
+struct Pmg {
+  std::vector<std::unique_ptr<PmgLevel>> lv;  // lv[0] finest
+  DevBuf r, z, zo, p, q;       // outer flexible CG vectors (fine)
+  DevBuf dots;                 // device scalars of the inner products
+};
+
+// Flexible CG on the fine operator preconditioned by one p-multigrid V-cycle per
+// iteration (Chebyshev-Jacobi smoothing, coarsest level by Jacobi-PCG); prec_inner:
+// the apply used inside the V-cycle.
+int op_pcg_pmg(Op& op, const double* b, double* x, const dogip_solve_opts& o, dogip_solve_stats& stats, int prec_inner,
+               hipStream_t st);
+
+}  // namespace dogip

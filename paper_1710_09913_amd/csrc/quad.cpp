@@ -115,4 +115,22 @@ void basis_table(int d, int k, int kind, const std::vector<double>& pts, std::ve
   }
 }
 
+void coarse_basis_at_nodes(int d, int kf, std::vector<double>& tab) {
+  const int kc = kf - 1, vf = dim_p(d, kf), vc = dim_p(d, kc);
+  tab.assign(size_t(vf) * vc, 0.0);
+  for (int l = 0; l < vf; ++l) {
+    int bf[4] = {0, 0, 0, 0};
+    ref::bary_index(d, kf, l, bf);
+    long double lam[4];
+    for (int j = 0; j <= d; ++j) lam[j] = (long double)bf[j] / kf;
+    for (int c = 0; c < vc; ++c) {
+      int b[4] = {0, 0, 0, 0};
+      if (kc > 0) ref::bary_index(d, kc, c, b);
+      long double v = 1.0L;
+      for (int j = 0; j <= d; ++j) v *= pf(kc, b[j], lam[j]);
+      tab[size_t(l) * vc + c] = std::fabs(double(v)) < 1e-13 ? 0.0 : double(v);
+    }
+  }
+}
+
 }  // namespace dogip

@@ -9,6 +9,7 @@
 #include <cstring>
 
 #include "internal.hpp"
+#include "pmg.hpp"
 #include "solve.hpp"
 
 namespace dogip {
@@ -212,6 +213,15 @@ static CgResult cg_run(Op& op, const double* b, double* x, bool x0_given, const 
   }
 }
 
+int cg_inner(Op& op, const double* b, double* x, double tol, int maxit, int prec, hipStream_t st) {
+  CgParams cp;
+  cp.tol = tol;
+  cp.maxit = std::max(1, maxit);
+  cp.prec = prec;
+  cp.reliable = false;
+  return cg_run(op, b, x, false, cp, st).iters;
+}
+
 // ||b - A x|| with the FP64 apply; writes the residual into r.
 static double true_residual(Op& op, const double* b, const double* x, double* r, hipStream_t st) {
   PcgWork& w = *op.pcg;
@@ -237,8 +247,9 @@ int op_pcg(Op& op, const double* b, double* x, const dogip_solve_opts& o, dogip_
   DOGIP_CHECK(b && x, DOGIP_E_NULL, "null vector");
   DOGIP_CHECK(b != x, DOGIP_E_INVALID, "b and x must differ");
   DOGIP_CHECK(o.tol > 0.0 && o.maxit >= 1, DOGIP_E_RANGE, "tol must be > 0 and maxit >= 1");
-  DOGIP_CHECK(o.mode >= DOGIP_SOLVE_F64 && o.mode <= DOGIP_SOLVE_MIXED_RESTART, DOGIP_E_RANGE, "unknown solve mode");
-  DOGIP_CHECK(o.mode == DOGIP_SOLVE_F64 || op.has32, DOGIP_E_STATE, "mixed mode needs DOGIP_OP_FP32");
+  DOGIP_CHECK(o.mode >= DOGIP_SOLVE_F64 && o.mode <= DOGIP_SOLVE_PMG_MIXED, DOGIP_E_RANGE, "unknown solve mode");
+  DOGIP_CHECK(o.mode == DOGIP_SOLVE_F64 || o.mode == DOGIP_SOLVE_PMG || op.has32, DOGIP_E_STATE,
+              "mixed mode needs DOGIP_OP_FP32");
   const auto t0 = std::chrono::steady_clock::now();
   std::memset(&stats, 0, sizeof stats);
   const int check = o.check_every > 0 ? o.check_every : 16;
@@ -248,7 +259,11 @@ int op_pcg(Op& op, const double* b, double* x, const dogip_solve_opts& o, dogip_
   cp.tol = o.tol;
   cp.maxit = o.maxit;
   cp.check_every = check;
-  if (o.mode == DOGIP_SOLVE_F64 || o.mode == DOGIP_SOLVE_MIXED) {
+  if (o.mode == DOGIP_SOLVE_PMG || o.mode == DOGIP_SOLVE_PMG_MIXED) {
+    // flexible CG preconditioned by p-multigrid V-cycles (FP64 outside; the V-cycle's
+    // applies in FP32 for PMG_MIXED)
+    status = op_pcg_pmg(op, b, x, o, stats, o.mode == DOGIP_SOLVE_PMG ? DOGIP_F64 : DOGIP_F32, st);
+  } else if (o.mode == DOGIP_SOLVE_F64 || o.mode == DOGIP_SOLVE_MIXED) {
     // FP64: plain Jacobi-PCG.  MIXED: the same iteration with the FP32 apply, the
     // vectors r, p, q in FP32 (x and the inner products FP64), and FP64 residual
     // replacement (reliable updates).  In both modes apparent convergence is verified
@@ -339,7 +354,9 @@ int op_pcg(Op& op, const double* b, double* x, const dogip_solve_opts& o, dogip_
   // verified residual with the FP64 apply
   if (status == DOGIP_OK || status == DOGIP_E_NOT_CONVERGED) {
     const double bn = std::sqrt(norm2(op, b, st));
-    stats.relres_true = bn > 0 ? true_residual(op, b, x, w.rout.as<double>(), st) / bn : 0.0;
+    // (op.pcg, not w: an inner solve of the multigrid's coarsest level on this same
+    // operator may have regrown the work buffers)
+    stats.relres_true = bn > 0 ? true_residual(op, b, x, op.pcg->rout.as<double>(), st) / bn : 0.0;
   }
   HIPCHK(hipStreamSynchronize(st));
   stats.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -53,8 +53,21 @@ void vk_resid(const double* b, const double* y, double* r, int64_t n, double* pa
 void vk_replace(const double* b, const double* y, const double* invd, double* r, double* p, int64_t n, double* part,
                 PcgScalars* s, hipStream_t st);
 void vk_dot(const double* a, const double* b, int64_t n, double* part, double* out, hipStream_t st);
+// Plain Jacobi-PCG from x = 0 to the recursive relative residual tol (at most maxit
+// iterations, no replacement): the inner solve of the multigrid coarsest level.
+// Returns the iterations run.
+int cg_inner(Op& op, const double* b, double* x, double tol, int maxit, int prec, hipStream_t st);
 void vk_axpy1(double* x, const double* d, int64_t n, hipStream_t st);
 void vk_fill(double* x, double v, int64_t n, hipStream_t st);
+// p-multigrid: CSR product, Chebyshev smoothing steps, axpby, difference, start vector
+void vk_csr(const int64_t* rowptr, const int32_t* col, const double* val, const double* x, double* y, int64_t nrows,
+            hipStream_t st);
+void vk_cheb_init(const double* r, const double* invd, double* d, double s, int64_t n, hipStream_t st);
+void vk_cheb_step(double* x, double* r, double* d, const double* t, const double* invd, double c1, double c2, int64_t n,
+                  hipStream_t st);
+void vk_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t st);
+void vk_sub(const double* b, const double* t, double* r, int64_t n, hipStream_t st);
+void vk_hash_fill(double* v, int64_t n, hipStream_t st);
 // The iteration on FP32 vectors (x FP64): the counterparts of vk_pcg_init, vk_pcg_xr,
 // vk_pcg_p and vk_replace; the inner products stay FP64.
 void vk_pcg_init32(const double* b, const double* y, const float* invd, float* r, float* p, int64_t n, double* part,

@@ -18,7 +18,8 @@ BC = {"none": capi.DOGIP_BC_NONE, "dirichlet": capi.DOGIP_BC_DIRICHLET0}
 COEF = {"scalar": capi.DOGIP_COEF_SCALAR, "sym": capi.DOGIP_COEF_SYM, "logscalar": capi.DOGIP_COEF_LOGSCALAR,
         "raw_d": capi.DOGIP_COEF_RAW_D}
 PREC = {"f64": capi.DOGIP_F64, "f32": capi.DOGIP_F32}
-SOLVE = {"f64": capi.DOGIP_SOLVE_F64, "mixed": capi.DOGIP_SOLVE_MIXED, "mixed_restart": capi.DOGIP_SOLVE_MIXED_RESTART}
+SOLVE = {"f64": capi.DOGIP_SOLVE_F64, "mixed": capi.DOGIP_SOLVE_MIXED, "mixed_restart": capi.DOGIP_SOLVE_MIXED_RESTART,
+         "pmg": capi.DOGIP_SOLVE_PMG, "pmg_mixed": capi.DOGIP_SOLVE_PMG_MIXED}
 
 
 def stream_ptr(stream=None) -> int:
