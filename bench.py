@@ -561,7 +561,7 @@ def main(argv=None):
                                   "replacement (reliable updates)")
         res["mixed_restart"]["method"] = "FP64 iterative refinement around restarted FP32-apply PCG (inner 1e-4)"
         res["pmg"]["method"] = ("flexible CG, p-multigrid V-cycle preconditioner (orders k..1 on the same mesh, "
-                                "Chebyshev degree 2 smoothing, P1 level by Jacobi-PCG to 0.1); first call builds "
+                                "Chebyshev degree 3 smoothing on [lmax/8, 1.1 lmax], P1 level by Jacobi-PCG to 0.1); first call builds "
                                 "the hierarchy")
         res["pmg_mixed"]["method"] = "the same with the V-cycle's applies in FP32"
         res["speedup_pmg_mixed_vs_f64"] = round(res["f64"]["seconds"] / res["pmg_mixed"]["seconds"], 3)

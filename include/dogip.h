@@ -98,12 +98,13 @@ extern "C" {
  * structure, which Section 4 leaves to future work): the orders k, k-1, ..., 1 on the
  * same mesh, each a DoGIP operator rebuilt from the operator's coefficient; the
  * prolongation embeds P_{j-1} in P_j (nodal values), the restriction is its transpose;
- * Chebyshev smoothing in D^-1 A (degree 2 on [lmax/30, 1.1 lmax], lmax by power
+ * Chebyshev smoothing in D^-1 A (degree 3 on [lmax/8, 1.1 lmax], lmax by power
  * iteration) before and after the coarse correction; the P_1 level solved by
- * Jacobi-PCG to a relative residual of 0.1.  The hierarchy is built at the first such
- * solve and kept until the coefficient changes.  Needs an element-wise operator built
- * from a SCALAR, SYM or LOGSCALAR coefficient (else DOGIP_E_STATE).  iters counts outer
- * iterations; convergence is verified on the true FP64 residual. */
+ * Jacobi-PCG to a relative residual of 0.1 (or inner_tol, when in (0, 1)).  The
+ * hierarchy is built at the first such solve and kept until the coefficient changes.
+ * Needs an element-wise operator built from a SCALAR, SYM or LOGSCALAR coefficient
+ * (else DOGIP_E_STATE).  iters counts outer iterations; convergence is verified on
+ * the true FP64 residual. */
 #define DOGIP_SOLVE_PMG 3
 /* The same with the V-cycle's applies (smoothing, coarse solve) in FP32; the outer CG
  * and its residuals stay FP64.  Needs DOGIP_OP_FP32. */
@@ -153,8 +154,9 @@ typedef struct {
 typedef struct {
   double tol;          /* stop when ||b - A x||_2 <= tol ||b||_2 */
   int32_t maxit;       /* CG iteration cap (all inner iterations in mixed mode) */
-  int32_t mode;        /* DOGIP_SOLVE_F64, DOGIP_SOLVE_MIXED or DOGIP_SOLVE_MIXED_RESTART */
-  double inner_tol;    /* MIXED: replacement factor delta; MIXED_RESTART: reduction per inner solve */
+  int32_t mode;        /* one of the DOGIP_SOLVE_* modes above */
+  double inner_tol;    /* MIXED: replacement factor delta; MIXED_RESTART: reduction per inner solve;
+                          PMG modes: the coarsest level's relative residual */
   int32_t max_outer;   /* mixed: refinement steps cap */
   int32_t check_every; /* CG iterations between host-side convergence checks (>= 1) */
   int32_t x0_given;    /* nonzero: x holds the initial guess; else x0 = 0 */

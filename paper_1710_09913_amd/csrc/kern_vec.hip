@@ -1,6 +1,7 @@
 // Vector kernels of the Jacobi-preconditioned CG (FP64 vectors and inner products).
 // Reductions are deterministic: a fixed grid of RED_BLOCKS x 256 threads writes
 // per-block partials, and a single 1024-thread block sums them in a fixed order.
+#include <algorithm>
 #include "kern_common.hpp"
 #include "solve.hpp"
 
@@ -195,13 +196,23 @@ __global__ __launch_bounds__(256) void k_fill(double* __restrict__ x, double v, 
 // ---- p-multigrid pieces ----
 
 // y = M x for a CSR matrix (rows ascending; the sums in column order, deterministic)
+// y = A x (ACC: y += A x) for a CSR matrix, G lanes per row: the lanes of a group stride
+// over the row's entries (coalesced reads of col and val), then a butterfly inside the
+// group adds their partial sums in a fixed order
+template <int G, bool ACC>
 __global__ __launch_bounds__(256) void k_csr(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                                              const double* __restrict__ val, const double* __restrict__ x,
                                              double* __restrict__ y, int64_t nrows) {
-  GRID_STRIDE(i, nrows) {
+  const int lane = int(threadIdx.x) % G;
+  const int64_t stride = int64_t(gridDim.x) * (256 / G);
+  // the loop bound is the same for all lanes of a group, so the shuffles see the
+  // whole group active
+  for (int64_t row = (int64_t(blockIdx.x) * 256 + threadIdx.x) / G; row < nrows; row += stride) {
     double s = 0.0;
-    for (int64_t j = rowptr[i]; j < rowptr[i + 1]; ++j) s = fma(val[j], x[col[j]], s);
-    y[i] = s;
+    const int64_t e = rowptr[row + 1];
+    for (int64_t j = rowptr[row] + lane; j < e; j += G) s = fma(val[j], x[col[j]], s);
+    for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
+    if (lane == 0) y[row] = ACC ? y[row] + s : s;
   }
 }
 
@@ -373,10 +384,28 @@ void vk_replace32(const double* b, const double* y, const float* invd, float* r,
   hipLaunchKernelGGL(dev::k_fin_replace, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, s);
 }
 
+template <int G>
+static void csr_launch(const int64_t* rowptr, const int32_t* col, const double* val, const double* x, double* y,
+                       int64_t nrows, bool acc, hipStream_t st) {
+  const int64_t g = std::min<int64_t>((nrows + 256 / G - 1) / (256 / G), 16384);
+  if (acc)
+    hipLaunchKernelGGL((dev::k_csr<G, true>), dim3(unsigned(g)), dim3(256), 0, st, rowptr, col, val, x, y, nrows);
+  else
+    hipLaunchKernelGGL((dev::k_csr<G, false>), dim3(unsigned(g)), dim3(256), 0, st, rowptr, col, val, x, y, nrows);
+}
+
 void vk_csr(const int64_t* rowptr, const int32_t* col, const double* val, const double* x, double* y, int64_t nrows,
-            hipStream_t st) {
+            int64_t nnz, bool accumulate, hipStream_t st) {
   if (nrows <= 0) return;
-  hipLaunchKernelGGL(dev::k_csr, dim3(red_grid(nrows) * 4), dim3(256), 0, st, rowptr, col, val, x, y, nrows);
+  const double mean = double(nnz) / double(nrows);
+  if (mean <= 3.0)
+    csr_launch<2>(rowptr, col, val, x, y, nrows, accumulate, st);
+  else if (mean <= 6.0)
+    csr_launch<4>(rowptr, col, val, x, y, nrows, accumulate, st);
+  else if (mean <= 24.0)
+    csr_launch<8>(rowptr, col, val, x, y, nrows, accumulate, st);
+  else
+    csr_launch<16>(rowptr, col, val, x, y, nrows, accumulate, st);
 }
 void vk_cheb_init(const double* r, const double* invd, double* d, double s, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(dev::k_cheb_init, dim3(red_grid(n) * 4), dim3(256), 0, st, r, invd, d, s, n);

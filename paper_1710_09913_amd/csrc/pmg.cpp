@@ -6,8 +6,8 @@
 // operator's coefficient.  The prolongation from P_{j-1} to P_j is the embedding of the
 // coarse space: a fine dof takes the coarse function's value at its node, evaluated in
 // one cell holding it (all agree, the functions being continuous); the restriction is its
-// transpose.  A V-cycle smooths with Chebyshev polynomials in D^-1 A (degree 2 on
-// [lmax/30, 1.1 lmax], lmax by power iteration) before and after the coarse correction,
+// transpose.  A V-cycle smooths with Chebyshev polynomials in D^-1 A (degree 3 on
+// [lmax/8, 1.1 lmax], lmax by power iteration) before and after the coarse correction,
 // and solves the P_1 level by Jacobi-PCG to a relative residual of 0.1.  The inner solve
 // makes the preconditioner vary between applications, hence the flexible
 // (Polak-Ribiere) CG outside.
@@ -22,8 +22,8 @@ namespace dogip {
 
 namespace {
 
-constexpr int CHEB_DEGREE = 2;
-constexpr double CHEB_RANGE = 30.0;
+constexpr int CHEB_DEGREE = 3;
+constexpr double CHEB_RANGE = 8.0;
 constexpr double COARSE_TOL = 0.1;
 constexpr int COARSE_MAXIT = 400;
 constexpr int POWER_ITERS = 15;
@@ -97,6 +97,7 @@ void build_transfer(const Space& F, const Space& Cs, PmgLevel& C) {
   up(C.rcol, rcol);
   up(C.rval, rval);
   C.nfine = F.ndofs;
+  C.nnz = int64_t(pcol.size());
 }
 
 double power_lmax(Op& op, PmgLevel& L, Dots& dd, hipStream_t st) {
@@ -140,8 +141,10 @@ void build(Op& op, hipStream_t st) {
   for (auto& Lp : P->lv) {
     PmgLevel& L = *Lp;
     const size_t vb = std::max<int64_t>(L.n, 1) * sizeof(double);
-    L.x.alloc(vb);
-    L.b.alloc(vb);
+    if (Lp != P->lv.front()) {
+      L.x.alloc(vb);
+      L.b.alloc(vb);
+    }
     L.r.alloc(vb);
     L.d.alloc(vb);
     L.t.alloc(vb);
@@ -158,12 +161,12 @@ void build(Op& op, hipStream_t st) {
   op.pmg = std::move(P);
 }
 
-// Chebyshev smoothing of A x = b at level L (from x = 0 when first)
-void smooth(PmgLevel& L, int prec, bool first, hipStream_t st) {
+// Chebyshev smoothing of A x = b at level L (from x = 0 when first).  On return r holds
+// the recursively updated residual b - A x (each step subtracts A d as it adds d to x).
+void smooth(PmgLevel& L, double* x, const double* b, int prec, bool first, hipStream_t st) {
   Op& A = *L.op;
   const int64_t n = L.n;
-  double *x = L.x.as<double>(), *b = L.b.as<double>(), *r = L.r.as<double>(), *d = L.d.as<double>(),
-         *t = L.t.as<double>();
+  double *r = L.r.as<double>(), *d = L.d.as<double>(), *t = L.t.as<double>();
   const double* invd = A.invdiag.as<double>();
   const double hi = 1.1 * L.lmax, lo = L.lmax / CHEB_RANGE;
   const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
@@ -184,33 +187,26 @@ void smooth(PmgLevel& L, int prec, bool first, hipStream_t st) {
   }
 }
 
-void vcycle(Pmg& P, size_t j, int prec, hipStream_t st) {
+// x ~= A^-1 b at level j
+void vcycle(Pmg& P, size_t j, const double* b, double* x, int prec, hipStream_t st) {
   PmgLevel& L = *P.lv[j];
   Op& A = *L.op;
   const int64_t n = L.n;
   if (j + 1 == P.lv.size()) {
-    vk_fill(L.x.as<double>(), 0.0, n, st);
-    cg_inner(A, L.b.as<double>(), L.x.as<double>(), COARSE_TOL, COARSE_MAXIT, prec, st);
+    vk_fill(x, 0.0, n, st);
+    cg_inner(A, b, x, P.coarse_tol, COARSE_MAXIT, prec, st);
     return;
   }
-  smooth(L, prec, true, st);
-  op_apply(A, L.x.as<double>(), L.t.as<double>(), prec, st);
-  vk_sub(L.b.as<double>(), L.t.as<double>(), L.r.as<double>(), n, st);
+  smooth(L, x, b, prec, true, st);
+  // restrict the residual the smoother leaves in r; zero the coarse Dirichlet rows
   PmgLevel& C = *P.lv[j + 1];
-  vk_csr(C.rrow.as<int64_t>(), C.rcol.as<int32_t>(), C.rval.as<double>(), L.r.as<double>(), C.b.as<double>(), C.n, st);
+  vk_csr(C.rrow.as<int64_t>(), C.rcol.as<int32_t>(), C.rval.as<double>(), L.r.as<double>(), C.b.as<double>(), C.n,
+         C.nnz, false, st);
   launch_zero_indexed(C.b.as<double>(), C.op->bnd.as<int32_t>(), int64_t(C.op->space->boundary.size()), st);
-  vcycle(P, j + 1, prec, st);
-  vk_csr(C.prow.as<int64_t>(), C.pcol.as<int32_t>(), C.pval.as<double>(), C.x.as<double>(), L.t.as<double>(), n, st);
-  vk_axpby(1.0, L.t.as<double>(), 1.0, L.x.as<double>(), n, st);
-  smooth(L, prec, false, st);
-}
-
-// z = M^-1 r by one V-cycle
-void precondition(Pmg& P, const double* r, double* z, int prec, hipStream_t st) {
-  PmgLevel& L = *P.lv[0];
-  copy(L.b.as<double>(), r, L.n, st);
-  vcycle(P, 0, prec, st);
-  copy(z, L.x.as<double>(), L.n, st);
+  vcycle(P, j + 1, C.b.as<double>(), C.x.as<double>(), prec, st);
+  // x += P x_c
+  vk_csr(C.prow.as<int64_t>(), C.pcol.as<int32_t>(), C.pval.as<double>(), C.x.as<double>(), x, n, C.nnz, true, st);
+  smooth(L, x, b, prec, false, st);
 }
 
 }  // namespace
@@ -219,6 +215,7 @@ int op_pcg_pmg(Op& op, const double* b, double* x, const dogip_solve_opts& o, do
                hipStream_t st) {
   if (!op.pmg) build(op, st);
   Pmg& P = *op.pmg;
+  P.coarse_tol = (o.inner_tol > 0.0 && o.inner_tol < 1.0) ? o.inner_tol : COARSE_TOL;
   const int64_t n = op.space->ndofs;
   Dots dd{P.dots.as<double>(), P.dots.as<double>() + RED_BLOCKS};
   double *r = P.r.as<double>(), *p = P.p.as<double>(), *q = P.q.as<double>();
@@ -243,7 +240,7 @@ int op_pcg_pmg(Op& op, const double* b, double* x, const dogip_solve_opts& o, do
   double rr = dot(dd, r, r, n, st);
   stats.relres = std::sqrt(rr / bb);
   if (rr <= thr) return DOGIP_OK;
-  precondition(P, r, z, prec, st);
+  vcycle(P, 0, r, z, prec, st);
   copy(p, z, n, st);
   double rz = dot(dd, r, z, n, st);
   while (it < o.maxit) {
@@ -278,13 +275,13 @@ int op_pcg_pmg(Op& op, const double* b, double* x, const dogip_solve_opts& o, do
         break;
       }
       if (++restarts > MAX_RESTARTS) break;
-      precondition(P, r, z, prec, st);
+      vcycle(P, 0, r, z, prec, st);
       copy(p, z, n, st);
       rz = dot(dd, r, z, n, st);
       continue;
     }
     std::swap(z, zo);
-    precondition(P, r, z, prec, st);
+    vcycle(P, 0, r, z, prec, st);
     const double rzn = dot(dd, r, z, n, st), rzo = dot(dd, r, zo, n, st);
     const double beta = (rzn - rzo) / rz;
     vk_axpby(1.0, z, beta, p, n, st);

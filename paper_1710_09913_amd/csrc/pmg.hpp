@@ -16,15 +16,18 @@ struct PmgLevel {
   // prolongation to the next finer level (this level's vector -> the finer one), and
   // restriction (its transpose), both CSR with rows in ascending order
   DevBuf prow, pcol, pval, rrow, rcol, rval;
-  int64_t n = 0, nfine = 0;
+  int64_t n = 0, nfine = 0, nnz = 0;
   double lmax = 0.0;           // largest eigenvalue of D^-1 A (power iteration)
-  DevBuf x, b, r, d, t;        // V-cycle work vectors
+  DevBuf x, b;                 // the level's correction and right-hand side (not on level 0,
+                               // which works on the outer CG's vectors)
+  DevBuf r, d, t;              // V-cycle work vectors
 };
 
 struct Pmg {
   std::vector<std::unique_ptr<PmgLevel>> lv;  // lv[0] finest
   DevBuf r, z, zo, p, q;       // outer flexible CG vectors (fine)
   DevBuf dots;                 // device scalars of the inner products
+  double coarse_tol = 0.1;     // relative residual of the coarsest level's inner solve
 };
 
 // Flexible CG on the fine operator preconditioned by one p-multigrid V-cycle per

@@ -60,8 +60,10 @@ int cg_inner(Op& op, const double* b, double* x, double tol, int maxit, int prec
 void vk_axpy1(double* x, const double* d, int64_t n, hipStream_t st);
 void vk_fill(double* x, double v, int64_t n, hipStream_t st);
 // p-multigrid: CSR product, Chebyshev smoothing steps, axpby, difference, start vector
+// y = A x (accumulate: y += A x); a group of lanes per row, the group size from the
+// mean row length nnz / nrows; deterministic (fixed reduction order)
 void vk_csr(const int64_t* rowptr, const int32_t* col, const double* val, const double* x, double* y, int64_t nrows,
-            hipStream_t st);
+            int64_t nnz, bool accumulate, hipStream_t st);
 void vk_cheb_init(const double* r, const double* invd, double* d, double s, int64_t n, hipStream_t st);
 void vk_cheb_step(double* x, double* r, double* d, const double* t, const double* invd, double c1, double c2, int64_t n,
                   hipStream_t st);
