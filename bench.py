@@ -394,7 +394,7 @@ def run_inclusions(a):
     suits): 3D 64^3 P3 elliptic with a = 100 inside 64 random balls (radius 0.04..0.1) and
     1 outside.  D comes from sub-cell quadrature (red refinement of cut sub-simplices, depth
     3, collapsed Gauss 3^3 per leaf); reports its build time and quadrature points per
-    cell, the apply (unchanged), FP64 vs mixed PCG to 1e-8, and a quadrature-point apply
+    cell, the apply (unchanged), PCG to 1e-8 (FP64, mixed, p-multigrid), and a quadrature-point apply
     that would evaluate about as many points at every apply."""
     import numpy as np
     import torch
@@ -422,13 +422,20 @@ def run_inclusions(a):
         ms, tms, fms = time_apply(op, u, y, prec, a.steps, a.warmup)
         res["apply_" + prec] = {"ms": round(ms, 5), "GDoF_s": round(space.ndofs / (ms * 1e-3) / 1e9, 3)}
     b = _rhs_f1(space, mesh, a.k)
-    for mode in ("f64", "mixed"):
+    for mode in ("f64", "mixed", "pmg", "pmg_mixed"):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        # warm-up: workspace (and, for the multigrid modes, the hierarchy: each level's D by
+        # the same sub-cell quadrature)
         op.pcg(b, tol=1e-8, maxit=100000, mode=mode, raise_on_error=False)
         torch.cuda.synchronize()
+        first = time.time() - t0
         t0 = time.time()
         _, st = op.pcg(b, tol=1e-8, maxit=100000, mode=mode, raise_on_error=False)
         res["pcg_" + mode] = {"seconds": round(time.time() - t0, 4), "iters": st["iters"], "status": st["status"],
                               "relres_true": st["relres_true"]}
+        if mode.startswith("pmg"):
+            res["pcg_" + mode]["first_call_seconds"] = round(first, 4)
         log(f"[incl] pcg {mode} {res['pcg_' + mode]}")
     n_eq = max(2, int(round(mean_pts ** (1.0 / 3.0))))
     q = Operator.quadrature(space, n_eq, torch.ones(space.ncells * n_eq ** 3, dtype=torch.float64))

@@ -102,8 +102,9 @@ extern "C" {
  * iteration) before and after the coarse correction; the P_1 level solved by
  * Jacobi-PCG to a relative residual of 0.1 (or inner_tol, when in (0, 1)).  The
  * hierarchy is built at the first such solve and kept until the coefficient changes.
- * Needs an element-wise operator built from a SCALAR, SYM or LOGSCALAR coefficient
- * (else DOGIP_E_STATE).  iters counts outer iterations; convergence is verified on
+ * Needs an element-wise operator whose D came from a SCALAR, SYM or LOGSCALAR
+ * coefficient or from dogip_op_set_inclusions (each level's D is rebuilt the same way),
+ * else DOGIP_E_STATE.  iters counts outer iterations; convergence is verified on
  * the true FP64 residual. */
 #define DOGIP_SOLVE_PMG 3
 /* The same with the V-cycle's applies (smoothing, coarse solve) in FP32; the outer CG

@@ -132,6 +132,10 @@ struct Op {
   // preconditioner); coef_kind_copy < 0 when D did not come from a coefficient form
   int coef_kind_copy = -1;
   DevBuf coef_copy;
+  // or the inclusion coefficient D was built from by sub-cell quadrature (inc_depth >= 0)
+  std::vector<double> inc_balls;
+  double inc_in = 0.0, inc_out = 0.0;
+  int inc_depth = -1, inc_ng = 0;
   std::unique_ptr<Pmg> pmg;  // p-multigrid hierarchy, built at the first multigrid solve
   ~Op();
 };

@@ -92,6 +92,7 @@ static void check_coef(const Space& s, int coef_kind) {
 static void build_d(Op& op, int coef_kind, const double* coef, hipStream_t st) {
   const Space& s = *op.space;
   op.pmg.reset();
+  op.inc_depth = -1;
   if (coef_kind == DOGIP_COEF_RAW_D || op.global_w) {
     op.coef_kind_copy = -1;
   } else {
@@ -311,6 +312,7 @@ void op_set_inclusions(Op& op, int nballs, const double* balls, double a_in, dou
   }
   op.pmg.reset();
   op.coef_kind_copy = -1;
+  op.inc_depth = -1;
   std::vector<double> pts, wts;
   collapsed_rule(s.dim, ng, pts, wts);
   DevBuf db(size_t(nballs) * (s.dim + 1) * sizeof(double)), dp(pts.size() * sizeof(double)),
@@ -354,6 +356,11 @@ void op_set_inclusions(Op& op, int nballs, const double* balls, double a_in, dou
     *mean_points = s.nc ? sum / double(s.nc) : 0.0;
   }
   HIPCHK(hipStreamSynchronize(st));
+  op.inc_balls.assign(balls, balls + size_t(nballs) * (s.dim + 1));
+  op.inc_in = a_in;
+  op.inc_out = a_out;
+  op.inc_ng = ng;
+  op.inc_depth = depth;
 }
 
 static ApplyLaunch apply_args(const Op& op, int prec) {

@@ -121,8 +121,14 @@ double power_lmax(Op& op, PmgLevel& L, Dots& dd, hipStream_t st) {
 
 void build(Op& op, hipStream_t st) {
   const Space& s0 = *op.space;
-  DOGIP_CHECK(op.coef_kind_copy >= 0 && !op.global_w && op.nq == 0, DOGIP_E_STATE,
-              "the multigrid solve needs an element-wise operator built from a coefficient form");
+  const bool inc = op.inc_depth >= 0;
+  DOGIP_CHECK((op.coef_kind_copy >= 0 || inc) && !op.global_w && op.nq == 0, DOGIP_E_STATE,
+              "the multigrid solve needs an element-wise operator built from a coefficient form or inclusions");
+  DevBuf ones;
+  if (inc) {
+    ones.alloc(size_t(std::max<int64_t>(s0.nc, 1)) * sizeof(double));
+    vk_fill(ones.as<double>(), 1.0, s0.nc, st);
+  }
   auto P = std::make_unique<Pmg>();
   for (int j = 0; j < s0.k; ++j) P->lv.push_back(std::make_unique<PmgLevel>());
   P->lv[0]->op = &op;
@@ -130,8 +136,15 @@ void build(Op& op, hipStream_t st) {
   for (int j = 1; j < s0.k; ++j) {
     auto sp = make_space(s0.mesh, s0.k - j, s0.kind, s0.bc);
     PmgLevel& L = *P->lv[size_t(j)];
-    L.own = make_op(sp, op.coef_kind_copy, op.coef_copy.as<double>(), op.has32 ? DOGIP_OP_FP32 : 0u, 0,
-                    DOGIP_VARIANT_AUTO, st);
+    const unsigned fl = op.has32 ? DOGIP_OP_FP32 : 0u;
+    if (inc) {
+      // the same inclusions, integrated by the same sub-cell rule for this level's W
+      L.own = make_op(sp, DOGIP_COEF_SCALAR, ones.as<double>(), fl, 0, DOGIP_VARIANT_AUTO, st);
+      op_set_inclusions(*L.own, int(op.inc_balls.size() / size_t(s0.dim + 1)), op.inc_balls.data(), op.inc_in,
+                        op.inc_out, op.inc_depth, op.inc_ng, nullptr, st);
+    } else {
+      L.own = make_op(sp, op.coef_kind_copy, op.coef_copy.as<double>(), fl, 0, DOGIP_VARIANT_AUTO, st);
+    }
     L.space = sp;
     L.op = L.own.get();
     L.n = sp->ndofs;

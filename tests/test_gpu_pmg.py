@@ -10,7 +10,8 @@ import numpy as np
 import pytest
 
 from helpers import match_dofs, rel_err
-from oracle import fem, solve
+from oracle import dogip as odg
+from oracle import fem, solve, subcell
 from workloads import coef_aniso_2d, coef_aniso_3d, coef_uniform, random_vector, theta_normal, unit_mesh
 
 pytestmark = pytest.mark.gpu
@@ -130,7 +131,7 @@ def test_pmg_zero_rhs():
 
 
 def test_pmg_state_errors():
-    """The multigrid solve needs an element-wise D built from a coefficient."""
+    """The multigrid solve needs an element-wise D built from a coefficient (or inclusions)."""
     from paper_1710_09913_amd import Mesh, Operator, Space
     from paper_1710_09913_amd.capi import DogipError
 
@@ -145,10 +146,6 @@ def test_pmg_state_errors():
     raw = Operator(sp, nofp32.export_d().reshape(-1).cpu(), "raw_d")
     with pytest.raises(DogipError):
         raw.pcg(b, mode="pmg")
-    inc = Operator(sp, ones, "scalar")
-    inc.set_inclusions(np.array([[0.5, 0.5, 0.2]]), 5.0, 1.0)
-    with pytest.raises(DogipError):
-        inc.pcg(b, mode="pmg")
     qp = Operator.quadrature(sp, 3, torch.ones(sp.ncells, 9, dtype=torch.float64))
     with pytest.raises(DogipError):
         qp.pcg(b, mode="pmg")
@@ -157,6 +154,37 @@ def test_pmg_state_errors():
     with pytest.raises(DogipError):
         g.pcg(torch.ones(wp.ndofs, dtype=torch.float64, device="cuda"), mode="pmg")
     # set_coef makes it available again
-    inc.set_coef(ones)
-    _, st = inc.pcg(b, mode="pmg")
+    raw.set_coef(ones)
+    _, st = raw.pcg(b, mode="pmg")
     assert st["status"] == 0
+
+
+@pytest.mark.parametrize("d,n,k,mode", [(2, 12, 3, "pmg"), (2, 12, 4, "pmg_mixed"), (3, 4, 3, "pmg")])
+def test_pmg_inclusions_solves_the_oracle_system(d, n, k, mode):
+    """Coefficient jumps inside cells (a = 100 in balls, 1 outside): the levels take their D
+    from the same sub-cell quadrature; x solves the oracle's system B^T D B x = b."""
+    from paper_1710_09913_amd import Mesh, Operator, Space
+
+    print(f"[pmg incl] d={d} n={n} k={k} {mode}", flush=True)
+    coords, cells = unit_mesh(d, n, jitter=0.1, seed=k)
+    rng = np.random.default_rng(k)
+    balls = np.hstack([rng.uniform(0.2, 0.8, size=(4, d)), rng.uniform(0.1, 0.25, size=(4, 1))])
+    sp = Space(Mesh(coords, cells), k, "se", "dirichlet")
+    op = Operator(sp, torch.ones(sp.ncells, dtype=torch.float64), "scalar", fp32=True)
+    op.set_inclusions(balls, 100.0, 1.0, depth=3, ng=3)
+    osp = fem.make_space(coords, cells, k)
+    perm = match_dofs(sp.dof_coords(), osp.dof_coords)
+    Do = subcell.build_d_subcell(osp, balls, 100.0, 1.0, "se", depth=3, ng=3)
+    b = fem.load_vector(osp, 1.0)
+    b[osp.boundary] = 0.0
+    x, st = op.pcg(_gpu(b[perm]), tol=1e-10, maxit=2000, mode=mode)
+    assert st["status"] == 0 and st["relres_true"] <= 1.05e-10
+    xo = np.empty(osp.ndofs)
+    xo[perm] = x.cpu().numpy()
+    res = b - odg.apply_dirichlet(osp, Do, xo, "se")
+    # the solve's own residual plus the rounding of D and of the apply (|B^T| |D| |B^| |x|)
+    ab = odg.apply_abs(osp, Do, np.abs(xo), "se", True)
+    assert np.linalg.norm(res) <= 1.05e-10 * np.linalg.norm(b) + 1e-12 * np.linalg.norm(ab)
+    _, sj = op.pcg(_gpu(b[perm]), tol=1e-10, maxit=20000, mode="f64")
+    print(f"[pmg incl] outer iterations {st['iters']}, Jacobi-PCG {sj['iters']}", flush=True)
+    assert st["iters"] * 3 <= sj["iters"]
