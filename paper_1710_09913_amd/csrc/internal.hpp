@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -41,12 +42,26 @@ struct DevBuf {
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
+// Edges and (3D) faces of a mesh, numbered in the lexicographic order of their sorted
+// vertex tuples: per cell and local entity the entity id, and the cells sharing each.
+struct MeshEntities {
+  std::vector<int32_t> cell_edge, edge_cells;  // [nc][(d+1)d/2], [ne]
+  std::vector<int32_t> cell_face, face_cells;  // [nc][4] (face opposite local vertex j), [nf]
+  int64_t ne = 0, nf = 0;
+};
+
 struct Mesh {
   int dim = 0;
   int64_t nv = 0, nc = 0;
   std::vector<double> xyz;     // [nv][dim]
   std::vector<int32_t> cells;  // [nc][dim+1]
+  // built at the first space on this mesh and shared by the others (the orders of a
+  // p-multigrid hierarchy, the double-grid lattice)
+  mutable std::mutex ent_mu;
+  mutable std::shared_ptr<const MeshEntities> ent;
 };
+// the mesh's entities, built once
+std::shared_ptr<const MeshEntities> mesh_entities(const Mesh& m);
 
 struct Space {
   std::shared_ptr<const Mesh> mesh;

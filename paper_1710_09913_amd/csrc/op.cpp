@@ -91,7 +91,7 @@ static void check_coef(const Space& s, int coef_kind) {
 
 static void build_d(Op& op, int coef_kind, const double* coef, hipStream_t st) {
   const Space& s = *op.space;
-  op.pmg.reset();
+  if (op.pmg) op.pmg->stale = true;  // levels keep their spaces and transfers; D is redone
   op.inc_depth = -1;
   if (coef_kind == DOGIP_COEF_RAW_D || op.global_w) {
     op.coef_kind_copy = -1;
@@ -310,7 +310,7 @@ void op_set_inclusions(Op& op, int nballs, const double* balls, double a_in, dou
     for (int x = 0; x <= s.dim; ++x)
       DOGIP_CHECK(std::isfinite(balls[j * (s.dim + 1) + x]), DOGIP_E_INVALID, "non-finite ball");
   }
-  op.pmg.reset();
+  if (op.pmg) op.pmg->stale = true;
   op.coef_kind_copy = -1;
   op.inc_depth = -1;
   std::vector<double> pts, wts;

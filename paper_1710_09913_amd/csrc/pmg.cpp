@@ -119,16 +119,27 @@ double power_lmax(Op& op, PmgLevel& L, Dots& dd, hipStream_t st) {
   return lam;
 }
 
+// D of a coarser level from the fine operator's coefficient (or inclusions)
+void level_d(const Op& op, Op& lop, hipStream_t st) {
+  if (op.inc_depth >= 0) {
+    // the same inclusions, integrated by the same sub-cell rule for this level's W
+    op_set_inclusions(lop, int(op.inc_balls.size() / size_t(op.space->dim + 1)), op.inc_balls.data(), op.inc_in,
+                      op.inc_out, op.inc_depth, op.inc_ng, nullptr, st);
+  } else {
+    op_set_coef(lop, op.coef_kind_copy, op.coef_copy.as<double>(), st);
+  }
+}
+
+void check_source(const Op& op) {
+  DOGIP_CHECK((op.coef_kind_copy >= 0 || op.inc_depth >= 0) && !op.global_w && op.nq == 0, DOGIP_E_STATE,
+              "the multigrid solve needs an element-wise operator built from a coefficient form or inclusions");
+}
+
 void build(Op& op, hipStream_t st) {
   const Space& s0 = *op.space;
-  const bool inc = op.inc_depth >= 0;
-  DOGIP_CHECK((op.coef_kind_copy >= 0 || inc) && !op.global_w && op.nq == 0, DOGIP_E_STATE,
-              "the multigrid solve needs an element-wise operator built from a coefficient form or inclusions");
-  DevBuf ones;
-  if (inc) {
-    ones.alloc(size_t(std::max<int64_t>(s0.nc, 1)) * sizeof(double));
-    vk_fill(ones.as<double>(), 1.0, s0.nc, st);
-  }
+  check_source(op);
+  DevBuf ones(size_t(std::max<int64_t>(s0.nc, 1)) * sizeof(double));
+  vk_fill(ones.as<double>(), 1.0, s0.nc, st);
   auto P = std::make_unique<Pmg>();
   for (int j = 0; j < s0.k; ++j) P->lv.push_back(std::make_unique<PmgLevel>());
   P->lv[0]->op = &op;
@@ -137,11 +148,9 @@ void build(Op& op, hipStream_t st) {
     auto sp = make_space(s0.mesh, s0.k - j, s0.kind, s0.bc);
     PmgLevel& L = *P->lv[size_t(j)];
     const unsigned fl = op.has32 ? DOGIP_OP_FP32 : 0u;
-    if (inc) {
-      // the same inclusions, integrated by the same sub-cell rule for this level's W
+    if (op.inc_depth >= 0) {
       L.own = make_op(sp, DOGIP_COEF_SCALAR, ones.as<double>(), fl, 0, DOGIP_VARIANT_AUTO, st);
-      op_set_inclusions(*L.own, int(op.inc_balls.size() / size_t(s0.dim + 1)), op.inc_balls.data(), op.inc_in,
-                        op.inc_out, op.inc_depth, op.inc_ng, nullptr, st);
+      level_d(op, *L.own, st);
     } else {
       L.own = make_op(sp, op.coef_kind_copy, op.coef_copy.as<double>(), fl, 0, DOGIP_VARIANT_AUTO, st);
     }
@@ -172,6 +181,17 @@ void build(Op& op, hipStream_t st) {
   Dots dd{P->dots.as<double>(), P->dots.as<double>() + RED_BLOCKS};
   for (auto& L : P->lv) L->lmax = power_lmax(*L->op, *L, dd, st);
   op.pmg = std::move(P);
+}
+
+// after a coefficient change: each level's D, diagonal and lmax again; the spaces, tiles
+// and transfers stay
+void refresh(Op& op, hipStream_t st) {
+  check_source(op);
+  Pmg& P = *op.pmg;
+  for (size_t j = 1; j < P.lv.size(); ++j) level_d(op, *P.lv[j]->op, st);
+  Dots dd{P.dots.as<double>(), P.dots.as<double>() + RED_BLOCKS};
+  for (auto& L : P.lv) L->lmax = power_lmax(*L->op, *L, dd, st);
+  P.stale = false;
 }
 
 // Chebyshev smoothing of A x = b at level L (from x = 0 when first).  On return r holds
@@ -226,7 +246,10 @@ void vcycle(Pmg& P, size_t j, const double* b, double* x, int prec, hipStream_t 
 
 int op_pcg_pmg(Op& op, const double* b, double* x, const dogip_solve_opts& o, dogip_solve_stats& stats, int prec,
                hipStream_t st) {
-  if (!op.pmg) build(op, st);
+  if (!op.pmg)
+    build(op, st);
+  else if (op.pmg->stale)
+    refresh(op, st);
   Pmg& P = *op.pmg;
   P.coarse_tol = (o.inner_tol > 0.0 && o.inner_tol < 1.0) ? o.inner_tol : COARSE_TOL;
   const int64_t n = op.space->ndofs;

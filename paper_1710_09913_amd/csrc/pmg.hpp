@@ -28,6 +28,7 @@ struct Pmg {
   DevBuf r, z, zo, p, q;       // outer flexible CG vectors (fine)
   DevBuf dots;                 // device scalars of the inner products
   double coarse_tol = 0.1;     // relative residual of the coarsest level's inner solve
+  bool stale = false;          // the fine D changed: the levels' D and lmax are redone
 };
 
 // Flexible CG on the fine operator preconditioned by one p-multigrid V-cycle per

@@ -165,7 +165,22 @@ static std::vector<int64_t> morton_order(const double* xyz, int64_t n, int d) {
     }
     key[i] = {code, i};
   }
-  std::sort(key.begin(), key.end());
+  // LSD radix sort on 16-bit digits: each pass is a stable counting sort, so equal codes
+  // keep ascending index order (the order of sorting the (code, index) pairs)
+  std::vector<std::pair<uint64_t, int64_t>> tmp(n);
+  std::vector<int64_t> cnt(65537);
+  for (int shift = 0; shift < 64; shift += 16) {
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (int64_t i = 0; i < n; ++i) cnt[((key[i].first >> shift) & 0xffff) + 1]++;
+    bool trivial = false;
+    for (int b = 1; b <= 65536; ++b) {
+      if (cnt[b] == n) trivial = true;
+      cnt[b] += cnt[b - 1];
+    }
+    if (trivial) continue;  // one digit value throughout: the pass would not move anything
+    for (int64_t i = 0; i < n; ++i) tmp[cnt[(key[i].first >> shift) & 0xffff]++] = key[i];
+    key.swap(tmp);
+  }
   std::vector<int64_t> order(n);
   for (int64_t i = 0; i < n; ++i) order[i] = key[i].second;
   return order;
@@ -198,7 +213,19 @@ EntityIds number_entities(const Mesh& m, const std::vector<std::array<int, NV>>&
       std::sort(k.v.begin(), k.v.end());
       k.slot = c * nl + e;
     }
-  std::sort(keys.begin(), keys.end(), [](const Key& a, const Key& b) { return a.v < b.v; });
+  // lexicographic order of the tuples: a counting sort by the smallest vertex id, then
+  // each bucket (the entities around one vertex, a few dozen) sorted on the full tuple
+  {
+    std::vector<int64_t> start(size_t(m.nv) + 1, 0);
+    for (const Key& k : keys) start[size_t(k.v[0]) + 1]++;
+    for (int64_t v = 0; v < m.nv; ++v) start[v + 1] += start[v];
+    std::vector<Key> by(keys.size());
+    std::vector<int64_t> at(start.begin(), start.end() - 1);
+    for (const Key& k : keys) by[at[k.v[0]]++] = k;
+    for (int64_t v = 0; v < m.nv; ++v)
+      std::sort(by.begin() + start[v], by.begin() + start[v + 1], [](const Key& a, const Key& b) { return a.v < b.v; });
+    keys.swap(by);
+  }
   EntityIds ids;
   ids.cell_ent.assign(size_t(m.nc) * nl, -1);
   int64_t id = -1;
@@ -216,7 +243,49 @@ EntityIds number_entities(const Mesh& m, const std::vector<std::array<int, NV>>&
 
 int tri_index(int i, int j, int n) { return i * (n + 1) - i * (i - 1) / 2 + j; }
 
+// local edges (a, b), a < b, in the order (0,1), (0,2), ..., (d-1,d)
+std::vector<std::array<int, 2>> local_edges(int d) {
+  std::vector<std::array<int, 2>> e;
+  for (int a = 0; a <= d; ++a)
+    for (int b = a + 1; b <= d; ++b) e.push_back({a, b});
+  return e;
+}
+
+int local_edge_of(const std::vector<std::array<int, 2>>& le, int a, int b) {
+  if (a > b) std::swap(a, b);
+  for (size_t e = 0; e < le.size(); ++e)
+    if (le[e][0] == a && le[e][1] == b) return int(e);
+  return -1;
+}
+
 }  // namespace
+
+std::shared_ptr<const MeshEntities> mesh_entities(const Mesh& m) {
+  std::lock_guard<std::mutex> lock(m.ent_mu);
+  if (m.ent) return m.ent;
+  auto out = std::make_shared<MeshEntities>();
+  EntityIds E = number_entities<2>(m, local_edges(m.dim));
+  out->cell_edge.swap(E.cell_ent);
+  out->edge_cells.swap(E.count);
+  out->ne = E.n;
+  if (m.dim == 3) {
+    // face opposite local vertex j
+    std::vector<std::array<int, 3>> lf;
+    for (int j = 0; j < 4; ++j) {
+      std::array<int, 3> f{};
+      int t = 0;
+      for (int a = 0; a < 4; ++a)
+        if (a != j) f[t++] = a;
+      lf.push_back(f);
+    }
+    EntityIds F = number_entities<3>(m, lf);
+    out->cell_face.swap(F.cell_ent);
+    out->face_cells.swap(F.count);
+    out->nf = F.n;
+  }
+  m.ent = out;
+  return out;
+}
 
 // Lagrange nodes of order q on every cell of the mesh, numbered globally:
 // vertices, then the q-1 nodes of each edge, the (q-1)(q-2)/2 of each face (3D),
@@ -228,109 +297,100 @@ LatticeDofs number_lattice(const Mesh& m, int q, bool xyz) {
   const int d = m.dim, d1 = d + 1;
   LatticeDofs out;
   out.nl = dim_p(d, q);
-  // local edges (pairs) and facets
-  std::vector<std::array<int, 2>> ledges;
-  for (int a = 0; a <= d; ++a)
-    for (int b = a + 1; b <= d; ++b) ledges.push_back({a, b});
-  EntityIds E = number_entities<2>(m, ledges);
-  EntityIds F;
-  std::vector<std::array<int, 3>> lfaces;  // face opposite local vertex j (3D)
-  if (d == 3) {
-    for (int j = 0; j < 4; ++j) {
-      std::array<int, 3> f{};
-      int t = 0;
-      for (int a = 0; a < 4; ++a)
-        if (a != j) f[t++] = a;
-      lfaces.push_back(f);
-    }
-    F = number_entities<3>(m, lfaces);
-  }
+  const std::vector<std::array<int, 2>> ledges = local_edges(d);
+  const int nle = int(ledges.size());
+  const std::shared_ptr<const MeshEntities> ent = mesh_entities(m);
+  const MeshEntities& M = *ent;
   const int64_t ne1 = q - 1, nf1 = d == 3 ? int64_t(q - 1) * (q - 2) / 2 : 0;
   const int64_t nint = d == 2 ? int64_t(q - 1) * (q - 2) / 2 : int64_t(q - 1) * (q - 2) * (q - 3) / 6;
-  const int64_t base_e = m.nv, base_f = base_e + E.n * ne1, base_c = base_f + (d == 3 ? F.n * nf1 : 0);
+  const int64_t base_e = m.nv, base_f = base_e + M.ne * ne1, base_c = base_f + (d == 3 ? M.nf * nf1 : 0);
   out.ndofs = base_c + m.nc * nint;
   DOGIP_CHECK(out.ndofs <= int64_t(TD_MASK), DOGIP_E_RANGE, "too many dofs for the tile encoding");
 
-  // local node barycentric indices and interior ordinals
+  // per local node: barycentric index, support (local vertices where it is positive,
+  // ascending) with multiplicities, the local edge or opposite face, the interior ordinal
+  struct Node {
+    int b[4];
+    int ns, sup[4], mult[4];
+    int edge, opp, iord;
+  };
   const int vt = out.nl;
-  std::vector<std::array<int, 4>> bv(vt);
-  std::vector<int> iord(vt, -1);
+  std::vector<Node> nd(vt);
   int cnt = 0;
   for (int l = 0; l < vt; ++l) {
+    Node& n = nd[l];
     int b[4] = {0, 0, 0, 0};
     ref::bary_index(d, q, l, b);
-    bool inner = true;
-    for (int j = 0; j < 4; ++j) bv[l][j] = b[j];
-    for (int j = 0; j <= d; ++j) inner = inner && b[j] > 0;
-    if (inner) iord[l] = cnt++;
+    n.ns = 0;
+    n.edge = n.opp = n.iord = -1;
+    for (int j = 0; j < 4; ++j) n.b[j] = b[j];
+    for (int j = 0; j <= d; ++j)
+      if (b[j] > 0) {
+        n.sup[n.ns] = j;
+        n.mult[n.ns] = b[j];
+        ++n.ns;
+      }
+    if (n.ns == 2) n.edge = local_edge_of(ledges, n.sup[0], n.sup[1]);
+    if (n.ns == 3 && d == 3)
+      for (int j = 0; j < 4; ++j)
+        if (b[j] == 0) n.opp = j;
+    if (n.ns == d1) n.iord = cnt++;
   }
-  auto edge_local = [&](int a, int b) {
-    for (size_t e = 0; e < ledges.size(); ++e)
-      if ((ledges[e][0] == a && ledges[e][1] == b) || (ledges[e][0] == b && ledges[e][1] == a)) return int(e);
-    return -1;
-  };
+  // 2D: the local edge opposite local vertex j
+  int opp_edge[3] = {-1, -1, -1};
+  if (d == 2)
+    for (int j = 0; j < 3; ++j) opp_edge[j] = local_edge_of(ledges, (j + 1) % 3, (j + 2) % 3);
 
   out.cell_dofs.assign(size_t(m.nc) * vt, -1);
+  std::vector<uint8_t> seen;
   if (xyz) {
     out.xyz.assign(size_t(out.ndofs) * d, 0.0);
     out.is_bnd.assign(out.ndofs, 0);
+    seen.assign(out.ndofs, 0);
   }
-  const int nle = int(ledges.size());
   for (int64_t c = 0; c < m.nc; ++c) {
     const int32_t* cv = &m.cells[c * d1];
     // boundary facets of this cell: facet opposite local vertex j
     bool fb[4] = {false, false, false, false};
-    for (int j = 0; j <= d; ++j) {
-      if (d == 2) {
-        int a = (j + 1) % 3, b = (j + 2) % 3;
-        fb[j] = E.count[E.cell_ent[c * nle + edge_local(a, b)]] == 1;
-      } else {
-        fb[j] = F.count[F.cell_ent[c * 4 + j]] == 1;
-      }
-    }
-    for (int l = 0; l < vt; ++l) {
-      int sup[4], mult[4], ns = 0;
+    if (xyz)
       for (int j = 0; j <= d; ++j)
-        if (bv[l][j] > 0) {
-          sup[ns] = j;
-          mult[ns] = bv[l][j];
-          ++ns;
-        }
+        fb[j] = d == 2 ? M.edge_cells[M.cell_edge[c * nle + opp_edge[j]]] == 1 : M.face_cells[M.cell_face[c * 4 + j]] == 1;
+    for (int l = 0; l < vt; ++l) {
+      const Node& n = nd[l];
       int64_t dof;
-      if (ns == 1) {
-        dof = cv[sup[0]];
-      } else if (ns == 2) {
-        int a = sup[0], b = sup[1];
-        int64_t eid = E.cell_ent[c * nle + edge_local(a, b)];
-        int mb = cv[a] < cv[b] ? mult[1] : mult[0];  // multiplicity at the larger vertex id
+      if (n.ns == 1) {
+        dof = cv[n.sup[0]];
+      } else if (n.ns == 2) {
+        const int a = n.sup[0], b = n.sup[1];
+        const int64_t eid = M.cell_edge[c * nle + n.edge];
+        const int mb = cv[a] < cv[b] ? n.mult[1] : n.mult[0];  // multiplicity at the larger vertex id
         dof = base_e + eid * ne1 + (mb - 1);
-      } else if (ns == 3 && d == 3) {
-        int opp = 0;
-        for (int j = 0; j < 4; ++j)
-          if (bv[l][j] == 0) opp = j;
-        int64_t fid = F.cell_ent[c * 4 + opp];
+      } else if (n.ns == 3 && d == 3) {
+        const int64_t fid = M.cell_face[c * 4 + n.opp];
         // order the three (vertex, multiplicity) pairs by vertex id
-        std::array<std::pair<int32_t, int>, 3> vm = {
-            std::make_pair(cv[sup[0]], mult[0]), std::make_pair(cv[sup[1]], mult[1]),
-            std::make_pair(cv[sup[2]], mult[2])};
+        std::array<std::pair<int32_t, int>, 3> vm = {std::make_pair(cv[n.sup[0]], n.mult[0]),
+                                                     std::make_pair(cv[n.sup[1]], n.mult[1]),
+                                                     std::make_pair(cv[n.sup[2]], n.mult[2])};
         std::sort(vm.begin(), vm.end());
         dof = base_f + fid * nf1 + tri_index(vm[1].second - 1, vm[2].second - 1, q - 3);
       } else {
-        dof = base_c + c * nint + iord[l];
+        dof = base_c + c * nint + n.iord;
       }
       out.cell_dofs[c * vt + l] = int32_t(dof);
       if (!xyz) continue;
-      // coordinates, summed in ascending vertex-id order so every cell gives the same bits
+      for (int j = 0; j <= d; ++j)
+        if (n.b[j] == 0 && fb[j]) out.is_bnd[dof] = 1;
+      if (seen[dof]) continue;
+      seen[dof] = 1;
+      // coordinates, summed in ascending vertex-id order so they do not depend on the cell
       std::array<std::pair<int32_t, int>, 4> vw;
-      for (int t = 0; t < ns; ++t) vw[t] = {cv[sup[t]], mult[t]};
-      std::sort(vw.begin(), vw.begin() + ns);
+      for (int t = 0; t < n.ns; ++t) vw[t] = {cv[n.sup[t]], n.mult[t]};
+      std::sort(vw.begin(), vw.begin() + n.ns);
       for (int x = 0; x < d; ++x) {
         double acc = 0.0;
-        for (int t = 0; t < ns; ++t) acc += (double(vw[t].second) / q) * m.xyz[int64_t(vw[t].first) * d + x];
+        for (int t = 0; t < n.ns; ++t) acc += (double(vw[t].second) / q) * m.xyz[int64_t(vw[t].first) * d + x];
         out.xyz[dof * d + x] = acc;
       }
-      for (int j = 0; j <= d; ++j)
-        if (bv[l][j] == 0 && fb[j]) out.is_bnd[dof] = 1;
     }
   }
   return out;

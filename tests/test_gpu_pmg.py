@@ -188,3 +188,34 @@ def test_pmg_inclusions_solves_the_oracle_system(d, n, k, mode):
     _, sj = op.pcg(_gpu(b[perm]), tol=1e-10, maxit=20000, mode="f64")
     print(f"[pmg incl] outer iterations {st['iters']}, Jacobi-PCG {sj['iters']}", flush=True)
     assert st["iters"] * 3 <= sj["iters"]
+
+
+def test_pmg_refresh_after_coefficient_kind_changes():
+    """After set_coef / set_inclusions the next multigrid solve redoes only the levels' D:
+    it gives what a fresh operator with that D gives; a raw D is refused."""
+    from paper_1710_09913_amd import Mesh, Operator, Space
+    from paper_1710_09913_amd.capi import DogipError
+
+    sp = Space(Mesh.unit(2, 10), 3, "se", "dirichlet")
+    b = _gpu(random_vector(sp.ndofs, seed=2))
+    b[torch.from_numpy(sp.boundary()).cuda().long()] = 0.0
+    ones = torch.ones(sp.ncells, dtype=torch.float64)
+    balls = np.array([[0.3, 0.4, 0.2], [0.7, 0.6, 0.15]])
+    op = Operator(sp, ones, "scalar", fp32=True)
+    op.pcg(b, tol=1e-10, mode="pmg")
+    steps = [("sym", torch.from_numpy(coef_aniso_2d(sp.ncells, 3))), ("inclusions", None),
+             ("logscalar", torch.from_numpy(theta_normal(sp.ncells, 5)))]
+    for kind, c in steps:
+        fresh = Operator(sp, ones if c is None else c, "scalar" if c is None else kind, fp32=True)
+        if c is None:
+            op.set_inclusions(balls, 50.0, 1.0, depth=2, ng=3)
+            fresh.set_inclusions(balls, 50.0, 1.0, depth=2, ng=3)
+        else:
+            op.set_coef(c, kind)
+        x1, s1 = op.pcg(b, tol=1e-10, mode="pmg")
+        x2, s2 = fresh.pcg(b, tol=1e-10, mode="pmg")
+        assert s1["status"] == 0 and s1["iters"] == s2["iters"], (kind, s1, s2)
+        assert float(torch.linalg.norm(x1 - x2) / torch.linalg.norm(x2)) <= 1e-13, kind
+    op.set_coef(op.export_d().reshape(-1).cpu(), "raw_d")
+    with pytest.raises(DogipError):
+        op.pcg(b, mode="pmg")
