@@ -13,7 +13,9 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def test_autograd_matches_oracle_gradient():
+@pytest.mark.parametrize("mode", ["f64", "pmg"])
+def test_autograd_matches_oracle_gradient(mode):
+    """Forward and adjoint solves by Jacobi-PCG or by multigrid-preconditioned CG."""
     from paper_1710_09913_amd import Mesh, Operator, Space
     from paper_1710_09913_amd.autograd import solve
 
@@ -34,7 +36,7 @@ def test_autograd_matches_oracle_gradient():
     op = Operator(sp, torch.zeros(nel, dtype=torch.float64), "logscalar", fp32=False)
     theta = torch.from_numpy(theta0).cuda().requires_grad_(True)
     bt = torch.from_numpy(b[perm]).cuda().requires_grad_(True)
-    u = solve(theta, bt, op, tol=1e-13)
+    u = solve(theta, bt, op, tol=1e-13, mode=mode)
     J = 0.5 * ((u - torch.from_numpy(u_obs[perm]).cuda()) ** 2).sum()
     J.backward()
     assert abs(J.item() - J_o) <= 1e-9 * J_o
