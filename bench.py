@@ -9,7 +9,7 @@ D resident in HBM; value = dofs / (seconds per apply) in GDoF/s.
 The same line carries: the FP32 apply, PCG time-to-1e-8 (FP64, mixed precision, and
 p-multigrid preconditioned, FP64 and mixed),
 the roofline of the apply's two kernels (algorithmic bytes / their measured time, HBM
-peak 8 TB/s; traffic = HBM bytes from the committed counter summary of this build)
+peak 8 TB/s; traffic = HBM bytes from the committed counter summary of these apply kernels)
 and the CPU oracle timed on a bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 64] [--k 3] [--no-solve] [--no-cpu]
@@ -87,15 +87,16 @@ def time_apply(op, u, y, prec, steps, warmup):
 def measured_traffic(n, k):
     """HBM bytes per apply from the committed rocprofv3 counter summary of this workload
     (FETCH_SIZE and WRITE_SIZE, calibrated by a copy of known size), per precision; empty
-    when the summary is missing or was measured on a build of other sources."""
-    from paper_1710_09913_amd.build import source_hash
+    when the summary is missing or was measured on other apply kernels (their sources,
+    tile planning, launch code or compiler flags changed since)."""
+    from paper_1710_09913_amd.build import apply_hash
 
     path = os.path.join(ROOT, "profiles", f"traffic_k_apply_3d{n}_p{k}_se.json")
     if not os.path.exists(path):
         return {}
     with open(path) as fh:
         doc = json.load(fh)
-    if doc.get("source_hash") != source_hash():
+    if doc.get("apply_hash") != apply_hash():
         return {}
     return {p: round(v["bytes_per_apply"]) for p, v in doc.get("traffic", {}).items()}
 

@@ -54,6 +54,27 @@ def _headers_mtime():
     return max((os.path.getmtime(h) for h in hs), default=0.0)
 
 
+# the sources the element-wise apply is built from: its tile and finish kernels, their
+# headers and B^ tables, the host code that plans the tiles and launches them, and the
+# compiler flags in this file
+APPLY_SOURCES = ("kern_apply.hpp", "kern_apply_u2.hip", "kern_apply_u3.hip", "kern_apply_l2.hip",
+                 "kern_apply_l3.hip", "kern_aux.hip", "kern_common.hpp", "reftab.hpp", "internal.hpp", "setup.cpp",
+                 "op.cpp")
+
+
+def apply_hash() -> str:
+    """SHA-256 over the apply's sources (identifies the kernels that counter summaries
+    were taken on)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in sorted(os.path.join(CSRC, n) for n in APPLY_SOURCES) + [os.path.abspath(__file__)]:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def source_hash() -> str:
     """SHA-256 over the kernel and host sources and the public header (identifies a build)."""
     import hashlib

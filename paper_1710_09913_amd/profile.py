@@ -45,7 +45,7 @@ def run(argv=None):
     import torch
 
     from paper_1710_09913_amd import Mesh, Operator, Space
-    from paper_1710_09913_amd.build import source_hash
+    from paper_1710_09913_amd.build import apply_hash, source_hash
     from workloads import random_vector
 
     torch.cuda.set_device(0)
@@ -63,7 +63,7 @@ def run(argv=None):
     torch.cuda.synchronize()
     print(json.dumps({"ndofs": sp.ndofs, "ncells": sp.ncells, "alg_bytes_f64": op.info["alg_bytes_f64"],
                       "alg_bytes_f32": op.info["alg_bytes_f32"], "copy_bytes_each": 2 * x.numel() * 8,
-                      "source_hash": source_hash()}), flush=True)
+                      "source_hash": source_hash(), "apply_hash": apply_hash()}), flush=True)
 
 
 def _csv(path):
@@ -181,14 +181,15 @@ def summarize(argv=None):
                      "bytes_per_apply": tile_r + tile_w + fin_r + fin_w,
                      "alg_bytes_per_apply": info["alg_bytes_" + prec]}
     os.makedirs(a.out, exist_ok=True)
-    doc = {"name": a.name, "source_hash": info["source_hash"], "ndofs": info["ndofs"], "ncells": info["ncells"],
+    doc = {"name": a.name, "source_hash": info["source_hash"], "apply_hash": info.get("apply_hash"), "ndofs": info["ndofs"], "ncells": info["ncells"],
            "fetch_scale": fscale, "write_scale": wscale, "traffic": res}
     with open(os.path.join(a.out, f"traffic_{a.name}.json"), "w") as fh:
         json.dump(doc, fh, indent=1)
     lines = [f"# {a.name}: rocprofv3 kernel durations and HBM traffic", ""]
     if a.command:
         lines += ["Commands (from the repository root):", "", "```", a.command, "```", ""]
-    lines += [f"Build source hash `{info['source_hash']}`; {info['ncells']} cells, {info['ndofs']} dofs.", "",
+    lines += [f"Build source hash `{info['source_hash']}`, apply sources hash `{info.get('apply_hash')}`; "
+              f"{info['ncells']} cells, {info['ndofs']} dofs.", "",
               "## Kernel trace (--kernel-trace --stats)", ""] + _durations(stats)
     lines += ["", "## Traffic (--pmc FETCH_SIZE, then --pmc WRITE_SIZE)", "",
               f"Calibration: a 1 GiB device copy reads {copy_read} B and the counters report "
