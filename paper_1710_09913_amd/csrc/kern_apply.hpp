@@ -101,14 +101,25 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
     else
       return a.y;
   }();
+  int64_t e = t * a.te + threadIdx.x;
+  if (int(threadIdx.x) >= a.te) e = a.nel;  // lanes beyond a smaller tile do no cell work
+  // the first D chunks of each cell are requested before the gather, so their latency
+  // overlaps it (element-wise form, unrolled body, FP64 D: measured 2% faster there and
+  // 1.7% slower with FP32 D)
+  constexpr bool PRE = MODE == 0 && VARIANT == DOGIP_VARIANT_UNROLLED && sizeof(T) == 8;
+  typename E::V pre[E::NPRE];
+  if constexpr (PRE) {
+    if (e < a.nel) {
+      const int64_t w0 = t * (a.te >> 6) + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+      E::preload(reinterpret_cast<const typename E::V*>(a.D) + (w0 * a.nch) * 64 + (threadIdx.x & 63), pre);
+    }
+  }
   if (one) {
     gather_batch<T>(td, nd, threadIdx.x, uin, us, ys, ent);
   } else {
     for (int64_t j0 = threadIdx.x; j0 < nd; j0 += int64_t(GB) * blockDim.x) gather_batch<T>(td, nd, j0, uin, us, ys, ent);
   }
   __syncthreads();
-  int64_t e = t * a.te + threadIdx.x;
-  if (int(threadIdx.x) >= a.te) e = a.nel;  // lanes beyond a smaller tile do no cell work
   double yacc[VT];
   int sl[VT];
   if (e < a.nel) {
@@ -124,7 +135,7 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
       ElemQ<D, K, KIND, T>::run(a, w, lane, ue, ye);
     } else {
       const typename E::V* dp = reinterpret_cast<const typename E::V*>(a.D) + (w * a.nch) * 64 + lane;
-      E::run(dp, ue, ye);
+      E::template run<PRE>(dp, ue, ye, pre);
     }
     sfor<VT>([&](auto L) { yacc[L] = double(ye[L]); sl[L] = li[L]; });
   }

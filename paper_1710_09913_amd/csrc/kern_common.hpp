@@ -113,14 +113,26 @@ struct Elem {
     return j;
   }
 
-  __device__ __forceinline__ static T run(const V* __restrict__ dp, const T (&ue)[VT], T (&ye)[VT]) {
+  // the chunks requested before the first node is computed (unrolled body): a caller may
+  // request them early (preload) and hand them to run
+  static constexpr int NPRE = WT > 1 ? first_chunk(1) : NCH;
+  __device__ __forceinline__ static void preload(const V* __restrict__ dp, V (&pre)[NPRE]) {
+    sfor<NPRE>([&](auto J) { pre[J] = ld_stream(dp + J * 64); });
+  }
+
+  template <bool PRE = false>
+  __device__ __forceinline__ static T run(const V* __restrict__ dp, const T (&ue)[VT], T (&ye)[VT],
+                                          const V* pre = nullptr) {
     T en = T(0);
     sfor<VT>([&](auto L) { ye[L] = T(-0.0); });
     if constexpr (VARIANT == DOGIP_VARIANT_UNROLLED) {
       V ch[NCH];
       sfor<WT>([&](auto I) {
-        sfor_range<first_chunk(I), (I + 1 < WT ? first_chunk(I + 1) : NCH)>(
-            [&](auto J) { ch[J] = ld_stream(dp + J * 64); });
+        if constexpr (PRE && I == 0)
+          sfor<NPRE>([&](auto J) { ch[J] = pre[J]; });
+        else
+          sfor_range<first_chunk(I), (I + 1 < WT ? first_chunk(I + 1) : NCH)>(
+              [&](auto J) { ch[J] = ld_stream(dp + J * 64); });
         T g[NB];
         sfor<NB>([&](auto R) {
           T acc = T(-0.0);
