@@ -219,3 +219,34 @@ def test_pmg_refresh_after_coefficient_kind_changes():
     op.set_coef(op.export_d().reshape(-1).cpu(), "raw_d")
     with pytest.raises(DogipError):
         op.pcg(b, mode="pmg")
+
+
+@pytest.mark.parametrize("d,k", [(2, 1), (2, 3), (3, 1), (3, 2)])
+def test_pmg_degenerate_meshes_and_boundary_values(d, k):
+    """One cube (2 or 6 cells): few or no interior dofs; nonzero values on the Dirichlet
+    rows (identity rows) come back to the tolerance."""
+    from paper_1710_09913_amd import Mesh, Operator, Space
+
+    sp = Space(Mesh.unit(d, 1), k, "se", "dirichlet")
+    op = Operator(sp, torch.ones(sp.ncells, dtype=torch.float64), "scalar", fp32=True)
+    bnd = torch.from_numpy(sp.boundary().astype(np.int64)).cuda()
+    b = torch.from_numpy(random_vector(sp.ndofs, seed=d * 10 + k)).cuda()
+    for mode in ("pmg", "pmg_mixed"):
+        x, st = op.pcg(b, tol=1e-12, mode=mode)
+        assert st["status"] == 0, st
+        assert float((x[bnd] - b[bnd]).abs().max()) <= 1e-11 * float(b.abs().max())
+        r = b - op.apply(x)
+        assert float(torch.linalg.norm(r) / torch.linalg.norm(b)) <= 1e-11
+
+
+def test_pmg_not_converged_status():
+    """maxit bounds the outer iterations; the status says so and x is the last iterate."""
+    from paper_1710_09913_amd import Mesh, Operator, Space
+
+    sp = Space(Mesh.unit(2, 16), 3, "se", "dirichlet")
+    op = Operator(sp, torch.from_numpy(coef_uniform(sp.ncells, 1.0, 100.0, 3)), "scalar", fp32=True)
+    b = torch.from_numpy(random_vector(sp.ndofs, seed=8)).cuda()
+    b[torch.from_numpy(sp.boundary().astype(np.int64)).cuda()] = 0.0
+    x, st = op.pcg(b, tol=1e-14, maxit=2, mode="pmg", raise_on_error=False)
+    assert st["status"] == 6 and st["iters"] == 2, st
+    assert 0.0 < st["relres_true"] < 1.0
