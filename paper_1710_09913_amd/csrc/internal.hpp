@@ -55,6 +55,9 @@ struct Mesh {
   int64_t nv = 0, nc = 0;
   std::vector<double> xyz;     // [nv][dim]
   std::vector<int32_t> cells;  // [nc][dim+1]
+  // n for the unit-cube mesh of n^dim cubes split into Kuhn simplices (make_unit_mesh),
+  // whose halving is nested in it; 0 for other meshes
+  int unit_n = 0;
   // built at the first space on this mesh and shared by the others (the orders of a
   // p-multigrid hierarchy, the double-grid lattice)
   mutable std::mutex ent_mu;

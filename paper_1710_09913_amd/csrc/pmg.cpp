@@ -8,9 +8,17 @@
 // one cell holding it (all agree, the functions being continuous); the restriction is its
 // transpose.  A V-cycle smooths with Chebyshev polynomials in D^-1 A (degree 3 on
 // [lmax/8, 1.1 lmax], lmax by power iteration) before and after the coarse correction,
-// and solves the P_1 level by Jacobi-PCG to a relative residual of 0.1.  The inner solve
-// makes the preconditioner vary between applications, hence the flexible
+// and solves the coarsest level by Jacobi-PCG to a relative residual of 0.1.  The inner
+// solve makes the preconditioner vary between applications, hence the flexible
 // (Polak-Ribiere) CG outside.
+//
+// On a unit-cube mesh of Kuhn simplices (n^d cubes) the halved mesh is nested in it: each
+// coarse simplex is the union of 2^d fine ones, and every fine vertex is a coarse vertex or
+// the midpoint of a coarse edge.  There the hierarchy continues below P_1 with P_1 on the
+// meshes n/2, n/4, ... down to 16 (degree-4 smoothing on [lmax/20, 1.1 lmax]): the
+// coefficient of a coarse cell is the mean over its children (of the logarithm for a
+// log-coefficient; inclusions are integrated again on each mesh), and the prolongation
+// is P_1 interpolation (a midpoint takes the mean of the edge's ends).
 #include "pmg.hpp"
 
 #include <cmath>
@@ -22,8 +30,13 @@ namespace dogip {
 
 namespace {
 
+// Chebyshev smoothing: degree and range for the order levels and for the geometric ones
+// (tuned on 3D 64^3 P3 with the lognormal coefficient)
 constexpr int CHEB_DEGREE = 3;
 constexpr double CHEB_RANGE = 8.0;
+constexpr int CHEB_DEGREE_H = 4;
+constexpr double CHEB_RANGE_H = 20.0;
+constexpr int H_MIN_N = 16;  // coarsest unit mesh (n^d cubes)
 constexpr double COARSE_TOL = 0.1;
 constexpr int COARSE_MAXIT = 400;
 constexpr int POWER_ITERS = 15;
@@ -46,7 +59,38 @@ void copy(double* dst, const double* src, int64_t n, hipStream_t st) {
   if (n > 0) HIPCHK(hipMemcpyAsync(dst, src, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, st));
 }
 
-// CSR of the prolongation (fine rows) and of its transpose (coarse rows)
+// the prolongation's CSR (fine rows) and its transpose (coarse rows), uploaded to level C
+void set_transfer(PmgLevel& C, int64_t nfine, int64_t ncoarse, const std::vector<int64_t>& prow,
+                  const std::vector<int32_t>& pcol, const std::vector<double>& pval) {
+  // transpose, entries of a coarse row in ascending fine row
+  std::vector<int64_t> rrow(ncoarse + 1, 0);
+  for (int32_t c : pcol) rrow[c + 1]++;
+  for (int64_t i = 0; i < ncoarse; ++i) rrow[i + 1] += rrow[i];
+  std::vector<int32_t> rcol(pcol.size());
+  std::vector<double> rval(pcol.size());
+  std::vector<int64_t> fill(rrow.begin(), rrow.end() - 1);
+  for (int64_t f = 0; f < nfine; ++f)
+    for (int64_t j = prow[f]; j < prow[f + 1]; ++j) {
+      const int64_t at = fill[pcol[j]]++;
+      rcol[at] = int32_t(f);
+      rval[at] = pval[j];
+    }
+  auto up = [](DevBuf& b, const auto& v) {
+    using T = typename std::decay_t<decltype(v)>::value_type;
+    b.alloc(std::max<size_t>(v.size(), 1) * sizeof(T));
+    if (!v.empty()) HIPCHK(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  };
+  up(C.prow, prow);
+  up(C.pcol, pcol);
+  up(C.pval, pval);
+  up(C.rrow, rrow);
+  up(C.rcol, rcol);
+  up(C.rval, rval);
+  C.nfine = nfine;
+  C.nnz = int64_t(pcol.size());
+}
+
+// order levels: P_{k-1} embedded in P_k on the same mesh
 void build_transfer(const Space& F, const Space& Cs, PmgLevel& C) {
   const int d = F.dim, vf = F.vt, vc = Cs.vt;
   std::vector<double> tab;
@@ -72,32 +116,107 @@ void build_transfer(const Space& F, const Space& Cs, PmgLevel& C) {
     }
     prow[f + 1] = int64_t(pcol.size());
   }
-  // transpose, entries of a coarse row in ascending fine row
-  std::vector<int64_t> rrow(Cs.ndofs + 1, 0);
-  for (int32_t c : pcol) rrow[c + 1]++;
-  for (int64_t i = 0; i < Cs.ndofs; ++i) rrow[i + 1] += rrow[i];
-  std::vector<int32_t> rcol(pcol.size());
-  std::vector<double> rval(pcol.size());
-  std::vector<int64_t> fill(rrow.begin(), rrow.end() - 1);
-  for (int64_t f = 0; f < F.ndofs; ++f)
-    for (int64_t j = prow[f]; j < prow[f + 1]; ++j) {
-      const int64_t at = fill[pcol[j]]++;
-      rcol[at] = int32_t(f);
-      rval[at] = pval[j];
+  set_transfer(C, F.ndofs, Cs.ndofs, prow, pcol, pval);
+}
+
+// geometric levels: P_1 on the unit mesh nf/2 interpolated on the unit mesh nf (both
+// spaces P_1, dofs located by their lattice coordinates)
+void build_h_transfer(const Space& F, const Space& Cs, int nf, PmgLevel& C) {
+  const int d = F.dim, nc = nf / 2;
+  const int64_t m = nc + 1;
+  std::vector<int32_t> at(size_t(d == 2 ? m * m : m * m * m), -1);
+  for (int64_t i = 0; i < Cs.ndofs; ++i) {
+    int64_t key = 0;
+    for (int x = d - 1; x >= 0; --x) key = key * m + std::llround(Cs.dof_xyz[i * d + x] * nc);
+    DOGIP_CHECK(key >= 0 && key < int64_t(at.size()), DOGIP_E_INVALID, "coarse vertex off the lattice");
+    at[size_t(key)] = int32_t(i);
+  }
+  std::vector<int64_t> prow(F.ndofs + 1, 0);
+  std::vector<int32_t> pcol;
+  std::vector<double> pval;
+  pcol.reserve(size_t(F.ndofs) * 2);
+  pval.reserve(size_t(F.ndofs) * 2);
+  for (int64_t f = 0; f < F.ndofs; ++f) {
+    int64_t I[3] = {0, 0, 0}, off[3] = {0, 0, 0};
+    int nodd = 0;
+    for (int x = 0; x < d; ++x) {
+      I[x] = std::llround(F.dof_xyz[f * d + x] * nf);
+      off[x] = I[x] & 1;
+      nodd += int(off[x]);
     }
-  auto up = [](DevBuf& b, const auto& v) {
-    using T = typename std::decay_t<decltype(v)>::value_type;
-    b.alloc(std::max<size_t>(v.size(), 1) * sizeof(T));
-    if (!v.empty()) HIPCHK(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
-  };
-  up(C.prow, prow);
-  up(C.pcol, pcol);
-  up(C.pval, pval);
-  up(C.rrow, rrow);
-  up(C.rcol, rcol);
-  up(C.rval, rval);
-  C.nfine = F.ndofs;
-  C.nnz = int64_t(pcol.size());
+    // a vertex of the coarse mesh, or the midpoint of the coarse edge from (I - off) / 2
+    // to (I + off) / 2 (Kuhn edges run in the + direction of every axis they span)
+    auto coarse = [&](int sgn) {
+      int64_t key = 0;
+      for (int x = d - 1; x >= 0; --x) key = key * m + (I[x] + sgn * off[x]) / 2;
+      const int32_t c = at[size_t(key)];
+      DOGIP_CHECK(c >= 0, DOGIP_E_INVALID, "fine vertex without coarse neighbours");
+      return c;
+    };
+    if (nodd == 0) {
+      pcol.push_back(coarse(0));
+      pval.push_back(1.0);
+    } else {
+      pcol.push_back(coarse(-1));
+      pval.push_back(0.5);
+      pcol.push_back(coarse(1));
+      pval.push_back(0.5);
+    }
+    prow[f + 1] = int64_t(pcol.size());
+  }
+  set_transfer(C, F.ndofs, Cs.ndofs, prow, pcol, pval);
+}
+
+// for each cell of the unit mesh nf, the cell of the unit mesh nf/2 holding it: the coarse
+// cube of its centroid, and the Kuhn simplex of that cube given by the descending order of
+// the centroid's coordinates inside it (the cell order of make_unit_mesh)
+std::vector<int32_t> parent_cells(const Mesh& mf, int nf) {
+  const int d = mf.dim, d1 = d + 1, nc = nf / 2;
+  static const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  std::vector<int32_t> par(size_t(mf.nc));
+  for (int64_t c = 0; c < mf.nc; ++c) {
+    double g[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < d1; ++j)
+      for (int x = 0; x < d; ++x) g[x] += mf.xyz[int64_t(mf.cells[c * d1 + j]) * d + x] / d1;
+    int64_t ci[3] = {0, 0, 0};
+    double xi[3] = {0.0, 0.0, 0.0};
+    for (int x = 0; x < d; ++x) {
+      const double t = g[x] * nc;
+      ci[x] = std::min<int64_t>(std::max<int64_t>(int64_t(std::floor(t)), 0), nc - 1);
+      xi[x] = t - double(ci[x]);
+    }
+    int sub = -1;
+    if (d == 2) {
+      sub = xi[0] >= xi[1] ? 0 : 1;
+      par[c] = int32_t((ci[1] * nc + ci[0]) * 2 + sub);
+    } else {
+      for (int p = 0; p < 6 && sub < 0; ++p)
+        if (xi[perms[p][0]] >= xi[perms[p][1]] && xi[perms[p][1]] >= xi[perms[p][2]]) sub = p;
+      par[c] = int32_t(((ci[2] * nc + ci[1]) * nc + ci[0]) * 6 + sub);
+    }
+  }
+  return par;
+}
+
+// the mean of each coarse cell's children (per values per cell)
+std::vector<double> restrict_coef(const std::vector<double>& cf, const std::vector<int32_t>& par, int per,
+                                  int64_t ncoarse) {
+  std::vector<double> out(size_t(ncoarse) * per, 0.0);
+  std::vector<int32_t> cnt(size_t(ncoarse), 0);
+  for (size_t c = 0; c < par.size(); ++c) {
+    cnt[size_t(par[c])]++;
+    for (int v = 0; v < per; ++v) out[size_t(par[c]) * per + v] += cf[c * per + v];
+  }
+  for (int64_t c = 0; c < ncoarse; ++c) {
+    DOGIP_CHECK(cnt[size_t(c)] > 0, DOGIP_E_INVALID, "coarse cell without children");
+    for (int v = 0; v < per; ++v) out[size_t(c) * per + v] /= cnt[size_t(c)];
+  }
+  return out;
+}
+
+void upload(DevBuf& b, const std::vector<double>& v) {
+  b.alloc(std::max<size_t>(v.size(), 1) * sizeof(double));
+  if (!v.empty()) HIPCHK(hipMemcpy(b.p, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
 }
 
 double power_lmax(Op& op, PmgLevel& L, Dots& dd, hipStream_t st) {
@@ -130,6 +249,67 @@ void level_d(const Op& op, Op& lop, hipStream_t st) {
   }
 }
 
+int coef_per_cell(const Op& op) { return op.coef_kind_copy == DOGIP_COEF_SYM ? op.space->nsym : 1; }
+
+// the fine operator's coefficient on the host
+std::vector<double> host_coef(const Op& op, hipStream_t st) {
+  std::vector<double> cf(size_t(coef_per_cell(op)) * size_t(op.space->nc));
+  HIPCHK(hipStreamSynchronize(st));
+  if (!cf.empty()) HIPCHK(hipMemcpy(cf.data(), op.coef_copy.p, cf.size() * sizeof(double), hipMemcpyDeviceToHost));
+  return cf;
+}
+
+// D of the geometric levels (P.lv[first..]) from the fine coefficient, restricted level by
+// level, or from the inclusions
+void h_levels_d(const Op& op, Pmg& P, size_t first, hipStream_t st) {
+  if (first >= P.lv.size()) return;
+  std::vector<double> cf;
+  if (op.inc_depth < 0) cf = host_coef(op, st);
+  for (size_t j = first; j < P.lv.size(); ++j) {
+    PmgLevel& L = *P.lv[j];
+    if (op.inc_depth >= 0) {
+      level_d(op, *L.op, st);
+    } else {
+      cf = restrict_coef(cf, L.parent, coef_per_cell(op), L.space->nc);
+      DevBuf dc;
+      upload(dc, cf);
+      op_set_coef(*L.op, op.coef_kind_copy, dc.as<double>(), st);
+      HIPCHK(hipStreamSynchronize(st));
+    }
+  }
+}
+
+// geometric levels below P_1 when the mesh is a unit-cube Kuhn mesh
+void add_h_levels(Op& op, Pmg& P, hipStream_t st) {
+  const Space& s0 = *op.space;
+  int n = s0.mesh->unit_n;
+  if (n <= 0) return;
+  const size_t first = P.lv.size();
+  std::shared_ptr<const Mesh> mf = s0.mesh;
+  while (n % 2 == 0 && n / 2 >= H_MIN_N) {
+    std::shared_ptr<const Mesh> mc = make_unit_mesh(s0.dim, n / 2);
+    auto sc = make_space(mc, 1, s0.kind, s0.bc);
+    auto L = std::make_unique<PmgLevel>();
+    L->hlevel = true;
+    L->parent = parent_cells(*mf, n);
+    // created with a = 1; h_levels_d sets the coefficient below
+    DevBuf ones(size_t(std::max<int64_t>(mc->nc, 1)) * sizeof(double));
+    vk_fill(ones.as<double>(), 1.0, mc->nc, st);
+    L->own = make_op(sc, DOGIP_COEF_SCALAR, ones.as<double>(), op.has32 ? DOGIP_OP_FP32 : 0u, 0, DOGIP_VARIANT_AUTO,
+                     st);
+    HIPCHK(hipStreamSynchronize(st));
+    build_h_transfer(*P.lv.back()->op->space, *sc, n, *L);
+    L->space = sc;
+    L->op = L->own.get();
+    L->n = sc->ndofs;
+    L->range = CHEB_RANGE_H;
+    P.lv.push_back(std::move(L));
+    mf = mc;
+    n /= 2;
+  }
+  h_levels_d(op, P, first, st);
+}
+
 void check_source(const Op& op) {
   DOGIP_CHECK((op.coef_kind_copy >= 0 || op.inc_depth >= 0) && !op.global_w && op.nq == 0, DOGIP_E_STATE,
               "the multigrid solve needs an element-wise operator built from a coefficient form or inclusions");
@@ -160,6 +340,8 @@ void build(Op& op, hipStream_t st) {
   }
   for (size_t j = 0; j + 1 < P->lv.size(); ++j)
     build_transfer(*P->lv[j]->op->space, *P->lv[j + 1]->op->space, *P->lv[j + 1]);
+  for (auto& L : P->lv) L->range = CHEB_RANGE;
+  add_h_levels(op, *P, st);
   for (auto& Lp : P->lv) {
     PmgLevel& L = *Lp;
     const size_t vb = std::max<int64_t>(L.n, 1) * sizeof(double);
@@ -188,7 +370,15 @@ void build(Op& op, hipStream_t st) {
 void refresh(Op& op, hipStream_t st) {
   check_source(op);
   Pmg& P = *op.pmg;
-  for (size_t j = 1; j < P.lv.size(); ++j) level_d(op, *P.lv[j]->op, st);
+  size_t first_h = P.lv.size();
+  for (size_t j = 1; j < P.lv.size(); ++j) {
+    if (P.lv[j]->hlevel) {
+      first_h = j;
+      break;
+    }
+    level_d(op, *P.lv[j]->op, st);
+  }
+  h_levels_d(op, P, first_h, st);
   Dots dd{P.dots.as<double>(), P.dots.as<double>() + RED_BLOCKS};
   for (auto& L : P.lv) L->lmax = power_lmax(*L->op, *L, dd, st);
   P.stale = false;
@@ -201,7 +391,8 @@ void smooth(PmgLevel& L, double* x, const double* b, int prec, bool first, hipSt
   const int64_t n = L.n;
   double *r = L.r.as<double>(), *d = L.d.as<double>(), *t = L.t.as<double>();
   const double* invd = A.invdiag.as<double>();
-  const double hi = 1.1 * L.lmax, lo = L.lmax / CHEB_RANGE;
+  const double hi = 1.1 * L.lmax, lo = L.lmax / L.range;
+  const int degree = L.hlevel ? CHEB_DEGREE_H : CHEB_DEGREE;
   const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
   if (first) {
     vk_fill(x, 0.0, n, st);
@@ -212,7 +403,7 @@ void smooth(PmgLevel& L, double* x, const double* b, int prec, bool first, hipSt
   }
   vk_cheb_init(r, invd, d, 1.0 / theta, n, st);
   double rho = 1.0 / sigma;
-  for (int i = 0; i < CHEB_DEGREE; ++i) {
+  for (int i = 0; i < degree; ++i) {
     op_apply(A, d, t, prec, st);
     const double rn = 1.0 / (2.0 * sigma - rho);
     vk_cheb_step(x, r, d, t, invd, rn * rho, 2.0 * rn / delta, n, st);

@@ -18,6 +18,11 @@ struct PmgLevel {
   DevBuf prow, pcol, pval, rrow, rcol, rval;
   int64_t n = 0, nfine = 0, nnz = 0;
   double lmax = 0.0;           // largest eigenvalue of D^-1 A (power iteration)
+  double range = 0.0;          // the smoother damps [lmax / range, 1.1 lmax]
+  // geometric level (P1 on the halved unit mesh): the cell of this level holding each
+  // cell of the finer mesh
+  bool hlevel = false;
+  std::vector<int32_t> parent;
   DevBuf x, b;                 // the level's correction and right-hand side (not on level 0,
                                // which works on the outer CG's vectors)
   DevBuf r, d, t;              // V-cycle work vectors

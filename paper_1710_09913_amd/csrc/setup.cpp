@@ -102,7 +102,9 @@ std::shared_ptr<Mesh> make_unit_mesh(int dim, int n) {
             ++c;
           }
   }
-  return make_mesh(dim, nv, xyz.data(), int64_t(cells.size()) / (dim + 1), cells.data());
+  auto out = make_mesh(dim, nv, xyz.data(), int64_t(cells.size()) / (dim + 1), cells.data());
+  out->unit_n = n;
+  return out;
 }
 
 // ---------------------------------------------------------------- reference tables

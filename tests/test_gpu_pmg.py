@@ -250,3 +250,37 @@ def test_pmg_not_converged_status():
     x, st = op.pcg(b, tol=1e-14, maxit=2, mode="pmg", raise_on_error=False)
     assert st["status"] == 6 and st["iters"] == 2, st
     assert 0.0 < st["relres_true"] < 1.0
+
+
+@pytest.mark.parametrize("k,coef_kind", [(1, "scalar"), (2, "logscalar"), (3, "sym")])
+def test_pmg_geometric_levels_match_direct(k, coef_kind):
+    """Unit mesh 64^2: below P_1 the hierarchy continues on the nested meshes 32 and 16
+    (averaged coefficient, P_1 interpolation); the solution still matches the direct solve
+    and the outer iterations stay few."""
+    from paper_1710_09913_amd import Mesh, Operator, Space
+
+    n = 64
+    print(f"[pmg h] unit {n}^2 P{k} {coef_kind}", flush=True)
+    coords, cells = unit_mesh(2, n)
+    nel = len(cells)
+    if coef_kind == "scalar":
+        c = oc = coef_uniform(nel, 1.0, 100.0, 5)
+    elif coef_kind == "logscalar":
+        c = theta_normal(nel, 5, sigma=1.0)
+        oc = np.exp(c)
+    else:
+        c = oc = coef_aniso_2d(nel, 5)
+    sp = Space(Mesh.unit(2, n), k, "se", "dirichlet")
+    op = Operator(sp, torch.from_numpy(np.ascontiguousarray(c)), coef_kind, fp32=True)
+    osp = fem.make_space(coords, cells, k)
+    perm = match_dofs(sp.dof_coords(), osp.dof_coords)
+    A = fem.assemble(osp, fem.element_matrices(osp, oc, "se"))
+    b = fem.load_vector(osp, 1.0)
+    b[osp.boundary] = 0.0
+    x_lu = solve.direct_dirichlet(A, b, osp.boundary)
+    for mode in ("pmg", "pmg_mixed"):
+        x, st = op.pcg(_gpu(b[perm]), tol=1e-10, maxit=500, mode=mode)
+        assert st["status"] == 0 and st["relres_true"] <= 1.05e-10, st
+        assert rel_err(x.cpu().numpy(), x_lu[perm]) <= 1e-6
+        print(f"[pmg h] {mode}: {st['iters']} outer iterations", flush=True)
+        assert st["iters"] <= 30
