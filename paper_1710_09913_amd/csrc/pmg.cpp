@@ -15,7 +15,8 @@
 // On a unit-cube mesh of Kuhn simplices (n^d cubes) the halved mesh is nested in it: each
 // coarse simplex is the union of 2^d fine ones, and every fine vertex is a coarse vertex or
 // the midpoint of a coarse edge.  There the hierarchy continues below P_1 with P_1 on the
-// meshes n/2, n/4, ... down to 16 (degree-4 smoothing on [lmax/20, 1.1 lmax]): the
+// meshes n/2, n/4, ... down to 16 for the elliptic problem (degree-4 smoothing on
+// [lmax/20, 1.1 lmax]): the
 // coefficient of a coarse cell is the mean over its children (of the logarithm for a
 // log-coefficient; inclusions are integrated again on each mesh), and the prolongation
 // is P_1 interpolation (a midpoint takes the mean of the edge's ends).
@@ -283,7 +284,10 @@ void h_levels_d(const Op& op, Pmg& P, size_t first, hipStream_t st) {
 void add_h_levels(Op& op, Pmg& P, hipStream_t st) {
   const Space& s0 = *op.space;
   int n = s0.mesh->unit_n;
-  if (n <= 0) return;
+  // the projection's (mass) matrix has a condition number bounded in h, so coarser
+  // meshes have nothing to correct there (64^2 P3 with inclusions: 62 outer iterations
+  // with or without them); the order levels are kept
+  if (n <= 0 || s0.kind != DOGIP_SE) return;
   const size_t first = P.lv.size();
   std::shared_ptr<const Mesh> mf = s0.mesh;
   while (n % 2 == 0 && n / 2 >= H_MIN_N) {

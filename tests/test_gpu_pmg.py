@@ -284,3 +284,50 @@ def test_pmg_geometric_levels_match_direct(k, coef_kind):
         assert rel_err(x.cpu().numpy(), x_lu[perm]) <= 1e-6
         print(f"[pmg h] {mode}: {st['iters']} outer iterations", flush=True)
         assert st["iters"] <= 30
+
+
+def _oracle_residual_ok(osp, D, xo, b, kind, tol):
+    """x solves the oracle's DoGIP system B^T D B x = b to tol plus the apply's rounding."""
+    dirichlet = kind == "se"
+    y = (odg.apply_dirichlet if dirichlet else odg.apply)(osp, D, xo, kind)
+    ab = odg.apply_abs(osp, D, np.abs(xo), kind, dirichlet)
+    return np.linalg.norm(b - y) <= 1.05 * tol * np.linalg.norm(b) + 1e-12 * np.linalg.norm(ab)
+
+
+@pytest.mark.parametrize("d,n,k,kind,incl", [(2, 64, 2, "wp", False), (2, 64, 2, "se", True), (2, 64, 3, "wp", True),
+                                             (3, 32, 2, "se", False)])
+def test_pmg_geometric_levels_solve_oracle_system(d, n, k, kind, incl):
+    """Geometric levels with inclusions (D of every level by sub-cell quadrature on its
+    mesh) and in 3D, and the projection form (which keeps to the order levels on unit
+    meshes too): x solves the oracle's system."""
+    from paper_1710_09913_amd import Mesh, Operator, Space
+
+    print(f"[pmg h] unit {n}^{d} P{k} {kind} inclusions={incl}", flush=True)
+    coords, cells = unit_mesh(d, n)
+    nel = len(cells)
+    sp = Space(Mesh.unit(d, n), k, kind, "dirichlet" if kind == "se" else "none")
+    osp = fem.make_space(coords, cells, k)
+    perm = match_dofs(sp.dof_coords(), osp.dof_coords)
+    if incl:
+        rng = np.random.default_rng(3)
+        balls = np.hstack([rng.uniform(0.2, 0.8, size=(5, d)), rng.uniform(0.08, 0.2, size=(5, 1))])
+        op = Operator(sp, torch.ones(nel, dtype=torch.float64), "scalar", fp32=True)
+        op.set_inclusions(balls, 50.0, 1.0, depth=2, ng=2)
+        D = subcell.build_d_subcell(osp, balls, 50.0, 1.0, kind, depth=2, ng=2)
+    else:
+        c = coef_uniform(nel, 1.0, 20.0, 7)
+        op = Operator(sp, torch.from_numpy(c), "scalar", fp32=True)
+        D = odg.build_d(osp, c, kind)
+    b = fem.load_vector(osp, 1.0)
+    if kind == "se":
+        b[osp.boundary] = 0.0
+    for mode in ("pmg", "pmg_mixed"):
+        x, st = op.pcg(_gpu(b[perm]), tol=1e-10, maxit=500, mode=mode)
+        assert st["status"] == 0, st
+        print(f"[pmg h] {mode}: {st['iters']} outer iterations", flush=True)
+        xo = np.empty(osp.ndofs)
+        xo[perm] = x.cpu().numpy()
+        assert _oracle_residual_ok(osp, D, xo, b, kind, 1e-10)
+    _, sj = op.pcg(_gpu(b[perm]), tol=1e-10, maxit=20000, mode="f64")
+    print(f"[pmg h] Jacobi-PCG: {sj['iters']} iterations", flush=True)
+    assert st["iters"] <= (sj["iters"] + 2 if kind == "wp" else sj["iters"] // 3)
