@@ -234,6 +234,12 @@ class Operator:
 
     def pcg(self, b, x=None, tol=1e-8, maxit=20000, mode="f64", inner_tol=0.0, max_outer=20, check_every=16,
             stream=None, raise_on_error=True):
+        """Solve A x = b (dogip_pcg); returns (x, stats).  mode: "f64" (Jacobi-PCG),
+        "mixed" (FP32 apply and vectors, FP64 residual replacement), "mixed_restart"
+        (FP64 refinement around restarted FP32 solves), "pmg" / "pmg_mixed" (flexible CG
+        preconditioned by a multigrid V-cycle over the orders k..1 and, for the elliptic
+        problem on a unit mesh, over halved meshes; FP64 or FP32 applies inside the
+        cycle).  x, when given, is the start and is overwritten."""
         import torch
 
         x0 = x is not None
