@@ -216,6 +216,26 @@ __global__ __launch_bounds__(256) void k_csr(const int64_t* __restrict__ rowptr,
   }
 }
 
+// x[idx[i]] = sum_j M[i][j] b[idx[j]] for a dense m x m matrix M (row-major), one block per
+// row, the products summed in a fixed order
+__global__ __launch_bounds__(256) void k_dense_solve(const double* __restrict__ M, const int32_t* __restrict__ idx,
+                                                     int64_t m, const double* __restrict__ b, double* __restrict__ x) {
+  __shared__ double red[4];
+  const int64_t i = blockIdx.x;
+  double s = 0.0;
+  for (int64_t j = threadIdx.x; j < m; j += blockDim.x) s = fma(M[i * m + j], b[idx[j]], s);
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) x[idx[i]] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// x[idx[i]] = b[idx[i]]
+__global__ __launch_bounds__(256) void k_copy_indexed(double* __restrict__ x, const double* __restrict__ b,
+                                                      const int32_t* __restrict__ idx, int64_t n) {
+  GRID_STRIDE(i, n) x[idx[i]] = b[idx[i]];
+}
+
 // d = s D^-1 r
 __global__ __launch_bounds__(256) void k_cheb_init(const double* __restrict__ r, const double* __restrict__ invd,
                                                    double* __restrict__ d, double s, int64_t n) {
@@ -419,6 +439,14 @@ void vk_axpby(double a, const double* x, double b, double* y, int64_t n, hipStre
 }
 void vk_sub(const double* b, const double* t, double* r, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(dev::k_sub, dim3(red_grid(n) * 4), dim3(256), 0, st, b, t, r, n);
+}
+void vk_dense_solve(const double* M, const int32_t* idx, int64_t m, const double* b, double* x, hipStream_t st) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(dev::k_dense_solve, dim3(unsigned(m)), dim3(256), 0, st, M, idx, m, b, x);
+}
+void vk_copy_indexed(double* x, const double* b, const int32_t* idx, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(dev::k_copy_indexed, dim3(red_grid(n)), dim3(256), 0, st, x, b, idx, n);
 }
 void vk_hash_fill(double* v, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(dev::k_hash_fill, dim3(red_grid(n) * 4), dim3(256), 0, st, v, n);

@@ -37,7 +37,11 @@ constexpr int CHEB_DEGREE = 3;
 constexpr double CHEB_RANGE = 8.0;
 constexpr int CHEB_DEGREE_H = 4;
 constexpr double CHEB_RANGE_H = 20.0;
-constexpr int H_MIN_N = 16;  // coarsest unit mesh (n^d cubes)
+// geometric coarsening continues while the coarsest level has more interior dofs than
+// DENSE_TARGET; a coarsest level with at most DENSE_MAX interior dofs is solved with its
+// dense inverse (Cholesky on the host at set-up), a larger one by Jacobi-PCG
+constexpr int64_t DENSE_TARGET = 400;
+constexpr int64_t DENSE_MAX = 1000;
 constexpr double COARSE_TOL = 0.1;
 constexpr int COARSE_MAXIT = 400;
 constexpr int POWER_ITERS = 15;
@@ -290,7 +294,8 @@ void add_h_levels(Op& op, Pmg& P, hipStream_t st) {
   if (n <= 0 || s0.kind != DOGIP_SE) return;
   const size_t first = P.lv.size();
   std::shared_ptr<const Mesh> mf = s0.mesh;
-  while (n % 2 == 0 && n / 2 >= H_MIN_N) {
+  auto interior = [](const Space& s) { return s.ndofs - int64_t(s.boundary.size()); };
+  while (n % 2 == 0 && n / 2 >= 2 && interior(*P.lv.back()->op->space) > DENSE_TARGET) {
     std::shared_ptr<const Mesh> mc = make_unit_mesh(s0.dim, n / 2);
     auto sc = make_space(mc, 1, s0.kind, s0.bc);
     auto L = std::make_unique<PmgLevel>();
@@ -312,6 +317,64 @@ void add_h_levels(Op& op, Pmg& P, hipStream_t st) {
     n /= 2;
   }
   h_levels_d(op, P, first, st);
+}
+
+// the coarsest level's A on its interior dofs, column by column (A e_j), factored
+// A = L L^T on the host and inverted; leaves nint = 0 (Jacobi-PCG instead) when the level
+// is too large or the factorization meets a non-positive pivot
+void build_dense(PmgLevel& L, hipStream_t st) {
+  L.nint = 0;
+  const Space& s = *L.op->space;
+  std::vector<uint8_t> isb(size_t(s.ndofs), 0);
+  for (int32_t b : s.boundary) isb[size_t(b)] = 1;
+  std::vector<int32_t> idx;
+  for (int64_t i = 0; i < s.ndofs; ++i)
+    if (!isb[size_t(i)]) idx.push_back(int32_t(i));
+  const int64_t m = int64_t(idx.size());
+  if (m == 0 || m > DENSE_MAX) return;
+  std::vector<double> A(static_cast<size_t>(m * m));
+  std::vector<double> col(static_cast<size_t>(s.ndofs));
+  DevBuf e(size_t(s.ndofs) * sizeof(double)), y(size_t(s.ndofs) * sizeof(double));
+  for (int64_t j = 0; j < m; ++j) {
+    vk_fill(e.as<double>(), 0.0, s.ndofs, st);
+    vk_fill(e.as<double>() + idx[size_t(j)], 1.0, 1, st);
+    op_apply(*L.op, e.as<double>(), y.as<double>(), DOGIP_F64, st);
+    HIPCHK(hipMemcpyAsync(col.data(), y.p, col.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int64_t i = 0; i < m; ++i) A[size_t(i * m + j)] = col[size_t(idx[size_t(i)])];
+  }
+  // Cholesky (lower triangle of A overwritten by L) from the symmetric part
+  for (int64_t j = 0; j < m; ++j) {
+    double d = 0.5 * (A[size_t(j * m + j)] + A[size_t(j * m + j)]);
+    for (int64_t k = 0; k < j; ++k) d -= A[size_t(j * m + k)] * A[size_t(j * m + k)];
+    if (!(d > 0.0) || !std::isfinite(d)) return;
+    const double ljj = std::sqrt(d);
+    A[size_t(j * m + j)] = ljj;
+    for (int64_t i = j + 1; i < m; ++i) {
+      double v = 0.5 * (A[size_t(i * m + j)] + A[size_t(j * m + i)]);
+      for (int64_t k = 0; k < j; ++k) v -= A[size_t(i * m + k)] * A[size_t(j * m + k)];
+      A[size_t(i * m + j)] = v / ljj;
+    }
+  }
+  // inverse column by column: L z = e_c, L^T x = z
+  std::vector<double> inv(static_cast<size_t>(m * m));
+  std::vector<double> z(static_cast<size_t>(m));
+  for (int64_t c = 0; c < m; ++c) {
+    for (int64_t i = 0; i < m; ++i) {
+      double v = i == c ? 1.0 : 0.0;
+      for (int64_t k = c; k < i; ++k) v -= A[size_t(i * m + k)] * z[size_t(k)];
+      z[size_t(i)] = i < c ? 0.0 : v / A[size_t(i * m + i)];
+    }
+    for (int64_t i = m - 1; i >= 0; --i) {
+      double v = z[size_t(i)];
+      for (int64_t k = i + 1; k < m; ++k) v -= A[size_t(k * m + i)] * inv[size_t(k * m + c)];
+      inv[size_t(i * m + c)] = v / A[size_t(i * m + i)];
+    }
+  }
+  upload(L.dinv, inv);
+  L.didx.alloc(size_t(m) * sizeof(int32_t));
+  HIPCHK(hipMemcpy(L.didx.p, idx.data(), size_t(m) * sizeof(int32_t), hipMemcpyHostToDevice));
+  L.nint = m;
 }
 
 void check_source(const Op& op) {
@@ -366,6 +429,7 @@ void build(Op& op, hipStream_t st) {
   P->dots.alloc(size_t(RED_BLOCKS + 8) * sizeof(double));
   Dots dd{P->dots.as<double>(), P->dots.as<double>() + RED_BLOCKS};
   for (auto& L : P->lv) L->lmax = power_lmax(*L->op, *L, dd, st);
+  build_dense(*P->lv.back(), st);
   op.pmg = std::move(P);
 }
 
@@ -385,6 +449,7 @@ void refresh(Op& op, hipStream_t st) {
   h_levels_d(op, P, first_h, st);
   Dots dd{P.dots.as<double>(), P.dots.as<double>() + RED_BLOCKS};
   for (auto& L : P.lv) L->lmax = power_lmax(*L->op, *L, dd, st);
+  build_dense(*P.lv.back(), st);
   P.stale = false;
 }
 
@@ -422,7 +487,13 @@ void vcycle(Pmg& P, size_t j, const double* b, double* x, int prec, hipStream_t 
   const int64_t n = L.n;
   if (j + 1 == P.lv.size()) {
     vk_fill(x, 0.0, n, st);
-    cg_inner(A, b, x, P.coarse_tol, COARSE_MAXIT, prec, st);
+    if (L.nint > 0) {
+      // exact: A^-1 on the interior, identity rows on the Dirichlet boundary
+      vk_dense_solve(L.dinv.as<double>(), L.didx.as<int32_t>(), L.nint, b, x, st);
+      vk_copy_indexed(x, b, A.bnd.as<int32_t>(), int64_t(A.space->boundary.size()), st);
+    } else {
+      cg_inner(A, b, x, P.coarse_tol, COARSE_MAXIT, prec, st);
+    }
     return;
   }
   smooth(L, x, b, prec, true, st);

@@ -23,6 +23,9 @@ struct PmgLevel {
   // cell of the finer mesh
   bool hlevel = false;
   std::vector<int32_t> parent;
+  // coarsest level when small: the inverse of A on its interior dofs (dense, row-major)
+  DevBuf dinv, didx;
+  int64_t nint = 0;
   DevBuf x, b;                 // the level's correction and right-hand side (not on level 0,
                                // which works on the outer CG's vectors)
   DevBuf r, d, t;              // V-cycle work vectors

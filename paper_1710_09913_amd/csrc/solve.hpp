@@ -70,6 +70,10 @@ void vk_cheb_step(double* x, double* r, double* d, const double* t, const double
 void vk_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t st);
 void vk_sub(const double* b, const double* t, double* r, int64_t n, hipStream_t st);
 void vk_hash_fill(double* v, int64_t n, hipStream_t st);
+// x[idx[i]] = b[idx[i]] for i < n
+void vk_copy_indexed(double* x, const double* b, const int32_t* idx, int64_t n, hipStream_t st);
+// x[idx[i]] = sum_j M[i][j] b[idx[j]], M dense m x m row-major (other entries of x untouched)
+void vk_dense_solve(const double* M, const int32_t* idx, int64_t m, const double* b, double* x, hipStream_t st);
 // The iteration on FP32 vectors (x FP64): the counterparts of vk_pcg_init, vk_pcg_xr,
 // vk_pcg_p and vk_replace; the inner products stay FP64.
 void vk_pcg_init32(const double* b, const double* y, const float* invd, float* r, float* p, int64_t n, double* part,
