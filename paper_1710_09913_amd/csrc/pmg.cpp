@@ -332,16 +332,55 @@ void build_dense(PmgLevel& L, hipStream_t st) {
     if (!isb[size_t(i)]) idx.push_back(int32_t(i));
   const int64_t m = int64_t(idx.size());
   if (m == 0 || m > DENSE_MAX) return;
-  std::vector<double> A(static_cast<size_t>(m * m));
-  std::vector<double> col(static_cast<size_t>(s.ndofs));
-  DevBuf e(size_t(s.ndofs) * sizeof(double)), y(size_t(s.ndofs) * sizeof(double));
+  // columns by probing: dofs of one colour share no cell neighbour (distance-2 colouring
+  // of the cell graph), so A applied to the sum of their unit vectors gives each column on
+  // its own rows (the dofs sharing a cell with it)
+  const int vt = s.vt;
+  std::vector<std::vector<int64_t>> cells_of(size_t(s.ndofs));
+  for (int64_t c = 0; c < s.nc; ++c)
+    for (int l = 0; l < vt; ++l) cells_of[size_t(s.cell_dofs[c * vt + l])].push_back(c);
+  std::vector<int32_t> colour(size_t(s.ndofs), -1), pos(size_t(s.ndofs), -1);
+  for (int64_t i = 0; i < m; ++i) pos[size_t(idx[size_t(i)])] = int32_t(i);
+  std::vector<int32_t> stamp;
+  int ncol = 0;
   for (int64_t j = 0; j < m; ++j) {
-    vk_fill(e.as<double>(), 0.0, s.ndofs, st);
-    vk_fill(e.as<double>() + idx[size_t(j)], 1.0, 1, st);
+    const int32_t dj = idx[size_t(j)];
+    // colours taken by the dofs within distance 2 (sharing a cell with a neighbour)
+    std::vector<int32_t> nb;
+    for (int64_t c : cells_of[size_t(dj)])
+      for (int l = 0; l < vt; ++l) nb.push_back(s.cell_dofs[c * vt + l]);
+    stamp.assign(size_t(ncol) + 1, 0);
+    for (int32_t a : nb)
+      for (int64_t c : cells_of[size_t(a)])
+        for (int l = 0; l < vt; ++l) {
+          const int32_t o = colour[size_t(s.cell_dofs[c * vt + l])];
+          if (o >= 0) stamp[size_t(o)] = 1;
+        }
+    int k = 0;
+    while (k < ncol && stamp[size_t(k)]) ++k;
+    colour[size_t(dj)] = k;
+    ncol = std::max(ncol, k + 1);
+  }
+  std::vector<double> A(static_cast<size_t>(m * m), 0.0);
+  std::vector<double> col(static_cast<size_t>(s.ndofs));
+  std::vector<double> probe(static_cast<size_t>(s.ndofs));
+  DevBuf e(size_t(s.ndofs) * sizeof(double)), y(size_t(s.ndofs) * sizeof(double));
+  for (int k = 0; k < ncol; ++k) {
+    for (int64_t i = 0; i < s.ndofs; ++i) probe[size_t(i)] = colour[size_t(i)] == k ? 1.0 : 0.0;
+    HIPCHK(hipMemcpy(e.p, probe.data(), probe.size() * sizeof(double), hipMemcpyHostToDevice));
     op_apply(*L.op, e.as<double>(), y.as<double>(), DOGIP_F64, st);
     HIPCHK(hipMemcpyAsync(col.data(), y.p, col.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    for (int64_t i = 0; i < m; ++i) A[size_t(i * m + j)] = col[size_t(idx[size_t(i)])];
+    // row i of column j (colour k): the dofs sharing a cell with j
+    for (int64_t j = 0; j < m; ++j) {
+      const int32_t dj = idx[size_t(j)];
+      if (colour[size_t(dj)] != k) continue;
+      for (int64_t c : cells_of[size_t(dj)])
+        for (int l = 0; l < vt; ++l) {
+          const int32_t di = s.cell_dofs[c * vt + l];
+          if (pos[size_t(di)] >= 0) A[size_t(int64_t(pos[size_t(di)]) * m + j)] = col[size_t(di)];
+        }
+    }
   }
   // Cholesky (lower triangle of A overwritten by L) from the symmetric part
   for (int64_t j = 0; j < m; ++j) {
