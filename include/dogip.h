@@ -99,14 +99,15 @@ extern "C" {
  * same mesh, each a DoGIP operator rebuilt from the operator's coefficient; the
  * prolongation embeds P_{j-1} in P_j (nodal values), the restriction is its transpose;
  * Chebyshev smoothing in D^-1 A (degree 3 on [lmax/8, 1.1 lmax], lmax by power
- * iteration) before and after the coarse correction; the P_1 level solved by
- * Jacobi-PCG to a relative residual of 0.1 (or inner_tol, when in (0, 1)).  For the
- * elliptic problem on a mesh from dogip_mesh_unit with n even, the hierarchy continues
- * below P_1 with P_1 on the
- * nested unit meshes n/2, n/4, ... (not below 16; coefficient averaged over the 2^d
- * children, P_1 interpolation between them), and the coarsest of those is the one solved
- * by Jacobi-PCG.  The hierarchy is built at the first such solve; after a coefficient
- * change the next one rebuilds only the levels' D, diagonals and lmax.
+ * iteration) before and after the coarse correction.  For the elliptic problem on a
+ * mesh from dogip_mesh_unit with n even, the hierarchy continues below P_1 with P_1 on
+ * the nested unit meshes n/2, n/4, ... (coefficient averaged over the 2^d children, P_1
+ * interpolation between them) until the coarsest has at most 400 interior dofs.  A
+ * coarsest level with at most 1000 interior dofs is solved exactly (its dense inverse,
+ * formed at set-up); a larger one by Jacobi-PCG to a relative residual of 0.1 (or
+ * inner_tol, when in (0, 1)).  The hierarchy is built at the first such solve; after a
+ * coefficient change the next one rebuilds only the levels' D, diagonals, lmax and the
+ * coarse inverse.
  * Needs an element-wise operator whose D came from a SCALAR, SYM or LOGSCALAR
  * coefficient or from dogip_op_set_inclusions (each level's D is rebuilt the same way),
  * else DOGIP_E_STATE.  iters counts outer iterations; convergence is verified on

@@ -8,18 +8,19 @@
 // one cell holding it (all agree, the functions being continuous); the restriction is its
 // transpose.  A V-cycle smooths with Chebyshev polynomials in D^-1 A (degree 3 on
 // [lmax/8, 1.1 lmax], lmax by power iteration) before and after the coarse correction,
-// and solves the coarsest level by Jacobi-PCG to a relative residual of 0.1.  The inner
-// solve makes the preconditioner vary between applications, hence the flexible
+// and solves a large coarsest level by Jacobi-PCG to a relative residual of 0.1.  That
+// inner solve makes the preconditioner vary between applications, hence the flexible
 // (Polak-Ribiere) CG outside.
 //
 // On a unit-cube mesh of Kuhn simplices (n^d cubes) the halved mesh is nested in it: each
 // coarse simplex is the union of 2^d fine ones, and every fine vertex is a coarse vertex or
 // the midpoint of a coarse edge.  There the hierarchy continues below P_1 with P_1 on the
-// meshes n/2, n/4, ... down to 16 for the elliptic problem (degree-4 smoothing on
-// [lmax/20, 1.1 lmax]): the
-// coefficient of a coarse cell is the mean over its children (of the logarithm for a
-// log-coefficient; inclusions are integrated again on each mesh), and the prolongation
-// is P_1 interpolation (a midpoint takes the mean of the edge's ends).
+// meshes n/2, n/4, ... for the elliptic problem (degree-4 smoothing on [lmax/20, 1.1 lmax])
+// until the coarsest has at most 400 interior dofs: the coefficient of a coarse cell is
+// the mean over its children (of the logarithm for a log-coefficient; inclusions are
+// integrated again on each mesh), and the prolongation is P_1 interpolation (a midpoint
+// takes the mean of the edge's ends).  A coarsest level that small is solved exactly by
+// its dense inverse.
 #include "pmg.hpp"
 
 #include <cmath>
