@@ -39,6 +39,9 @@
  *     the reference vertex j (0 -> origin).
  *   - Symmetric d x d tensors are packed as the upper triangle row by row:
  *     2D (00, 01, 11), 3D (00, 01, 02, 11, 12, 22).
+ *   - Threads: calls on different operators (or batches) may run concurrently
+ *     from different host threads, each on its own stream; every operator owns
+ *     its work buffers.  Calls on one operator must not overlap.
  */
 #ifndef DOGIP_H
 #define DOGIP_H
