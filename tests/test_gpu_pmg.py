@@ -331,3 +331,37 @@ def test_pmg_geometric_levels_solve_oracle_system(d, n, k, kind, incl):
     _, sj = op.pcg(_gpu(b[perm]), tol=1e-10, maxit=20000, mode="f64")
     print(f"[pmg h] Jacobi-PCG: {sj['iters']} iterations", flush=True)
     assert st["iters"] <= (sj["iters"] + 2 if kind == "wp" else sj["iters"] // 3)
+
+
+def test_concurrent_solves_on_separate_streams():
+    """Operators solved from several host threads, each on its own stream, give the same
+    bits as the solves one after another (every operator owns its buffers)."""
+    import concurrent.futures
+
+    from paper_1710_09913_amd import Mesh, Operator, Space
+
+    probs = []
+    for i, (n, k) in enumerate([(32, 2), (24, 3), (40, 1), (32, 4), (16, 3), (48, 2)]):
+        sp = Space(Mesh.unit(2, n), k, "se", "dirichlet")
+        op = Operator(sp, torch.from_numpy(coef_uniform(sp.ncells, 1.0, 10.0, i)), "scalar", fp32=True)
+        b = _gpu(random_vector(sp.ndofs, seed=i))
+        b[torch.from_numpy(sp.boundary().astype(np.int64)).cuda()] = 0.0
+        probs.append((op, b))
+    modes = ["pmg_mixed", "mixed", "pmg", "f64", "pmg_mixed", "mixed"]
+    ref = [op.pcg(b, tol=1e-9, mode=m)[0].clone() for (op, b), m in zip(probs, modes)]
+    streams = [torch.cuda.Stream() for _ in probs]
+    torch.cuda.synchronize()
+
+    def run(i):
+        op, b = probs[i]
+        with torch.cuda.stream(streams[i]):
+            x, st = op.pcg(b, tol=1e-9, mode=modes[i], stream=streams[i])
+            streams[i].synchronize()
+        return x, st
+
+    with concurrent.futures.ThreadPoolExecutor(len(probs)) as ex:
+        out = list(ex.map(run, range(len(probs))))
+    torch.cuda.synchronize()
+    for (x, st), xr in zip(out, ref):
+        assert st["status"] == 0
+        assert torch.equal(x, xr)
