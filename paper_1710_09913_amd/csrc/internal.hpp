@@ -4,10 +4,12 @@
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <memory>
 #include <mutex>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/dogip.h"
@@ -62,7 +64,12 @@ struct Mesh {
   // p-multigrid hierarchy, the double-grid lattice)
   mutable std::mutex ent_mu;
   mutable std::shared_ptr<const MeshEntities> ent;
+  // cells in the Morton order of their centroids (the tile order of every operator on
+  // this mesh), built once
+  mutable std::shared_ptr<const std::vector<int32_t>> cell_order;
 };
+// the mesh's cell order, built once
+std::shared_ptr<const std::vector<int32_t>> mesh_cell_order(const Mesh& m);
 // the mesh's entities, built once
 std::shared_ptr<const MeshEntities> mesh_entities(const Mesh& m);
 
@@ -157,6 +164,23 @@ struct Op {
   std::unique_ptr<Pmg> pmg;  // p-multigrid hierarchy, built at the first multigrid solve
   ~Op();
 };
+
+// f(i) for i in [0, n) on up to 16 host threads (contiguous ranges); f must not throw
+template <class F>
+inline void parallel_for(int64_t n, F&& f) {
+  const int64_t nt = std::min<int64_t>(std::max<unsigned>(1u, std::thread::hardware_concurrency()), 16);
+  if (nt <= 1 || n < 2 * nt) {
+    for (int64_t i = 0; i < n; ++i) f(i);
+    return;
+  }
+  const int64_t chunk = (n + nt - 1) / nt;
+  std::vector<std::thread> th;
+  for (int64_t k = 0; k < nt; ++k)
+    th.emplace_back([&f, k, chunk, n] {
+      for (int64_t i = k * chunk; i < std::min(n, (k + 1) * chunk); ++i) f(i);
+    });
+  for (auto& x : th) x.join();
+}
 
 // Global numbering of the order-q Lagrange nodes of a mesh (see setup.cpp).
 struct LatticeDofs {

@@ -23,6 +23,8 @@
 // its dense inverse.
 #include "pmg.hpp"
 
+#include <atomic>
+#include <climits>
 #include <cmath>
 #include <utility>
 
@@ -101,27 +103,43 @@ void build_transfer(const Space& F, const Space& Cs, PmgLevel& C) {
   const int d = F.dim, vf = F.vt, vc = Cs.vt;
   std::vector<double> tab;
   coarse_basis_at_nodes(d, F.k, tab);
-  std::vector<int64_t> first(F.ndofs, -1);
-  for (int64_t c = 0; c < F.nc; ++c)
+  // each fine dof's row comes from its first cell node in cell order (the smallest
+  // c * vf + l holding it); cells are scanned in parallel with an atomic minimum
+  std::vector<std::atomic<int64_t>> first(size_t(F.ndofs));
+  for (auto& a : first) a.store(INT64_MAX, std::memory_order_relaxed);
+  parallel_for(F.nc, [&](int64_t c) {
     for (int l = 0; l < vf; ++l) {
-      const int32_t f = F.cell_dofs[c * vf + l];
-      if (first[f] < 0) first[f] = c * vf + l;
+      const int64_t v = c * vf + l;
+      std::atomic<int64_t>& a = first[size_t(F.cell_dofs[c * vf + l])];
+      int64_t cur = a.load(std::memory_order_relaxed);
+      while (v < cur && !a.compare_exchange_weak(cur, v, std::memory_order_relaxed)) {
+      }
     }
+  });
+  std::vector<int> nnz_l(size_t(vf), 0);
+  for (int l = 0; l < vf; ++l)
+    for (int cc = 0; cc < vc; ++cc) nnz_l[size_t(l)] += tab[size_t(l) * vc + cc] != 0.0 ? 1 : 0;
   std::vector<int64_t> prow(F.ndofs + 1, 0);
-  std::vector<int32_t> pcol;
-  std::vector<double> pval;
   for (int64_t f = 0; f < F.ndofs; ++f) {
-    DOGIP_CHECK(first[f] >= 0, DOGIP_E_INVALID, "dof held by no cell");
-    const int64_t c = first[f] / vf;
-    const int l = int(first[f] % vf);
+    const int64_t v = first[size_t(f)].load(std::memory_order_relaxed);
+    DOGIP_CHECK(v != INT64_MAX, DOGIP_E_INVALID, "dof held by no cell");
+    prow[f + 1] = prow[f] + nnz_l[size_t(v % vf)];
+  }
+  const size_t nnz = static_cast<size_t>(prow[F.ndofs]);
+  std::vector<int32_t> pcol(nnz);
+  std::vector<double> pval(nnz);
+  parallel_for(F.ndofs, [&](int64_t f) {
+    const int64_t v = first[size_t(f)].load(std::memory_order_relaxed);
+    const int64_t c = v / vf;
+    const int l = int(v % vf);
+    int64_t at = prow[f];
     for (int cc = 0; cc < vc; ++cc) {
       const double w = tab[size_t(l) * vc + cc];
       if (w == 0.0) continue;
-      pcol.push_back(Cs.cell_dofs[c * vc + cc]);
-      pval.push_back(w);
+      pcol[size_t(at)] = Cs.cell_dofs[c * vc + cc];
+      pval[size_t(at++)] = w;
     }
-    prow[f + 1] = int64_t(pcol.size());
-  }
+  });
   set_transfer(C, F.ndofs, Cs.ndofs, prow, pcol, pval);
 }
 

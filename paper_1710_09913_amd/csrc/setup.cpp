@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 #include "internal.hpp"
 #include "reftab.hpp"
@@ -450,49 +451,61 @@ std::shared_ptr<Space> make_space(std::shared_ptr<const Mesh> mesh, int k, int k
 
 // ---------------------------------------------------------------- tiling
 
-TilePlan make_tiles(const Space& s, int te) {
-  const Mesh& m = *s.mesh;
-  const int d = m.dim, d1 = d + 1, vt = s.vt;
-  TilePlan p;
-  p.te = te;
-  p.ntiles = (s.nc + te - 1) / te;
-  p.nel_pad = p.ntiles * te;
-  // Morton order of cell centroids
-  std::vector<double> cen(size_t(s.nc) * d, 0.0);
-  for (int64_t c = 0; c < s.nc; ++c)
+std::shared_ptr<const std::vector<int32_t>> mesh_cell_order(const Mesh& m) {
+  std::lock_guard<std::mutex> lock(m.ent_mu);
+  if (m.cell_order) return m.cell_order;
+  const int d = m.dim, d1 = d + 1;
+  std::vector<double> cen(size_t(m.nc) * d, 0.0);
+  for (int64_t c = 0; c < m.nc; ++c)
     for (int x = 0; x < d; ++x) {
       double cx = 0;
       for (int j = 0; j < d1; ++j) cx += m.xyz[int64_t(m.cells[c * d1 + j]) * d + x];
       cen[c * d + x] = cx / d1;
     }
-  const std::vector<int64_t> order = morton_order(cen.data(), s.nc, d);
-  p.perm.resize(s.nc);
-  for (int64_t c = 0; c < s.nc; ++c) p.perm[c] = int32_t(order[c]);
+  const std::vector<int64_t> order = morton_order(cen.data(), m.nc, d);
+  auto out = std::make_shared<std::vector<int32_t>>(size_t(m.nc));
+  for (int64_t c = 0; c < m.nc; ++c) (*out)[size_t(c)] = int32_t(order[c]);
+  m.cell_order = out;
+  return out;
+}
+
+TilePlan make_tiles(const Space& s, int te) {
+  const Mesh& m = *s.mesh;
+  const int vt = s.vt;
+  TilePlan p;
+  p.te = te;
+  p.ntiles = (s.nc + te - 1) / te;
+  p.nel_pad = p.ntiles * te;
+  // Morton order of cell centroids (shared by every operator on the mesh)
+  p.perm = *mesh_cell_order(m);
 
   p.nlc = (vt + 7) / 8;
   p.lidx.assign(size_t(p.nel_pad / 64) * p.nlc * 64 * 8, 0);
   p.tile_off.assign(p.ntiles + 1, 0);
-  // pass 1: distinct dofs of every tile, and how many tiles touch each dof
-  std::vector<int32_t> ntile_of(s.ndofs, 0), first_tile(s.ndofs, -1), slot(s.ndofs, -1);
-  std::vector<int32_t> tmp, all;
-  all.reserve(size_t(s.nc) * vt / 2);
-  for (int64_t t = 0; t < p.ntiles; ++t) {
+  // pass 1 (tiles in parallel): distinct dofs of every tile, ascending
+  std::vector<std::vector<int32_t>> lists(size_t(p.ntiles));
+  parallel_for(p.ntiles, [&](int64_t t) {
     const int64_t e0 = t * te, e1 = std::min<int64_t>(s.nc, e0 + te);
-    tmp.clear();
+    std::vector<int32_t>& l = lists[size_t(t)];
+    l.reserve(size_t(e1 - e0) * vt);
     for (int64_t e = e0; e < e1; ++e) {
       const int32_t* cd = &s.cell_dofs[int64_t(p.perm[e]) * vt];
-      tmp.insert(tmp.end(), cd, cd + vt);
+      l.insert(l.end(), cd, cd + vt);
     }
-    std::sort(tmp.begin(), tmp.end());
-    tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
-    DOGIP_CHECK(tmp.size() <= 65535, DOGIP_E_RANGE, "tile touches too many dofs");
-    for (int32_t dof : tmp) {
+    std::sort(l.begin(), l.end());
+    l.erase(std::unique(l.begin(), l.end()), l.end());
+  });
+  // how many tiles touch each dof, and the first of them (tile order)
+  std::vector<int32_t> ntile_of(s.ndofs, 0), first_tile(s.ndofs, -1);
+  for (int64_t t = 0; t < p.ntiles; ++t) {
+    const auto& l = lists[size_t(t)];
+    DOGIP_CHECK(l.size() <= 65535, DOGIP_E_RANGE, "tile touches too many dofs");
+    for (int32_t dof : l) {
       ntile_of[dof]++;
       if (first_tile[dof] < 0) first_tile[dof] = int32_t(t);
     }
-    all.insert(all.end(), tmp.begin(), tmp.end());
-    p.tile_off[t + 1] = int64_t(all.size());
-    p.max_tile_dofs = std::max<int64_t>(p.max_tile_dofs, int64_t(tmp.size()));
+    p.tile_off[t + 1] = p.tile_off[t] + int64_t(l.size());
+    p.max_tile_dofs = std::max<int64_t>(p.max_tile_dofs, int64_t(l.size()));
   }
   // shared (non-Dirichlet) dofs, numbered in ascending dof order
   std::vector<int32_t> sh_index(s.ndofs, -1);
@@ -501,41 +514,51 @@ TilePlan make_tiles(const Space& s, int te) {
       sh_index[i] = int32_t(p.shared.size());
       p.shared.push_back(int32_t(i));
     }
-  // pass 2: order each tile's list as [shared | exclusive | Dirichlet] (ascending dof within
-  // each group); the shared group's partial sums go to stage[stage_off[t] + j]
-  p.tile_dofs.resize(all.size());
-  p.stage_off.assign(p.ntiles + 1, 0);
-  std::vector<uint32_t> cnt(p.shared.size() + 1, 0);
-  for (int64_t t = 0; t < p.ntiles; ++t) {
-    const int64_t o0 = p.tile_off[t], o1 = p.tile_off[t + 1];
-    int64_t w = o0;
+  // pass 2 (tiles in parallel): order each tile's list as [shared | exclusive | Dirichlet]
+  // (ascending dof within each group); the shared group's partial sums go to
+  // stage[stage_off[t] + j].  Local indices of the cells' nodes by binary search in the
+  // ascending list.
+  p.tile_dofs.resize(size_t(p.tile_off[p.ntiles]));
+  std::vector<int64_t> nsh(size_t(p.ntiles), 0);
+  parallel_for(p.ntiles, [&](int64_t t) {
+    const auto& l = lists[size_t(t)];
+    const int64_t o0 = p.tile_off[t];
+    std::vector<uint16_t> at(l.size());
+    int64_t w = 0;
     for (int grp = 0; grp < 3; ++grp)
-      for (int64_t j = o0; j < o1; ++j) {
-        const int32_t dof = all[j];
+      for (size_t j = 0; j < l.size(); ++j) {
+        const int32_t dof = l[j];
         const int g = s.is_bnd[dof] ? 2 : (sh_index[dof] >= 0 ? 0 : 1);
         if (g != grp) continue;
         uint32_t v = uint32_t(dof);
         if (g == 2) v |= TD_BND;
         if (g == 0) v |= TD_SHARED;
         if (first_tile[dof] == t) v |= TD_OWNER;
-        slot[dof] = int32_t(w - o0);
-        p.tile_dofs[w++] = v;
-        if (g == 0) cnt[sh_index[dof] + 1]++;
+        at[j] = uint16_t(w);
+        p.tile_dofs[size_t(o0 + w++)] = v;
+        if (g == 0) nsh[size_t(t)]++;
       }
-    int64_t nsh = 0;
-    for (int64_t j = o0; j < o1; ++j) nsh += (p.tile_dofs[j] & TD_SHARED) ? 1 : 0;
-    p.stage_off[t + 1] = p.stage_off[t] + nsh;
     const int64_t e0 = t * te, e1 = std::min<int64_t>(s.nc, e0 + te);
     for (int64_t e = e0; e < e1; ++e) {
       const int32_t* cd = &s.cell_dofs[int64_t(p.perm[e]) * vt];
-      for (int l = 0; l < vt; ++l) {
-        size_t at = ((size_t(e >> 6) * p.nlc + l / 8) * 64 + (e & 63)) * 8 + (l % 8);
-        p.lidx[at] = uint16_t(slot[cd[l]]);
+      for (int lo = 0; lo < vt; ++lo) {
+        const size_t j = size_t(std::lower_bound(l.begin(), l.end(), cd[lo]) - l.begin());
+        const size_t pos = ((size_t(e >> 6) * p.nlc + lo / 8) * 64 + (e & 63)) * 8 + (lo % 8);
+        p.lidx[pos] = at[j];
       }
     }
-  }
+  });
+  p.stage_off.assign(p.ntiles + 1, 0);
+  for (int64_t t = 0; t < p.ntiles; ++t) p.stage_off[t + 1] = p.stage_off[t] + nsh[size_t(t)];
   DOGIP_CHECK(p.stage_off[p.ntiles] < (int64_t(1) << 32), DOGIP_E_RANGE, "too many shared entries");
   // reduction lists: for each shared dof, its staging slots in ascending tile order
+  std::vector<uint32_t> cnt(p.shared.size() + 1, 0);
+  for (int64_t t = 0; t < p.ntiles; ++t)
+    for (int64_t j = p.tile_off[t]; j < p.tile_off[t + 1]; ++j) {
+      const uint32_t v = p.tile_dofs[size_t(j)];
+      if (!(v & TD_SHARED)) break;  // shared entries come first
+      cnt[size_t(sh_index[v & TD_MASK]) + 1]++;
+    }
   for (size_t i = 1; i < cnt.size(); ++i) cnt[i] += cnt[i - 1];
   p.sh_rowptr = cnt;
   p.sh_slots.assign(p.stage_off[p.ntiles], 0);
