@@ -38,7 +38,7 @@ class QCase:
         self.space = Space(Mesh(self.coords, self.cells), k, kind, "dirichlet" if self.dirichlet else "none")
         pts, _ = quadrature_rule(d, nq1)
         self.samples = samples_at(self.coords, self.cells, pts, coef)
-        self.op = Operator.quadrature(self.space, nq1, torch.from_numpy(self.samples), tile_waves=tile_waves)
+        self.op = Operator.quadrature(self.space, nq1, torch.from_numpy(np.array(self.samples)), tile_waves=tile_waves)
         self.osp = fem.make_space(self.coords, self.cells, k)
         self.A = fem.assemble(self.osp, fem.element_matrices(self.osp, coef, kind, nquad=nq1)).tocsr()
         self.perm = match_dofs(self.space.dof_coords(), self.osp.dof_coords)
