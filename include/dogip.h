@@ -277,7 +277,8 @@ int dogip_op_set_inclusions(dogip_op op, int nballs, const double* balls, double
  * degree <= 2n - dim (so its weights sum to |T^| when 2n >= dim).
  * dogip_op_create_qp: coef is a device array [ncells][n^dim] (mesh cell order) of the
  * scalar coefficient at the mapped points x_q = X_0 + R_T xhat_q, read during the
- * call.  flags: DOGIP_OP_FP32 or 0.  The operator supports dogip_apply, dogip_diag,
+ * call.  flags: DOGIP_OP_FP32 or 0.  tile_waves: as for dogip_op_create, 0 meaning 4
+ * here.  The operator supports dogip_apply, dogip_diag,
  * dogip_pcg and the timer; dogip_op_set_coef, dogip_op_export_d and
  * dogip_grad_logcoef return DOGIP_E_STATE.  Orders: 2D k <= 5, 3D k <= 3
  * (projection) or 4 (elliptic), else DOGIP_E_RANGE.  Synchronizes the stream. */
