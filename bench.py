@@ -351,11 +351,11 @@ def run_c5(a):
         pmg[rep] = time.time() - t0
     log(f"[c5] one problem after another (multigrid, FP32 V-cycle): {pmg['timed']:.3f}s "
         f"(first pass with the hierarchies {pmg['first_pass']:.3f}s), worst relres {worst:.2e}")
-    # the same solves from 8 host threads, each on its own stream (every operator owns its
+    # the same solves from several host threads, each on its own stream (every operator owns its
     # work buffers and hierarchy, so the small, latency-bound solves overlap on the GPU)
     import concurrent.futures
 
-    nthreads = 8
+    nthreads = max(1, a.threads)
     streams = [torch.cuda.Stream() for _ in range(nthreads)]
     torch.cuda.synchronize()
 
@@ -520,6 +520,7 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--threads", type=int, default=16, help="host threads for the batch's concurrent solves")
     ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "c5", "qp", "incl"],
                     help="c3: 3D 64^3 P3 (default, the headline); c2: 2D 512^2 P1..P5 sweep; "
                          "c4: 2D 256^2 P3 adjoint gradient; c5: batch of 256 uneven 2D problems; "
