@@ -230,6 +230,32 @@ __global__ __launch_bounds__(256) void k_dense_solve(const double* __restrict__ 
   if (threadIdx.x == 0) x[idx[i]] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// flexible CG scalars kept on the device: s[0] r.z, s[1] p.Ap, s[2] alpha, s[3] r.r,
+// s[4] r.z (new z), s[5] r.z (previous z), s[6] beta, s[7] flag (1 breakdown, 2 non-finite)
+__global__ void k_fcg_alpha(double* s) {
+  const double rz = s[0], pq = s[1];
+  const bool finite = isfinite(rz) && isfinite(pq);
+  const bool ok = finite && pq > 0.0;
+  s[2] = ok ? rz / pq : 0.0;
+  if (!ok) s[7] = finite ? 1.0 : 2.0;
+}
+__global__ void k_fcg_beta(double* s) {
+  s[6] = (s[4] - s[5]) / s[0];
+  s[0] = s[4];
+}
+// y += sign s[k] x (the fma of y = a x + y)
+__global__ __launch_bounds__(256) void k_axpy_s(double* y, const double* __restrict__ x, const double* __restrict__ s,
+                                                int k, double sign, int64_t n) {
+  const double a = sign * s[k];
+  GRID_STRIDE(i, n) y[i] = fma(a, x[i], y[i]);
+}
+// p = z + s[k] p (the fma of p = 1 z + beta p)
+__global__ __launch_bounds__(256) void k_xpby_s(double* p, const double* __restrict__ z, const double* __restrict__ s,
+                                                int k, int64_t n) {
+  const double beta = s[k];
+  GRID_STRIDE(i, n) p[i] = fma(1.0, z[i], beta * p[i]);
+}
+
 // x[idx[i]] = b[idx[i]]
 __global__ __launch_bounds__(256) void k_copy_indexed(double* __restrict__ x, const double* __restrict__ b,
                                                       const int32_t* __restrict__ idx, int64_t n) {
@@ -443,6 +469,14 @@ void vk_sub(const double* b, const double* t, double* r, int64_t n, hipStream_t 
 void vk_dense_solve(const double* M, const int32_t* idx, int64_t m, const double* b, double* x, hipStream_t st) {
   if (m <= 0) return;
   hipLaunchKernelGGL(dev::k_dense_solve, dim3(unsigned(m)), dim3(256), 0, st, M, idx, m, b, x);
+}
+void vk_fcg_alpha(double* s, hipStream_t st) { hipLaunchKernelGGL(dev::k_fcg_alpha, dim3(1), dim3(1), 0, st, s); }
+void vk_fcg_beta(double* s, hipStream_t st) { hipLaunchKernelGGL(dev::k_fcg_beta, dim3(1), dim3(1), 0, st, s); }
+void vk_axpy_s(double* y, const double* x, const double* s, int k, double sign, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_axpy_s, dim3(red_grid(n) * 4), dim3(256), 0, st, y, x, s, k, sign, n);
+}
+void vk_xpby_s(double* p, const double* z, const double* s, int k, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_xpby_s, dim3(red_grid(n) * 4), dim3(256), 0, st, p, z, s, k, n);
 }
 void vk_copy_indexed(double* x, const double* b, const int32_t* idx, int64_t n, hipStream_t st) {
   if (n <= 0) return;

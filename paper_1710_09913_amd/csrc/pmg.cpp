@@ -485,6 +485,7 @@ void build(Op& op, hipStream_t st) {
   P->p.alloc(vb);
   P->q.alloc(vb);
   P->dots.alloc(size_t(RED_BLOCKS + 8) * sizeof(double));
+  P->fcg.alloc(8 * sizeof(double));
   Dots dd{P->dots.as<double>(), P->dots.as<double>() + RED_BLOCKS};
   for (auto& L : P->lv) L->lmax = power_lmax(*L->op, *L, dd, st);
   build_dense(*P->lv.back(), st);
@@ -600,25 +601,29 @@ int op_pcg_pmg(Op& op, const double* b, double* x, const dogip_solve_opts& o, do
   double rr = dot(dd, r, r, n, st);
   stats.relres = std::sqrt(rr / bb);
   if (rr <= thr) return DOGIP_OK;
+  // the iteration keeps its scalars on the device (one host synchronization per
+  // iteration, for r.r and the flag)
+  double* S = P.fcg.as<double>();
+  vk_fill(S, 0.0, 8, st);
   vcycle(P, 0, r, z, prec, st);
   copy(p, z, n, st);
-  double rz = dot(dd, r, z, n, st);
+  vk_dot(r, z, n, dd.part, S + 0, st);
   while (it < o.maxit) {
     op_apply(op, p, q, DOGIP_F64, st);
-    const double pq = dot(dd, p, q, n, st);
-    if (!std::isfinite(pq) || !std::isfinite(rz)) {
-      status = DOGIP_E_NONFINITE;
+    vk_dot(p, q, n, dd.part, S + 1, st);
+    vk_fcg_alpha(S, st);
+    vk_axpy_s(x, p, S, 2, 1.0, n, st);
+    vk_axpy_s(r, q, S, 2, -1.0, n, st);
+    vk_dot(r, r, n, dd.part, S + 3, st);
+    double h[8];
+    HIPCHK(hipMemcpyAsync(h, S, sizeof h, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (h[7] != 0.0) {
+      status = h[7] == 1.0 ? DOGIP_E_BREAKDOWN : DOGIP_E_NONFINITE;
       break;
     }
-    if (!(pq > 0.0)) {
-      status = DOGIP_E_BREAKDOWN;
-      break;
-    }
-    const double alpha = rz / pq;
-    vk_axpby(alpha, p, 1.0, x, n, st);
-    vk_axpby(-alpha, q, 1.0, r, n, st);
     ++it;
-    rr = dot(dd, r, r, n, st);
+    rr = h[3];
     stats.relres = std::sqrt(rr / bb);
     if (!std::isfinite(rr)) {
       status = DOGIP_E_NONFINITE;
@@ -637,15 +642,15 @@ int op_pcg_pmg(Op& op, const double* b, double* x, const dogip_solve_opts& o, do
       if (++restarts > MAX_RESTARTS) break;
       vcycle(P, 0, r, z, prec, st);
       copy(p, z, n, st);
-      rz = dot(dd, r, z, n, st);
+      vk_dot(r, z, n, dd.part, S + 0, st);
       continue;
     }
     std::swap(z, zo);
     vcycle(P, 0, r, z, prec, st);
-    const double rzn = dot(dd, r, z, n, st), rzo = dot(dd, r, zo, n, st);
-    const double beta = (rzn - rzo) / rz;
-    vk_axpby(1.0, z, beta, p, n, st);
-    rz = rzn;
+    vk_dot(r, z, n, dd.part, S + 4, st);
+    vk_dot(r, zo, n, dd.part, S + 5, st);
+    vk_fcg_beta(S, st);
+    vk_xpby_s(p, z, S, 6, n, st);
   }
   stats.iters = it;
   stats.outer = it + restarts;

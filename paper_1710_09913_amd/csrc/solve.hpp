@@ -70,6 +70,13 @@ void vk_cheb_step(double* x, double* r, double* d, const double* t, const double
 void vk_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t st);
 void vk_sub(const double* b, const double* t, double* r, int64_t n, hipStream_t st);
 void vk_hash_fill(double* v, int64_t n, hipStream_t st);
+// flexible CG on device scalars s[8] (r.z, p.Ap, alpha, r.r, new r.z, old r.z, beta, flag):
+// alpha = r.z / p.Ap (flag 1 if p.Ap <= 0, 2 if not finite); beta = (new - old) / r.z,
+// r.z = new; y += sign s[k] x; p = z + s[k] p
+void vk_fcg_alpha(double* s, hipStream_t st);
+void vk_fcg_beta(double* s, hipStream_t st);
+void vk_axpy_s(double* y, const double* x, const double* s, int k, double sign, int64_t n, hipStream_t st);
+void vk_xpby_s(double* p, const double* z, const double* s, int k, int64_t n, hipStream_t st);
 // x[idx[i]] = b[idx[i]] for i < n
 void vk_copy_indexed(double* x, const double* b, const int32_t* idx, int64_t n, hipStream_t st);
 // x[idx[i]] = sum_j M[i][j] b[idx[j]], M dense m x m row-major (other entries of x untouched)
