@@ -7,7 +7,9 @@ The full operator is too large for the oracle, so each case checks
     dof (a row of A only involves the cells around its dof), FP64 to 1e-12 of
     |B^|^T|D||B^||u| and FP32 within 2 gamma_m of it;
   * properties that hold at any size: symmetry v.(A u) = u.(A v), identity rows
-    on the Dirichlet dofs (bit-exact), bitwise-reproducible repeated applies.
+    on the Dirichlet dofs (bit-exact), bitwise-reproducible repeated applies;
+  * the multigrid-preconditioned solve to 1e-8: the oracle's rows of b - A x at
+    sampled dofs stay within the solve's residual norm.
 """
 
 import numpy as np
@@ -33,7 +35,7 @@ class FullCase:
     def __init__(self, d, n, k, kind, seed=0, global_w=False):
         from paper_1710_09913_amd import Mesh, Operator, Space
 
-        self.d, self.k, self.kind = d, k, kind
+        self.d, self.k, self.kind, self.global_w = d, k, kind, global_w
         self.coords, self.cells = unit_mesh(d, n)
         nel = len(self.cells)
         if d == 3:
@@ -51,8 +53,10 @@ class FullCase:
         self.cd = self.space.cell_dofs()
         self.bnd = self.space.boundary() if self.dirichlet else np.zeros(0, np.int32)
 
-    def sampled_rows(self, samples):
-        """Oracle rows of A u at the sampled dofs, and |B^|^T|D||B^||u| there."""
+    def sampled_rows(self, samples, u=None):
+        """Oracle rows of A u (u: the case's random vector unless given) at the sampled
+        dofs, and |B^|^T|D||B^||u| there."""
+        u = self.u if u is None else u
         touch = np.isin(self.cd, samples).any(axis=1)
         sub = np.nonzero(touch)[0]
         verts, local = np.unique(self.cells[sub], return_inverse=True)
@@ -65,7 +69,7 @@ class FullCase:
         pid = np.unique(self.cd[sub])
         perm = match_dofs(self.space.dof_coords()[pid], osp.dof_coords)
         uo = np.zeros(osp.ndofs)
-        uo[perm] = self.u[pid]
+        uo[perm] = u[pid]
         if self.dirichlet:
             uo[perm[np.isin(pid, self.bnd)]] = 0.0  # boundary columns drop out of interior rows
         yo = odg.apply(osp, D, uo, self.kind)
@@ -136,3 +140,21 @@ def test_fullsize_bitwise_reproducible(full):
     z1 = c.op.apply(c.ug, prec="f32")
     z2 = c.op.apply(c.ug, prec="f32")
     assert torch.equal(z1, z2)
+
+
+def test_fullsize_multigrid_solve_sampled_residual(full):
+    """Multigrid-preconditioned CG with the FP32 V-cycle to 1e-8 at the benchmark size;
+    every sampled row of b - A x, with A x from the oracle, is within the solve's
+    residual norm (plus the apply's rounding)."""
+    c = full
+    if c.global_w:
+        pytest.skip("the multigrid solve needs the element-wise D")
+    b = random_vector(c.space.ndofs, 21)
+    if c.dirichlet:
+        b[c.bnd] = 0.0
+    x, st = c.op.pcg(torch.from_numpy(b).cuda(), tol=1e-8, maxit=500, mode="pmg_mixed")
+    print(f"[full] multigrid: {st['iters']} iterations, relres {st['relres_true']:.2e}", flush=True)
+    assert st["status"] == 0 and st["relres_true"] <= 1.05e-8
+    s = _samples(c, seed=5)
+    yo, ab = c.sampled_rows(s, x.cpu().numpy())
+    assert np.all(np.abs(b[s] - yo) <= 1.05e-8 * np.linalg.norm(b) + 1e-11 * ab)
