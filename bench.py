@@ -276,11 +276,10 @@ def run_c4(a):
     return out
 
 
-def run_c5(a):
-    """256 independent 2D elliptic problems (N ~ logU[32,256], k ~ U{1..4}, a ~ U[1,10]):
-    tuned tiles, one persistent launch per apply, batched FP64 vs mixed PCG to 1e-8,
-    against solving the problems one after another."""
-    import numpy as np
+def c5_problems(seed):
+    """The batch workload: 256 2D elliptic problems (N ~ logU[32,256], k ~ U{1..4},
+    a ~ U[1,10], zero Dirichlet) with tuned tiles, as operators, their Batch, and the
+    coefficients (mesh cell order)."""
     import torch
 
     from paper_1710_09913_amd import Batch, Mesh, Operator, Space, tune
@@ -289,17 +288,27 @@ def run_c5(a):
     for k in (1, 2, 3, 4):
         if tune.tuned(2, k, "se", "f32") == (0, 0):
             tune.tune(2, k, "se", "f32", max_tile_cells=256)
-    spec = batch_spec(256, a.seed)
-    ops, meshes = [], {}
-    t0 = time.time()
+    spec = batch_spec(256, seed)
+    ops, coefs, meshes = [], [], {}
     for n, k, sub in spec:
         if n not in meshes:
             meshes[n] = Mesh.unit(2, n)
         sp = Space(meshes[n], k, "se", "dirichlet")
         tw, var = tune.tuned(2, k, "se", "f32")
-        ops.append(Operator(sp, torch.from_numpy(coef_uniform(sp.ncells, 1, 10, a.seed, sub)), "scalar", fp32=True,
-                            tile_waves=tw, variant=1))
-    bt = Batch(ops)
+        coefs.append(coef_uniform(sp.ncells, 1, 10, seed, sub))
+        ops.append(Operator(sp, torch.from_numpy(coefs[-1]), "scalar", fp32=True, tile_waves=tw, variant=1))
+    return ops, Batch(ops), coefs
+
+
+def run_c5(a):
+    """256 independent 2D elliptic problems (N ~ logU[32,256], k ~ U{1..4}, a ~ U[1,10]):
+    tuned tiles, one persistent launch per apply, batched FP64 vs mixed PCG to 1e-8,
+    against solving the problems one after another."""
+    import numpy as np
+    import torch
+
+    t0 = time.time()
+    ops, bt, _ = c5_problems(a.seed)
     log(f"[c5] {len(ops)} problems, {bt.ndofs} dofs, setup {time.time() - t0:.1f}s")
     rhs = torch.ones(bt.ndofs, dtype=torch.float64, device="cuda")
     for i, op in enumerate(ops):

@@ -100,3 +100,35 @@ def test_batch_errors():
     rhs = torch.ones(b.ndofs, dtype=torch.float64, device="cuda")
     with pytest.raises(DogipError):
         b.pcg(rhs, x=torch.zeros_like(rhs))
+
+
+def test_batch_fullsize_in_bench_configuration():
+    """The batch workload at its full size (256 problems, 34.6M dofs, tuned tiles, one
+    persistent launch): the batched apply equals each problem's own apply bit for bit
+    on a sample of problems, in FP64 and FP32, and the smallest problems match the
+    oracle's Algorithm 1."""
+    import bench
+
+    ops, bt, coefs = bench.c5_problems(0)
+    print(f"[batch full] {len(ops)} problems, {bt.ndofs} dofs", flush=True)
+    u = torch.from_numpy(random_vector(bt.ndofs, 4)).cuda()
+    rng = np.random.default_rng(9)
+    pick = rng.choice(len(ops), 16, replace=False)
+    for prec in ("f64", "f32"):
+        y = bt.apply(u, prec=prec)
+        for i in pick:
+            lo, hi = int(bt.offsets[i]), int(bt.offsets[i + 1])
+            assert torch.equal(y[lo:hi], ops[i].apply(u[lo:hi].contiguous(), prec=prec)), (prec, i)
+    y = bt.apply(u).cpu().numpy()
+    uh = u.cpu().numpy()
+    for i in np.argsort([op.ndofs for op in ops])[:3]:
+        op = ops[i]
+        lo, hi = int(bt.offsets[i]), int(bt.offsets[i + 1])
+        n = int(round(np.sqrt(op.space.ncells / 2)))
+        coords, cells = unit_mesh(2, n)
+        osp = fem.make_space(coords, cells, op.space.info["k"])
+        perm = match_dofs(op.space.dof_coords(), osp.dof_coords)
+        uo = np.empty(hi - lo)
+        uo[perm] = uh[lo:hi]
+        yo = odg.apply_dirichlet(osp, odg.build_d(osp, coefs[i], "se"), uo, "se")[perm]
+        assert rel_err(y[lo:hi], yo) <= 1e-11
