@@ -182,6 +182,18 @@ inline void parallel_for(int64_t n, F&& f) {
   for (auto& x : th) x.join();
 }
 
+// f(t) for t in [0, ntasks), one host thread per task (ntasks small); f must not throw
+template <class F>
+inline void parallel_tasks(int64_t ntasks, F&& f) {
+  if (ntasks <= 1) {
+    if (ntasks == 1) f(0);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int64_t t = 0; t < ntasks; ++t) th.emplace_back([&f, t] { f(t); });
+  for (auto& x : th) x.join();
+}
+
 // Global numbering of the order-q Lagrange nodes of a mesh (see setup.cpp).
 struct LatticeDofs {
   int nl = 0;                      // nodes per cell

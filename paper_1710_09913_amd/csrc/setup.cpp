@@ -2,6 +2,8 @@
 // the cell tiling used by the device kernels.
 #include <algorithm>
 #include <array>
+#include <atomic>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -159,7 +161,7 @@ static std::vector<int64_t> morton_order(const double* xyz, int64_t n, int d) {
     }
   const double bits = d == 3 ? 2097151.0 : 4294967295.0;
   std::vector<std::pair<uint64_t, int64_t>> key(n);
-  for (int64_t i = 0; i < n; ++i) {
+  parallel_for(n, [&](int64_t i) {
     uint64_t code = 0;
     for (int x = 0; x < d; ++x) {
       const double t = hi[x] > lo[x] ? (xyz[i * d + x] - lo[x]) / (hi[x] - lo[x]) : 0.0;
@@ -167,25 +169,45 @@ static std::vector<int64_t> morton_order(const double* xyz, int64_t n, int d) {
       code |= (d == 3 ? spread3(qv) : spread2(qv)) << x;
     }
     key[i] = {code, i};
-  }
+  });
   // LSD radix sort on 16-bit digits: each pass is a stable counting sort, so equal codes
-  // keep ascending index order (the order of sorting the (code, index) pairs)
+  // keep ascending index order (the order of sorting the (code, index) pairs).  A pass
+  // splits the keys into contiguous ranges, one per thread: per-range digit counts, then
+  // each range scatters from its own offsets (range r's keys of a digit follow those of
+  // ranges < r), which keeps the pass stable
+  const int64_t nr = std::max<int64_t>(
+      1, std::min<int64_t>({n / 65536, 16, int64_t(std::max(1u, std::thread::hardware_concurrency()))}));
+  const int64_t chunk = (n + nr - 1) / nr;
   std::vector<std::pair<uint64_t, int64_t>> tmp(n);
-  std::vector<int64_t> cnt(65537);
+  std::vector<int64_t> cnt(size_t(nr) * 65536);
   for (int shift = 0; shift < 64; shift += 16) {
     std::fill(cnt.begin(), cnt.end(), 0);
-    for (int64_t i = 0; i < n; ++i) cnt[((key[i].first >> shift) & 0xffff) + 1]++;
+    parallel_tasks(nr, [&](int64_t r) {
+      int64_t* c = &cnt[size_t(r) * 65536];
+      for (int64_t i = r * chunk; i < std::min(n, (r + 1) * chunk); ++i) c[(key[i].first >> shift) & 0xffff]++;
+    });
+    // offsets in (digit, range) order; a single digit value throughout leaves the order as is
     bool trivial = false;
-    for (int b = 1; b <= 65536; ++b) {
-      if (cnt[b] == n) trivial = true;
-      cnt[b] += cnt[b - 1];
+    int64_t run = 0;
+    for (int b = 0; b < 65536; ++b) {
+      int64_t tot = 0;
+      for (int64_t r = 0; r < nr; ++r) {
+        const int64_t c = cnt[size_t(r) * 65536 + b];
+        cnt[size_t(r) * 65536 + b] = run + tot;
+        tot += c;
+      }
+      if (tot == n) trivial = true;
+      run += tot;
     }
-    if (trivial) continue;  // one digit value throughout: the pass would not move anything
-    for (int64_t i = 0; i < n; ++i) tmp[cnt[(key[i].first >> shift) & 0xffff]++] = key[i];
+    if (trivial) continue;
+    parallel_tasks(nr, [&](int64_t r) {
+      int64_t* c = &cnt[size_t(r) * 65536];
+      for (int64_t i = r * chunk; i < std::min(n, (r + 1) * chunk); ++i) tmp[c[(key[i].first >> shift) & 0xffff]++] = key[i];
+    });
     key.swap(tmp);
   }
   std::vector<int64_t> order(n);
-  for (int64_t i = 0; i < n; ++i) order[i] = key[i].second;
+  parallel_for(n, [&](int64_t i) { order[i] = key[i].second; });
   return order;
 }
 
@@ -209,13 +231,14 @@ EntityIds number_entities(const Mesh& m, const std::vector<std::array<int, NV>>&
     int64_t slot;
   };
   std::vector<Key> keys(size_t(m.nc) * nl);
-  for (int64_t c = 0; c < m.nc; ++c)
+  parallel_for(m.nc, [&](int64_t c) {
     for (int e = 0; e < nl; ++e) {
       Key& k = keys[size_t(c) * nl + e];
       for (int t = 0; t < NV; ++t) k.v[t] = m.cells[c * d1 + loc[e][t]];
       std::sort(k.v.begin(), k.v.end());
       k.slot = c * nl + e;
     }
+  });
   // lexicographic order of the tuples: a counting sort by the smallest vertex id, then
   // each bucket (the entities around one vertex, a few dozen) sorted on the full tuple
   {
@@ -225,8 +248,10 @@ EntityIds number_entities(const Mesh& m, const std::vector<std::array<int, NV>>&
     std::vector<Key> by(keys.size());
     std::vector<int64_t> at(start.begin(), start.end() - 1);
     for (const Key& k : keys) by[at[k.v[0]]++] = k;
-    for (int64_t v = 0; v < m.nv; ++v)
+    // (equal tuples get one id whatever their order, so the buckets sort independently)
+    parallel_for(m.nv, [&](int64_t v) {
       std::sort(by.begin() + start[v], by.begin() + start[v + 1], [](const Key& a, const Key& b) { return a.v < b.v; });
+    });
     keys.swap(by);
   }
   EntityIds ids;
@@ -345,19 +370,9 @@ LatticeDofs number_lattice(const Mesh& m, int q, bool xyz) {
     for (int j = 0; j < 3; ++j) opp_edge[j] = local_edge_of(ledges, (j + 1) % 3, (j + 2) % 3);
 
   out.cell_dofs.assign(size_t(m.nc) * vt, -1);
-  std::vector<uint8_t> seen;
-  if (xyz) {
-    out.xyz.assign(size_t(out.ndofs) * d, 0.0);
-    out.is_bnd.assign(out.ndofs, 0);
-    seen.assign(out.ndofs, 0);
-  }
-  for (int64_t c = 0; c < m.nc; ++c) {
+  // the dof of every cell node (cells in parallel; a pure function of the cell)
+  parallel_for(m.nc, [&](int64_t c) {
     const int32_t* cv = &m.cells[c * d1];
-    // boundary facets of this cell: facet opposite local vertex j
-    bool fb[4] = {false, false, false, false};
-    if (xyz)
-      for (int j = 0; j <= d; ++j)
-        fb[j] = d == 2 ? M.edge_cells[M.cell_edge[c * nle + opp_edge[j]]] == 1 : M.face_cells[M.cell_face[c * 4 + j]] == 1;
     for (int l = 0; l < vt; ++l) {
       const Node& n = nd[l];
       int64_t dof;
@@ -380,22 +395,47 @@ LatticeDofs number_lattice(const Mesh& m, int q, bool xyz) {
         dof = base_c + c * nint + n.iord;
       }
       out.cell_dofs[c * vt + l] = int32_t(dof);
-      if (!xyz) continue;
-      for (int j = 0; j <= d; ++j)
-        if (n.b[j] == 0 && fb[j]) out.is_bnd[dof] = 1;
-      if (seen[dof]) continue;
-      seen[dof] = 1;
-      // coordinates, summed in ascending vertex-id order so they do not depend on the cell
-      std::array<std::pair<int32_t, int>, 4> vw;
-      for (int t = 0; t < n.ns; ++t) vw[t] = {cv[n.sup[t]], n.mult[t]};
-      std::sort(vw.begin(), vw.begin() + n.ns);
-      for (int x = 0; x < d; ++x) {
-        double acc = 0.0;
-        for (int t = 0; t < n.ns; ++t) acc += (double(vw[t].second) / q) * m.xyz[int64_t(vw[t].first) * d + x];
-        out.xyz[dof * d + x] = acc;
+    }
+  });
+  if (!xyz) return out;
+  out.xyz.assign(size_t(out.ndofs) * d, 0.0);
+  out.is_bnd.assign(out.ndofs, 0);
+  // boundary flags: nodes on a facet held by one cell only
+  for (int64_t c = 0; c < m.nc; ++c)
+    for (int j = 0; j <= d; ++j) {
+      const bool fb = d == 2 ? M.edge_cells[M.cell_edge[c * nle + opp_edge[j]]] == 1
+                             : M.face_cells[M.cell_face[c * 4 + j]] == 1;
+      if (!fb) continue;
+      for (int l = 0; l < vt; ++l)
+        if (nd[l].b[j] == 0) out.is_bnd[out.cell_dofs[c * vt + l]] = 1;
+    }
+  // coordinates, once per dof from its first cell node (an atomic minimum over the cells
+  // in parallel), summed in ascending vertex-id order so they do not depend on the cell
+  std::vector<std::atomic<int64_t>> first(size_t(out.ndofs));
+  for (auto& f : first) f.store(INT64_MAX, std::memory_order_relaxed);
+  parallel_for(m.nc, [&](int64_t c) {
+    for (int l = 0; l < vt; ++l) {
+      const int64_t v = c * vt + l;
+      std::atomic<int64_t>& f = first[size_t(out.cell_dofs[v])];
+      int64_t cur = f.load(std::memory_order_relaxed);
+      while (v < cur && !f.compare_exchange_weak(cur, v, std::memory_order_relaxed)) {
       }
     }
-  }
+  });
+  parallel_for(out.ndofs, [&](int64_t dof) {
+    const int64_t v = first[size_t(dof)].load(std::memory_order_relaxed);
+    const int64_t c = v / vt;
+    const Node& n = nd[size_t(v % vt)];
+    const int32_t* cv = &m.cells[c * d1];
+    std::array<std::pair<int32_t, int>, 4> vw;
+    for (int t = 0; t < n.ns; ++t) vw[t] = {cv[n.sup[t]], n.mult[t]};
+    std::sort(vw.begin(), vw.begin() + n.ns);
+    for (int x = 0; x < d; ++x) {
+      double acc = 0.0;
+      for (int t = 0; t < n.ns; ++t) acc += (double(vw[t].second) / q) * m.xyz[int64_t(vw[t].first) * d + x];
+      out.xyz[dof * d + x] = acc;
+    }
+  });
   return out;
 }
 
@@ -429,14 +469,14 @@ std::shared_ptr<Space> make_space(std::shared_ptr<const Mesh> mesh, int k, int k
   {
     const std::vector<int64_t> order = morton_order(s->dof_xyz.data(), s->ndofs, d);
     std::vector<int32_t> inv(s->ndofs);
-    for (int64_t i = 0; i < s->ndofs; ++i) inv[order[i]] = int32_t(i);
-    for (auto& v : s->cell_dofs) v = inv[v];
+    parallel_for(s->ndofs, [&](int64_t i) { inv[order[i]] = int32_t(i); });
+    parallel_for(int64_t(s->cell_dofs.size()), [&](int64_t i) { s->cell_dofs[size_t(i)] = inv[s->cell_dofs[size_t(i)]]; });
     std::vector<double> xyz(s->dof_xyz.size());
     std::vector<uint8_t> bnd(s->ndofs);
-    for (int64_t i = 0; i < s->ndofs; ++i) {
+    parallel_for(s->ndofs, [&](int64_t i) {
       for (int x = 0; x < d; ++x) xyz[i * d + x] = s->dof_xyz[order[i] * d + x];
       bnd[i] = s->is_bnd[order[i]];
-    }
+    });
     s->dof_xyz.swap(xyz);
     s->is_bnd.swap(bnd);
   }
