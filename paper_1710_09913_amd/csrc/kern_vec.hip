@@ -199,9 +199,9 @@ __global__ __launch_bounds__(256) void k_fill(double* __restrict__ x, double v, 
 // y = A x (ACC: y += A x) for a CSR matrix, G lanes per row: the lanes of a group stride
 // over the row's entries (coalesced reads of col and val), then a butterfly inside the
 // group adds their partial sums in a fixed order
-template <int G, bool ACC>
+template <int G, bool ACC, typename TX>
 __global__ __launch_bounds__(256) void k_csr(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                                             const double* __restrict__ val, const double* __restrict__ x,
+                                             const double* __restrict__ val, const TX* __restrict__ x,
                                              double* __restrict__ y, int64_t nrows) {
   const int lane = int(threadIdx.x) % G;
   const int64_t stride = int64_t(gridDim.x) * (256 / G);
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(256) void k_csr(const int64_t* __restrict__ rowptr,
   for (int64_t row = (int64_t(blockIdx.x) * 256 + threadIdx.x) / G; row < nrows; row += stride) {
     double s = 0.0;
     const int64_t e = rowptr[row + 1];
-    for (int64_t j = rowptr[row] + lane; j < e; j += G) s = fma(val[j], x[col[j]], s);
+    for (int64_t j = rowptr[row] + lane; j < e; j += G) s = fma(val[j], double(x[col[j]]), s);
     for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
     if (lane == 0) y[row] = ACC ? y[row] + s : s;
   }
@@ -291,6 +291,28 @@ __global__ __launch_bounds__(256) void k_axpby(double a, const double* x, double
 __global__ __launch_bounds__(256) void k_sub(const double* __restrict__ b, const double* __restrict__ t,
                                              double* __restrict__ r, int64_t n) {
   GRID_STRIDE(i, n) r[i] = b[i] - t[i];
+}
+// the same smoother steps with the residual and the search direction stored in FP32
+// (the iterate x stays FP64; every operation is done in FP64 and rounded once on store)
+__global__ __launch_bounds__(256) void k_sub_to32(const double* __restrict__ b, const double* __restrict__ t,
+                                                  float* __restrict__ r, int64_t n) {
+  GRID_STRIDE(i, n) r[i] = float(b[i] - t[i]);
+}
+__global__ __launch_bounds__(256) void k_cheb_init32(const float* __restrict__ r, const double* __restrict__ invd,
+                                                     float* __restrict__ d, double s, int64_t n) {
+  GRID_STRIDE(i, n) d[i] = float(s * invd[i] * double(r[i]));
+}
+__global__ __launch_bounds__(256) void k_cheb_step32(double* __restrict__ x, float* __restrict__ r,
+                                                     float* __restrict__ d, const float* __restrict__ t,
+                                                     const double* __restrict__ invd, double c1, double c2,
+                                                     int64_t n) {
+  GRID_STRIDE(i, n) {
+    const double di = double(d[i]);
+    x[i] += di;
+    const double ri = double(r[i]) - double(t[i]);
+    r[i] = float(ri);
+    d[i] = float(fma(c1, di, c2 * invd[i] * ri));
+  }
 }
 
 // deterministic start vector in [-1, 1): a multiplicative hash of the index
@@ -430,18 +452,19 @@ void vk_replace32(const double* b, const double* y, const float* invd, float* r,
   hipLaunchKernelGGL(dev::k_fin_replace, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, s);
 }
 
-template <int G>
-static void csr_launch(const int64_t* rowptr, const int32_t* col, const double* val, const double* x, double* y,
+template <int G, typename TX>
+static void csr_launch(const int64_t* rowptr, const int32_t* col, const double* val, const TX* x, double* y,
                        int64_t nrows, bool acc, hipStream_t st) {
   const int64_t g = std::min<int64_t>((nrows + 256 / G - 1) / (256 / G), 16384);
   if (acc)
-    hipLaunchKernelGGL((dev::k_csr<G, true>), dim3(unsigned(g)), dim3(256), 0, st, rowptr, col, val, x, y, nrows);
+    hipLaunchKernelGGL((dev::k_csr<G, true, TX>), dim3(unsigned(g)), dim3(256), 0, st, rowptr, col, val, x, y, nrows);
   else
-    hipLaunchKernelGGL((dev::k_csr<G, false>), dim3(unsigned(g)), dim3(256), 0, st, rowptr, col, val, x, y, nrows);
+    hipLaunchKernelGGL((dev::k_csr<G, false, TX>), dim3(unsigned(g)), dim3(256), 0, st, rowptr, col, val, x, y, nrows);
 }
 
-void vk_csr(const int64_t* rowptr, const int32_t* col, const double* val, const double* x, double* y, int64_t nrows,
-            int64_t nnz, bool accumulate, hipStream_t st) {
+template <typename TX>
+static void csr_any(const int64_t* rowptr, const int32_t* col, const double* val, const TX* x, double* y,
+                    int64_t nrows, int64_t nnz, bool accumulate, hipStream_t st) {
   if (nrows <= 0) return;
   const double mean = double(nnz) / double(nrows);
   if (mean <= 3.0)
@@ -453,6 +476,17 @@ void vk_csr(const int64_t* rowptr, const int32_t* col, const double* val, const 
   else
     csr_launch<16>(rowptr, col, val, x, y, nrows, accumulate, st);
 }
+
+void vk_csr_x32(const int64_t* rowptr, const int32_t* col, const double* val, const float* x, double* y,
+                int64_t nrows, int64_t nnz, hipStream_t st) {
+  csr_any(rowptr, col, val, x, y, nrows, nnz, false, st);
+}
+
+void vk_csr(const int64_t* rowptr, const int32_t* col, const double* val, const double* x, double* y, int64_t nrows,
+            int64_t nnz, bool accumulate, hipStream_t st) {
+  csr_any(rowptr, col, val, x, y, nrows, nnz, accumulate, st);
+}
+
 void vk_cheb_init(const double* r, const double* invd, double* d, double s, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(dev::k_cheb_init, dim3(red_grid(n) * 4), dim3(256), 0, st, r, invd, d, s, n);
 }
@@ -465,6 +499,16 @@ void vk_axpby(double a, const double* x, double b, double* y, int64_t n, hipStre
 }
 void vk_sub(const double* b, const double* t, double* r, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(dev::k_sub, dim3(red_grid(n) * 4), dim3(256), 0, st, b, t, r, n);
+}
+void vk_sub_to32(const double* b, const double* t, float* r, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_sub_to32, dim3(red_grid(n) * 4), dim3(256), 0, st, b, t, r, n);
+}
+void vk_cheb_init32(const float* r, const double* invd, float* d, double s, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_cheb_init32, dim3(red_grid(n) * 4), dim3(256), 0, st, r, invd, d, s, n);
+}
+void vk_cheb_step32(double* x, float* r, float* d, const float* t, const double* invd, double c1, double c2,
+                    int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(dev::k_cheb_step32, dim3(red_grid(n) * 4), dim3(256), 0, st, x, r, d, t, invd, c1, c2, n);
 }
 void vk_dense_solve(const double* M, const int32_t* idx, int64_t m, const double* b, double* x, hipStream_t st) {
   if (m <= 0) return;

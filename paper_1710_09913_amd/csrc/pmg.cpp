@@ -486,6 +486,7 @@ void build(Op& op, hipStream_t st) {
   P->q.alloc(vb);
   P->dots.alloc(size_t(RED_BLOCKS + 8) * sizeof(double));
   P->fcg.alloc(8 * sizeof(double));
+  if (op_has_v32(op)) P->e32.alloc(size_t(op.plan.ntiles + op_finish_energy_count(op)) * sizeof(double));
   Dots dd{P->dots.as<double>(), P->dots.as<double>() + RED_BLOCKS};
   for (auto& L : P->lv) L->lmax = power_lmax(*L->op, *L, dd, st);
   build_dense(*P->lv.back(), st);
@@ -539,6 +540,36 @@ void smooth(PmgLevel& L, double* x, const double* b, int prec, bool first, hipSt
   }
 }
 
+// smooth() for the FP32 mode on the finest level: r, d and A d are stored in FP32 (in the
+// first half of the level's FP64 work vectors) and A d comes from the FP32-vector apply,
+// which halves the vector traffic of the smoothing steps; x, b and the arithmetic of the
+// updates stay FP64
+void smooth32(PmgLevel& L, double* x, const double* b, bool first, double* energy, hipStream_t st) {
+  Op& A = *L.op;
+  const int64_t n = L.n;
+  float *r = L.r.as<float>(), *d = L.d.as<float>(), *t = L.t.as<float>();
+  const double* invd = A.invdiag.as<double>();
+  const double hi = 1.1 * L.lmax, lo = L.lmax / L.range;
+  const int degree = L.hlevel ? CHEB_DEGREE_H : CHEB_DEGREE;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  if (first) {
+    vk_fill(x, 0.0, n, st);
+    launch_to_f32(b, r, n, st);
+  } else {
+    // the FP64 t is read before the FP32 t (its first half) is written
+    op_apply(A, x, L.t.as<double>(), DOGIP_F32, st);
+    vk_sub_to32(b, L.t.as<double>(), r, n, st);
+  }
+  vk_cheb_init32(r, invd, d, 1.0 / theta, n, st);
+  double rho = 1.0 / sigma;
+  for (int i = 0; i < degree; ++i) {
+    op_apply_v32(A, d, t, st, energy);
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    vk_cheb_step32(x, r, d, t, invd, rn * rho, 2.0 * rn / delta, n, st);
+    rho = rn;
+  }
+}
+
 // x ~= A^-1 b at level j
 void vcycle(Pmg& P, size_t j, const double* b, double* x, int prec, hipStream_t st) {
   PmgLevel& L = *P.lv[j];
@@ -555,16 +586,27 @@ void vcycle(Pmg& P, size_t j, const double* b, double* x, int prec, hipStream_t 
     }
     return;
   }
-  smooth(L, x, b, prec, true, st);
+  const bool v32 = j == 0 && prec == DOGIP_F32 && P.e32.bytes > 0;
+  if (v32)
+    smooth32(L, x, b, true, P.e32.as<double>(), st);
+  else
+    smooth(L, x, b, prec, true, st);
   // restrict the residual the smoother leaves in r; zero the coarse Dirichlet rows
   PmgLevel& C = *P.lv[j + 1];
-  vk_csr(C.rrow.as<int64_t>(), C.rcol.as<int32_t>(), C.rval.as<double>(), L.r.as<double>(), C.b.as<double>(), C.n,
-         C.nnz, false, st);
+  if (v32)
+    vk_csr_x32(C.rrow.as<int64_t>(), C.rcol.as<int32_t>(), C.rval.as<double>(), L.r.as<float>(), C.b.as<double>(),
+               C.n, C.nnz, st);
+  else
+    vk_csr(C.rrow.as<int64_t>(), C.rcol.as<int32_t>(), C.rval.as<double>(), L.r.as<double>(), C.b.as<double>(), C.n,
+           C.nnz, false, st);
   launch_zero_indexed(C.b.as<double>(), C.op->bnd.as<int32_t>(), int64_t(C.op->space->boundary.size()), st);
   vcycle(P, j + 1, C.b.as<double>(), C.x.as<double>(), prec, st);
   // x += P x_c
   vk_csr(C.prow.as<int64_t>(), C.pcol.as<int32_t>(), C.pval.as<double>(), C.x.as<double>(), x, n, C.nnz, true, st);
-  smooth(L, x, b, prec, false, st);
+  if (v32)
+    smooth32(L, x, b, false, P.e32.as<double>(), st);
+  else
+    smooth(L, x, b, prec, false, st);
 }
 
 }  // namespace

@@ -36,6 +36,7 @@ struct Pmg {
   DevBuf r, z, zo, p, q;       // outer flexible CG vectors (fine)
   DevBuf dots;                 // device scalars of the inner products
   DevBuf fcg;                  // the outer CG's scalars (vk_fcg_alpha)
+  DevBuf e32;                  // tile partials the FP32-vector apply writes (unused)
   double coarse_tol = 0.1;     // relative residual of the coarsest level's inner solve
   bool stale = false;          // the fine D changed: the levels' D and lmax are redone
 };

@@ -64,11 +64,20 @@ void vk_fill(double* x, double v, int64_t n, hipStream_t st);
 // mean row length nnz / nrows; deterministic (fixed reduction order)
 void vk_csr(const int64_t* rowptr, const int32_t* col, const double* val, const double* x, double* y, int64_t nrows,
             int64_t nnz, bool accumulate, hipStream_t st);
+// y = A x for an FP32 x (FP64 products and sums)
+void vk_csr_x32(const int64_t* rowptr, const int32_t* col, const double* val, const float* x, double* y,
+                int64_t nrows, int64_t nnz, hipStream_t st);
 void vk_cheb_init(const double* r, const double* invd, double* d, double s, int64_t n, hipStream_t st);
 void vk_cheb_step(double* x, double* r, double* d, const double* t, const double* invd, double c1, double c2, int64_t n,
                   hipStream_t st);
 void vk_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t st);
 void vk_sub(const double* b, const double* t, double* r, int64_t n, hipStream_t st);
+// FP32-storage forms of the smoother steps: r = float(b - t); d = float(s D^-1 r);
+// x += d, r -= t, d = c1 d + c2 D^-1 r (FP64 arithmetic, FP32 r, d, t)
+void vk_sub_to32(const double* b, const double* t, float* r, int64_t n, hipStream_t st);
+void vk_cheb_init32(const float* r, const double* invd, float* d, double s, int64_t n, hipStream_t st);
+void vk_cheb_step32(double* x, float* r, float* d, const float* t, const double* invd, double c1, double c2,
+                    int64_t n, hipStream_t st);
 void vk_hash_fill(double* v, int64_t n, hipStream_t st);
 // flexible CG on device scalars s[8] (r.z, p.Ap, alpha, r.r, new r.z, old r.z, beta, flag):
 // alpha = r.z / p.Ap (flag 1 if p.Ap <= 0, 2 if not finite); beta = (new - old) / r.z,
