@@ -629,10 +629,12 @@ def main(argv=None):
         res["mixed"]["method"] = ("FP32 apply, r/p/q stored in FP32 (x and inner products FP64), FP64 residual "
                                   "replacement (reliable updates)")
         res["mixed_restart"]["method"] = "FP64 iterative refinement around restarted FP32-apply PCG (inner 1e-4)"
-        res["pmg"]["method"] = ("flexible CG, p-multigrid V-cycle preconditioner (orders k..1 on the same mesh, "
-                                "Chebyshev degree 3 smoothing on [lmax/8, 1.1 lmax], P1 level by Jacobi-PCG to 0.1); first call builds "
-                                "the hierarchy")
-        res["pmg_mixed"]["method"] = "the same with the V-cycle's applies in FP32"
+        res["pmg"]["method"] = ("flexible CG, multigrid V-cycle preconditioner: orders k..1 on the mesh "
+                                "(Chebyshev degree 3 on [lmax/8, 1.1 lmax]), then P1 on nested meshes halved down to "
+                                "at most 400 interior dofs (degree 4 on [lmax/20, 1.1 lmax]), the coarsest solved "
+                                "with its dense inverse; first call builds the hierarchy")
+        res["pmg_mixed"]["method"] = ("the same with the V-cycle's applies in FP32 and the finest smoother's "
+                                      "residual and direction stored in FP32")
         res["speedup_pmg_mixed_vs_f64"] = round(res["f64"]["seconds"] / res["pmg_mixed"]["seconds"], 3)
         out["pcg_time_to_1e-8"] = res
     if not a.no_cpu:
