@@ -292,6 +292,39 @@ __global__ __launch_bounds__(256) void k_sub(const double* __restrict__ b, const
                                              double* __restrict__ r, int64_t n) {
   GRID_STRIDE(i, n) r[i] = b[i] - t[i];
 }
+// k_csr for a matrix whose values are a few exact constants: each entry is one 32-bit word,
+// the column in the low 24 bits and the index of its value in a 256-entry table in the high
+// 8 (4 bytes per entry instead of 12).  The table sits in LDS.  Two entries per lane are
+// loaded before either is used; each lane still adds its entries in ascending order, so the
+// result is bit for bit that of k_csr on the unpacked matrix.
+template <int G, bool ACC, typename TX>
+__global__ __launch_bounds__(256) void k_csr_pk(const int64_t* __restrict__ rowptr, const uint32_t* __restrict__ ent,
+                                                const double* __restrict__ tab, const TX* __restrict__ x,
+                                                double* __restrict__ y, int64_t nrows) {
+  __shared__ double t[256];
+  t[threadIdx.x] = tab[threadIdx.x];
+  __syncthreads();
+  const int lane = int(threadIdx.x) % G;
+  const int64_t stride = int64_t(gridDim.x) * (256 / G);
+  for (int64_t row = (int64_t(blockIdx.x) * 256 + threadIdx.x) / G; row < nrows; row += stride) {
+    double s = 0.0;
+    const int64_t e = rowptr[row + 1];
+    int64_t j = rowptr[row] + lane;
+    for (; j + G < e; j += 2 * G) {
+      const uint32_t a = ent[j], b = ent[j + G];
+      const double xa = double(x[a & 0xFFFFFFu]), xb = double(x[b & 0xFFFFFFu]);
+      s = fma(t[a >> 24], xa, s);
+      s = fma(t[b >> 24], xb, s);
+    }
+    if (j < e) {
+      const uint32_t a = ent[j];
+      s = fma(t[a >> 24], double(x[a & 0xFFFFFFu]), s);
+    }
+    for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
+    if (lane == 0) y[row] = ACC ? y[row] + s : s;
+  }
+}
+
 // the same smoother steps with the residual and the search direction stored in FP32
 // (the iterate x stays FP64; every operation is done in FP64 and rounded once on store)
 __global__ __launch_bounds__(256) void k_sub_to32(const double* __restrict__ b, const double* __restrict__ t,
@@ -475,6 +508,42 @@ static void csr_any(const int64_t* rowptr, const int32_t* col, const double* val
     csr_launch<8>(rowptr, col, val, x, y, nrows, accumulate, st);
   else
     csr_launch<16>(rowptr, col, val, x, y, nrows, accumulate, st);
+}
+
+template <int G, typename TX>
+static void csr_pk_launch(const int64_t* rowptr, const uint32_t* ent, const double* tab, const TX* x, double* y,
+                          int64_t nrows, bool acc, hipStream_t st) {
+  const int64_t g = std::min<int64_t>((nrows + 256 / G - 1) / (256 / G), 16384);
+  if (acc)
+    hipLaunchKernelGGL((dev::k_csr_pk<G, true, TX>), dim3(unsigned(g)), dim3(256), 0, st, rowptr, ent, tab, x, y,
+                       nrows);
+  else
+    hipLaunchKernelGGL((dev::k_csr_pk<G, false, TX>), dim3(unsigned(g)), dim3(256), 0, st, rowptr, ent, tab, x, y,
+                       nrows);
+}
+
+template <typename TX>
+static void csr_pk_any(const int64_t* rowptr, const uint32_t* ent, const double* tab, const TX* x, double* y,
+                       int64_t nrows, int64_t nnz, bool accumulate, hipStream_t st) {
+  if (nrows <= 0) return;
+  const double mean = double(nnz) / double(nrows);
+  if (mean <= 3.0)
+    csr_pk_launch<2>(rowptr, ent, tab, x, y, nrows, accumulate, st);
+  else if (mean <= 6.0)
+    csr_pk_launch<4>(rowptr, ent, tab, x, y, nrows, accumulate, st);
+  else if (mean <= 24.0)
+    csr_pk_launch<8>(rowptr, ent, tab, x, y, nrows, accumulate, st);
+  else
+    csr_pk_launch<16>(rowptr, ent, tab, x, y, nrows, accumulate, st);
+}
+
+void vk_csr_pk(const int64_t* rowptr, const uint32_t* ent, const double* tab, const double* x, double* y,
+               int64_t nrows, int64_t nnz, bool accumulate, hipStream_t st) {
+  csr_pk_any(rowptr, ent, tab, x, y, nrows, nnz, accumulate, st);
+}
+void vk_csr_pk_x32(const int64_t* rowptr, const uint32_t* ent, const double* tab, const float* x, double* y,
+                   int64_t nrows, int64_t nnz, hipStream_t st) {
+  csr_pk_any(rowptr, ent, tab, x, y, nrows, nnz, false, st);
 }
 
 void vk_csr_x32(const int64_t* rowptr, const int32_t* col, const double* val, const float* x, double* y,

@@ -25,6 +25,9 @@
 
 #include <atomic>
 #include <climits>
+#include <algorithm>
+#include <cstring>
+#include <set>
 #include <cmath>
 #include <utility>
 
@@ -89,11 +92,49 @@ void set_transfer(PmgLevel& C, int64_t nfine, int64_t ncoarse, const std::vector
     if (!v.empty()) HIPCHK(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
   };
   up(C.prow, prow);
-  up(C.pcol, pcol);
-  up(C.pval, pval);
   up(C.rrow, rrow);
-  up(C.rcol, rcol);
-  up(C.rval, rval);
+  // value table, keyed by bit pattern so that packing changes no value; a value's index is
+  // its rank among the distinct bit patterns
+  auto bits = [](double v) {
+    uint64_t k;
+    std::memcpy(&k, &v, sizeof k);
+    return k;
+  };
+  // distinct values per chunk on host threads (a sorted list that stops past 256), merged
+  const int64_t nval = int64_t(pval.size()), nt = 16, chunk = (nval + nt - 1) / nt;
+  std::vector<std::vector<uint64_t>> part(nt);
+  parallel_tasks(nt, [&](int64_t t) {
+    auto& u = part[size_t(t)];
+    for (int64_t j = t * chunk; j < std::min(nval, (t + 1) * chunk) && u.size() <= 256; ++j) {
+      const uint64_t k = bits(pval[size_t(j)]);
+      const auto at = std::lower_bound(u.begin(), u.end(), k);
+      if (at == u.end() || *at != k) u.insert(at, k);
+    }
+  });
+  std::set<uint64_t> seen;
+  for (const auto& u : part) seen.insert(u.begin(), u.end());
+  C.packed = seen.size() <= 256 && nfine < (int64_t(1) << 24) && ncoarse < (int64_t(1) << 24);
+  if (C.packed) {
+    const std::vector<uint64_t> keys(seen.begin(), seen.end());
+    std::vector<double> tab(256, 0.0);
+    for (size_t c = 0; c < keys.size(); ++c) std::memcpy(&tab[c], &keys[c], sizeof(double));
+    auto pack = [&](const std::vector<int32_t>& col, const std::vector<double>& val) {
+      std::vector<uint32_t> e(col.size());
+      parallel_for(int64_t(col.size()), [&](int64_t j) {
+        const auto at = std::lower_bound(keys.begin(), keys.end(), bits(val[size_t(j)])) - keys.begin();
+        e[size_t(j)] = uint32_t(col[size_t(j)]) | (uint32_t(at) << 24);
+      });
+      return e;
+    };
+    up(C.ppk, pack(pcol, pval));
+    up(C.rpk, pack(rcol, rval));
+    up(C.ptab, tab);
+  } else {
+    up(C.pcol, pcol);
+    up(C.pval, pval);
+    up(C.rcol, rcol);
+    up(C.rval, rval);
+  }
   C.nfine = nfine;
   C.nnz = int64_t(pcol.size());
 }
@@ -593,7 +634,13 @@ void vcycle(Pmg& P, size_t j, const double* b, double* x, int prec, hipStream_t 
     smooth(L, x, b, prec, true, st);
   // restrict the residual the smoother leaves in r; zero the coarse Dirichlet rows
   PmgLevel& C = *P.lv[j + 1];
-  if (v32)
+  if (C.packed && v32)
+    vk_csr_pk_x32(C.rrow.as<int64_t>(), C.rpk.as<uint32_t>(), C.ptab.as<double>(), L.r.as<float>(), C.b.as<double>(),
+                  C.n, C.nnz, st);
+  else if (C.packed)
+    vk_csr_pk(C.rrow.as<int64_t>(), C.rpk.as<uint32_t>(), C.ptab.as<double>(), L.r.as<double>(), C.b.as<double>(),
+              C.n, C.nnz, false, st);
+  else if (v32)
     vk_csr_x32(C.rrow.as<int64_t>(), C.rcol.as<int32_t>(), C.rval.as<double>(), L.r.as<float>(), C.b.as<double>(),
                C.n, C.nnz, st);
   else
@@ -602,7 +649,11 @@ void vcycle(Pmg& P, size_t j, const double* b, double* x, int prec, hipStream_t 
   launch_zero_indexed(C.b.as<double>(), C.op->bnd.as<int32_t>(), int64_t(C.op->space->boundary.size()), st);
   vcycle(P, j + 1, C.b.as<double>(), C.x.as<double>(), prec, st);
   // x += P x_c
-  vk_csr(C.prow.as<int64_t>(), C.pcol.as<int32_t>(), C.pval.as<double>(), C.x.as<double>(), x, n, C.nnz, true, st);
+  if (C.packed)
+    vk_csr_pk(C.prow.as<int64_t>(), C.ppk.as<uint32_t>(), C.ptab.as<double>(), C.x.as<double>(), x, n, C.nnz, true,
+              st);
+  else
+    vk_csr(C.prow.as<int64_t>(), C.pcol.as<int32_t>(), C.pval.as<double>(), C.x.as<double>(), x, n, C.nnz, true, st);
   if (v32)
     smooth32(L, x, b, false, P.e32.as<double>(), st);
   else

@@ -16,6 +16,10 @@ struct PmgLevel {
   // prolongation to the next finer level (this level's vector -> the finer one), and
   // restriction (its transpose), both CSR with rows in ascending order
   DevBuf prow, pcol, pval, rrow, rcol, rval;
+  // packed form when the values are at most 256 distinct constants and both sizes are
+  // below 2^24 (then pcol/pval/rcol/rval stay empty): column | (value index << 24)
+  bool packed = false;
+  DevBuf ppk, rpk, ptab;
   int64_t n = 0, nfine = 0, nnz = 0;
   double lmax = 0.0;           // largest eigenvalue of D^-1 A (power iteration)
   double range = 0.0;          // the smoother damps [lmax / range, 1.1 lmax]

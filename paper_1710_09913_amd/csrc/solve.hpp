@@ -67,6 +67,12 @@ void vk_csr(const int64_t* rowptr, const int32_t* col, const double* val, const 
 // y = A x for an FP32 x (FP64 products and sums)
 void vk_csr_x32(const int64_t* rowptr, const int32_t* col, const double* val, const float* x, double* y,
                 int64_t nrows, int64_t nnz, hipStream_t st);
+// the same for a packed matrix: ent[j] = column | (value index << 24), tab[256] the values
+// (the column below 2^24); bit for bit equal to vk_csr on the unpacked matrix
+void vk_csr_pk(const int64_t* rowptr, const uint32_t* ent, const double* tab, const double* x, double* y,
+               int64_t nrows, int64_t nnz, bool accumulate, hipStream_t st);
+void vk_csr_pk_x32(const int64_t* rowptr, const uint32_t* ent, const double* tab, const float* x, double* y,
+                   int64_t nrows, int64_t nnz, hipStream_t st);
 void vk_cheb_init(const double* r, const double* invd, double* d, double s, int64_t n, hipStream_t st);
 void vk_cheb_step(double* x, double* r, double* d, const double* t, const double* invd, double c1, double c2, int64_t n,
                   hipStream_t st);
