@@ -283,6 +283,8 @@ struct DiagLaunch {
   int nlc, te, lds_slots;
   const uint32_t* gw_mask;  // global projection form (D one value per W dof), else null
   const int64_t* gw_woff;
+  double* stage;             // the apply's staging buffer: tile partials of shared dofs
+  const int64_t* stage_off;
 };
 void launch_diag(int dim, int k, int kind, const DiagLaunch& a, hipStream_t st);
 void launch_diag_global(int dim, int k, const DiagLaunch& a, hipStream_t st);

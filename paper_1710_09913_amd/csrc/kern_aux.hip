@@ -230,14 +230,14 @@ __global__ __launch_bounds__(512) void k_diag(DiagLaunch a) {
   for (int64_t j = threadIdx.x; j < nd; j += blockDim.x) ys[j] = 0.0;
   __syncthreads();
   const int64_t e = t * a.te + threadIdx.x;
+  int li[VT];
+  double ye[VT];
   if (e < a.nel) {
     const int lane = threadIdx.x & 63;
     const int64_t w = e >> 6;
-    int li[VT];
     load_lidx<VT>(a.lidx, w, a.nlc, lane, li);
     const double* dsc = a.D + (w * a.nch) * 128 + lane * 2;
     const double* bt = ctab<D, K, KIND, double>.v;
-    double ye[VT];
     sfor<VT>([&](auto L) { ye[L] = 0.0; });
     for (int i = 0; i < WT; ++i) {
       double dv[S];
@@ -255,19 +255,8 @@ __global__ __launch_bounds__(512) void k_diag(DiagLaunch a) {
         ye[L] += s;
       });
     }
-    sfor<VT>([&](auto L) { atomicAdd(&ys[li[L]], ye[L]); });
   }
-  __syncthreads();
-  for (int64_t j = threadIdx.x; j < nd; j += blockDim.x) {
-    const uint32_t td = a.tile_dofs[o0 + j];
-    const uint32_t dof = td & TD_MASK;
-    if (td & TD_BND)
-      a.out[dof] = 1.0;
-    else if (td & TD_SHARED)
-      unsafeAtomicAdd(&a.out[dof], ys[j]);
-    else
-      a.out[dof] = ys[j];
-  }
+  diag_flush<VT>(a, t, e, li, ye, ys, a.out);
 }
 
 // ---- Jacobi diagonal of the global projection form: diag_l = sum_j B_jl^2 D_j, each
@@ -283,15 +272,15 @@ __global__ __launch_bounds__(512) void k_diag_g(DiagLaunch a) {
   for (int64_t j = threadIdx.x; j < nd; j += blockDim.x) ys[j] = 0.0;
   __syncthreads();
   const int64_t e = t * a.te + threadIdx.x;
+  int li[VT];
+  double ye[VT];
   if (e < a.nel) {
     const int lane = threadIdx.x & 63;
-    int li[VT];
     load_lidx<VT>(a.lidx, e >> 6, a.nlc, lane, li);
     const uint32_t mask = a.gw_mask[e];
     const WaveSlots<D, K> ws(mask);
     const double* dw = a.D + a.gw_woff[e >> 6];
     const double* bt = ctab<D, K, KIND_WP, double>.v;
-    double ye[VT];
     sfor<VT>([&](auto L) { ye[L] = 0.0; });
     sfor<gw_slots(D)>([&](auto E) {
       constexpr int ne = ref::entity_nodes(D, 2 * K, E);
@@ -308,19 +297,8 @@ __global__ __launch_bounds__(512) void k_diag_g(DiagLaunch a) {
         }
       }
     });
-    sfor<VT>([&](auto L) { atomicAdd(&ys[li[L]], ye[L]); });
   }
-  __syncthreads();
-  for (int64_t j = threadIdx.x; j < nd; j += blockDim.x) {
-    const uint32_t td = a.tile_dofs[o0 + j];
-    const uint32_t dof = td & TD_MASK;
-    if (td & TD_BND)
-      a.out[dof] = 1.0;
-    else if (td & TD_SHARED)
-      unsafeAtomicAdd(&a.out[dof], ys[j]);
-    else
-      a.out[dof] = ys[j];
-  }
+  diag_flush<VT>(a, t, e, li, ye, ys, a.out);
 }
 
 // ---- adjoint contraction: g_T = -(B^ lam_T) . D_T (B^ u_T), boundary entries zero ----

@@ -368,5 +368,31 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
+// Last step of a Jacobi-diagonal tile: the cells' terms ye are added into the tile's LDS
+// slots one wave after the other; then the tile writes its own dofs, 1 on Dirichlet rows,
+// and its partial sums of shared dofs into the apply's staging buffer, which the finish
+// kernel adds in a fixed order.  The diagonal is the same bit for bit from run to run.
+template <int VT, typename L>
+__device__ __forceinline__ void diag_flush(const L& a, int64_t t, int64_t e, const int (&li)[VT],
+                                           const double (&ye)[VT], double* ys, double* __restrict__ out) {
+  const int nw = (a.te + 63) >> 6, me = int(threadIdx.x >> 6);
+  for (int wv = 0; wv < nw; ++wv) {
+    if (me == wv && e < a.nel) sfor<VT>([&](auto J) { atomicAdd(&ys[li[J]], ye[J]); });
+    __syncthreads();
+  }
+  const int64_t o0 = a.tile_off[t], nd = a.tile_off[t + 1] - o0;
+  double* stage = a.stage + a.stage_off[t];
+  for (int64_t j = threadIdx.x; j < nd; j += blockDim.x) {
+    const uint32_t td = a.tile_dofs[o0 + j];
+    const uint32_t dof = td & TD_MASK;
+    if (td & TD_BND)
+      out[dof] = 1.0;
+    else if (td & TD_SHARED)
+      stage[j] = ys[j];
+    else
+      out[dof] = ys[j];
+  }
+}
+
 }  // namespace dev
 }  // namespace dogip

@@ -101,10 +101,11 @@ __global__ __launch_bounds__(512) void k_diag_q(ApplyLaunch a, double* __restric
   for (int64_t j = threadIdx.x; j < nd; j += blockDim.x) ys[j] = 0.0;
   __syncthreads();
   const int64_t e = t * a.te + threadIdx.x;
+  int li[VT];
+  double ye[VT];
   if (e < a.nel) {
     const int lane = threadIdx.x & 63;
     const int64_t w = e >> 6;
-    int li[VT];
     load_lidx<VT>(a.lidx, w, a.nlc, lane, li);
     const double* qs = static_cast<const double*>(a.qs) + (w * a.nq) * 64 + lane;
     const double* G = static_cast<const double*>(a.qtab);
@@ -113,7 +114,6 @@ __global__ __launch_bounds__(512) void k_diag_q(ApplyLaunch a, double* __restric
       const double* qk = static_cast<const double*>(a.qk) + (w * S) * 64 + lane;
       sfor<S>([&](auto C) { kc[C] = qk[C * 64]; });
     }
-    double ye[VT];
     sfor<VT>([&](auto L) { ye[L] = 0.0; });
     for (int q = 0; q < a.nq; ++q) {
       const double sq = qs[q * 64];
@@ -130,19 +130,8 @@ __global__ __launch_bounds__(512) void k_diag_q(ApplyLaunch a, double* __restric
         ye[L] = fma(sq, s, ye[L]);
       });
     }
-    sfor<VT>([&](auto L) { atomicAdd(&ys[li[L]], ye[L]); });
   }
-  __syncthreads();
-  for (int64_t j = threadIdx.x; j < nd; j += blockDim.x) {
-    const uint32_t td = a.tile_dofs[o0 + j];
-    const uint32_t dof = td & TD_MASK;
-    if (td & TD_BND)
-      out[dof] = 1.0;
-    else if (td & TD_SHARED)
-      unsafeAtomicAdd(&out[dof], ys[j]);
-    else
-      out[dof] = ys[j];
-  }
+  diag_flush<VT>(a, t, e, li, ye, ys, out);
 }
 
 template <int D, int K, int KIND>

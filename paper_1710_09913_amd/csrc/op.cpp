@@ -444,10 +444,18 @@ void op_apply_v32(Op& op, const float* u, float* y, hipStream_t st, double* ener
 void op_diag(Op& op, double* diag, hipStream_t st) {
   const Space& s = *op.space;
   DOGIP_CHECK(diag != nullptr, DOGIP_E_NULL, "null output");
-  launch_zero_indexed(diag, op.shared.as<int32_t>(), int64_t(op.plan.shared.size()), st);
+  // the tiles' partial sums of shared dofs go through the staging buffer and are added
+  // by the finish kernel in a fixed order (no Dirichlet rows there: the tiles write those)
+  auto finish = [&] {
+    launch_apply_finish(op.stage.as<double>(), op.sh_rowptr.as<uint32_t>(), op.sh_slots.as<uint32_t>(),
+                        op.shared.as<int32_t>(), int64_t(op.plan.shared.size()), nullptr, 0, nullptr, diag, nullptr,
+                        st);
+    HIPCHK(hipGetLastError());
+  };
   if (op.nq > 0) {
     launch_diag_qp(s.dim, s.k, s.kind, apply_args(op, DOGIP_F64), diag, st);
     HIPCHK(hipGetLastError());
+    finish();
     return;
   }
   DiagLaunch a{};
@@ -462,6 +470,8 @@ void op_diag(Op& op, double* diag, hipStream_t st) {
   a.nlc = op.plan.nlc;
   a.te = op.plan.te;
   a.lds_slots = int(op.plan.max_tile_dofs);
+  a.stage = op.stage.as<double>();
+  a.stage_off = op.stage_off.as<int64_t>();
   if (op.global_w) {
     a.D = op.dg64.as<double>();
     a.gw_mask = op.gw_rec.as<uint32_t>();
@@ -471,6 +481,7 @@ void op_diag(Op& op, double* diag, hipStream_t st) {
     launch_diag(s.dim, s.k, s.kind, a, st);
   }
   HIPCHK(hipGetLastError());
+  finish();
 }
 
 void op_grad(Op& op, const double* u, const double* lam, double* g, hipStream_t st) {

@@ -155,15 +155,21 @@ def summarize(argv=None):
     fscale = copy_read / (sum(copies_f) / len(copies_f) * 1024)
     wscale = copy_read / (sum(copies_w) / len(copies_w) * 1024)
 
-    # apply dispatches in order: reps x (tile, finish) in FP64, then the same in FP32
+    # apply dispatches in order: reps x (tile, finish) in FP64, then the same in FP32; a
+    # finish with no tile kernel before it (the one after the Jacobi diagonal) is skipped
     def apply_pairs(disp):
         seq = [(n, v) for _, n, v in disp if "k_apply" in n]
         pairs = []
-        for i in range(0, len(seq) - 1, 2):
-            (n0, v0), (n1, v1) = seq[i], seq[i + 1]
-            if "k_apply_finish" in n0 or "k_apply_finish" not in n1:
+        i = 0
+        while i < len(seq):
+            n0, v0 = seq[i]
+            if "k_apply_finish" in n0:
+                i += 1
+                continue
+            if i + 1 >= len(seq) or "k_apply_finish" not in seq[i + 1][0]:
                 raise ValueError("unexpected dispatch order")
-            pairs.append(("float" in n0.split(",")[3] if n0.count(",") >= 3 else False, v0, v1))
+            pairs.append(("float" in n0.split(",")[3] if n0.count(",") >= 3 else False, v0, seq[i + 1][1]))
+            i += 2
         return pairs
 
     res = {}

@@ -105,6 +105,8 @@ def test_global_diagonal_and_pcg(d, n, k):
     diag = c.op.diag().cpu().numpy()
     do = (c.B.multiply(c.B)).T @ c.Dg
     assert rel_err(diag, do[c.perm]) <= 1e-12
+    for _ in range(3):
+        np.testing.assert_array_equal(c.op.diag().cpu().numpy(), diag)
     xs = random_vector(c.space.ndofs, seed=6)
     b = c.oracle(xs)
     x, st = c.op.pcg(_gpu(b), tol=1e-10, mode="f64")

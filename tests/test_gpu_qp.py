@@ -104,6 +104,8 @@ def test_qp_f32_diag_and_pcg(d, n, k, kind):
     if c.dirichlet:
         do[c.osp.boundary] = 1.0
     assert rel_err(diag, do[c.perm]) <= 1e-12
+    for _ in range(3):
+        np.testing.assert_array_equal(c.op.diag().cpu().numpy(), diag)
     xs = random_vector(c.space.ndofs, seed=9)
     if c.dirichlet:
         xs[c.space.boundary()] = 0.0
