@@ -300,7 +300,8 @@ int dogip_op_export_d(dogip_op op, double* d_out, dogip_stream stream);
  * The operator owns a staging buffer used by every apply, diag, solve and
  * gradient call: calls on one operator must be ordered (one stream). */
 int dogip_apply(dogip_op op, const double* u, double* y, int prec, dogip_stream stream);
-/* diag <- diagonal of A (1 on Dirichlet rows).  device [ndofs].  async. */
+/* diag <- diagonal of A (1 on Dirichlet rows).  device [ndofs].  async.  Bitwise
+ * reproducible like dogip_apply (fixed summation order; uses the staging buffer). */
 int dogip_diag(dogip_op op, double* diag, dogip_stream stream);
 /* Solve A x = b.  b, x: device [ndofs].  Returns DOGIP_OK, DOGIP_E_NOT_CONVERGED,
  * DOGIP_E_BREAKDOWN or DOGIP_E_NONFINITE; stats (may be NULL) are filled in all
