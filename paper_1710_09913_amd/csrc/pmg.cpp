@@ -21,14 +21,18 @@
 // integrated again on each mesh), and the prolongation is P_1 interpolation (a midpoint
 // takes the mean of the edge's ends).  A coarsest level that small is solved exactly by
 // its dense inverse.
+//
+// The transfer weights are a few constants, so a transfer entry is stored as its column
+// and the index of its weight in a small table.  In the FP32 mode the finest level's
+// smoother keeps its residual and direction in FP32 vectors.
 #include "pmg.hpp"
 
+#include <algorithm>
 #include <atomic>
 #include <climits>
-#include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <set>
-#include <cmath>
 #include <utility>
 
 #include "solve.hpp"
