@@ -115,14 +115,18 @@ def cpu_baseline(k, n_sample=20):
     osp = fem.make_space(coords, cells, k)
     D = odg.build_d(osp, coef, "se")
     u = random_vector(osp.ndofs, 0)
-    odg.apply_dirichlet(osp, D, u, "se")  # warm-up
-    reps, t0 = 0, time.time()
-    while reps < 3 or time.time() - t0 < 10.0:
-        odg.apply_dirichlet(osp, D, u, "se")
-        reps += 1
-        if time.time() - t0 > 30.0:
-            break
-    dt = (time.time() - t0) / reps
+    from threadpoolctl import threadpool_limits
+
+    # one core: any BLAS call inside the oracle is held to one thread
+    with threadpool_limits(limits=1):
+        odg.apply_dirichlet(osp, D, u, "se")  # warm-up
+        reps, t0 = 0, time.time()
+        while reps < 3 or time.time() - t0 < 10.0:
+            odg.apply_dirichlet(osp, D, u, "se")
+            reps += 1
+            if time.time() - t0 > 30.0:
+                break
+        dt = (time.time() - t0) / reps
     return {
         "value": round(osp.ndofs / dt / 1e9, 6),
         "unit": "GDoF/s",
