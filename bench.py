@@ -626,6 +626,11 @@ def main(argv=None):
             dt = time.time() - t0
             res[mode] = {"seconds": round(dt, 4), "iters": st["iters"], "outer": st["outer"],
                          "relres_true": st["relres_true"]}
+            # each solution against the FP64 Jacobi-PCG one (both to 1e-8, so they differ by
+            # up to about cond(A) * 1e-8 in norm)
+            if mode == "f64":
+                x64 = x.clone()
+            res[mode]["rel_diff_vs_f64"] = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
             if mode.startswith("pmg"):
                 res[mode]["first_call_seconds"] = round(first, 4)
             log(f"[pcg {mode}] {dt:.3f}s (first call {first:.3f}s) {st}")
