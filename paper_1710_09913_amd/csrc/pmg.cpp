@@ -17,8 +17,8 @@
 // the midpoint of a coarse edge.  There the hierarchy continues below P_1 with P_1 on the
 // meshes n/2, n/4, ... for the elliptic problem (degree-4 smoothing on [lmax/20, 1.1 lmax])
 // until the coarsest has at most 400 interior dofs: the coefficient of a coarse cell is
-// the mean over its children (of the logarithm for a log-coefficient; inclusions are
-// integrated again on each mesh), and the prolongation is P_1 interpolation (a midpoint
+// the mean over its children (of the logarithm for a log-coefficient; for inclusions the
+// geometric mean of a at points of the cell), and the prolongation is P_1 interpolation (a midpoint
 // takes the mean of the edge's ends).  A coarsest level that small is solved exactly by
 // its dense inverse.
 //
@@ -28,6 +28,7 @@
 #include "pmg.hpp"
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <climits>
 #include <cmath>
@@ -328,6 +329,47 @@ std::vector<double> host_coef(const Op& op, hipStream_t st) {
   return cf;
 }
 
+// Coefficient of a geometric level's cells for inclusions: the geometric mean of a over
+// the order-6 barycentric lattice of each cell (28 points in 2D, 84 in 3D).  Integrating
+// the inclusions again (the arithmetic mean) makes a coarse cell that a ball only partly
+// covers too stiff; on 3D 64^3 P3 with a = 100 in 64 balls the geometric mean takes 29
+// outer iterations against 35, the harmonic mean 43.
+std::vector<double> inclusion_mean(const Op& op, const Mesh& m) {
+  constexpr int M = 6;
+  const int d = m.dim;
+  std::vector<std::array<double, 4>> bary;
+  for (int i = 0; i <= M; ++i)
+    for (int j = 0; i + j <= M; ++j) {
+      if (d == 2)
+        bary.push_back({double(i) / M, double(j) / M, double(M - i - j) / M, 0.0});
+      else
+        for (int k = 0; i + j + k <= M; ++k)
+          bary.push_back({double(i) / M, double(j) / M, double(k) / M, double(M - i - j - k) / M});
+    }
+  const size_t nb = op.inc_balls.size() / size_t(d + 1);
+  const double lin = std::log(op.inc_in), lout = std::log(op.inc_out);
+  std::vector<double> out(size_t(m.nc));
+  parallel_for(m.nc, [&](int64_t c) {
+    const int32_t* cv = m.cells.data() + size_t(c) * size_t(d + 1);
+    double acc = 0.0;
+    for (const auto& b : bary) {
+      double x[3] = {0.0, 0.0, 0.0};
+      for (int v = 0; v <= d; ++v)
+        for (int r = 0; r < d; ++r) x[r] += b[size_t(v)] * m.xyz[size_t(cv[v]) * size_t(d) + size_t(r)];
+      bool in = false;
+      for (size_t q = 0; q < nb && !in; ++q) {
+        const double* ball = op.inc_balls.data() + q * size_t(d + 1);
+        double r2 = 0.0;
+        for (int r = 0; r < d; ++r) r2 += (x[r] - ball[r]) * (x[r] - ball[r]);
+        in = r2 < ball[d] * ball[d];
+      }
+      acc += in ? lin : lout;
+    }
+    out[size_t(c)] = std::exp(acc / double(bary.size()));
+  });
+  return out;
+}
+
 // D of the geometric levels (P.lv[first..]) from the fine coefficient, restricted level by
 // level, or from the inclusions
 void h_levels_d(const Op& op, Pmg& P, size_t first, hipStream_t st) {
@@ -337,7 +379,11 @@ void h_levels_d(const Op& op, Pmg& P, size_t first, hipStream_t st) {
   for (size_t j = first; j < P.lv.size(); ++j) {
     PmgLevel& L = *P.lv[j];
     if (op.inc_depth >= 0) {
-      level_d(op, *L.op, st);
+      const std::vector<double> cm = inclusion_mean(op, *L.space->mesh);
+      DevBuf dc;
+      upload(dc, cm);
+      op_set_coef(*L.op, DOGIP_COEF_SCALAR, dc.as<double>(), st);
+      HIPCHK(hipStreamSynchronize(st));
     } else {
       cf = restrict_coef(cf, L.parent, coef_per_cell(op), L.space->nc);
       DevBuf dc;
