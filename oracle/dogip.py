@@ -16,6 +16,10 @@
 
 D layouts returned: [nel, W_T] (weighted projection) and [nel, W_T, d, d] (elliptic).
 Pinned by the identity B^^T D B^ = A against ``fem`` (tests/test_oracle_dogip.py).
+``apply_abs`` (the rounding scale of the parity checks) is pinned in
+tests/test_oracle_apply_abs.py: it equals the assembled operator where nothing is
+negative, lies between sum_T |A_T||u_T| and |A u| by the triangle inequality, is the
+absolute textbook P1 stiffness on the reference simplex, and keeps Dirichlet rows.
 """
 
 from __future__ import annotations
