@@ -102,19 +102,24 @@ extern "C" {
  * same mesh, each a DoGIP operator rebuilt from the operator's coefficient; the
  * prolongation embeds P_{j-1} in P_j (nodal values), the restriction is its transpose;
  * Chebyshev smoothing in D^-1 A (degree 3 on [lmax/8, 1.1 lmax], lmax by power
- * iteration) before and after the coarse correction.  For the elliptic problem on a
- * mesh from dogip_mesh_unit with n even, the hierarchy continues below P_1 with P_1 on
- * the nested unit meshes n/2, n/4, ... (coefficient averaged over the 2^d children, P_1
- * interpolation between them) until the coarsest has at most 400 interior dofs.  A
+ * iteration) before and after the coarse correction.  Each order level's D is rebuilt
+ * from the operator's coefficient, or by the same sub-cell quadrature for inclusions.
+ * For the elliptic problem on a mesh from dogip_mesh_unit with n even, the hierarchy
+ * continues below P_1 with P_1 on the nested unit meshes n/2, n/4, ... until the
+ * coarsest has at most 400 interior dofs: a coarse cell's coefficient is the mean over
+ * its 2^d children (of the logarithm for LOGSCALAR), or for inclusions the geometric
+ * mean of the inclusion coefficient over a lattice of points of the coarse cell; P_1
+ * interpolation between the meshes; Chebyshev degree 4 on [lmax/20, 1.1 lmax] there.  A
  * coarsest level with at most 1000 interior dofs is solved exactly (its dense inverse,
  * formed at set-up); a larger one by Jacobi-PCG to a relative residual of 0.1 (or
- * inner_tol, when in (0, 1)).  The hierarchy is built at the first such solve; after a
- * coefficient change the next one rebuilds only the levels' D, diagonals, lmax and the
- * coarse inverse.
+ * inner_tol, when in (0, 1)).  That inner solve varies the preconditioner, so the outer
+ * CG is the flexible one: beta = -(z_{k+1} . A p_k) / (p_k . A p_k).  The hierarchy is
+ * built at the first such solve; after a coefficient change the next one rebuilds only
+ * the levels' D, diagonals, lmax and the coarse inverse.
  * Needs an element-wise operator whose D came from a SCALAR, SYM or LOGSCALAR
- * coefficient or from dogip_op_set_inclusions (each level's D is rebuilt the same way),
- * else DOGIP_E_STATE.  iters counts outer iterations; convergence is verified on
- * the true FP64 residual. */
+ * coefficient or from dogip_op_set_inclusions, else DOGIP_E_STATE.  iters counts outer
+ * iterations; convergence is verified on the true FP64 residual; DOGIP_E_BREAKDOWN if
+ * p.Ap or r.z (the preconditioned residual) is not positive. */
 #define DOGIP_SOLVE_PMG 3
 /* The same with the V-cycle's applies (smoothing, coarse solve) in FP32; the outer CG
  * and its residuals stay FP64.  Needs DOGIP_OP_FP32. */
@@ -260,7 +265,9 @@ int dogip_op_create(dogip_space s, int coef_kind, const double* coef, unsigned f
  * ones.  mean_points (optional host output): quadrature points evaluated per cell,
  * averaged.  The apply's cost does not change.  Synchronizes the stream.
  * DOGIP_E_STATE for a DOGIP_OP_GLOBAL_W or quadrature-point operator;
- * DOGIP_E_RANGE for double-grid orders above 8 (2D) or 6 (3D). */
+ * DOGIP_E_RANGE for double-grid orders above 8 (2D) or 6 (3D); DOGIP_E_INVALID unless
+ * a_in and a_out are finite and positive (the elliptic form needs a positive
+ * coefficient). */
 int dogip_op_set_inclusions(dogip_op op, int nballs, const double* balls, double a_in, double a_out, int depth,
                             int ng, double* mean_points, dogip_stream stream);
 

@@ -239,9 +239,16 @@ __global__ void k_fcg_alpha(double* s) {
   s[2] = ok ? rz / pq : 0.0;
   if (!ok) s[7] = finite ? 1.0 : 2.0;
 }
+// flexible CG: beta = -(z_{k+1} . A p_k) / (p_k . A p_k) (s5, s1; s1 > 0 was checked by
+// k_fcg_alpha), and r.z of the new iterate (s4) becomes the next numerator of alpha; a
+// non-finite s4 or s5, or r.z <= 0 (the preconditioner is not positive there), is flagged
 __global__ void k_fcg_beta(double* s) {
-  s[6] = (s[4] - s[5]) / s[0];
-  s[0] = s[4];
+  const double rz = s[4], zq = s[5];
+  const bool finite = isfinite(rz) && isfinite(zq);
+  const bool ok = finite && rz > 0.0;
+  s[6] = ok ? -zq / s[1] : 0.0;
+  s[0] = rz;
+  if (!ok) s[7] = finite ? 1.0 : 2.0;
 }
 // y += sign s[k] x (the fma of y = a x + y)
 __global__ __launch_bounds__(256) void k_axpy_s(double* y, const double* __restrict__ x, const double* __restrict__ s,

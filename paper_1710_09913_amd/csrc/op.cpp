@@ -307,6 +307,9 @@ void op_set_inclusions(Op& op, int nballs, const double* balls, double a_in, dou
   DOGIP_CHECK(depth >= 0 && depth <= 6, DOGIP_E_RANGE, "depth must be 0..6");
   DOGIP_CHECK(ng >= 1 && ng <= 8, DOGIP_E_RANGE, "points per direction must be 1..8");
   DOGIP_CHECK(std::isfinite(a_in) && std::isfinite(a_out), DOGIP_E_INVALID, "non-finite coefficient");
+  // the elliptic form needs a positive coefficient (and the multigrid's coarse levels
+  // take its logarithm)
+  DOGIP_CHECK(a_in > 0.0 && a_out > 0.0, DOGIP_E_INVALID, "inclusion coefficients must be positive");
   for (int j = 0; j < nballs; ++j) {
     DOGIP_CHECK(balls[j * (s.dim + 1) + s.dim] > 0.0, DOGIP_E_INVALID, "ball radius must be positive");
     for (int x = 0; x <= s.dim; ++x)

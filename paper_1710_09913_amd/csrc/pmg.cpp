@@ -10,7 +10,10 @@
 // [lmax/8, 1.1 lmax], lmax by power iteration) before and after the coarse correction,
 // and solves a large coarsest level by Jacobi-PCG to a relative residual of 0.1.  That
 // inner solve makes the preconditioner vary between applications, hence the flexible
-// (Polak-Ribiere) CG outside.
+// CG outside: each new direction is made A-orthogonal to the previous one,
+// beta = -(z_{k+1} . A p_k) / (p_k . A p_k), which stays right when the preconditioner
+// changes from one application to the next (r_{k+1} . z_k, the form that assumes a fixed
+// symmetric preconditioner, does not).
 //
 // On a unit-cube mesh of Kuhn simplices (n^d cubes) the halved mesh is nested in it: each
 // coarse simplex is the union of 2^d fine ones, and every fine vertex is a coarse vertex or
@@ -572,7 +575,6 @@ void build(Op& op, hipStream_t st) {
   const size_t vb = std::max<int64_t>(s0.ndofs, 1) * sizeof(double);
   P->r.alloc(vb);
   P->z.alloc(vb);
-  P->zo.alloc(vb);
   P->p.alloc(vb);
   P->q.alloc(vb);
   P->dots.alloc(size_t(RED_BLOCKS + 8) * sizeof(double));
@@ -724,7 +726,6 @@ int op_pcg_pmg(Op& op, const double* b, double* x, const dogip_solve_opts& o, do
   Dots dd{P.dots.as<double>(), P.dots.as<double>() + RED_BLOCKS};
   double *r = P.r.as<double>(), *p = P.p.as<double>(), *q = P.q.as<double>();
   double* z = P.z.as<double>();
-  double* zo = P.zo.as<double>();
   const double bb = dot(dd, b, b, n, st);
   if (!std::isfinite(bb)) return DOGIP_E_NONFINITE;
   if (bb == 0.0) {
@@ -788,10 +789,9 @@ int op_pcg_pmg(Op& op, const double* b, double* x, const dogip_solve_opts& o, do
       vk_dot(r, z, n, dd.part, S + 0, st);
       continue;
     }
-    std::swap(z, zo);
     vcycle(P, 0, r, z, prec, st);
     vk_dot(r, z, n, dd.part, S + 4, st);
-    vk_dot(r, zo, n, dd.part, S + 5, st);
+    vk_dot(z, q, n, dd.part, S + 5, st);  // q still holds A p_k
     vk_fcg_beta(S, st);
     vk_xpby_s(p, z, S, 6, n, st);
   }

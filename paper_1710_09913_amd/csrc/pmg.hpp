@@ -37,7 +37,7 @@ struct PmgLevel {
 
 struct Pmg {
   std::vector<std::unique_ptr<PmgLevel>> lv;  // lv[0] finest
-  DevBuf r, z, zo, p, q;       // outer flexible CG vectors (fine)
+  DevBuf r, z, p, q;           // outer flexible CG vectors (fine)
   DevBuf dots;                 // device scalars of the inner products
   DevBuf fcg;                  // the outer CG's scalars (vk_fcg_alpha)
   DevBuf e32;                  // tile partials the FP32-vector apply writes (unused)

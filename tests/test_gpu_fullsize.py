@@ -8,8 +8,9 @@ The full operator is too large for the oracle, so each case checks
     |B^|^T|D||B^||u| and FP32 within 2 gamma_m of it;
   * properties that hold at any size: symmetry v.(A u) = u.(A v), identity rows
     on the Dirichlet dofs (bit-exact), bitwise-reproducible repeated applies;
-  * the multigrid-preconditioned solve to 1e-8: the oracle's rows of b - A x at
-    sampled dofs stay within the solve's residual norm.
+  * the multigrid-preconditioned solve and the mixed-precision Jacobi-PCG solve (FP32
+    apply, FP64 residual replacement) to 1e-8: the oracle's rows of b - A x at sampled
+    dofs stay within the solve's residual norm.
 """
 
 import numpy as np
@@ -26,8 +27,9 @@ torch = pytest.importorskip("torch")
 
 # (id, dim, n, k, kind, global form): the 3D headline operator, the largest 2D sweep
 # operators and the global projection form (Theorem 1 gives the same rows as Theorem 2)
-FULL = [("3d64_p3_se", 3, 64, 3, "se", False), ("2d512_p5_se", 2, 512, 5, "se", False),
-        ("2d512_p5_wp", 2, 512, 5, "wp", False), ("2d512_p2_wp_global", 2, 512, 2, "wp", True)]
+FULL = [("3d64_p3_se", 3, 64, 3, "se", False), ("3d64_p2_se", 3, 64, 2, "se", False),
+        ("2d512_p5_se", 2, 512, 5, "se", False), ("2d512_p5_wp", 2, 512, 5, "wp", False),
+        ("2d512_p2_wp_global", 2, 512, 2, "wp", True)]
 NSAMPLE = 160
 
 
@@ -163,5 +165,23 @@ def test_fullsize_multigrid_solve_sampled_residual(full):
     print(f"[full] multigrid: {st['iters']} iterations, relres {st['relres_true']:.2e}", flush=True)
     assert st["status"] == 0 and st["relres_true"] <= 1.05e-8
     s = _samples(c, seed=5)
+    yo, ab = c.sampled_rows(s, x.cpu().numpy())
+    assert np.all(np.abs(b[s] - yo) <= 1.05e-8 * np.linalg.norm(b) + 1e-11 * ab)
+
+
+def test_fullsize_mixed_jacobi_solve_sampled_residual(full):
+    """The mixed Jacobi-PCG (FP32 apply; r, p and A p stored in FP32; FP64 x, inner
+    products and residual replacement) to 1e-8 at the benchmark size: the oracle's rows
+    of b - A x at sampled dofs are within the solve's residual norm, so the reduced
+    precision did not move the solution off the FP64 system."""
+    c = full
+    b = random_vector(c.space.ndofs, 23)
+    if c.dirichlet:
+        b[c.bnd] = 0.0
+    x, st = c.op.pcg(torch.from_numpy(b).cuda(), tol=1e-8, maxit=100000, mode="mixed")
+    print(f"[full] mixed Jacobi-PCG: {st['iters']} iterations, {st['outer']} outer, "
+          f"relres {st['relres_true']:.2e}", flush=True)
+    assert st["status"] == 0 and st["relres_true"] <= 1.05e-8
+    s = _samples(c, seed=6)
     yo, ab = c.sampled_rows(s, x.cpu().numpy())
     assert np.all(np.abs(b[s] - yo) <= 1.05e-8 * np.linalg.norm(b) + 1e-11 * ab)

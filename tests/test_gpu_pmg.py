@@ -295,11 +295,12 @@ def _oracle_residual_ok(osp, D, xo, b, kind, tol):
 
 
 @pytest.mark.parametrize("d,n,k,kind,incl", [(2, 64, 2, "wp", False), (2, 64, 2, "se", True), (2, 64, 3, "wp", True),
-                                             (3, 32, 2, "se", False)])
+                                             (3, 32, 2, "se", False), (3, 16, 2, "se", True)])
 def test_pmg_geometric_levels_solve_oracle_system(d, n, k, kind, incl):
-    """Geometric levels with inclusions (D of every level by sub-cell quadrature on its
-    mesh) and in 3D, and the projection form (which keeps to the order levels on unit
-    meshes too): x solves the oracle's system."""
+    """Geometric levels with inclusions (the order levels' D by the same sub-cell
+    quadrature, the geometric levels' coefficient the geometric mean over a lattice of
+    each coarse cell), in 2D and 3D, and the projection form (which keeps to the order
+    levels on unit meshes too): x solves the oracle's system."""
     from paper_1710_09913_amd import Mesh, Operator, Space
 
     print(f"[pmg h] unit {n}^{d} P{k} {kind} inclusions={incl}", flush=True)
@@ -365,3 +366,21 @@ def test_concurrent_solves_on_separate_streams():
     for (x, st), xr in zip(out, ref):
         assert st["status"] == 0
         assert torch.equal(x, xr)
+
+
+@pytest.mark.parametrize("kind,n", [("se", 40), ("wp", 48)])
+def test_pmg_flexible_cg_with_inner_coarse_solve(kind, n):
+    """A jittered mesh (no geometric levels) whose P_1 level has more than 1000 interior
+    dofs: the coarsest level is solved by Jacobi-PCG to 0.1, which varies the
+    preconditioner from one application to the next.  The flexible CG still solves the
+    oracle's system, in few outer iterations."""
+    print(f"[pmg fcg] jittered {n}^2 P3 {kind}", flush=True)
+    sp, op, osp, perm, A, b, bnd = _problem(2, n, 3, kind, "scalar", 0.1, seed=11)
+    assert (n + 1) ** 2 > 1000
+    x_lu = solve.direct_dirichlet(A, b, bnd)
+    for mode in ("pmg", "pmg_mixed"):
+        x, st = op.pcg(_gpu(b[perm]), tol=1e-10, maxit=500, mode=mode)
+        assert st["status"] == 0 and st["relres_true"] <= 1.05e-10, st
+        print(f"[pmg fcg] {mode}: {st['iters']} outer iterations", flush=True)
+        assert rel_err(x.cpu().numpy(), x_lu[perm]) <= 1e-6
+        assert st["iters"] <= (12 if kind == "wp" else 30), st["iters"]

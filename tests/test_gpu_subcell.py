@@ -91,6 +91,13 @@ def test_subcell_errors():
         op.set_inclusions(np.array([[0.5, 0.5, -0.1]]), 2.0, 1.0)
     with pytest.raises(ValueError):
         op.set_inclusions(np.array([[0.5, 0.5]]), 2.0, 1.0)
+    # the coefficient must be positive on both sides (the coarse levels take its logarithm)
+    from paper_1710_09913_amd.capi import DOGIP_E_INVALID
+
+    for a_in, a_out in ((0.0, 1.0), (2.0, -1.0), (float("nan"), 1.0)):
+        with pytest.raises(DogipError) as e:
+            op.set_inclusions(good, a_in, a_out)
+        assert e.value.code == DOGIP_E_INVALID
     wp = Space(Mesh.unit(2, 3), 1, "wp", "none")
     g = Operator(wp, torch.ones(wp.ncells, dtype=torch.float64), "scalar", global_w=True)
     with pytest.raises(DogipError):

@@ -13,7 +13,9 @@ keeps every simplex valid: the smallest altitude of these simplices is h/sqrt(2)
 
 from __future__ import annotations
 
+import concurrent.futures
 import itertools
+import os
 
 import numpy as np
 
@@ -166,9 +168,21 @@ def gaussian_field_rff(points: np.ndarray, seed: int, ell: float = 0.1, std: flo
     b = rng.uniform(0.0, 2.0 * np.pi, size=n_features)
     out = np.empty(points.shape[0])
     scale = std * np.sqrt(2.0 / n_features)
-    for s in range(0, points.shape[0], chunk):
+
+    def one(s):
         p = points[s:s + chunk]
         out[s:s + chunk] = scale * np.cos(p @ w.T + b).sum(axis=1)
+
+    # chunks on host threads (numpy releases the GIL): every chunk is computed the same
+    # way as on one thread, so the field is the same bit for bit
+    starts = range(0, points.shape[0], chunk)
+    workers = min(16, os.cpu_count() or 1, len(starts))
+    if workers <= 1:
+        for s in starts:
+            one(s)
+    else:
+        with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+            list(ex.map(one, starts))
     return out
 
 
