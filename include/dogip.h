@@ -124,6 +124,11 @@ extern "C" {
 /* The same with the V-cycle's applies (smoothing, coarse solve) in FP32; the outer CG
  * and its residuals stay FP64.  Needs DOGIP_OP_FP32. */
 #define DOGIP_SOLVE_PMG_MIXED 4
+/* As DOGIP_SOLVE_MIXED (FP32 apply, FP64 residual replacement) with the residual,
+ * direction and A p stored in FP64: only the apply (D, element arithmetic) is FP32;
+ * x, r, every inner product and D's construction stay FP64.  Element-wise, global and
+ * quadrature-point operators alike.  Needs DOGIP_OP_FP32. */
+#define DOGIP_SOLVE_MIXED_V64 5
 
 /* ---- dogip_op_create flags ---- */
 #define DOGIP_OP_FP32 1u /* also build the FP32 copy of D (needed by DOGIP_F32 and MIXED) */

@@ -39,6 +39,7 @@ DOGIP_SOLVE_MIXED = 1
 DOGIP_SOLVE_MIXED_RESTART = 2
 DOGIP_SOLVE_PMG = 3
 DOGIP_SOLVE_PMG_MIXED = 4
+DOGIP_SOLVE_MIXED_V64 = 5
 DOGIP_OP_FP32 = 1
 DOGIP_OP_GLOBAL_W = 2
 DOGIP_VARIANT_AUTO = 0

@@ -247,7 +247,7 @@ int op_pcg(Op& op, const double* b, double* x, const dogip_solve_opts& o, dogip_
   DOGIP_CHECK(b && x, DOGIP_E_NULL, "null vector");
   DOGIP_CHECK(b != x, DOGIP_E_INVALID, "b and x must differ");
   DOGIP_CHECK(o.tol > 0.0 && o.maxit >= 1, DOGIP_E_RANGE, "tol must be > 0 and maxit >= 1");
-  DOGIP_CHECK(o.mode >= DOGIP_SOLVE_F64 && o.mode <= DOGIP_SOLVE_PMG_MIXED, DOGIP_E_RANGE, "unknown solve mode");
+  DOGIP_CHECK(o.mode >= DOGIP_SOLVE_F64 && o.mode <= DOGIP_SOLVE_MIXED_V64, DOGIP_E_RANGE, "unknown solve mode");
   DOGIP_CHECK(o.mode == DOGIP_SOLVE_F64 || o.mode == DOGIP_SOLVE_PMG || op.has32, DOGIP_E_STATE,
               "mixed mode needs DOGIP_OP_FP32");
   const auto t0 = std::chrono::steady_clock::now();
@@ -263,12 +263,13 @@ int op_pcg(Op& op, const double* b, double* x, const dogip_solve_opts& o, dogip_
     // flexible CG preconditioned by p-multigrid V-cycles (FP64 outside; the V-cycle's
     // applies in FP32 for PMG_MIXED)
     status = op_pcg_pmg(op, b, x, o, stats, o.mode == DOGIP_SOLVE_PMG ? DOGIP_F64 : DOGIP_F32, st);
-  } else if (o.mode == DOGIP_SOLVE_F64 || o.mode == DOGIP_SOLVE_MIXED) {
+  } else if (o.mode == DOGIP_SOLVE_F64 || o.mode == DOGIP_SOLVE_MIXED || o.mode == DOGIP_SOLVE_MIXED_V64) {
     // FP64: plain Jacobi-PCG.  MIXED: the same iteration with the FP32 apply, the
     // vectors r, p, q in FP32 (x and the inner products FP64), and FP64 residual
-    // replacement (reliable updates).  In both modes apparent convergence is verified
-    // on the true FP64 residual (a replacement); MIXED also replaces whenever the
-    // residual has dropped by delta, which re-rounds r from the FP64 residual.
+    // replacement (reliable updates); MIXED_V64 keeps r, p, q in FP64.  In every mode
+    // apparent convergence is verified on the true FP64 residual (a replacement); the
+    // mixed modes also replace whenever the residual has dropped by delta, which
+    // re-rounds r from the FP64 residual.
     cp.prec = o.mode == DOGIP_SOLVE_F64 ? DOGIP_F64 : DOGIP_F32;
     cp.reliable = true;
     cp.delta = o.mode == DOGIP_SOLVE_F64 ? 0.0 : ((o.inner_tol > 0 && o.inner_tol < 1) ? o.inner_tol : 0.1);

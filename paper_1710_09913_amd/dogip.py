@@ -19,7 +19,8 @@ COEF = {"scalar": capi.DOGIP_COEF_SCALAR, "sym": capi.DOGIP_COEF_SYM, "logscalar
         "raw_d": capi.DOGIP_COEF_RAW_D}
 PREC = {"f64": capi.DOGIP_F64, "f32": capi.DOGIP_F32}
 SOLVE = {"f64": capi.DOGIP_SOLVE_F64, "mixed": capi.DOGIP_SOLVE_MIXED, "mixed_restart": capi.DOGIP_SOLVE_MIXED_RESTART,
-         "pmg": capi.DOGIP_SOLVE_PMG, "pmg_mixed": capi.DOGIP_SOLVE_PMG_MIXED}
+         "pmg": capi.DOGIP_SOLVE_PMG, "pmg_mixed": capi.DOGIP_SOLVE_PMG_MIXED,
+         "mixed_v64": capi.DOGIP_SOLVE_MIXED_V64}
 
 
 def stream_ptr(stream=None) -> int:
@@ -235,7 +236,8 @@ class Operator:
     def pcg(self, b, x=None, tol=1e-8, maxit=20000, mode="f64", inner_tol=0.0, max_outer=20, check_every=16,
             stream=None, raise_on_error=True):
         """Solve A x = b (dogip_pcg); returns (x, stats).  mode: "f64" (Jacobi-PCG),
-        "mixed" (FP32 apply and vectors, FP64 residual replacement), "mixed_restart"
+        "mixed" (FP32 apply and vectors, FP64 residual replacement), "mixed_v64" (the
+        same with r, p and A p in FP64: only the apply is FP32), "mixed_restart"
         (FP64 refinement around restarted FP32 solves), "pmg" / "pmg_mixed" (flexible CG
         preconditioned by a multigrid V-cycle over the orders k..1 and, for the elliptic
         problem on a unit mesh, over halved meshes; FP64 or FP32 applies inside the

@@ -51,20 +51,21 @@ def test_pcg_f64_matches_direct(jitter):
     assert abs(st["iters"] - it_o) <= max(5, 0.1 * it_o)
 
 
-@pytest.mark.parametrize("mode", ["mixed", "mixed_restart"])
+@pytest.mark.parametrize("mode", ["mixed", "mixed_v64", "mixed_restart"])
 def test_pcg_mixed_reaches_fp64_accuracy(mode):
     """FP32 apply inside FP64 refinement (residual replacement, or restarted inner solves)
     reaches the FP64 tolerance on the true residual and the direct solution."""
     sp, op, osp, perm, A, b = _c1(0.1, seed=2)
     x_lu = solve.direct_dirichlet(A, b, osp.boundary)
-    x, st = op.pcg(_gpu(b[perm]), tol=1e-10, maxit=5000, mode=mode, inner_tol=1e-4 if mode != "mixed" else 0.0)
+    x, st = op.pcg(_gpu(b[perm]), tol=1e-10, maxit=5000, mode=mode,
+                   inner_tol=1e-4 if mode == "mixed_restart" else 0.0)
     print(mode, st, flush=True)
     assert st["status"] == 0
     assert st["relres_true"] <= 1e-10
     if mode == "mixed_restart":
         assert st["outer"] >= 2
     _, st64 = op.pcg(_gpu(b[perm]), tol=1e-10, maxit=5000)
-    if mode == "mixed":  # no restarts: close to the FP64 iteration count
+    if mode != "mixed_restart":  # no restarts: close to the FP64 iteration count
         assert st["iters"] <= 1.15 * st64["iters"] + 5
     Ab = solve.dirichlet_matrix(A, osp.boundary).toarray()
     ev = np.linalg.eigvalsh(Ab)
