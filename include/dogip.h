@@ -169,6 +169,7 @@ typedef struct {
   double alg_bytes_f32;
   double alg_flops;     /* 2 [2 (nnz B^ - nnz_pm1 B^) + d^2 W_T] ncells (Section 3 count, x2 for FMA) */
   int64_t ndofs_w;      /* DOGIP_OP_GLOBAL_W: dofs of C_{N,2k} (D values held); 0 otherwise */
+  int64_t stage_entries; /* partial sums an apply stages for dofs shared by tiles (doubles) */
 } dogip_op_info;
 
 typedef struct {
@@ -312,6 +313,18 @@ int dogip_op_export_d(dogip_op op, double* d_out, dogip_stream stream);
  * The operator owns a staging buffer used by every apply, diag, solve and
  * gradient call: calls on one operator must be ordered (one stream). */
 int dogip_apply(dogip_op op, const double* u, double* y, int prec, dogip_stream stream);
+/* For callers that cannot allocate device memory at the call (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): dogip_apply with the
+ * same kernels and the same result bit for bit, its staging buffer taken from a static
+ * device array of DOGIP_NOALLOC_MAX_STAGE doubles (32 MiB) that each device holds until
+ * the process ends, instead of the operator's own.  Calls no hipMalloc, hipFree or
+ * allocating library routine, issues no memset, and does not record the kernel timer.
+ * DOGIP_E_RANGE if the operator's info.stage_entries exceeds DOGIP_NOALLOC_MAX_STAGE.
+ * Every call on a device shares that device's array: calls that overlap in time on one
+ * device (other streams or host threads) race and must be ordered by the caller.
+ * async. */
+#define DOGIP_NOALLOC_MAX_STAGE (1 << 22)
+int dogip_apply_noalloc(dogip_op op, const double* u, double* y, int prec, dogip_stream stream);
 /* diag <- diagonal of A (1 on Dirichlet rows).  device [ndofs].  async.  Bitwise
  * reproducible like dogip_apply (fixed summation order; uses the staging buffer). */
 int dogip_diag(dogip_op op, double* diag, dogip_stream stream);

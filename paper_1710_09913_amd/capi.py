@@ -45,6 +45,7 @@ DOGIP_OP_GLOBAL_W = 2
 DOGIP_VARIANT_AUTO = 0
 DOGIP_VARIANT_UNROLLED = 1
 DOGIP_VARIANT_LOOPED = 2
+DOGIP_NOALLOC_MAX_STAGE = 1 << 22
 
 
 class SpaceInfo(C.Structure):
@@ -59,7 +60,8 @@ class OpInfo(C.Structure):
                 ("ntiles", C.c_int64), ("tile_dofs_total", C.c_int64), ("nshared", C.c_int64),
                 ("max_tile_dofs", C.c_int64), ("bytes_d64", C.c_int64), ("bytes_d32", C.c_int64),
                 ("bytes_index", C.c_int64), ("alg_bytes_f64", C.c_double), ("alg_bytes_f32", C.c_double),
-                ("alg_flops", C.c_double), ("ndofs_w", C.c_int64)]
+                ("alg_flops", C.c_double), ("ndofs_w", C.c_int64),
+                ("stage_entries", C.c_int64)]
 
 
 class SolveOpts(C.Structure):
@@ -103,6 +105,7 @@ SIGNATURES = {
     "dogip_op_get_info": (C.c_int, [H, C.POINTER(OpInfo)]),
     "dogip_op_export_d": (C.c_int, [H, P, P]),
     "dogip_apply": (C.c_int, [H, P, P, C.c_int, P]),
+    "dogip_apply_noalloc": (C.c_int, [H, P, P, C.c_int, P]),
     "dogip_diag": (C.c_int, [H, P, P]),
     "dogip_pcg": (C.c_int, [H, P, P, C.POINTER(SolveOpts), C.POINTER(SolveStats), P]),
     "dogip_grad_logcoef": (C.c_int, [H, P, P, P, P]),

@@ -72,7 +72,7 @@ extern "C" {
 
 const char* dogip_last_error(void) { return g_err.c_str(); }
 
-int dogip_version(void) { return 1; }
+int dogip_version(void) { return 2; }
 
 int dogip_device_count(void) {
   int n = 0;
@@ -288,6 +288,14 @@ int dogip_apply(dogip_op op, const double* u, double* y, int prec, dogip_stream 
   return guard([&] {
     need(op);
     dogip::op_apply(*op->op, u, y, prec, S(stream));
+    return DOGIP_OK;
+  });
+}
+
+int dogip_apply_noalloc(dogip_op op, const double* u, double* y, int prec, dogip_stream stream) {
+  return guard([&] {
+    need(op);
+    dogip::op_apply_noalloc(*op->op, u, y, prec, S(stream));
     return DOGIP_OK;
   });
 }

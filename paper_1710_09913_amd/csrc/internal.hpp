@@ -229,6 +229,13 @@ void op_set_coef(Op& op, int coef_kind, const double* coef, hipStream_t st);
 // energy (optional): [ntiles] tile partials of u . A u, followed by op_finish_energy_count(op)
 // partials of the Dirichlet rows
 void op_apply(Op& op, const double* u, double* y, int prec, hipStream_t st, double* energy_partials = nullptr);
+// partial sums an apply stages for shared dofs (the staging buffer's length in doubles)
+int64_t op_stage_entries(const Op& op);
+// the apply with a caller's staging buffer of at least op_stage_entries(op) doubles
+// (device memory; the operator's own is left alone); allocates nothing
+void op_apply_staged(Op& op, const double* u, double* y, int prec, double* stage, hipStream_t st);
+// the apply with the library's per-device static staging buffer (noalloc.hip)
+void op_apply_noalloc(Op& op, const double* u, double* y, int prec, hipStream_t st);
 void op_diag(Op& op, double* diag, hipStream_t st);
 void op_grad(Op& op, const double* u, const double* lam, double* g, hipStream_t st);
 void op_export_d(Op& op, double* out, hipStream_t st);

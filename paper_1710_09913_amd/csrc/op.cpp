@@ -399,7 +399,9 @@ static ApplyLaunch apply_args(const Op& op, int prec) {
   return a;
 }
 
-void op_apply(Op& op, const double* u, double* y, int prec, hipStream_t st, double* energy) {
+// The apply's two launches with the staging buffer `stage` (op.stage, or a caller's buffer
+// of at least op_stage_entries(op) doubles); the timer records only with op.stage.
+static void apply_impl(Op& op, const double* u, double* y, int prec, hipStream_t st, double* energy, double* stage) {
   const Space& s = *op.space;
   DOGIP_CHECK(u && y, DOGIP_E_NULL, "null vector");
   DOGIP_CHECK(u != y, DOGIP_E_INVALID, "apply needs u != y");
@@ -409,8 +411,10 @@ void op_apply(Op& op, const double* u, double* y, int prec, hipStream_t st, doub
   a.u = u;
   a.y = y;
   a.energy = energy;
+  a.stage = stage;
+  const bool timed = op.timer->on && stage == op.stage.as<double>();
   std::array<hipEvent_t, 3> ev{};
-  if (op.timer->on) {
+  if (timed) {
     for (auto& x : ev) HIPCHK(hipEventCreate(&x));
     op.timer->ev.push_back(ev);
     HIPCHK(hipEventRecord(ev[0], st));
@@ -419,12 +423,23 @@ void op_apply(Op& op, const double* u, double* y, int prec, hipStream_t st, doub
                   : op.global_w ? launch_apply_global(s.dim, s.k, prec, op.variant, a, st)
                                 : launch_apply(s.dim, s.k, s.kind, prec, op.variant, a, st);
   DOGIP_CHECK(ok, DOGIP_E_RANGE, "no apply kernel for this (dim, k, kind, variant)");
-  if (op.timer->on) HIPCHK(hipEventRecord(ev[1], st));
-  launch_apply_finish(op.stage.as<double>(), op.sh_rowptr.as<uint32_t>(), op.sh_slots.as<uint32_t>(),
-                      op.shared.as<int32_t>(), int64_t(op.plan.shared.size()), op.bnd.as<int32_t>(),
-                      int64_t(s.boundary.size()), u, y, energy ? energy + op.plan.ntiles : nullptr, st);
+  if (timed) HIPCHK(hipEventRecord(ev[1], st));
+  launch_apply_finish(stage, op.sh_rowptr.as<uint32_t>(), op.sh_slots.as<uint32_t>(), op.shared.as<int32_t>(),
+                      int64_t(op.plan.shared.size()), op.bnd.as<int32_t>(), int64_t(s.boundary.size()), u, y,
+                      energy ? energy + op.plan.ntiles : nullptr, st);
   HIPCHK(hipGetLastError());
-  if (op.timer->on) HIPCHK(hipEventRecord(ev[2], st));
+  if (timed) HIPCHK(hipEventRecord(ev[2], st));
+}
+
+void op_apply(Op& op, const double* u, double* y, int prec, hipStream_t st, double* energy) {
+  apply_impl(op, u, y, prec, st, energy, op.stage.as<double>());
+}
+
+int64_t op_stage_entries(const Op& op) { return op.plan.stage_off.empty() ? 0 : op.plan.stage_off.back(); }
+
+void op_apply_staged(Op& op, const double* u, double* y, int prec, double* stage, hipStream_t st) {
+  DOGIP_CHECK(stage != nullptr, DOGIP_E_NULL, "null staging buffer");
+  apply_impl(op, u, y, prec, st, nullptr, stage);
 }
 
 bool op_has_v32(const Op& op) { return op.has32 && !op.global_w && op.nq == 0; }
@@ -535,6 +550,7 @@ dogip_op_info op_info(const Op& op) {
                           op.gw_rec.bytes + op.gw_off.bytes + op.gw_inc_ptr.bytes + op.gw_inc.bytes);
   i.ndofs_w = op.global_w ? op.gplan.nw : 0;
   i.nq = op.nq;
+  i.stage_entries = op_stage_entries(op);
   // values read per apply: D per cell and W node, D per global W dof, or (quadrature
   // points) one factor per cell and point plus the cell's R^-1 R^-T
   const double nd = op.nq > 0     ? (double(op.nq) + (s.kind == DOGIP_SE ? s.nsym : 0)) * s.nc

@@ -217,6 +217,15 @@ class Operator:
                                 PREC[prec], stream_ptr(stream)))
         return y
 
+    def apply_noalloc(self, u, y, prec: str = "f64", stream=None):
+        """dogip_apply_noalloc: the apply with the library's static staging buffer (no
+        device allocation in the call); y must be given."""
+        import torch
+
+        check(lib().dogip_apply_noalloc(self.h, _dev_ptr(u, torch.float64, self.ndofs),
+                                        _dev_ptr(y, torch.float64, self.ndofs), PREC[prec], stream_ptr(stream)))
+        return y
+
     def diag(self, out=None, stream=None):
         import torch
 
