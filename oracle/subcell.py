@@ -24,7 +24,10 @@ The paper does not fix the decomposition; the reading taken here:
 Pinned in tests/test_oracle_subcell.py by: cells wholly inside or outside the balls
 give the closed form a |T| w^_i; the children of a red refinement tile the parent
 (volumes); sum_{T,i} int_T a phi^W_i = int_Omega a converges to the exact ball
-volume, within the bound |a_in - a_out| * (volume of the cut leaves).
+volume, within the bound |a_in - a_out| * (volume of the cut leaves); and the node
+integrals of one cut cell reproduce the exact moments int_T 1_B x^alpha, |alpha| <= q
+(closed forms for a ball at a vertex and a ball inside the cell), within twice the
+volume of the cut leaves.
 """
 
 from __future__ import annotations

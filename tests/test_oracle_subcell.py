@@ -1,5 +1,6 @@
 """Pins of the oracle's sub-cell quadrature D for a coefficient with jumps inside cells."""
 
+import itertools
 import math
 
 import numpy as np
@@ -84,3 +85,76 @@ def test_leaf_rule_is_exact_for_the_w_basis_on_inside_cells():
     X = np.vstack([np.zeros(d), np.eye(d)]) * 0.1
     s, _ = subcell.subcell_integrals(X, np.array([[0.0, 0.0, 0.0, 5.0]]), q, depth=2, ng=(q + d + 2) // 2)
     assert np.abs(s - ref.what(d, q) / math.factorial(d)).max() <= 1e-15
+
+
+def _cut_leaf_volume(X, balls, depth):
+    """Reference-cell volume of the cut sub-simplices at the last level."""
+    d = X.shape[1]
+    R = (X[1:] - X[0]).T
+
+    def count(v, level):
+        cls = subcell.classify(X[0] + v @ R.T, balls)
+        if cls != 2:
+            return 0.0
+        if level == depth:
+            return abs(np.linalg.det((v[1:] - v[0]).T)) / math.factorial(d)
+        return sum(count(ch, level + 1) for ch in subcell.red_children(v))
+
+    return count(np.vstack([np.zeros(d), np.eye(d)]), 0)
+
+
+def _ball_orthant_moment(alpha, r):
+    """int over {x >= 0, |x| < r} of x^alpha: r^(|a|+n)/(|a|+n) * 2^(1-n) prod Gamma((a_i+1)/2) / Gamma((|a|+n)/2)
+    (polar coordinates; the sphere part is the orthant share of the Dirichlet integral)."""
+    n, s = len(alpha), sum(alpha)
+    g = math.prod(math.gamma((a + 1) / 2) for a in alpha) / math.gamma((s + n) / 2)
+    return r ** (s + n) / (s + n) * 2.0 ** (1 - n) * g
+
+
+def _ball_moment(alpha, c, r):
+    """int over the full ball |x - c| < r of x^alpha, expanding (c + y)^alpha; odd powers of
+    y integrate to zero, even ones are 2^n times the orthant moment."""
+    n = len(alpha)
+    total = 0.0
+    for beta in itertools.product(*[range(a + 1) for a in alpha]):
+        if any(b % 2 for b in beta):
+            continue
+        coef = math.prod(math.comb(a, b) * ci ** (a - b) for a, b, ci in zip(alpha, beta, c))
+        total += coef * 2.0 ** n * _ball_orthant_moment(beta, r)
+    return total
+
+
+@pytest.mark.parametrize("d,q", [(2, 4), (3, 4), (2, 2)])
+@pytest.mark.parametrize("where", ["vertex", "inside"])
+def test_cut_cell_node_integrals_reproduce_exact_moments(d, q, where):
+    """One cut cell, the reference simplex, against exact values that do not use the
+    oracle's basis: the W basis reproduces polynomials of degree <= q, so
+    sum_i I_i x_i^alpha = int_T 1_B x^alpha for every |alpha| <= q, and these W_T moments
+    determine the node integrals I_i.  The exact moments are closed forms: a ball centred
+    at the vertex 0 whose sphere stays inside T (T cut to the orthant sector of the ball),
+    and a ball inside T around the incentre (T cut to the whole ball).  The oracle's error
+    is bounded by twice the volume of the cut leaves (|x^alpha| <= 1 on T, positive
+    weights) and shrinks with the depth."""
+    X = np.vstack([np.zeros(d), np.eye(d)])
+    if where == "vertex":
+        r = 0.5  # < 1/sqrt(d): the far facet x_1 + .. + x_d = 1 is not reached
+        balls = np.array([[0.0] * d + [r]])
+        exact = {a: _ball_orthant_moment(a, r) for a in ref.multi_indices(d, q)}
+    else:
+        rin = 1.0 / (d + math.sqrt(d))  # inradius of the reference simplex, incentre (rin, .., rin)
+        c, r = np.full(d, rin), 0.8 * rin
+        balls = np.array([[*c, r]])
+        exact = {a: _ball_moment(a, c, r) for a in ref.multi_indices(d, q)}
+    nodes = np.array(ref.lattice(d, q), dtype=np.float64)
+    ng = (q + d + 1) // 2 + 1  # 2 ng - d >= q: exact on inside leaves
+    errs = []
+    for depth in ((2, 4, 6) if d == 2 else (2, 3, 4)):
+        s, _ = subcell.subcell_integrals(X, balls, q, depth, ng)
+        bound = 2.0 * _cut_leaf_volume(X, balls, depth) + 1e-14
+        worst = 0.0
+        for a, m in exact.items():
+            mom = float(s @ np.prod(nodes ** np.array(a), axis=1))
+            assert abs(mom - m) <= bound, (depth, a, mom, m, bound)
+            worst = max(worst, abs(mom - m))
+        errs.append(worst)
+    assert errs[-1] < errs[0] / 3
