@@ -6,13 +6,26 @@ coefficient exp(g) with g a Gaussian field (std 1, correlation length 0.1), zero
 Dirichlet boundary.  A step is one FP64 operator apply y = A u (Algorithm 1) with u and
 D resident in HBM; value = dofs / (seconds per apply) in GDoF/s.
 
-The same line carries: the FP32 apply, PCG time-to-1e-8 (FP64, mixed precision, and
-p-multigrid preconditioned, FP64 and mixed),
-the roofline of the apply's two kernels (algorithmic bytes / their measured time, HBM
-peak 8 TB/s; traffic = HBM bytes from the committed counter summary of these apply kernels)
-and the CPU oracle timed on a bounded sample.
+The same line carries:
+  * roofline: the apply's two kernels (tile kernel + shared-dof finish), algorithmic
+    bytes / their measured time against 8 TB/s; traffic = HBM bytes from the committed
+    counter summary of these kernels (null once their sources changed);
+  * apply_f32: the FP32 apply (FP32 copy of D) with its fraction;
+  * pcg_time_to_1e-8: time to a true FP64 relative residual of 1e-8 per solve mode
+    (Jacobi FP64; mixed with FP32-stored residual; mixed_v64 with every vector FP64 and
+    only the apply FP32; restarted refinement; multigrid with FP32 and FP64 V-cycles,
+    the first multigrid call timed with its hierarchy build), each with its speedup and
+    its difference from the FP64 solution;
+  * p2: the same operator at P2 (apply fractions, Jacobi and multigrid solves);
+  * secondary: the batch of 256 uneven 2D problems (batched apply, batched FP64 vs mixed
+    PCG) and the 2D 512^2 P5 anisotropic operator (apply fractions, PCG modes);
+  * cpu_baseline: the CPU oracle on a bounded sample at 1 thread and all cores (CSR SpMV
+    of the quadrature-assembled matrix, Algorithm 1, Jacobi-PCG), every solve mode's
+    error against the oracle's direct solve on that sample, and the oracle's rows of
+    b - A x at sampled dofs of each full-size solve.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 64] [--k 3] [--no-solve] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 64] [--k 3] [--no-solve]
+                    [--no-cpu] [--no-p2] [--no-secondary] [--workload c3|c2|c4|c5|qp|incl]
 """
 
 from __future__ import annotations
@@ -101,40 +114,177 @@ def measured_traffic(n, k):
     return {p: round(v["bytes_per_apply"]) for p, v in doc.get("traffic", {}).items()}
 
 
-def cpu_baseline(k, n_sample=20):
-    """The oracle's vectorised Algorithm 1 (numpy, float64) on a bounded sample of the same
-    workload family: a 20^3 Kuhn mesh at the same order."""
+def _host_threads():
+    """Threads for the all-cores legs: the CPUs this process may run on, at most 16 (a
+    one-GPU share of the host)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return max(1, min(16, n))
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _match(product_xyz, oracle_xyz):
+    """Oracle dof of each product dof, matched by coordinates."""
+    from scipy.spatial import cKDTree
+
+    dist, idx = cKDTree(oracle_xyz).query(product_xyz)
+    assert dist.max() < 1e-9 and len(set(idx.tolist())) == len(idx), "dof matching failed"
+    return idx
+
+
+def _timed(fn, min_s=1.5, max_reps=50):
+    fn()  # warm-up
+    reps, t0 = 0, time.time()
+    while reps < 3 or (time.time() - t0 < min_s and reps < max_reps):
+        fn()
+        reps += 1
+    return (time.time() - t0) / reps, reps
+
+
+def cpu_baseline(k, sample_solves=None, full_check=None, n_sample=10):
+    """The CPU FP64 oracle on the host, on a bounded sample of the same workload (3D
+    n_sample^3 Kuhn mesh, same order, lognormal coefficient), each leg at one thread and
+    at all cores (threads = host CPUs available, at most 16):
+      (i)   CSR SpMV of the quadrature-assembled matrix (scipy; all cores: row blocks on
+            threads);
+      (ii)  the oracle's Algorithm 1 (numpy; all cores: cell blocks on threads, outputs
+            summed), the leg quoted as value;
+      (iii) the oracle's Jacobi-PCG to 1e-8 with the Algorithm-1 apply.
+    With sample_solves (GPU solutions of the same sample problem per solve mode), each
+    is compared with the oracle's direct solve; with full_check (GPU solutions at full
+    size), the oracle's rows of b - A x at sampled dofs are reported per mode."""
+    import concurrent.futures as cf
+
     import numpy as np
+    import scipy.sparse.linalg as spla
+    from threadpoolctl import threadpool_limits
 
     from oracle import dogip as odg
     from oracle import fem
+    from oracle import solve as osolve
     from workloads import coef_lognormal, random_vector, unit_mesh
 
+    nthr = _host_threads()
     coords, cells = unit_mesh(3, n_sample)
     coef = coef_lognormal(coords, cells, 0)
     osp = fem.make_space(coords, cells, k)
     D = odg.build_d(osp, coef, "se")
     u = random_vector(osp.ndofs, 0)
-    from threadpoolctl import threadpool_limits
+    # 2k + 1 - 3 >= 2k - 2: the collapsed rule with k + 1 points per direction is exact for
+    # the integrand of a per-cell constant coefficient
+    A = fem.assemble(osp, fem.element_matrices(osp, coef, "se", nquad=k + 1))
+    parts = np.array_split(np.arange(len(cells)), nthr)
+    subs = [(fem.Space(coords, cells[p], k, osp.cell_dofs[p], osp.dof_coords, osp.boundary), D[p]) for p in parts]
+    rows = np.array_split(np.arange(osp.ndofs), nthr)
+    blocks = [A[r] for r in rows]
+    legs = {}
+    with threadpool_limits(limits=1), cf.ThreadPoolExecutor(nthr) as ex:
+        t1, r1 = _timed(lambda: A @ u)
+        tn, rn = _timed(lambda: np.concatenate(list(ex.map(lambda b: b @ u, blocks))))
+        legs["csr_spmv"] = {"GDoF_s_1_thread": round(osp.ndofs / t1 / 1e9, 6),
+                            "GDoF_s_all_cores": round(osp.ndofs / tn / 1e9, 6), "nnz": int(A.nnz),
+                            "ms_1_thread": round(t1 * 1e3, 3), "ms_all_cores": round(tn * 1e3, 3)}
+        t1, r1 = _timed(lambda: odg.apply(osp, D, u, "se"))
+        tn, rn = _timed(lambda: sum(ex.map(lambda sd: odg.apply(sd[0], sd[1], u, "se"), subs)))
+        legs["dogip_apply"] = {"GDoF_s_1_thread": round(osp.ndofs / t1 / 1e9, 6),
+                               "GDoF_s_all_cores": round(osp.ndofs / tn / 1e9, 6),
+                               "ms_1_thread": round(t1 * 1e3, 3), "ms_all_cores": round(tn * 1e3, 3)}
+        value = osp.ndofs / tn / 1e9
+        # (iii) Jacobi-PCG to 1e-8, f = 1, zero Dirichlet (identity rows)
+        b = fem.load_vector(osp, 1.0)
+        b[osp.boundary] = 0.0
+        dg = odg.diagonal(osp, D, "se", True)
+        mv1 = lambda v: odg.apply_dirichlet(osp, D, v, "se")  # noqa: E731
 
-    # one core: any BLAS call inside the oracle is held to one thread
-    with threadpool_limits(limits=1):
-        odg.apply_dirichlet(osp, D, u, "se")  # warm-up
-        reps, t0 = 0, time.time()
-        while reps < 3 or time.time() - t0 < 10.0:
-            odg.apply_dirichlet(osp, D, u, "se")
-            reps += 1
-            if time.time() - t0 > 30.0:
-                break
-        dt = (time.time() - t0) / reps
-    return {
-        "value": round(osp.ndofs / dt / 1e9, 6),
+        def mvn(v):
+            vt = v.copy()
+            vt[osp.boundary] = 0.0
+            y = sum(ex.map(lambda sd: odg.apply(sd[0], sd[1], vt, "se"), subs))
+            y[osp.boundary] = v[osp.boundary]
+            return y
+
+        t0 = time.time()
+        _, it1, rr1 = osolve.pcg(mv1, b, dg, 1e-8)
+        s1 = time.time() - t0
+        t0 = time.time()
+        _, itn, rrn = osolve.pcg(mvn, b, dg, 1e-8)
+        sn = time.time() - t0
+        legs["jacobi_pcg_1e-8"] = {"seconds_1_thread": round(s1, 3), "seconds_all_cores": round(sn, 3),
+                                   "iters": it1, "iters_all_cores": itn, "relres": max(rr1, rrn)}
+    out = {
+        "value": round(value, 6),
         "unit": "GDoF/s",
-        "cores": 1,
+        "cores": nthr,
         "kind": "oracle",
-        "sample": f"3D {n_sample}^3 Kuhn mesh ({len(cells)} cells, {osp.ndofs} dofs), P{k} elliptic, "
-                  f"FP64 numpy apply x{reps}, {dt * 1e3:.1f} ms each; host has {os.cpu_count()} logical CPUs",
+        "sample": f"3D {n_sample}^3 Kuhn mesh ({len(cells)} cells, {osp.ndofs} dofs), P{k} elliptic, lognormal "
+                  f"coefficient; value: the oracle's numpy Algorithm-1 apply on {nthr} threads (cell blocks); "
+                  f"legs at 1 thread and at {nthr}",
+        "cpu_model": _cpu_model(),
+        "logical_cpus": os.cpu_count(),
+        "legs": legs,
     }
+    if sample_solves is not None:
+        # the same problem solved by the oracle's sparse LU (interior block, x_B = 0)
+        mask = np.ones(osp.ndofs, bool)
+        mask[osp.boundary] = False
+        I = np.nonzero(mask)[0]
+        xo = np.zeros(osp.ndofs)
+        xo[I] = spla.splu(A[I][:, I].tocsc()).solve(b[I])
+        perm = _match(sample_solves["dof_coords"], osp.dof_coords)
+        chk = {}
+        for mode, x in sample_solves["x"].items():
+            xg = np.zeros(osp.ndofs)
+            xg[perm] = x
+            r = b[I] - A[I][:, I] @ xg[I]
+            chk[mode] = {"rel_err_vs_oracle_direct": float(np.linalg.norm(xg - xo) / np.linalg.norm(xo)),
+                         "oracle_relres": float(np.linalg.norm(r) / np.linalg.norm(b[I]))}
+        out["sample_solves_vs_oracle"] = chk
+    if full_check is not None:
+        out["full_size_solves_oracle_rows"] = _full_rows(full_check, k)
+    return out
+
+
+def _full_rows(fc, k, nsample=200, seed=77):
+    """Oracle rows of b - A x at a seeded sample of interior dofs of the full-size problem,
+    for each mode's x: rows of A from the oracle's Algorithm 1 on the sub-mesh of every cell
+    that touches a sampled dof, rows of b = int phi_i from the oracle's load vector there.
+    Reports ||(b - A x)_S|| / ||b_S|| per mode."""
+    import numpy as np
+
+    from oracle import dogip as odg
+    from oracle import fem
+
+    cd, bnd = fc["cell_dofs"], fc["boundary"]
+    rng = np.random.default_rng(seed)
+    interior = np.setdiff1d(np.arange(fc["ndofs"]), bnd)
+    samples = np.sort(rng.choice(interior, nsample, replace=False))
+    touch = np.isin(cd, samples).any(axis=1)
+    sub = np.nonzero(touch)[0]
+    verts, local = np.unique(fc["cells"][sub], return_inverse=True)
+    cells_sub = local.reshape(len(sub), -1).astype(fc["cells"].dtype)
+    osp = fem.make_space(fc["coords"][verts], cells_sub, k)
+    D = odg.build_d(osp, fc["coef"][sub], "se")
+    bo = fem.load_vector(osp, 1.0)
+    pid = np.unique(cd[sub])
+    perm = _match(fc["dof_coords"][pid], osp.dof_coords)
+    at = perm[np.searchsorted(pid, samples)]
+    out = {}
+    for mode, x in fc["x"].items():
+        xo = np.zeros(osp.ndofs)
+        xo[perm] = x[pid]
+        xo[perm[np.isin(pid, bnd)]] = 0.0
+        r = bo[at] - odg.apply(osp, D, xo, "se")[at]
+        out[mode] = float(np.linalg.norm(r) / np.linalg.norm(bo[at]))
+    return {"sampled_dofs": nsample, "relres_sampled": out}
 
 
 def _base(metric, unit, value, ms, a, config, dtype="f64", hib=True):
@@ -289,18 +439,19 @@ def c5_problems(seed):
     from paper_1710_09913_amd import Batch, Mesh, Operator, Space, tune
     from workloads import batch_spec, coef_uniform
 
+    unrolled = 1  # batched launches take the unrolled kernels with at most 256-cell tiles
     for k in (1, 2, 3, 4):
-        if tune.tuned(2, k, "se", "f32") == (0, 0):
-            tune.tune(2, k, "se", "f32", max_tile_cells=256)
+        if tune.tuned(2, k, "se", "f32", tag="batch") == (0, 0):
+            tune.tune(2, k, "se", "f32", max_tile_cells=256, variants=(unrolled,), tag="batch")
     spec = batch_spec(256, seed)
     ops, coefs, meshes = [], [], {}
     for n, k, sub in spec:
         if n not in meshes:
             meshes[n] = Mesh.unit(2, n)
         sp = Space(meshes[n], k, "se", "dirichlet")
-        tw, var = tune.tuned(2, k, "se", "f32")
+        tw, var = tune.tuned(2, k, "se", "f32", tag="batch")
         coefs.append(coef_uniform(sp.ncells, 1, 10, seed, sub))
-        ops.append(Operator(sp, torch.from_numpy(coefs[-1]), "scalar", fp32=True, tile_waves=tw, variant=1))
+        ops.append(Operator(sp, torch.from_numpy(coefs[-1]), "scalar", fp32=True, tile_waves=tw, variant=var))
     return ops, Batch(ops), coefs
 
 
@@ -533,6 +684,8 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-p2", action="store_true", help="skip the 3D P2 block")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the batch and 2D P5 rows")
     ap.add_argument("--threads", type=int, default=16, help="host threads for the batch's concurrent solves")
     ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "c5", "qp", "incl"],
                     help="c3: 3D 64^3 P3 (default, the headline); c2: 2D 512^2 P1..P5 sweep; "
@@ -610,48 +763,220 @@ def main(argv=None):
             "frac": round(info["alg_bytes_f32"] / (kms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         },
     }
+    full_check = sample_solves = None
     if not a.no_solve:
-        res = {}
-        for mode in ("f64", "mixed", "mixed_restart", "pmg", "pmg_mixed"):
-            x = torch.zeros_like(b)
-            torch.cuda.synchronize()
-            t0 = time.time()
-            # warm-up: allocates the workspace (and builds the multigrid hierarchy)
-            op.pcg(b, x, tol=1e-8, maxit=20000, mode=mode)
-            torch.cuda.synchronize()
-            first = time.time() - t0
-            t0 = time.time()
-            x, st = op.pcg(b, None, tol=1e-8, maxit=20000, mode=mode, inner_tol=1e-4 if mode == "mixed_restart" else 0.0)
-            torch.cuda.synchronize()
-            dt = time.time() - t0
-            res[mode] = {"seconds": round(dt, 4), "iters": st["iters"], "outer": st["outer"],
-                         "relres_true": st["relres_true"]}
-            # each solution against the FP64 Jacobi-PCG one (both to 1e-8, so they differ by
-            # up to about cond(A) * 1e-8 in norm)
-            if mode == "f64":
-                x64 = x.clone()
-            res[mode]["rel_diff_vs_f64"] = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
-            if mode.startswith("pmg"):
-                res[mode]["first_call_seconds"] = round(first, 4)
-            log(f"[pcg {mode}] {dt:.3f}s (first call {first:.3f}s) {st}")
-        res["speedup_mixed_vs_f64"] = round(res["f64"]["seconds"] / res["mixed"]["seconds"], 3)
-        res["mixed"]["method"] = ("FP32 apply, r/p/q stored in FP32 (x and inner products FP64), FP64 residual "
-                                  "replacement (reliable updates)")
-        res["mixed_restart"]["method"] = "FP64 iterative refinement around restarted FP32-apply PCG (inner 1e-4)"
-        res["pmg"]["method"] = ("flexible CG, multigrid V-cycle preconditioner: orders k..1 on the mesh "
-                                "(Chebyshev degree 3 on [lmax/8, 1.1 lmax]), then P1 on nested meshes halved down to "
-                                "at most 400 interior dofs (degree 4 on [lmax/20, 1.1 lmax]), the coarsest solved "
-                                "with its dense inverse; first call builds the hierarchy")
-        res["pmg_mixed"]["method"] = ("the same with the V-cycle's applies in FP32 and the finest smoother's "
-                                      "residual and direction stored in FP32")
-        res["speedup_pmg_mixed_vs_f64"] = round(res["f64"]["seconds"] / res["pmg_mixed"]["seconds"], 3)
+        res, xs = solve_modes(op, b, SOLVE_MODES, keep_x=not a.no_cpu)
         out["pcg_time_to_1e-8"] = res
+        if not a.no_cpu:
+            coords, cells = unit_mesh_np(a.n)
+            full_check = {"x": xs, "cell_dofs": space.cell_dofs(), "boundary": space.boundary(),
+                          "dof_coords": space.dof_coords(), "ndofs": space.ndofs, "coords": coords,
+                          "cells": cells, "coef": _lognormal(a.n, a.seed)}
+    del op
+    torch.cuda.empty_cache()
+    if not a.no_p2 and a.k == 3:
+        out["p2"] = run_p2_block(a)
+    if not a.no_secondary:
+        out["secondary"] = run_secondary(a)
     if not a.no_cpu:
+        if not a.no_solve:
+            sample_solves = solve_sample(a.k, 10)
         t0 = time.time()
-        out["cpu_baseline"] = cpu_baseline(a.k)
+        out["cpu_baseline"] = cpu_baseline(a.k, sample_solves, full_check)
         log(f"[cpu baseline] {time.time() - t0:.1f}s {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
     return 0
+
+
+# solve modes of the headline line, in this order: the multigrid's FP32-cycle mode first so
+# that its first call includes the hierarchy build
+SOLVE_MODES = ("f64", "mixed", "mixed_v64", "mixed_restart", "pmg_mixed", "pmg")
+MODE_METHOD = {
+    "f64": "Jacobi-PCG, FP64 throughout",
+    "mixed": "FP32 apply with r, p and A p STORED IN FP32 (x and inner products FP64), FP64 residual replacement "
+             "(reliable updates): the residual is kept in reduced precision between replacements",
+    "mixed_v64": "FP32 apply only (D copy and element arithmetic); x, r, p, A p, every inner product and the D "
+                 "construction FP64, FP64 residual replacement: the stated precision contract",
+    "mixed_restart": "FP64 iterative refinement around restarted FP32-apply Jacobi-PCG (inner 1e-4); residual "
+                     "and inner products FP64",
+    "pmg": "flexible CG, multigrid V-cycle preconditioner: orders k..1 on the mesh (Chebyshev degree 3 on "
+           "[lmax/8, 1.1 lmax]), then P1 on nested meshes halved down to at most 400 interior dofs (degree 4 on "
+           "[lmax/20, 1.1 lmax]), the coarsest solved with its dense inverse; FP64 cycle",
+    "pmg_mixed": "the same multigrid with the V-cycle's applies in FP32 and the finest smoother's residual and "
+                 "direction stored in FP32; outer CG residual and inner products FP64",
+}
+
+
+def solve_modes(op, b, modes, keep_x=False, tol=1e-8, maxit=20000):
+    """Time-to-tolerance per mode: a first call (workspace; for the multigrid modes, the
+    first of them also builds the hierarchy: its first_call_seconds is the set-up-inclusive
+    time), then a timed second call from x0 = 0."""
+    import torch
+
+    res, xs = {}, {}
+    for mode in modes:
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        op.pcg(b, x, tol=tol, maxit=maxit, mode=mode, inner_tol=1e-4 if mode == "mixed_restart" else 0.0)
+        torch.cuda.synchronize()
+        first = time.time() - t0
+        t0 = time.time()
+        x, st = op.pcg(b, None, tol=tol, maxit=maxit, mode=mode, inner_tol=1e-4 if mode == "mixed_restart" else 0.0)
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        res[mode] = {"seconds": round(dt, 4), "first_call_seconds": round(first, 4), "iters": st["iters"],
+                     "outer": st["outer"], "relres_true": st["relres_true"], "method": MODE_METHOD[mode]}
+        if mode == "f64":
+            x64 = x.clone()
+        # against the FP64 Jacobi-PCG solution (both to tol: they differ by up to about cond(A) tol)
+        res[mode]["rel_diff_vs_f64"] = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
+        if keep_x:
+            xs[mode] = x.cpu().numpy()
+        log(f"[pcg {mode}] {dt:.3f}s (first call {first:.3f}s) {st}")
+    f64 = res["f64"]["seconds"]
+    for m in modes:
+        if m != "f64":
+            res[m]["speedup_vs_f64"] = round(f64 / res[m]["seconds"], 3)
+    pm = [m for m in modes if m.startswith("pmg")]
+    if pm:
+        res[pm[0]]["setup_inclusive_seconds"] = res[pm[0]]["first_call_seconds"]
+        res[pm[0]]["speedup_vs_f64_setup_inclusive"] = round(f64 / res[pm[0]]["first_call_seconds"], 3)
+        res[pm[0]]["note"] = "first_call_seconds builds the multigrid hierarchy (set-up inclusive)"
+        for m in pm[1:]:
+            res[m]["note"] = "first_call_seconds reuses the hierarchy built by " + pm[0]
+    return res, xs
+
+
+def unit_mesh_np(n):
+    from workloads import unit_mesh
+
+    return unit_mesh(3, n)
+
+
+def solve_sample(k, n):
+    """The sample problem of the CPU leg (3D n^3, order k, lognormal, f = 1) solved on the
+    GPU in every mode, for the comparison with the oracle's direct solve."""
+    import torch
+
+    from paper_1710_09913_amd import Mesh, Operator, Space
+
+    mesh = Mesh.unit(3, n)
+    space = Space(mesh, k, "se", "dirichlet")
+    op = Operator(space, torch.from_numpy(_lognormal(n, 0)), "scalar", fp32=True)
+    b = _rhs_f1(space, mesh, k)
+    xs = {}
+    for mode in SOLVE_MODES:
+        x, st = op.pcg(b, None, tol=1e-8, maxit=20000, mode=mode, inner_tol=1e-4 if mode == "mixed_restart" else 0.0)
+        xs[mode] = x.cpu().numpy()
+    return {"x": xs, "dof_coords": space.dof_coords()}
+
+
+def run_p2_block(a):
+    """3D 64^3 P2 elliptic (the P2 operator of the same workload): FP64 and FP32 apply with
+    their roofline fractions, and PCG to 1e-8 in the Jacobi and multigrid modes."""
+    import torch
+
+    space, op, b = build_problem(a.n, 2, a.seed)
+    from workloads import random_vector
+
+    u = torch.from_numpy(random_vector(space.ndofs, a.seed)).cuda()
+    y = torch.empty_like(u)
+    blk = {"ndofs": space.ndofs, "tile_cells": op.info["tile_cells"]}
+    for prec in ("f64", "f32"):
+        ms, tms, fms = time_apply(op, u, y, prec, a.steps, a.warmup)
+        kms = tms + fms
+        ab = op.info["alg_bytes_" + prec]
+        blk["apply_" + prec] = {"GDoF_s": round(space.ndofs / (ms * 1e-3) / 1e9, 4), "ms": round(ms, 5),
+                                "kernel_ms": round(kms, 5), "alg_bytes": ab,
+                                "frac": round(ab / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if not a.no_solve:
+        res, _ = solve_modes(op, b, ("f64", "mixed", "mixed_v64", "pmg_mixed"))
+        blk["pcg_time_to_1e-8"] = res
+    log(f"[p2] {blk}")
+    del op
+    torch.cuda.empty_cache()
+    return blk
+
+
+def run_secondary(a):
+    """Compact rows of two more workloads: the batch of 256 uneven 2D problems (batched
+    apply, batched FP64 vs mixed PCG to 1e-8) and the 2D 512^2 P5 anisotropic elliptic
+    operator (apply fractions, FP64 vs mixed vs multigrid PCG to 1e-8)."""
+    import numpy as np
+    import torch
+
+    from paper_1710_09913_amd import Mesh, Operator, Space
+    from workloads import coef_aniso_2d, random_vector
+
+    out = {}
+    t0 = time.time()
+    ops, bt, _ = c5_problems(a.seed)
+    rhs = torch.ones(bt.ndofs, dtype=torch.float64, device="cuda")
+    for i, op in enumerate(ops):
+        rhs[torch.from_numpy(op.space.boundary().astype(np.int64) + int(bt.offsets[i])).cuda()] = 0.0
+    setup = time.time() - t0
+    u = torch.ones(bt.ndofs, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(u)
+    c5 = {"problems": len(ops), "ndofs_total": bt.ndofs, "setup_seconds": round(setup, 2)}
+    for prec in ("f64", "f32"):
+        for _ in range(a.warmup):
+            bt.apply(u, y, prec=prec)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(a.steps):
+            bt.apply(u, y, prec=prec)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / a.steps
+        c5["batch_apply_" + prec] = {"ms": round(ms, 5), "GDoF_s": round(bt.ndofs / (ms * 1e-3) / 1e9, 3)}
+    for mode in ("f64", "mixed"):
+        bt.pcg(rhs, tol=1e-8, maxit=8, mode=mode, raise_on_error=False)  # workspace
+        torch.cuda.synchronize()
+        t0 = time.time()
+        _, stats = bt.pcg(rhs, tol=1e-8, maxit=50000, mode=mode)
+        torch.cuda.synchronize()
+        c5["batched_pcg_" + mode] = {"seconds": round(time.time() - t0, 4),
+                                     "max_iters": max(s["iters"] for s in stats),
+                                     "failures": sum(1 for s in stats if s["status"] != 0),
+                                     "worst_relres_true": max(s["relres_true"] for s in stats)}
+    c5["speedup_mixed_vs_f64"] = round(c5["batched_pcg_f64"]["seconds"] / c5["batched_pcg_mixed"]["seconds"], 3)
+    log(f"[secondary c5] {c5}")
+    out["batch_256_uneven_2d"] = c5
+    del ops, bt
+    torch.cuda.empty_cache()
+
+    mesh = Mesh.unit(2, 512)
+    sp = Space(mesh, 5, "se", "dirichlet")
+    op = Operator(sp, torch.from_numpy(coef_aniso_2d(sp.ncells, a.seed)), "sym", fp32=True)
+    uu = torch.from_numpy(random_vector(sp.ndofs, a.seed)).cuda()
+    yy = torch.empty_like(uu)
+    c2 = {"ndofs": sp.ndofs}
+    for prec in ("f64", "f32"):
+        ms, tms, fms = time_apply(op, uu, yy, prec, a.steps, a.warmup)
+        ab = op.info["alg_bytes_" + prec]
+        c2["apply_" + prec] = {"GDoF_s": round(sp.ndofs / (ms * 1e-3) / 1e9, 3), "ms": round(ms, 5),
+                               "frac": round(ab / ((tms + fms) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    b = _rhs_f1(sp, mesh, 5)
+    for mode in ("pmg_mixed", "f64", "mixed"):
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        # first call: workspace (multigrid: the hierarchy, so this is its set-up-inclusive time)
+        op.pcg(b, x, tol=1e-8, maxit=200000 if mode == "pmg_mixed" else 8, mode=mode, raise_on_error=False)
+        torch.cuda.synchronize()
+        first = time.time() - t0
+        t0 = time.time()
+        _, st = op.pcg(b, None, tol=1e-8, maxit=200000, mode=mode, raise_on_error=False)
+        torch.cuda.synchronize()
+        c2["pcg_" + mode] = {"seconds": round(time.time() - t0, 4), "iters": st["iters"], "status": st["status"],
+                             "relres_true": st["relres_true"]}
+        if mode == "pmg_mixed":
+            c2["pcg_" + mode]["setup_inclusive_seconds"] = round(first, 4)
+    log(f"[secondary c2 p5] {c2}")
+    out["2d512_p5_aniso_se"] = c2
+    return out
 
 
 if __name__ == "__main__":

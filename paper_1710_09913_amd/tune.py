@@ -24,8 +24,8 @@ def cache_path() -> str:
     return os.environ.get("DOGIP_TUNE_CACHE") or os.path.join(os.path.expanduser("~"), ".cache", "dogip", "tune.json")
 
 
-def _key(dim, k, kind, prec):
-    return f"d{dim}-k{k}-{kind}-{prec}"
+def _key(dim, k, kind, prec, tag=""):
+    return f"d{dim}-k{k}-{kind}-{prec}" + (f"-{tag}" if tag else "")
 
 
 def load_cache() -> dict:
@@ -45,9 +45,11 @@ def save_cache(c: dict) -> None:
     os.replace(tmp, p)
 
 
-def tuned(dim, k, kind, prec="f64"):
-    """(tile_waves, variant) from the cache, or (0, 0) for the library defaults."""
-    e = load_cache().get(_key(dim, k, kind, prec))
+def tuned(dim, k, kind, prec="f64", tag=""):
+    """(tile_waves, variant) from the cache, or (0, 0) for the library defaults.  tag names
+    a restricted search (for instance "batch": unrolled kernels and at most 256-cell tiles,
+    what batched launches accept)."""
+    e = load_cache().get(_key(dim, k, kind, prec, tag))
     return (e["tile_waves"], e["variant"]) if e else (0, 0)
 
 
@@ -57,8 +59,9 @@ def _mesh_size(dim, k, cells_target):
 
 
 def tune(dim, k, kind, prec="f64", cells_target=400_000, reps=20, tile_waves=TILE_WAVES, variants=None,
-         max_tile_cells=512, verbose=False) -> dict:
-    """Time every candidate on a unit mesh of about cells_target cells; store and return the best."""
+         max_tile_cells=512, verbose=False, tag="") -> dict:
+    """Time every candidate on a unit mesh of about cells_target cells; store and return the
+    best under the key of (dim, k, kind, prec, tag)."""
     import torch
 
     from .dogip import Mesh, Operator, Space
@@ -98,7 +101,7 @@ def tune(dim, k, kind, prec="f64", cells_target=400_000, reps=20, tile_waves=TIL
     entry = {"tile_waves": best["tile_waves"], "variant": best["variant"], "ms": best["ms"],
              "mesh_n": n, "ndofs": space.ndofs, "candidates": rows}
     c = load_cache()
-    c[_key(dim, k, kind, prec)] = entry
+    c[_key(dim, k, kind, prec, tag)] = entry
     save_cache(c)
     return entry
 

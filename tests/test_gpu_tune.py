@@ -1,0 +1,58 @@
+"""The autotuner's choice against the library default on the tuning mesh: the tuned
+(tile_waves, variant) is never slower than the default configuration (to timing noise),
+and the default is among the candidates it timed."""
+
+import statistics
+
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _ms(op, u, y, prec, reps=10, rounds=5):
+    """Median over rounds of the mean apply time (tile kernel + finish, HIP events)."""
+    for _ in range(3):
+        op.apply(u, y, prec=prec)
+    torch.cuda.synchronize()
+    op.timer_enable(True)
+    out = []
+    for _ in range(rounds):
+        op.timer_read()
+        for _ in range(reps):
+            op.apply(u, y, prec=prec)
+        t, f, n = op.timer_read()
+        out.append((t + f) / n)
+    op.timer_enable(False)
+    return statistics.median(out)
+
+
+@pytest.mark.parametrize("dim,k,prec,tag,max_cells,variants", [
+    (2, 3, "f32", "", 512, None),
+    (2, 2, "f32", "batch", 256, (1,)),
+    (3, 2, "f64", "", 512, None),
+])
+def test_tuned_not_slower_than_default(tmp_path, monkeypatch, dim, k, prec, tag, max_cells, variants):
+    from paper_1710_09913_amd import Mesh, Operator, Space, tune
+
+    monkeypatch.setenv("DOGIP_TUNE_CACHE", str(tmp_path / "tune.json"))
+    print(f"[tune] d={dim} k={k} {prec} tag={tag!r}", flush=True)
+    e = tune.tune(dim, k, "se", prec, cells_target=200_000, reps=10, max_tile_cells=max_cells, variants=variants,
+                  tag=tag)
+    assert tune.tuned(dim, k, "se", prec, tag=tag) == (e["tile_waves"], e["variant"])
+    space = Space(Mesh.unit(dim, e["mesh_n"]), k, "se", "dirichlet")
+    coef = torch.ones(space.ncells, dtype=torch.float64)
+    default = Operator(space, coef, "scalar", fp32=prec == "f32")
+    dflt = (default.info["tile_cells"] // 64, default.info["variant"])
+    if default.info["tile_cells"] <= max_cells and (variants is None or dflt[1] in variants):
+        assert any((c["tile_waves"], c["variant"]) == dflt for c in e["candidates"]), "default not timed"
+    tuned = Operator(space, coef, "scalar", fp32=prec == "f32", tile_waves=e["tile_waves"], variant=e["variant"])
+    u = torch.ones(space.ndofs, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(u)
+    t_def = _ms(default, u, y, prec)
+    t_tun = _ms(tuned, u, y, prec)
+    print(f"[tune] default {dflt}: {t_def:.4f} ms, tuned {(e['tile_waves'], e['variant'])}: {t_tun:.4f} ms",
+          flush=True)
+    if default.info["tile_cells"] <= max_cells and (variants is None or dflt[1] in variants):
+        assert t_tun <= 1.10 * t_def
