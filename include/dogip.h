@@ -141,6 +141,13 @@ extern "C" {
 #define DOGIP_VARIANT_AUTO 0     /* tuned choice: unrolled where compiled, else looped */
 #define DOGIP_VARIANT_UNROLLED 1 /* B^ as compile-time constants, zero entries skipped, +-1 free */
 #define DOGIP_VARIANT_LOOPED 2   /* B^ read from device memory (wave-uniform loads), dense */
+/* 3D P3 elliptic only: FP64 applies as UNROLLED; FP32 applies form the two B^ products
+ * (eq. ep_dogip_mul) with bfloat16 matrix-core instructions.  B^ of 3D P3 is exact in
+ * bfloat16 and the vector operand (u_T, then D_T B^ u_T) is split into three bfloat16
+ * terms whose sum is the FP32 value exactly, so every product is exact and only the FP32
+ * accumulation rounds, as in the vector kernel.  The FP32 copy of D is held in this
+ * variant's own layout.  Not accepted by dogip_batch_create. */
+#define DOGIP_VARIANT_MFMA 3
 
 typedef struct dogip_mesh_s* dogip_mesh;
 typedef struct dogip_space_s* dogip_space;

@@ -45,6 +45,7 @@ DOGIP_OP_GLOBAL_W = 2
 DOGIP_VARIANT_AUTO = 0
 DOGIP_VARIANT_UNROLLED = 1
 DOGIP_VARIANT_LOOPED = 2
+DOGIP_VARIANT_MFMA = 3
 DOGIP_NOALLOC_MAX_STAGE = 1 << 22
 
 

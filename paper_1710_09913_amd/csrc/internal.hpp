@@ -276,6 +276,12 @@ struct ApplyLaunch {
 };
 
 bool launch_apply(int dim, int k, int kind, int prec, int variant, const ApplyLaunch& a, hipStream_t st);
+// FP32 apply of 3D P3 elliptic operators with the B^ products on the matrix cores
+// (kern_apply_mfma.hip); D32 in the layout of d32_pos with nch32 < 0
+bool launch_apply_mfma(bool energy, const ApplyLaunch& a, hipStream_t st);
+int64_t mfma_d32_per_wave();
+int64_t mfma_lds_tables();  // bytes of LDS the matrix-core kernel adds to a tile's arrays
+bool has_mfma(int dim, int k, int kind);
 bool launch_apply_global(int dim, int k, int prec, int variant, const ApplyLaunch& a, hipStream_t st);
 bool has_unrolled(int dim, int k, int kind);
 
@@ -339,7 +345,7 @@ struct BuildDLaunch {
   const double* coef;
   double* d64;
   float* d32;            // may be null
-  int64_t nel, nel_pad, nch64, nch32;
+  int64_t nel, nel_pad, nch64, nch32;  // nch32 < 0: the matrix-core layout of D32 (d32_pos)
   int dim, kind, coef_kind, wt, nsym;
 };
 void launch_build_d(const BuildDLaunch& a, hipStream_t st);

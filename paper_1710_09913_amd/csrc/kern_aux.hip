@@ -17,7 +17,7 @@ __global__ __launch_bounds__(256) void k_build_d(BuildDLaunch a) {
   const int64_t uc = a.perm[e];
   auto store = [&](int f, double v) {
     a.d64[((e >> 6) * a.nch64 + (f >> 1)) * 128 + (e & 63) * 2 + (f & 1)] = v;
-    if (a.d32) a.d32[((e >> 6) * a.nch32 + (f >> 2)) * 256 + (e & 63) * 4 + (f & 3)] = float(v);
+    if (a.d32) a.d32[d32_pos(e >> 6, int(e & 63), f, a.nch32)] = float(v);
   };
   if (a.coef_kind == DOGIP_COEF_RAW_D) {
     const int nd = wt * ns;

@@ -71,6 +71,17 @@ __device__ __forceinline__ void dmul(const T (&dv)[S], const T (&g)[NB], T (&h)[
   }
 }
 
+// Position of value f (= node * s + component) of cell lane of wave w in the FP32 copy of
+// D: AoSoA 16-byte chunks by 64 cells ([w][nch32][64][4]), or with nch32 < 0 the layout of
+// the matrix-core apply of 3D P3 (per wave, per block of 16 cells and group of 4 nodes,
+// the 64 lanes' 6 components as [4][64] then [2][64] floats; lane = 16 (node % 4) + cell % 16).
+__device__ __forceinline__ int64_t d32_pos(int64_t w, int lane, int f, int64_t nch32) {
+  if (nch32 >= 0) return (w * nch32 + (f >> 2)) * 256 + lane * 4 + (f & 3);
+  const int i = f / 6, c = f - 6 * i, l = 16 * (i & 3) + (lane & 15);
+  const int64_t base = ((w * 4 + (lane >> 4)) * 9 + (i >> 2)) * 384;
+  return c < 4 ? base + l * 4 + c : base + 256 + l * 2 + (c - 4);
+}
+
 // Compile-time reference table (exact rationals rounded once to double).
 template <int D, int K, int KIND>
 struct CT {

@@ -191,7 +191,7 @@ __global__ __launch_bounds__(128) void k_build_d_sub(SubLaunch a) {
   const int64_t w = e >> 6, lane = e & 63;
   auto store = [&](int f, double val) {
     a.d64[(w * a.nch64 + (f >> 1)) * 128 + lane * 2 + (f & 1)] = val;
-    if (a.d32) a.d32[(w * a.nch32 + (f >> 2)) * 256 + lane * 4 + (f & 3)] = float(val);
+    if (a.d32) a.d32[d32_pos(w, int(lane), f, a.nch32)] = float(val);
   };
   double K[6] = {};
   if (a.kind == KIND_SE) {

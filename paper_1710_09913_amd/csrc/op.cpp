@@ -52,8 +52,14 @@ bool has_unrolled(int dim, int k, int kind) {
   return kind == KIND_SE ? k <= 3 : k <= 2;
 }
 
+bool has_mfma(int dim, int k, int kind) { return dim == 3 && k == 3 && kind == KIND_SE; }
+
 bool launch_apply(int dim, int k, int kind, int prec, int variant, const ApplyLaunch& a, hipStream_t st) {
   const bool en = a.energy != nullptr;
+  if (variant == DOGIP_VARIANT_MFMA) {
+    if (prec == DOGIP_F32) return launch_apply_mfma(en, a, st);
+    variant = DOGIP_VARIANT_UNROLLED;  // FP64 applies take the unrolled vector kernel
+  }
   if (variant == DOGIP_VARIANT_UNROLLED)
     return dim == 2 ? launch_apply_unrolled_2d(k, kind, prec, en, a, st)
                     : launch_apply_unrolled_3d(k, kind, prec, en, a, st);
@@ -140,7 +146,7 @@ std::unique_ptr<Op> make_op(std::shared_ptr<const Space> sp, int coef_kind, cons
   check_coef(s, coef_kind);
   DOGIP_CHECK(coef != nullptr, DOGIP_E_NULL, "null coefficient pointer");
   DOGIP_CHECK(tile_waves >= 0 && tile_waves <= 8, DOGIP_E_RANGE, "tile_waves must be 0..8");
-  DOGIP_CHECK(variant >= DOGIP_VARIANT_AUTO && variant <= DOGIP_VARIANT_LOOPED, DOGIP_E_RANGE, "unknown variant");
+  DOGIP_CHECK(variant >= DOGIP_VARIANT_AUTO && variant <= DOGIP_VARIANT_MFMA, DOGIP_E_RANGE, "unknown variant");
   DOGIP_CHECK((flags & ~(DOGIP_OP_FP32 | DOGIP_OP_GLOBAL_W)) == 0, DOGIP_E_RANGE, "unknown operator flag");
   auto op = std::make_unique<Op>();
   op->space = sp;
@@ -151,19 +157,29 @@ std::unique_ptr<Op> make_op(std::shared_ptr<const Space> sp, int coef_kind, cons
   if (variant == DOGIP_VARIANT_AUTO) variant = has_unrolled(s.dim, s.k, s.kind) ? DOGIP_VARIANT_UNROLLED : DOGIP_VARIANT_LOOPED;
   DOGIP_CHECK(variant == DOGIP_VARIANT_LOOPED || has_unrolled(s.dim, s.k, s.kind), DOGIP_E_RANGE,
               "no unrolled kernel for this (dim, k, kind)");
+  DOGIP_CHECK(variant != DOGIP_VARIANT_MFMA || has_mfma(s.dim, s.k, s.kind), DOGIP_E_RANGE,
+              "the matrix-core apply covers the 3D P3 elliptic operator only");
+  DOGIP_CHECK(variant != DOGIP_VARIANT_MFMA || !op->global_w, DOGIP_E_RANGE,
+              "the matrix-core apply needs the element-wise D");
   op->variant = variant;
   // tile size: requested (default 4 waves), halved until the LDS arrays fit in 64 KB
+  // (FP64 tiles hold 16 bytes per dof; the matrix-core FP32 kernel 12 bytes per dof and its
+  // 19 KB of B^ operand tables)
+  auto lds = [&](int64_t slots) {
+    return std::max<int64_t>(16 * slots, variant == DOGIP_VARIANT_MFMA ? mfma_lds_tables() + 12 * slots : 0);
+  };
   int te = 64 * (tile_waves ? tile_waves : default_tile_waves(s));
   for (;;) {
     op->plan = make_tiles(s, te);
-    if (op->plan.max_tile_dofs * 16 <= 65536 || te == 64) break;
+    if (lds(op->plan.max_tile_dofs) <= 65536 || te == 64) break;
     te /= 2;
   }
-  DOGIP_CHECK(op->plan.max_tile_dofs * 16 <= 65536, DOGIP_E_RANGE, "tile dofs exceed the LDS budget");
+  DOGIP_CHECK(lds(op->plan.max_tile_dofs) <= 65536, DOGIP_E_RANGE, "tile dofs exceed the LDS budget");
   if (op->global_w) op->gplan = make_global_plan(s, op->plan);
   const TilePlan& p = op->plan;
   op->nch64 = d_chunks(s.wt, s.nsym, 2);
-  op->nch32 = d_chunks(s.wt, s.nsym, 4);
+  // the matrix-core variant keeps its FP32 copy of D in its own layout (nch32 < 0)
+  op->nch32 = variant == DOGIP_VARIANT_MFMA ? -1 : d_chunks(s.wt, s.nsym, 4);
   if (op->global_w) {
     const GlobalPlan& g = op->gplan;
     upload(op->gw_rec, g.mask);
@@ -177,7 +193,7 @@ std::unique_ptr<Op> make_op(std::shared_ptr<const Space> sp, int coef_kind, cons
     op->d64.alloc(ngrp * op->nch64 * 64 * 2 * sizeof(double));
     HIPCHK(hipMemset(op->d64.p, 0, op->d64.bytes));
     if (op->has32) {
-      op->d32.alloc(ngrp * op->nch32 * 64 * 4 * sizeof(float));
+      op->d32.alloc(ngrp * size_t(op->nch32 < 0 ? mfma_d32_per_wave() : op->nch32 * 64 * 4) * sizeof(float));
       HIPCHK(hipMemset(op->d32.p, 0, op->d32.bytes));
     }
   }

@@ -6,7 +6,8 @@ Run (each a process of its own; counters in separate passes):
     rocprofv3 --pmc FETCH_SIZE --output-format csv -d F -o run -- python3 -m paper_1710_09913_amd.profile > F.log
     rocprofv3 --pmc WRITE_SIZE --output-format csv -d W -o run -- python3 -m paper_1710_09913_amd.profile > W.log
 
-The run applies the operator --reps times in FP64, then --reps times in FP32 (default:
+The run applies the operator --reps times in FP64, then --reps times in FP32 (--variant 3:
+the FP32 applies on the matrix cores; default:
 3D 64^3 x 6 Kuhn tets, P3 elliptic, uniform coefficient: neither traffic nor time
 depends on its values), then makes --copies device-to-device copies of a 1 GiB
 buffer.  The copies' known byte counts calibrate the counters: FETCH_SIZE and
@@ -40,6 +41,7 @@ def run(argv=None):
     ap.add_argument("--kind", default="se")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--copies", type=int, default=3)
+    ap.add_argument("--variant", type=int, default=0, help="element-kernel variant (3: matrix-core FP32 apply)")
     a = ap.parse_args(argv)
 
     import torch
@@ -50,7 +52,7 @@ def run(argv=None):
 
     torch.cuda.set_device(0)
     sp = Space(Mesh.unit(a.dim, a.n), a.k, a.kind, "dirichlet" if a.kind == "se" else "none")
-    op = Operator(sp, torch.ones(sp.ncells, dtype=torch.float64), "scalar", fp32=True)
+    op = Operator(sp, torch.ones(sp.ncells, dtype=torch.float64), "scalar", fp32=True, variant=a.variant)
     u = torch.from_numpy(random_vector(sp.ndofs, 0)).cuda()
     y = torch.empty_like(u)
     for prec in ("f64", "f32"):
@@ -168,7 +170,8 @@ def summarize(argv=None):
                 continue
             if i + 1 >= len(seq) or "k_apply_finish" not in seq[i + 1][0]:
                 raise ValueError("unexpected dispatch order")
-            pairs.append(("float" in n0.split(",")[3] if n0.count(",") >= 3 else False, v0, seq[i + 1][1]))
+            is32 = "k_apply_mfma" in n0 or ("float" in n0.split(",")[3] if n0.count(",") >= 3 else False)
+            pairs.append((is32, v0, seq[i + 1][1]))
             i += 2
         return pairs
 

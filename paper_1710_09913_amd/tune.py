@@ -74,6 +74,8 @@ def tune(dim, k, kind, prec="f64", cells_target=400_000, reps=20, tile_waves=TIL
     has_unrolled = (dim == 2 and k <= 5) or (dim == 3 and (k <= 3 if kind == "se" else k <= 2))
     if variants is None:
         variants = (capi.DOGIP_VARIANT_UNROLLED, capi.DOGIP_VARIANT_LOOPED) if has_unrolled else (capi.DOGIP_VARIANT_LOOPED,)
+        if dim == 3 and k == 3 and kind == "se" and prec == "f32":  # the matrix-core FP32 apply
+            variants = variants + (capi.DOGIP_VARIANT_MFMA,)
     rows = []
     for var in variants:
         for tw in tile_waves:
