@@ -113,6 +113,13 @@ std::unique_ptr<Batch> make_batch(const std::vector<std::shared_ptr<Op>>& ops, h
   upload_vec(b->shared, shared);
   upload_vec(b->rowptr, rowptr);
   upload_vec(b->slots, slots);
+  {
+    std::vector<uint32_t> pair, more_off, more;
+    pair_lists(rowptr, slots, pair, more_off, more);
+    upload_vec(b->pair, pair);
+    upload_vec(b->more_off, more_off);
+    upload_vec(b->more, more);
+  }
   upload_vec(b->bnd, bnd);
   upload_vec(b->bnd_off, bnd_off);
   upload_vec(b->sh_off, sh_off);
@@ -158,8 +165,8 @@ static BatchLaunch launch_args(Batch& b, const double* u, double* y, int prec) {
 static void run_apply(Batch& b, const BatchLaunch& bl, bool energy, hipStream_t st) {
   const bool f64 = bl.prec == DOGIP_F64;
   launch_batch_apply(b.dim, b.kind, bl, f64 ? b.grid64 : b.grid32, f64 ? b.lds64 : b.lds32, energy, st);
-  launch_apply_finish(b.stage.as<double>(), b.rowptr.as<uint32_t>(), b.slots.as<uint32_t>(), b.shared.as<int32_t>(),
-                      b.nshared, b.bnd.as<int32_t>(), b.nbnd, bl.u, bl.y, nullptr, st);
+  launch_apply_finish(b.stage.as<double>(), b.pair.as<uint32_t>(), b.more_off.as<uint32_t>(), b.more.as<uint32_t>(),
+                      b.shared.as<int32_t>(), b.nshared, b.bnd.as<int32_t>(), b.nbnd, bl.u, bl.y, nullptr, st);
   HIPCHK(hipGetLastError());
 }
 

@@ -82,6 +82,7 @@ struct Batch {
   size_t lds64 = 0, lds32 = 0;
   unsigned grid64 = 0, grid32 = 0;
   DevBuf desc, items, counter, voff, stage, tile_base, shared, rowptr, slots, bnd, bnd_off, invd, sh_off;
+  DevBuf pair, more_off, more;  // the shared-dof lists as pair lists (apply's finish kernel)
   DevBuf invd32;  // FP32 copy of invd (all operators with DOGIP_OP_FP32)
   std::vector<uint64_t> items_host;  // work items, largest first
   std::unique_ptr<BatchWork> w;

@@ -106,6 +106,9 @@ struct TilePlan {
   std::vector<int64_t> stage_off;   // [ntiles+1] staging offsets of each tile's shared entries
   std::vector<uint32_t> sh_rowptr;  // [nshared+1] staging slots of shared dof i: sh_slots[rowptr[i]..]
   std::vector<uint32_t> sh_slots;   // grouped by shared dof, ascending tile order
+  // the same lists for the finish kernel (pair_lists): the first two slots of each shared
+  // dof side by side, the others apart
+  std::vector<uint32_t> sh_pair, sh_more_off, sh_more;
   int nlc = 0;                      // 16-byte chunks of local indices per cell
   int64_t max_tile_dofs = 0;
 };
@@ -145,7 +148,7 @@ struct Op {
   int64_t nch64 = 0, nch32 = 0;
   DevBuf d64, d32, lidx, tile_off, tile_dofs, shared, perm, cells, xyz, what, bhat64, bhat32, invdiag;
   DevBuf invdiag32;  // FP32 copy of the inverse diagonal (operators with DOGIP_OP_FP32)
-  DevBuf stage_off, sh_rowptr, sh_slots, stage, bnd;  // second pass: shared dofs, Dirichlet rows
+  DevBuf stage_off, sh_pair, sh_more_off, sh_more, stage, bnd;  // second pass: shared dofs, Dirichlet rows
   bool global_w = false;                               // global projection form
   GlobalPlan gplan;
   int nq = 0;                                          // quadrature-point operator: points per cell
@@ -375,9 +378,14 @@ void launch_build_dg(const BuildDLaunch& a, const int64_t* inc_ptr, const int64_
 void launch_export_d(const double* d64, const int32_t* perm, double* out, int64_t nel, int64_t nch64, int wt,
                      int nsym, hipStream_t st);
 void launch_zero_indexed(double* y, const int32_t* idx, int64_t n, hipStream_t st);
-// Second pass of an apply: y[shared[i]] = sum of stage[slots[rowptr[i] .. rowptr[i+1])]
-// (fixed order) and y[b] = u[b] on Dirichlet dofs; with benergy, the sums of u_b^2
-// per block of the Dirichlet range (finish_energy_count of them).
+// Second pass of an apply: y[shared[i]] = the sum of shared dof i's staged partials in
+// ascending tile order (fixed order) and y[b] = u[b] on Dirichlet dofs; with benergy, the
+// sums of u_b^2 per block of the Dirichlet range (finish_energy_count of them).
+// The partials' slots come as pair lists: pair[2i], pair[2i+1] are the first two slots
+// (every shared dof has at least two); bit 31 of pair[2i+1] set means more follow, at
+// more[more_off[i] .. more_off[i+1]).  One dependent load fewer than a CSR walk.
+void pair_lists(const std::vector<uint32_t>& rowptr, const std::vector<uint32_t>& slots, std::vector<uint32_t>& pair,
+                std::vector<uint32_t>& more_off, std::vector<uint32_t>& more);
 constexpr int FINISH_THREADS = 256;
 inline int64_t finish_blocks(int64_t nshared, int64_t nbnd) {
   return std::max<int64_t>(1, (nshared + nbnd + FINISH_THREADS - 1) / FINISH_THREADS);
@@ -391,17 +399,17 @@ inline int64_t finish_energy_count(int64_t nshared, int64_t nbnd) {
 inline int64_t op_finish_energy_count(const Op& op) {
   return finish_energy_count(int64_t(op.plan.shared.size()), int64_t(op.space->boundary.size()));
 }
-void launch_apply_finish(const double* stage, const uint32_t* rowptr, const uint32_t* slots, const int32_t* shared,
-                         int64_t nshared, const int32_t* bnd, int64_t nbnd, const double* u, double* y,
-                         double* benergy, hipStream_t st);
+void launch_apply_finish(const double* stage, const uint32_t* pair, const uint32_t* more_off, const uint32_t* more,
+                         const int32_t* shared, int64_t nshared, const int32_t* bnd, int64_t nbnd, const double* u,
+                         double* y, double* benergy, hipStream_t st);
 void launch_invert(const double* d, double* inv, int64_t n, hipStream_t st);
 void launch_to_f32(const double* x, float* y, int64_t n, hipStream_t st);
 // FP32 apply on FP32 vectors with the energy partials (the mixed CG iteration):
 // y32 = A32 u32, energy as op_apply.
 void op_apply_v32(Op& op, const float* u, float* y, hipStream_t st, double* energy_partials);
 bool op_has_v32(const Op& op);
-void launch_apply_finish32(const double* stage, const uint32_t* rowptr, const uint32_t* slots, const int32_t* shared,
-                           int64_t nshared, const int32_t* bnd, int64_t nbnd, const float* u, float* y,
-                           double* benergy, hipStream_t st);
+void launch_apply_finish32(const double* stage, const uint32_t* pair, const uint32_t* more_off, const uint32_t* more,
+                           const int32_t* shared, int64_t nshared, const int32_t* bnd, int64_t nbnd, const float* u,
+                           float* y, double* benergy, hipStream_t st);
 
 }  // namespace dogip

@@ -107,9 +107,25 @@ __global__ __launch_bounds__(256) void k_zero_indexed(double* __restrict__ y, co
 // Dirichlet identity row y[b] = u[b]; with benergy, every block from e0 on writes its
 // share of sum u_b^2 (the identity rows' part of u . A u) to benergy[blockIdx.x - e0].
 // One entry per thread: the grid covers nshared + nbnd exactly.
+// The partial sums of shared dof i, added in ascending tile order from zero (pair lists:
+// the first two slots, then any others).
+__device__ __forceinline__ double shared_sum(const double* __restrict__ stage, const uint32_t* __restrict__ pair,
+                                             const uint32_t* __restrict__ more_off, const uint32_t* __restrict__ more,
+                                             int64_t i) {
+  const vec_t<uint32_t, 2> pr = reinterpret_cast<const vec_t<uint32_t, 2>*>(pair)[i];
+  const double p0 = stage[pr[0]], p1 = stage[pr[1] & 0x7fffffffu];
+  double s = 0.0;
+  s += p0;
+  s += p1;
+  if (pr[1] >> 31)
+    for (uint32_t j = more_off[i]; j < more_off[i + 1]; ++j) s += stage[more[j]];
+  return s;
+}
+
 __global__ __launch_bounds__(FINISH_THREADS) void k_apply_finish(const double* __restrict__ stage,
-                                                      const uint32_t* __restrict__ rowptr,
-                                                      const uint32_t* __restrict__ slots,
+                                                      const uint32_t* __restrict__ pair,
+                                                      const uint32_t* __restrict__ more_off,
+                                                      const uint32_t* __restrict__ more,
                                                       const int32_t* __restrict__ shared, int64_t nshared,
                                                       const int32_t* __restrict__ bnd, int64_t nbnd,
                                                       const double* __restrict__ u, double* __restrict__ y,
@@ -118,10 +134,7 @@ __global__ __launch_bounds__(FINISH_THREADS) void k_apply_finish(const double* _
   const int64_t i = int64_t(blockIdx.x) * FINISH_THREADS + threadIdx.x;
   if (i < nshared + nbnd) {
     if (i < nshared) {
-      const uint32_t a = rowptr[i], b = rowptr[i + 1];
-      double s = 0.0;
-      for (uint32_t j = a; j < b; ++j) s += stage[slots[j]];
-      y[shared[i]] = s;
+      y[shared[i]] = shared_sum(stage, pair, more_off, more, i);
     } else {
       const int32_t d = bnd[i - nshared];
       const double ub = u[d];
@@ -138,8 +151,9 @@ __global__ __launch_bounds__(FINISH_THREADS) void k_apply_finish(const double* _
 
 // The second pass on FP32 vectors (mixed CG): partial sums added in FP64, stored in FP32.
 __global__ __launch_bounds__(FINISH_THREADS) void k_apply_finish32(const double* __restrict__ stage,
-                                                        const uint32_t* __restrict__ rowptr,
-                                                        const uint32_t* __restrict__ slots,
+                                                        const uint32_t* __restrict__ pair,
+                                                        const uint32_t* __restrict__ more_off,
+                                                        const uint32_t* __restrict__ more,
                                                         const int32_t* __restrict__ shared, int64_t nshared,
                                                         const int32_t* __restrict__ bnd, int64_t nbnd,
                                                         const float* __restrict__ u, float* __restrict__ y,
@@ -148,10 +162,7 @@ __global__ __launch_bounds__(FINISH_THREADS) void k_apply_finish32(const double*
   const int64_t i = int64_t(blockIdx.x) * FINISH_THREADS + threadIdx.x;
   if (i < nshared + nbnd) {
     if (i < nshared) {
-      const uint32_t a = rowptr[i], b = rowptr[i + 1];
-      double s = 0.0;
-      for (uint32_t j = a; j < b; ++j) s += stage[slots[j]];
-      y[shared[i]] = float(s);
+      y[shared[i]] = float(shared_sum(stage, pair, more_off, more, i));
     } else {
       const int32_t d = bnd[i - nshared];
       const float ub = u[d];
@@ -420,22 +431,22 @@ void launch_zero_indexed(double* y, const int32_t* idx, int64_t n, hipStream_t s
   hipLaunchKernelGGL(dev::k_zero_indexed, dim3(grid_for(n, 256)), dim3(256), 0, st, y, idx, n);
 }
 
-void launch_apply_finish(const double* stage, const uint32_t* rowptr, const uint32_t* slots, const int32_t* shared,
-                         int64_t nshared, const int32_t* bnd, int64_t nbnd, const double* u, double* y,
-                         double* benergy, hipStream_t st) {
+void launch_apply_finish(const double* stage, const uint32_t* pair, const uint32_t* more_off, const uint32_t* more,
+                         const int32_t* shared, int64_t nshared, const int32_t* bnd, int64_t nbnd, const double* u,
+                         double* y, double* benergy, hipStream_t st) {
   if (nshared + nbnd <= 0 && !benergy) return;
   const unsigned grid = unsigned(finish_blocks(nshared, nbnd));
-  hipLaunchKernelGGL(dev::k_apply_finish, dim3(grid), dim3(FINISH_THREADS), 0, st, stage, rowptr, slots, shared,
+  hipLaunchKernelGGL(dev::k_apply_finish, dim3(grid), dim3(FINISH_THREADS), 0, st, stage, pair, more_off, more, shared,
                      nshared, bnd, nbnd, u, y, benergy, finish_first_energy_block(nshared, nbnd));
 }
 
-void launch_apply_finish32(const double* stage, const uint32_t* rowptr, const uint32_t* slots, const int32_t* shared,
-                           int64_t nshared, const int32_t* bnd, int64_t nbnd, const float* u, float* y,
-                           double* benergy, hipStream_t st) {
+void launch_apply_finish32(const double* stage, const uint32_t* pair, const uint32_t* more_off, const uint32_t* more,
+                           const int32_t* shared, int64_t nshared, const int32_t* bnd, int64_t nbnd, const float* u,
+                           float* y, double* benergy, hipStream_t st) {
   if (nshared + nbnd <= 0 && !benergy) return;
   const unsigned grid = unsigned(finish_blocks(nshared, nbnd));
-  hipLaunchKernelGGL(dev::k_apply_finish32, dim3(grid), dim3(FINISH_THREADS), 0, st, stage, rowptr, slots, shared,
-                     nshared, bnd, nbnd, u, y, benergy, finish_first_energy_block(nshared, nbnd));
+  hipLaunchKernelGGL(dev::k_apply_finish32, dim3(grid), dim3(FINISH_THREADS), 0, st, stage, pair, more_off, more,
+                     shared, nshared, bnd, nbnd, u, y, benergy, finish_first_energy_block(nshared, nbnd));
 }
 
 void launch_to_f32(const double* x, float* y, int64_t n, hipStream_t st) {

@@ -202,8 +202,9 @@ std::unique_ptr<Op> make_op(std::shared_ptr<const Space> sp, int coef_kind, cons
   upload(op->tile_dofs, p.tile_dofs);
   upload(op->shared, p.shared);
   upload(op->stage_off, p.stage_off);
-  upload(op->sh_rowptr, p.sh_rowptr);
-  upload(op->sh_slots, p.sh_slots);
+  upload(op->sh_pair, p.sh_pair);
+  upload(op->sh_more_off, p.sh_more_off);
+  upload(op->sh_more, p.sh_more);
   upload(op->bnd, s.boundary);
   op->stage.alloc(size_t(std::max<int64_t>(p.stage_off.back(), 1)) * sizeof(double));
   upload(op->perm, p.perm);
@@ -251,8 +252,9 @@ std::unique_ptr<Op> make_op_qp(std::shared_ptr<const Space> sp, int n, const dou
   upload(op->tile_dofs, p.tile_dofs);
   upload(op->shared, p.shared);
   upload(op->stage_off, p.stage_off);
-  upload(op->sh_rowptr, p.sh_rowptr);
-  upload(op->sh_slots, p.sh_slots);
+  upload(op->sh_pair, p.sh_pair);
+  upload(op->sh_more_off, p.sh_more_off);
+  upload(op->sh_more, p.sh_more);
   upload(op->bnd, s.boundary);
   op->stage.alloc(size_t(std::max<int64_t>(p.stage_off.back(), 1)) * sizeof(double));
   upload(op->perm, p.perm);
@@ -440,9 +442,9 @@ static void apply_impl(Op& op, const double* u, double* y, int prec, hipStream_t
                                 : launch_apply(s.dim, s.k, s.kind, prec, op.variant, a, st);
   DOGIP_CHECK(ok, DOGIP_E_RANGE, "no apply kernel for this (dim, k, kind, variant)");
   if (timed) HIPCHK(hipEventRecord(ev[1], st));
-  launch_apply_finish(stage, op.sh_rowptr.as<uint32_t>(), op.sh_slots.as<uint32_t>(), op.shared.as<int32_t>(),
-                      int64_t(op.plan.shared.size()), op.bnd.as<int32_t>(), int64_t(s.boundary.size()), u, y,
-                      energy ? energy + op.plan.ntiles : nullptr, st);
+  launch_apply_finish(stage, op.sh_pair.as<uint32_t>(), op.sh_more_off.as<uint32_t>(), op.sh_more.as<uint32_t>(),
+                      op.shared.as<int32_t>(), int64_t(op.plan.shared.size()), op.bnd.as<int32_t>(),
+                      int64_t(s.boundary.size()), u, y, energy ? energy + op.plan.ntiles : nullptr, st);
   HIPCHK(hipGetLastError());
   if (timed) HIPCHK(hipEventRecord(ev[2], st));
 }
@@ -469,9 +471,9 @@ void op_apply_v32(Op& op, const float* u, float* y, hipStream_t st, double* ener
   a.energy = energy;
   DOGIP_CHECK(launch_apply(s.dim, s.k, s.kind, DOGIP_F32, op.variant, a, st), DOGIP_E_RANGE,
               "no apply kernel for this (dim, k, kind, variant)");
-  launch_apply_finish32(op.stage.as<double>(), op.sh_rowptr.as<uint32_t>(), op.sh_slots.as<uint32_t>(),
-                        op.shared.as<int32_t>(), int64_t(op.plan.shared.size()), op.bnd.as<int32_t>(),
-                        int64_t(s.boundary.size()), u, y, energy + op.plan.ntiles, st);
+  launch_apply_finish32(op.stage.as<double>(), op.sh_pair.as<uint32_t>(), op.sh_more_off.as<uint32_t>(),
+                        op.sh_more.as<uint32_t>(), op.shared.as<int32_t>(), int64_t(op.plan.shared.size()),
+                        op.bnd.as<int32_t>(), int64_t(s.boundary.size()), u, y, energy + op.plan.ntiles, st);
   HIPCHK(hipGetLastError());
 }
 
@@ -481,9 +483,9 @@ void op_diag(Op& op, double* diag, hipStream_t st) {
   // the tiles' partial sums of shared dofs go through the staging buffer and are added
   // by the finish kernel in a fixed order (no Dirichlet rows there: the tiles write those)
   auto finish = [&] {
-    launch_apply_finish(op.stage.as<double>(), op.sh_rowptr.as<uint32_t>(), op.sh_slots.as<uint32_t>(),
-                        op.shared.as<int32_t>(), int64_t(op.plan.shared.size()), nullptr, 0, nullptr, diag, nullptr,
-                        st);
+    launch_apply_finish(op.stage.as<double>(), op.sh_pair.as<uint32_t>(), op.sh_more_off.as<uint32_t>(),
+                        op.sh_more.as<uint32_t>(), op.shared.as<int32_t>(), int64_t(op.plan.shared.size()), nullptr,
+                        0, nullptr, diag, nullptr, st);
     HIPCHK(hipGetLastError());
   };
   if (op.nq > 0) {
@@ -562,7 +564,7 @@ dogip_op_info op_info(const Op& op) {
   i.bytes_d64 = int64_t(op.d64.bytes + op.dg64.bytes + op.qs64.bytes + op.qk64.bytes);
   i.bytes_d32 = int64_t(op.d32.bytes + op.dg32.bytes + op.qs32.bytes + op.qk32.bytes);
   i.bytes_index = int64_t(op.lidx.bytes + op.tile_off.bytes + op.tile_dofs.bytes + op.shared.bytes +
-                          op.stage_off.bytes + op.sh_rowptr.bytes + op.sh_slots.bytes + op.stage.bytes +
+                          op.stage_off.bytes + op.sh_pair.bytes + op.sh_more_off.bytes + op.sh_more.bytes + op.stage.bytes +
                           op.gw_rec.bytes + op.gw_off.bytes + op.gw_inc_ptr.bytes + op.gw_inc.bytes);
   i.ndofs_w = op.global_w ? op.gplan.nw : 0;
   i.nq = op.nq;

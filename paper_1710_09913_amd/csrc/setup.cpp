@@ -610,7 +610,25 @@ TilePlan make_tiles(const Space& s, int te) {
       const int32_t si = sh_index[v & TD_MASK];
       p.sh_slots[fill[si]++] = uint32_t(p.stage_off[t] + (j - p.tile_off[t]));
     }
+  pair_lists(p.sh_rowptr, p.sh_slots, p.sh_pair, p.sh_more_off, p.sh_more);
   return p;
+}
+
+void pair_lists(const std::vector<uint32_t>& rowptr, const std::vector<uint32_t>& slots, std::vector<uint32_t>& pair,
+                std::vector<uint32_t>& more_off, std::vector<uint32_t>& more) {
+  const size_t n = rowptr.empty() ? 0 : rowptr.size() - 1;
+  pair.assign(2 * n, 0);
+  more_off.assign(n + 1, 0);
+  more.clear();
+  for (size_t i = 0; i < n; ++i) {
+    const uint32_t a = rowptr[i], b = rowptr[i + 1];
+    DOGIP_CHECK(b >= a + 2, DOGIP_E_INVALID, "a shared dof with fewer than two partial sums");
+    DOGIP_CHECK(slots[a] < (1u << 31) && slots[a + 1] < (1u << 31), DOGIP_E_RANGE, "too many staged partial sums");
+    pair[2 * i] = slots[a];
+    pair[2 * i + 1] = slots[a + 1] | (b > a + 2 ? (1u << 31) : 0u);
+    for (uint32_t j = a + 2; j < b; ++j) more.push_back(slots[j]);
+    more_off[i + 1] = uint32_t(more.size());
+  }
 }
 
 // ---------------------------------------------------------------- global projection form
