@@ -5,6 +5,10 @@ Run (each a process of its own; counters in separate passes):
     rocprofv3 --kernel-trace --stats --output-format csv -d T -o run -- python3 -m paper_1710_09913_amd.profile > T.log
     rocprofv3 --pmc FETCH_SIZE --output-format csv -d F -o run -- python3 -m paper_1710_09913_amd.profile > F.log
     rocprofv3 --pmc WRITE_SIZE --output-format csv -d W -o run -- python3 -m paper_1710_09913_amd.profile > W.log
+    rocprofv3 --pmc TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum TCC_EA0_RDREQ_sum \
+        --output-format csv -d R -o run -- python3 -m paper_1710_09913_amd.profile > R.log
+    rocprofv3 --pmc TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum --output-format csv -d Q -o run \
+        -- python3 -m paper_1710_09913_amd.profile > Q.log
 
 The run applies the operator --reps times in FP64, then --reps times in FP32 (--variant 3:
 the FP32 applies on the matrix cores; default:
@@ -14,7 +18,7 @@ buffer.  The copies' known byte counts calibrate the counters: FETCH_SIZE and
 WRITE_SIZE (KiB per dispatch) are scaled by bytes moved / bytes counted.
 
     python3 -m paper_1710_09913_amd.profile summarize --trace T --fetch F --write W \
-        --log F.log --name k_apply_3d64_p3_se --out profiles
+        --log F.log --name k_apply_3d64_p3_se --out profiles [--rdreq R --wrreq Q]
 
 writes <out>/<name>.md (durations and calibrated traffic per kernel) and
 <out>/traffic_<name>.json (bytes per apply, with the source hash of the build
@@ -133,6 +137,8 @@ def summarize(argv=None):
     ap.add_argument("--name", required=True)
     ap.add_argument("--out", default="profiles")
     ap.add_argument("--command", default="", help="command line recorded in the summary")
+    ap.add_argument("--rdreq", help="run with TCC_EA0_RDREQ_32B/_64B/_128B/RDREQ (_sum): read bytes by request size")
+    ap.add_argument("--wrreq", help="run with TCC_EA0_WRREQ/_64B (_sum): write bytes by request size")
     a = ap.parse_args(argv)
     stats = _csv(_find(a.trace, "kernel_stats.csv"))
     if not (a.fetch and a.write and a.log):
@@ -189,9 +195,63 @@ def summarize(argv=None):
         res[prec] = {"tile_read": tile_r, "tile_write": tile_w, "finish_read": fin_r, "finish_write": fin_w,
                      "bytes_per_apply": tile_r + tile_w + fin_r + fin_w,
                      "alg_bytes_per_apply": info["alg_bytes_" + prec]}
+    # cross-check of the single copy-calibrated factor: HBM bytes counted request by request
+    # (32, 64 and 128-byte reads; 32 and 64-byte writes), for the copy and for each apply kernel
+    reqsize = {}
+    if a.rdreq and a.wrreq:
+        rrows = _csv(_find(a.rdreq, "counter_collection.csv"))
+        wrows = _csv(_find(a.wrreq, "counter_collection.csv"))
+
+        def by_dispatch(rows):
+            d = {}
+            for r in rows:
+                k = (int(r["Dispatch_Id"]), r["Kernel_Name"])
+                d.setdefault(k, {})[r["Counter_Name"]] = float(r["Counter_Value"])
+            return [(i, n, c) for (i, n), c in sorted(d.items())]
+
+        def rbytes(c):
+            n32, n64, n128 = (c.get(f"TCC_EA0_RDREQ_{w}B_sum", 0.0) for w in (32, 64, 128))
+            return 32 * n32 + 64 * n64 + 128 * n128, c.get("TCC_EA0_RDREQ_sum", 0.0) - (n32 + n64 + n128)
+
+        def wbytes(c):
+            n, n64 = c.get("TCC_EA0_WRREQ_sum", 0.0), c.get("TCC_EA0_WRREQ_64B_sum", 0.0)
+            return 32 * (n - n64) + 64 * n64
+
+        rd, wr = by_dispatch(rrows), by_dispatch(wrows)
+        cr = [rbytes(c)[0] for _, n, c in rd if "copyBuffer" in n and rbytes(c)[0] > copy_read / 8]
+        cw = [wbytes(c) for _, n, c in wr if "copyBuffer" in n and wbytes(c) > copy_read / 8]
+        seq_r = [(n, rbytes(c)) for _, n, c in rd if "k_apply" in n]
+        seq_w = [(n, wbytes(c)) for _, n, c in wr if "k_apply" in n]
+
+        def pairs_of(seq):
+            out, i = [], 0
+            while i < len(seq):
+                n0 = seq[i][0]
+                if "k_apply_finish" in n0 or i + 1 >= len(seq):
+                    i += 1
+                    continue
+                is32 = "k_apply_mfma" in n0 or ("float" in n0.split(",")[3] if n0.count(",") >= 3 else False)
+                out.append((is32, seq[i][1], seq[i + 1][1]))
+                i += 2
+            return out
+
+        pr, pw = pairs_of(seq_r), pairs_of(seq_w)
+        for prec, want32 in (("f64", False), ("f32", True)):
+            r_ = [(t, f) for is32, t, f in pr if is32 == want32]
+            w_ = [(t, f) for is32, t, f in pw if is32 == want32]
+            if not r_ or not w_:
+                continue
+            mean = lambda xs: sum(xs) / len(xs)  # noqa: E731
+            reqsize[prec] = {"tile_read": mean([t[0] for t, _ in r_]), "finish_read": mean([f[0] for _, f in r_]),
+                             "tile_write": mean([t for t, _ in w_]), "finish_write": mean([f for _, f in w_]),
+                             "unsized_read_requests": mean([t[1] + f[1] for t, f in r_])}
+            reqsize[prec]["bytes_per_apply"] = sum(reqsize[prec][k] for k in
+                                                   ("tile_read", "finish_read", "tile_write", "finish_write"))
+        reqsize["copy_read_ratio"] = (sum(cr) / len(cr)) / copy_read if cr else None
+        reqsize["copy_write_ratio"] = (sum(cw) / len(cw)) / copy_read if cw else None
     os.makedirs(a.out, exist_ok=True)
     doc = {"name": a.name, "source_hash": info["source_hash"], "apply_hash": info.get("apply_hash"), "ndofs": info["ndofs"], "ncells": info["ncells"],
-           "fetch_scale": fscale, "write_scale": wscale, "traffic": res}
+           "fetch_scale": fscale, "write_scale": wscale, "traffic": res, "by_request_size": reqsize}
     with open(os.path.join(a.out, f"traffic_{a.name}.json"), "w") as fh:
         json.dump(doc, fh, indent=1)
     lines = [f"# {a.name}: rocprofv3 kernel durations and HBM traffic", ""]
@@ -211,6 +271,21 @@ def summarize(argv=None):
                      f"{r['finish_read'] / 1e6:.1f} | {r['finish_write'] / 1e6:.1f} | "
                      f"{r['bytes_per_apply'] / 1e6:.1f} | {r['alg_bytes_per_apply'] / 1e6:.1f} | "
                      f"{r['bytes_per_apply'] / r['alg_bytes_per_apply']:.3f} |")
+    if reqsize:
+        lines += ["", "## Cross-check: bytes by request size (--pmc TCC_EA0_RDREQ_32B/64B/128B/RDREQ, then "
+                  "TCC_EA0_WRREQ/WRREQ_64B)", "",
+                  f"The same 1 GiB copy counts {reqsize['copy_read_ratio']:.4f} of its read bytes and "
+                  f"{reqsize['copy_write_ratio']:.4f} of its written bytes this way (no factor applied).", "",
+                  "| apply | tile read MB | tile write MB | finish read MB | finish write MB | total MB | "
+                  "vs FETCH/WRITE scaled | unsized read requests |", "|---|---|---|---|---|---|---|---|"]
+        for prec, r in reqsize.items():
+            if not isinstance(r, dict):
+                continue
+            lines.append(f"| {prec} | {r['tile_read'] / 1e6:.1f} | {r['tile_write'] / 1e6:.1f} | "
+                         f"{r['finish_read'] / 1e6:.1f} | {r['finish_write'] / 1e6:.1f} | "
+                         f"{r['bytes_per_apply'] / 1e6:.1f} | "
+                         f"{r['bytes_per_apply'] / res[prec]['bytes_per_apply']:.3f} | "
+                         f"{r['unsized_read_requests']:.0f} |")
     with open(os.path.join(a.out, f"{a.name}.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print(json.dumps(doc))
