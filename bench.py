@@ -18,7 +18,8 @@ The same line carries:
     its difference from the FP64 solution;
   * p2: the same operator at P2 (apply fractions, Jacobi and multigrid solves);
   * secondary: the batch of 256 uneven 2D problems (batched apply, batched FP64 vs mixed
-    PCG) and the 2D 512^2 P5 anisotropic operator (apply fractions, PCG modes);
+    PCG), the 2D 512^2 P5 anisotropic operator (apply fractions, PCG modes) and the 2D
+    256^2 P3 inverse problem (seconds per adjoint gradient, central-difference check);
   * cpu_baseline: the CPU oracle on a bounded sample at 1 thread and all cores (CSR SpMV
     of the quadrature-assembled matrix, Algorithm 1, Jacobi-PCG), every solve mode's
     error against the oracle's direct solve on that sample, and the oracle's rows of
@@ -900,9 +901,10 @@ def run_p2_block(a):
 
 
 def run_secondary(a):
-    """Compact rows of two more workloads: the batch of 256 uneven 2D problems (batched
-    apply, batched FP64 vs mixed PCG to 1e-8) and the 2D 512^2 P5 anisotropic elliptic
-    operator (apply fractions, FP64 vs mixed vs multigrid PCG to 1e-8)."""
+    """Compact rows of three more workloads: the batch of 256 uneven 2D problems (batched
+    apply, batched FP64 vs mixed PCG to 1e-8), the 2D 512^2 P5 anisotropic elliptic
+    operator (apply fractions, FP64 vs mixed vs multigrid PCG to 1e-8) and the 2D 256^2 P3
+    inverse problem (gradient_row)."""
     import numpy as np
     import torch
 
@@ -976,7 +978,64 @@ def run_secondary(a):
             c2["pcg_" + mode]["setup_inclusive_seconds"] = round(first, 4)
     log(f"[secondary c2 p5] {c2}")
     out["2d512_p5_aniso_se"] = c2
+    del op
+    torch.cuda.empty_cache()
+    out["inverse_2d256_p3_gradient"] = gradient_row(a)
     return out
+
+
+def gradient_row(a):
+    """The inverse problem (2D 256^2 P3, theta ~ N(0, 0.5^2), u_obs from a hidden theta* plus
+    1% noise): seconds per gradient dJ/dtheta (forward PCG to 1e-10, adjoint PCG, contraction
+    -lambda_T^T A_T u_T) with Jacobi (FP64, mixed) and multigrid preconditioning, the
+    gradients' difference from the FP64 one, and central differences (h = 1e-6) on two
+    random directions."""
+    import numpy as np
+    import torch
+
+    from paper_1710_09913_amd import Mesh, Operator, Space
+    from paper_1710_09913_amd.autograd import solve
+    from workloads import theta_normal
+
+    mesh = Mesh.unit(2, 256)
+    sp = Space(mesh, 3, "se", "dirichlet")
+    op = Operator(sp, torch.zeros(sp.ncells, dtype=torch.float64), "logscalar", fp32=True)
+    b = _rhs_f1(sp, mesh, 3)
+    bnd = torch.from_numpy(sp.boundary().astype(np.int64)).cuda()
+    with torch.no_grad():
+        u_star = solve(torch.from_numpy(theta_normal(sp.ncells, 99)).cuda(), b, op, tol=1e-12)
+        rms = torch.sqrt(torch.mean(u_star ** 2))
+        u_obs = u_star + 0.01 * rms * torch.from_numpy(np.random.default_rng(5).standard_normal(sp.ndofs)).cuda()
+        u_obs[bnd] = 0.0
+    theta0 = torch.from_numpy(theta_normal(sp.ncells, 1)).cuda()
+    row, grads = {"ndofs": sp.ndofs, "ncells": sp.ncells}, {}
+    for mode in ("f64", "mixed", "pmg_mixed"):
+        for rep in range(2):  # the first call allocates (multigrid: builds the hierarchy)
+            th = theta0.clone().requires_grad_(True)
+            torch.cuda.synchronize()
+            t0 = time.time()
+            u = solve(th, b, op, tol=1e-10, mode=mode)
+            J = 0.5 * ((u - u_obs) ** 2).sum()
+            J.backward()
+            torch.cuda.synchronize()
+            dt = time.time() - t0
+        grads[mode] = th.grad.detach()
+        row["gradient_seconds_" + mode] = round(dt, 4)
+    g64 = grads["f64"]
+    row["gradient_rel_diff_vs_f64"] = {m: float(torch.linalg.norm(g - g64) / torch.linalg.norm(g64))
+                                      for m, g in grads.items() if m != "f64"}
+    rng = np.random.default_rng(7)
+    errs = []
+    with torch.no_grad():
+        for _ in range(2):
+            v = torch.from_numpy(rng.standard_normal(sp.ncells)).cuda()
+            jp = 0.5 * ((solve(theta0 + 1e-6 * v, b, op, tol=1e-14) - u_obs) ** 2).sum()
+            jm = 0.5 * ((solve(theta0 - 1e-6 * v, b, op, tol=1e-14) - u_obs) ** 2).sum()
+            gv = torch.dot(g64, v).item()
+            errs.append(abs((jp - jm).item() / 2e-6 - gv) / abs(gv))
+    row["central_difference_rel_err_max"] = max(errs)
+    log(f"[secondary c4] {row}")
+    return row
 
 
 if __name__ == "__main__":

@@ -253,7 +253,7 @@ void dogip_space_destroy(dogip_space s);
 /* Build the operator.  coef: device pointer in the form coef_kind (cells in mesh
  * order), read during the call only.  flags: DOGIP_OP_FP32, DOGIP_OP_GLOBAL_W or
  * both.  tile_waves:
- * cells per tile / 64, 1..8, or 0 for the built-in default (8 for 3D with k >= 3,
+ * cells per tile / 64, 1..8, or 0 for the built-in default (8 for 3D with k >= 2,
  * else 4; halved while a tile's dofs exceed the 64 KB LDS budget).  variant:
  * DOGIP_VARIANT_*.  D is built by the HIP kernels (Theorem 2: m_T |T| w^_i;
  * Theorem 4: w^_i |T| R_T^-1 M_T R_T^-T; or copied for RAW_D).  The call

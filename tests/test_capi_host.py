@@ -101,6 +101,11 @@ def test_error_paths(L):
     # unused vertex
     with pytest.raises(DogipError):
         Mesh(np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0], [5.0, 5.0]]), np.array([[0, 1, 2]]))
+    # empty meshes: no vertices, or vertices but no cell
+    for xyz in (np.zeros((0, 2)), np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])):
+        with pytest.raises(DogipError) as e:
+            Mesh(xyz, np.zeros((0, 3), np.int32))
+        assert e.value.code == capi.DOGIP_E_INVALID and "empty" in str(e.value)
     # null handles and pointers
     assert L.dogip_space_create(None, 1, 0, 0, C.byref(C.c_void_p())) == capi.DOGIP_E_NULL
     assert L.dogip_apply(None, None, None, 0, None) == capi.DOGIP_E_NULL
