@@ -386,12 +386,14 @@ void launch_zero_indexed(double* y, const int32_t* idx, int64_t n, hipStream_t s
 // more[more_off[i] .. more_off[i+1]).  One dependent load fewer than a CSR walk.
 void pair_lists(const std::vector<uint32_t>& rowptr, const std::vector<uint32_t>& slots, std::vector<uint32_t>& pair,
                 std::vector<uint32_t>& more_off, std::vector<uint32_t>& more);
-constexpr int FINISH_THREADS = 256;
+// Each thread of the finish handles FINISH_PER_THREAD entries, FINISH_THREADS apart, so a
+// block covers FINISH_ENTRIES consecutive entries and a thread's loads are independent.
+constexpr int FINISH_THREADS = 256, FINISH_PER_THREAD = 4, FINISH_ENTRIES = FINISH_THREADS * FINISH_PER_THREAD;
 inline int64_t finish_blocks(int64_t nshared, int64_t nbnd) {
-  return std::max<int64_t>(1, (nshared + nbnd + FINISH_THREADS - 1) / FINISH_THREADS);
+  return std::max<int64_t>(1, (nshared + nbnd + FINISH_ENTRIES - 1) / FINISH_ENTRIES);
 }
 inline int64_t finish_first_energy_block(int64_t nshared, int64_t nbnd) {
-  return std::min(nshared / FINISH_THREADS, finish_blocks(nshared, nbnd) - 1);
+  return std::min(nshared / FINISH_ENTRIES, finish_blocks(nshared, nbnd) - 1);
 }
 inline int64_t finish_energy_count(int64_t nshared, int64_t nbnd) {
   return finish_blocks(nshared, nbnd) - finish_first_energy_block(nshared, nbnd);

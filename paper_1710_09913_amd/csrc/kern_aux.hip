@@ -102,26 +102,64 @@ __global__ __launch_bounds__(256) void k_zero_indexed(double* __restrict__ y, co
     y[idx[i]] = 0.0;
 }
 
+// The finish entries of one thread (FINISH_PER_THREAD of them, FINISH_THREADS apart from
+// i0): every index and partial sum is requested before any is used, so the loads of the
+// entries are in flight together.  Shared dof i: its partial sums added in ascending tile
+// order from zero (pair lists: the first two slots, then any others).  Dirichlet entry:
+// y[b] = u[b] and u_b^2 into eb.
+template <typename V>
+__device__ __forceinline__ void finish_entries(int64_t i0, const double* __restrict__ stage,
+                                               const uint32_t* __restrict__ pair, const uint32_t* __restrict__ more_off,
+                                               const uint32_t* __restrict__ more, const int32_t* __restrict__ shared,
+                                               int64_t nshared, const int32_t* __restrict__ bnd, int64_t nbnd,
+                                               const V* __restrict__ u, V* __restrict__ y, double& eb) {
+  constexpr int E = FINISH_PER_THREAD;
+  vec_t<uint32_t, 2> pr[E];
+  int32_t dst[E];
+  double p0[E], p1[E];
+#pragma unroll
+  for (int c = 0; c < E; ++c) {
+    const int64_t i = i0 + int64_t(c) * FINISH_THREADS;
+    if (i < nshared) {
+      pr[c] = reinterpret_cast<const vec_t<uint32_t, 2>*>(pair)[i];
+      dst[c] = shared[i];
+    } else if (i < nshared + nbnd) {
+      dst[c] = bnd[i - nshared];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < E; ++c) {
+    const int64_t i = i0 + int64_t(c) * FINISH_THREADS;
+    if (i < nshared) {
+      p0[c] = stage[pr[c][0]];
+      p1[c] = stage[pr[c][1] & 0x7fffffffu];
+    } else if (i < nshared + nbnd) {
+      p0[c] = double(u[dst[c]]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < E; ++c) {
+    const int64_t i = i0 + int64_t(c) * FINISH_THREADS;
+    if (i < nshared) {
+      double sum = 0.0;
+      sum += p0[c];
+      sum += p1[c];
+      if (pr[c][1] >> 31)
+        for (uint32_t j = more_off[i]; j < more_off[i + 1]; ++j) sum += stage[more[j]];
+      y[dst[c]] = V(sum);
+    } else if (i < nshared + nbnd) {
+      y[dst[c]] = V(p0[c]);
+      eb += p0[c] * p0[c];
+    }
+  }
+}
+
 // Second pass of the apply.  i < nshared: y[shared[i]] = sum of its staged partials,
 // added in ascending tile order (deterministic).  nshared <= i < nshared + nbnd:
 // Dirichlet identity row y[b] = u[b]; with benergy, every block from e0 on writes its
 // share of sum u_b^2 (the identity rows' part of u . A u) to benergy[blockIdx.x - e0].
-// One entry per thread: the grid covers nshared + nbnd exactly.
-// The partial sums of shared dof i, added in ascending tile order from zero (pair lists:
-// the first two slots, then any others).
-__device__ __forceinline__ double shared_sum(const double* __restrict__ stage, const uint32_t* __restrict__ pair,
-                                             const uint32_t* __restrict__ more_off, const uint32_t* __restrict__ more,
-                                             int64_t i) {
-  const vec_t<uint32_t, 2> pr = reinterpret_cast<const vec_t<uint32_t, 2>*>(pair)[i];
-  const double p0 = stage[pr[0]], p1 = stage[pr[1] & 0x7fffffffu];
-  double s = 0.0;
-  s += p0;
-  s += p1;
-  if (pr[1] >> 31)
-    for (uint32_t j = more_off[i]; j < more_off[i + 1]; ++j) s += stage[more[j]];
-  return s;
-}
-
+// FINISH_PER_THREAD entries per thread, FINISH_THREADS apart (independent loads in
+// flight, coalesced per step): the grid covers nshared + nbnd.
 __global__ __launch_bounds__(FINISH_THREADS) void k_apply_finish(const double* __restrict__ stage,
                                                       const uint32_t* __restrict__ pair,
                                                       const uint32_t* __restrict__ more_off,
@@ -131,17 +169,8 @@ __global__ __launch_bounds__(FINISH_THREADS) void k_apply_finish(const double* _
                                                       const double* __restrict__ u, double* __restrict__ y,
                                                       double* __restrict__ benergy, int64_t e0) {
   double eb = 0.0;
-  const int64_t i = int64_t(blockIdx.x) * FINISH_THREADS + threadIdx.x;
-  if (i < nshared + nbnd) {
-    if (i < nshared) {
-      y[shared[i]] = shared_sum(stage, pair, more_off, more, i);
-    } else {
-      const int32_t d = bnd[i - nshared];
-      const double ub = u[d];
-      y[d] = ub;
-      eb += ub * ub;
-    }
-  }
+  finish_entries(int64_t(blockIdx.x) * FINISH_ENTRIES + threadIdx.x, stage, pair, more_off, more, shared, nshared, bnd,
+                 nbnd, u, y, eb);
   if (benergy && int64_t(blockIdx.x) >= e0) {  // block-uniform
     __shared__ double red[8];
     const double s = block_sum(eb, red);
@@ -159,17 +188,8 @@ __global__ __launch_bounds__(FINISH_THREADS) void k_apply_finish32(const double*
                                                         const float* __restrict__ u, float* __restrict__ y,
                                                         double* __restrict__ benergy, int64_t e0) {
   double eb = 0.0;
-  const int64_t i = int64_t(blockIdx.x) * FINISH_THREADS + threadIdx.x;
-  if (i < nshared + nbnd) {
-    if (i < nshared) {
-      y[shared[i]] = float(shared_sum(stage, pair, more_off, more, i));
-    } else {
-      const int32_t d = bnd[i - nshared];
-      const float ub = u[d];
-      y[d] = ub;
-      eb += double(ub) * double(ub);
-    }
-  }
+  finish_entries(int64_t(blockIdx.x) * FINISH_ENTRIES + threadIdx.x, stage, pair, more_off, more, shared, nshared, bnd,
+                 nbnd, u, y, eb);
   if (benergy && int64_t(blockIdx.x) >= e0) {  // block-uniform
     __shared__ double red[8];
     const double s = block_sum(eb, red);
