@@ -307,6 +307,9 @@ int batch_pcg(Batch& b, const double* rhs, double* x, const dogip_solve_opts& o,
         vr.act = w.rep.as<int>();
         vr.nact = nrep;
         bk_replace(vr, rhs, w.yout.as<double>(), mixed ? 1 : 0, st);
+        // the problems whose replacement showed a gap restart their direction from the true
+        // residual (need 3; A64 x is still in yout); the others return at once
+        bk_replace(vr, rhs, w.yout.as<double>(), mixed ? 1 : 0, st);
         HIPCHK(hipMemcpyAsync(h_active, w.active.p, sizeof(int) * np, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(h_use64, w.use64.p, sizeof(int) * np, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));

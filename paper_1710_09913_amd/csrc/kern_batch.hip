@@ -246,7 +246,7 @@ __global__ __launch_bounds__(256) void k_b_replace(const int* __restrict__ act, 
                                                    V* __restrict__ pv, BatchPcgState s,
                                                    double* __restrict__ part) {
   if (!s.active[p_of(act)] || !s.need[p_of(act)]) return;
-  const bool restart = s.need[p_of(act)] == 2;
+  const bool restart = s.need[p_of(act)] >= 2;
   double v[2] = {0.0, 0.0};
   PROBLEM_RANGE(p, lo, hi) {
     const double rd = b[i] - y[i];
@@ -268,12 +268,19 @@ __global__ __launch_bounds__(256) void k_b_fin_replace(const int* __restrict__ a
   const double rr = bsum(part + int64_t(p) * gx * 3 + 1, gx, 3);
   if (threadIdx.x == 0) {
     PcgScalars& c = s.sc[p];
+    if (s.need[p] == 3) {
+      // the direction restart that follows a replacement with a gap (see below): the
+      // same residual again, no bookkeeping
+      c.rho = rz;
+      s.need[p] = 0;
+      return;
+    }
     if (!isfinite(rz) || !isfinite(rr)) c.flags |= PCG_NONFINITE;
+    const bool gap = rr > GAP_RR * fmax(c.rr, 1e-300);
     if (mixed && !s.use64[p]) {
       // FP32 operator: a stall is a true residual well above the recursive one (the
       // FP32 error dominates); a true residual far above its minimum is divergence
       const bool diverged = rr > DIVERGE_RR * s.rr_min[p];
-      const bool gap = rr > GAP_RR * fmax(c.rr, 1e-300);
       s.stalls[p] = diverged ? 3 : (gap ? s.stalls[p] + 1 : 0);
     } else {
       s.stalls[p] = rr > 0.25 * s.rr_true[p] ? s.stalls[p] + 1 : 0;
@@ -282,7 +289,11 @@ __global__ __launch_bounds__(256) void k_b_fin_replace(const int* __restrict__ a
     c.rho = rz;
     c.rr = rr;
     s.rr_true[p] = rr;
-    s.need[p] = 0;
+    // a recursive residual far below the true one no longer describes the iterate (it lost
+    // its accuracy, or the Krylov space ran out and the last steps ran on rounding noise):
+    // the kept direction belongs to it, so a second pass restarts the direction from the
+    // true residual (need 3)
+    s.need[p] = (gap && s.need[p] == 1 && !c.flags && rr > tol * tol * c.bb) ? 3 : 0;
     s.last_rep[p] = s.iters[p];
     if (c.flags) {
       s.active[p] = 0;

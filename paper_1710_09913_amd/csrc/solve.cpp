@@ -162,24 +162,37 @@ static CgResult cg_run(Op& op, const double* b, double* x, bool x0_given, const 
       // at apparent convergence the direction restarts from the true residual; the
       // replacements triggered by delta keep it
       op_apply(op, x, q, DOGIP_F64, st);
+      const bool restarted = conv;
       if (v32)
-        vk_replace32(b, q, invd32, r32, conv ? p32 : nullptr, n, part, sc, st);
+        vk_replace32(b, q, invd32, r32, restarted ? p32 : nullptr, n, part, sc, st);
       else
-        vk_replace(b, q, invd, r, conv ? p : nullptr, n, part, sc, st);
+        vk_replace(b, q, invd, r, restarted ? p : nullptr, n, part, sc, st);
       HIPCHK(hipMemcpyAsync(&hs, sc, sizeof hs, hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       if (hs.flags || !std::isfinite(hs.rr)) {
         res.status = DOGIP_E_NONFINITE;
         return res;
       }
+      const bool gap = hs.rr > GAP_RR * std::max(last, 1e-300);
       if (cp.prec == DOGIP_F32) {
         // the FP32 error dominates when the true residual is well above the recursive
         // one; far above its minimum, the iteration diverges: hand over at once
         const bool diverged = hs.rr > DIVERGE_RR * rr_min;
-        const bool gap = hs.rr > GAP_RR * std::max(last, 1e-300);
         stalls = diverged ? 3 : (gap ? stalls + 1 : 0);
       } else {
         stalls = hs.rr > 0.25 * rr_true ? stalls + 1 : 0;
+      }
+      if (gap && !restarted) {
+        // a recursive residual far below the true one no longer describes the iterate: it
+        // lost its accuracy, or the Krylov space ran out (a right-hand side in a few
+        // eigenvectors) and the last steps ran on rounding noise.  The kept direction
+        // belongs to that residual; keeping it took a huge step along noise (alpha =
+        // r.z / p.Ap with a tiny p) and diverged.  Restart the direction from the true
+        // residual (q still holds A64 x; the same r and r.z are recomputed).
+        if (v32)
+          vk_replace32(b, q, invd32, r32, p32, n, part, sc, st);
+        else
+          vk_replace(b, q, invd, r, p, n, part, sc, st);
       }
       rr_min = std::min(rr_min, hs.rr);
       rr_true = hs.rr;
