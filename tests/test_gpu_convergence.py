@@ -34,7 +34,8 @@ def _nodal_rms_error(d, n, k, mode):
     return float(np.sqrt(np.mean((uh.cpu().numpy() - uex) ** 2)))
 
 
-@pytest.mark.parametrize("d,k,ns", [(2, 1, (8, 16, 32)), (2, 2, (8, 16, 32)), (2, 3, (4, 8, 16)), (3, 2, (4, 8, 16))])
+@pytest.mark.parametrize("d,k,ns", [(2, 1, (8, 16, 32)), (2, 2, (8, 16, 32)), (2, 3, (4, 8, 16)), (3, 2, (4, 8, 16)),
+                                    (3, 3, (4, 8, 16))])
 @pytest.mark.parametrize("mode", ["f64", "mixed", "pmg_mixed"])
 def test_nodal_error_rate(d, k, ns, mode):
     print(f"[convergence] d={d} k={k} {mode}", flush=True)
@@ -43,3 +44,24 @@ def test_nodal_error_rate(d, k, ns, mode):
     print(f"errors {errs}, rates {rates}", flush=True)
     # the asymptotic rate is k + 1 (k + 2 at the nodes for even k would only help)
     assert min(rates[-1:]) >= k + 1 - 0.3, rates
+
+
+@pytest.mark.parametrize("d,k", [(2, 1), (2, 3), (2, 5), (3, 1), (3, 2), (3, 3)])
+def test_constants_in_the_neumann_null_space(d, k):
+    """Without boundary conditions the elliptic operator annihilates constants (the
+    gradients of the basis sum to zero), on a jittered mesh with an anisotropic
+    coefficient: |A 1| within the rounding of |B^|^T|D||B^| 1, in FP64 and FP32; and u^T A u
+    > 0 for a random u (positive semidefinite, zero only on constants)."""
+    from test_gpu_apply import Case
+
+    c = Case(d, 6 if d == 2 else 3, k, "se", seed=5, bc="none")
+    one = np.ones(c.space.ndofs)
+    bound = c.abs_bound(one)
+    info = c.space.info
+    m = info["vt"] + info["nb"] * info["wt"] + info["nb"] + c.n_incident_max() + 3
+    gam32 = 2 * m * 2.0 ** -24 / (1 - m * 2.0 ** -24)  # the FP32 bound of the apply tests
+    for prec, tol in (("f64", 1e-12), ("f32", gam32)):
+        y = c.op.apply(torch.from_numpy(one).cuda(), prec=prec).cpu().numpy()
+        assert np.all(np.abs(y) <= tol * bound + 1e-300), (prec, float(np.abs(y).max()))
+    u = np.random.default_rng(3).standard_normal(c.space.ndofs)
+    assert float(u @ c.op.apply(torch.from_numpy(u).cuda()).cpu().numpy()) > 0.0
