@@ -11,21 +11,29 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _ms(op, u, y, prec, reps=10, rounds=5):
-    """Median over rounds of the mean apply time (tile kernel + finish, HIP events)."""
-    for _ in range(3):
+def _mean_ms(op, u, y, prec, reps):
+    op.timer_read()
+    for _ in range(reps):
         op.apply(u, y, prec=prec)
-    torch.cuda.synchronize()
-    op.timer_enable(True)
-    out = []
-    for _ in range(rounds):
-        op.timer_read()
-        for _ in range(reps):
+    t, f, n = op.timer_read()
+    return (t + f) / n
+
+
+def _ms_pair(a, b, u, y, prec, reps=20, rounds=7):
+    """Medians over rounds of the mean apply time (tile kernel + finish, HIP events) of two
+    operators, timed in alternating rounds so that clock and thermal drift hit both."""
+    for op in (a, b):
+        for _ in range(3):
             op.apply(u, y, prec=prec)
-        t, f, n = op.timer_read()
-        out.append((t + f) / n)
-    op.timer_enable(False)
-    return statistics.median(out)
+        op.timer_enable(True)
+    torch.cuda.synchronize()
+    ta, tb = [], []
+    for _ in range(rounds):
+        ta.append(_mean_ms(a, u, y, prec, reps))
+        tb.append(_mean_ms(b, u, y, prec, reps))
+    for op in (a, b):
+        op.timer_enable(False)
+    return statistics.median(ta), statistics.median(tb)
 
 
 @pytest.mark.parametrize("dim,k,prec,tag,max_cells,variants", [
@@ -38,7 +46,7 @@ def test_tuned_not_slower_than_default(tmp_path, monkeypatch, dim, k, prec, tag,
 
     monkeypatch.setenv("DOGIP_TUNE_CACHE", str(tmp_path / "tune.json"))
     print(f"[tune] d={dim} k={k} {prec} tag={tag!r}", flush=True)
-    e = tune.tune(dim, k, "se", prec, cells_target=200_000, reps=10, max_tile_cells=max_cells, variants=variants,
+    e = tune.tune(dim, k, "se", prec, cells_target=1_000_000, reps=10, max_tile_cells=max_cells, variants=variants,
                   tag=tag)
     assert tune.tuned(dim, k, "se", prec, tag=tag) == (e["tile_waves"], e["variant"])
     space = Space(Mesh.unit(dim, e["mesh_n"]), k, "se", "dirichlet")
@@ -47,11 +55,12 @@ def test_tuned_not_slower_than_default(tmp_path, monkeypatch, dim, k, prec, tag,
     dflt = (default.info["tile_cells"] // 64, default.info["variant"])
     if default.info["tile_cells"] <= max_cells and (variants is None or dflt[1] in variants):
         assert any((c["tile_waves"], c["variant"]) == dflt for c in e["candidates"]), "default not timed"
+    if (e["tile_waves"], e["variant"]) == dflt:
+        return  # the tuner chose the default configuration: nothing to compare
     tuned = Operator(space, coef, "scalar", fp32=prec == "f32", tile_waves=e["tile_waves"], variant=e["variant"])
     u = torch.ones(space.ndofs, dtype=torch.float64, device="cuda")
     y = torch.empty_like(u)
-    t_def = _ms(default, u, y, prec)
-    t_tun = _ms(tuned, u, y, prec)
+    t_def, t_tun = _ms_pair(default, tuned, u, y, prec)
     print(f"[tune] default {dflt}: {t_def:.4f} ms, tuned {(e['tile_waves'], e['variant'])}: {t_tun:.4f} ms",
           flush=True)
     if default.info["tile_cells"] <= max_cells and (variants is None or dflt[1] in variants):
