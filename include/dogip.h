@@ -252,9 +252,12 @@ void dogip_space_destroy(dogip_space s);
 
 /* Build the operator.  coef: device pointer in the form coef_kind (cells in mesh
  * order), read during the call only.  flags: DOGIP_OP_FP32, DOGIP_OP_GLOBAL_W or
- * both.  tile_waves:
- * cells per tile / 64, 1..8, or 0 for the built-in default (8 for 3D with k >= 2,
- * else 4; halved while a tile's dofs exceed the 64 KB LDS budget).  variant:
+ * both.  tile_waves: cells per tile / 64, 1..48 (1..8 for the matrix-core variant),
+ * or 0 for the built-in default (24 for element-wise 3D operators with k >= 2, 8 for
+ * the matrix-core variant and the global form there, else 4), stepped down while a
+ * tile's LDS arrays (16 bytes per tile dof) exceed 159 KB (64 KB for the matrix-core
+ * variant).  A tile's cells are taken by one workgroup in passes of as many cells as
+ * it has lanes (see dogip_op_set_tile_lanes).  variant:
  * DOGIP_VARIANT_*.  D is built by the HIP kernels (Theorem 2: m_T |T| w^_i;
  * Theorem 4: w^_i |T| R_T^-1 M_T R_T^-T; or copied for RAW_D).  The call
  * synchronizes the stream before returning.  DOGIP_E_RANGE for a form that does
@@ -309,6 +312,15 @@ int dogip_op_create_qp(dogip_space s, int n, const double* coef, unsigned flags,
 /* Rebuild D (and the FP32 copy and the Jacobi diagonal) from a new coefficient.  async. */
 int dogip_op_set_coef(dogip_op op, int coef_kind, const double* coef, dogip_stream stream);
 int dogip_op_get_info(dogip_op op, dogip_op_info* info);
+/* Lanes of the workgroup that runs one tile of the FP64 (lanes64) and FP32 (lanes32)
+ * applies, for tuning: a multiple of 64 dividing info.tile_cells, at most the kernel's
+ * launch bound (512 FP64, 768 FP32 for the element-wise kernels), or 0 (the default) to
+ * take, per kernel, the count that keeps the most waves resident per compute unit.  The
+ * tile's cells are taken in ascending order in passes whatever the lanes, so results are
+ * the same bit for bit.  DOGIP_E_RANGE for a count that does not divide the tile (checked
+ * here) or exceeds the kernel's bound (checked at the next apply). */
+int dogip_op_set_tile_lanes(dogip_op op, int lanes64, int lanes32);
+
 /* Copy D to device memory [ncells][wt][nsym] in mesh cell order (FP64).  async.
  * DOGIP_E_STATE for a DOGIP_OP_GLOBAL_W operator (its D is not per cell). */
 int dogip_op_export_d(dogip_op op, double* d_out, dogip_stream stream);

@@ -103,6 +103,7 @@ SIGNATURES = {
                                           C.POINTER(C.c_double), P]),
     "dogip_op_create_qp": (C.c_int, [H, C.c_int, P, C.c_uint, C.c_int, P, PH]),
     "dogip_op_set_coef": (C.c_int, [H, C.c_int, P, P]),
+    "dogip_op_set_tile_lanes": (C.c_int, [H, C.c_int, C.c_int]),
     "dogip_op_get_info": (C.c_int, [H, C.POINTER(OpInfo)]),
     "dogip_op_export_d": (C.c_int, [H, P, P]),
     "dogip_apply": (C.c_int, [H, P, P, C.c_int, P]),

@@ -267,6 +267,14 @@ int dogip_op_set_coef(dogip_op op, int coef_kind, const double* coef, dogip_stre
   });
 }
 
+int dogip_op_set_tile_lanes(dogip_op op, int lanes64, int lanes32) {
+  return guard([&] {
+    need(op);
+    dogip::op_set_tile_lanes(*op->op, lanes64, lanes32);
+    return DOGIP_OK;
+  });
+}
+
 int dogip_op_get_info(dogip_op op, dogip_op_info* info) {
   return guard([&] {
     need(op);

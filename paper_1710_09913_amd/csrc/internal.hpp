@@ -97,6 +97,9 @@ constexpr uint32_t TD_MASK = 0x1fffffffu;    // dof index (< 2^29)
 // into tiles of TE cells; each tile lists the distinct dofs it touches.
 struct TilePlan {
   int te = 0;
+  // lanes of the FP64 and FP32 apply workgroups: a tile of te cells runs on `lanes` lanes
+  // in te / lanes passes; 0 lets each launch choose (tile_lanes)
+  int lanes64 = 0, lanes32 = 0;
   int64_t ntiles = 0, nel_pad = 0;
   std::vector<int32_t> perm;        // internal cell -> mesh cell
   std::vector<int64_t> tile_off;    // [ntiles+1]
@@ -241,6 +244,7 @@ void op_apply_staged(Op& op, const double* u, double* y, int prec, double* stage
 void op_apply_noalloc(Op& op, const double* u, double* y, int prec, hipStream_t st);
 void op_diag(Op& op, double* diag, hipStream_t st);
 void op_grad(Op& op, const double* u, const double* lam, double* g, hipStream_t st);
+void op_set_tile_lanes(Op& op, int lanes64, int lanes32);
 void op_export_d(Op& op, double* out, hipStream_t st);
 dogip_op_info op_info(const Op& op);
 int op_pcg(Op& op, const double* b, double* x, const dogip_solve_opts& o, dogip_solve_stats& stats, hipStream_t st);
@@ -265,7 +269,8 @@ struct ApplyLaunch {
   int64_t ntiles;
   int64_t nch;           // D chunks per cell
   int nlc;               // local-index chunks per cell
-  int te;
+  int te;                // cells per tile
+  int cpl;               // cells per lane (passes): the workgroup has te / cpl lanes; 0: chosen at launch
   int lds_slots;         // LDS slots per tile (>= max tile dofs)
   int tile_base;         // first tile of this launch (batch uses 0)
   const uint32_t* gw_mask;  // global projection form: owned slots per cell (else null)
@@ -278,6 +283,15 @@ struct ApplyLaunch {
   int nq;
 };
 
+// Dynamic LDS a tile kernel's workgroup may take (gfx950: 160 KB per compute unit and per
+// workgroup, less a little for the kernels' static arrays).
+constexpr int64_t LDS_TILE_MAX = 160 * 1024 - 1024;
+// Lanes of a tile kernel's workgroup for tiles of te cells and `lds` bytes of dynamic LDS:
+// `requested` when positive (checked: a multiple of 64 dividing te, within the kernel's
+// launch bound), else the count that keeps the most waves resident per compute unit, ties
+// going to fewer lanes (more, smaller workgroups); cached per (kernel, te, lds).  Passes
+// take a tile's cells in ascending order whatever the lanes, so results do not depend on it.
+int tile_lanes(const void* kernel, int te, size_t lds, int requested);
 bool launch_apply(int dim, int k, int kind, int prec, int variant, const ApplyLaunch& a, hipStream_t st);
 // FP32 apply of 3D P3 elliptic operators with the B^ products on the matrix cores
 // (kern_apply_mfma.hip); D32 in the layout of d32_pos with nch32 < 0
@@ -296,7 +310,7 @@ struct DiagLaunch {
   const double* bhat;
   double* out;
   int64_t nel, ntiles, nch;
-  int nlc, te, lds_slots;
+  int nlc, te, cpl, lds_slots;  // cells per tile, cells per lane (0: chosen at launch)
   const uint32_t* gw_mask;  // global projection form (D one value per W dof), else null
   const int64_t* gw_woff;
   double* stage;             // the apply's staging buffer: tile partials of shared dofs
@@ -336,7 +350,7 @@ struct GradLaunch {
   const int32_t* perm;
   double* g;
   int64_t nel, ntiles, nch;
-  int nlc, te, lds_slots;
+  int nlc, te, cpl, lds_slots;  // cells per tile, cells per lane (0: chosen at launch)
 };
 void launch_grad(int dim, int k, int kind, const GradLaunch& a, hipStream_t st);
 

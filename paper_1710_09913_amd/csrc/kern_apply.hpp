@@ -1,5 +1,5 @@
 // Tile kernel of the DoGIP apply (Algorithm 1 with the transpose of eq. ep_dogip_mul):
-// one workgroup per tile of TE cells, one lane per cell.
+// one workgroup per tile of te cells, one lane per cell in each of te / lanes passes.
 //
 //   1. gather: the tile's distinct dofs u[dof] -> LDS (0 for Dirichlet dofs)
 //   2. per cell: local slots -> u_T from LDS; y_T = B^^T D_T B^ u_T streaming D_T
@@ -32,9 +32,9 @@ constexpr int GB = 8;  // tile dof entries handled per thread in one batch
 
 // Gather of one batch: entries j = j0 + g * blockDim.x; u -> LDS (0 for Dirichlet
 // dofs), accumulation slots zeroed.  The GB loads of a thread are in flight together.
-template <typename T, typename VU>
+template <typename T, typename VU, typename A>
 __device__ __forceinline__ void gather_batch(const uint32_t* __restrict__ td, int64_t nd, int64_t j0,
-                                             const VU* __restrict__ u, T* us, double* ys, uint32_t (&e)[GB]) {
+                                             const VU* __restrict__ u, T* us, A* ys, uint32_t (&e)[GB]) {
   VU v[GB];
 #pragma unroll
   for (int g = 0; g < GB; ++g) {
@@ -48,33 +48,35 @@ __device__ __forceinline__ void gather_batch(const uint32_t* __restrict__ td, in
     const int64_t j = j0 + int64_t(g) * blockDim.x;
     if (j < nd) {
       us[j] = T(v[g]);
-      ys[j] = 0.0;
+      ys[j] = A(0);
     }
   }
 }
 
 // Flush of one batch: shared entries -> staging (second pass sums them), exclusive
 // entries -> y; Dirichlet entries are written by the second pass.
-template <bool ENERGY, typename T, typename VY>
-__device__ __forceinline__ void flush_batch(const uint32_t (&e)[GB], int64_t nd, int64_t j0, const double* ys,
+template <bool ENERGY, typename T, typename VY, typename A>
+__device__ __forceinline__ void flush_batch(const uint32_t (&e)[GB], int64_t nd, int64_t j0, const A* ys,
                                             const T* us, double* __restrict__ stage, VY* __restrict__ y,
                                             double& en) {
 #pragma unroll
   for (int g = 0; g < GB; ++g) {
     const int64_t j = j0 + int64_t(g) * blockDim.x;
     if (j >= nd || (e[g] & TD_BND)) continue;
-    if constexpr (ENERGY) en = fma(double(us[j]), ys[j], en);
+    if constexpr (ENERGY) en = fma(double(us[j]), double(ys[j]), en);
     if (e[g] & TD_SHARED)
-      stage[j] = ys[j];
+      stage[j] = double(ys[j]);
     else
       y[e[g] & TD_MASK] = VY(ys[j]);
   }
 }
 
 // Work of one tile (one workgroup).  T is the element arithmetic precision (D is
-// stored in T); the per-tile accumulation in LDS is always FP64 (ds_add_f64).
-// When the tile has at most GB * blockDim entries (the usual case) the entries
-// loaded by the gather stay in registers for the flush.  energy_out: where the
+// stored in T); the per-tile accumulation in LDS is always FP64 (ds_add_f64; FP32
+// accumulation, which would halve the LDS arrays, measured 10-45% slower).  The
+// flush reads the tile's entries again rather than holding them in registers through
+// the element passes (the FP32 kernel then needs 128 VGPRs, 4 waves per SIMD, instead
+// of 133).  energy_out: where the
 // tile's sum_T u_T^T A_T u_T goes (ENERGY only).  MODE 1: global projection form, D
 // holds one value per W dof in the per-wave layout of GlobalPlan; MODE 2: the
 // conventional quadrature-point apply (ElemQ).
@@ -87,7 +89,6 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
   T* us = reinterpret_cast<T*>(ys + a.lds_slots);
   const int64_t o0 = a.tile_off[t], nd = a.tile_off[t + 1] - o0;
   const uint32_t* td = a.tile_dofs + o0;
-  const bool one = nd <= int64_t(GB) * blockDim.x;
   uint32_t ent[GB];
   const auto* uin = [&] {
     if constexpr (V32)
@@ -101,63 +102,67 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
     else
       return a.y;
   }();
-  int64_t e = t * a.te + threadIdx.x;
-  if (int(threadIdx.x) >= a.te) e = a.nel;  // lanes beyond a smaller tile do no cell work
-  // the first D chunks of each cell are requested before the gather, so their latency
-  // overlaps it (element-wise form, unrolled body, FP64 D: measured 2% faster there and
-  // 1.7% slower with FP32 D)
+  // the tile's cells are taken in cpl passes of `lanes` cells, one per lane; pass c holds
+  // tile cells [c * lanes, (c + 1) * lanes), i.e. global waves t * te / 64 + c * lanes / 64 + wave
+  const int lanes = a.te / a.cpl, me = int(threadIdx.x >> 6), nw = (lanes + 63) >> 6;
+  auto cell_of = [&](int c) -> int64_t {
+    return int(threadIdx.x) < lanes ? t * a.te + int64_t(c) * lanes + threadIdx.x : a.nel;
+  };
+  auto wave_of = [&](int c) -> int64_t {
+    return t * (a.te >> 6) + c * (lanes >> 6) + __builtin_amdgcn_readfirstlane(me);
+  };
+  // the first D chunks of each cell are requested before the gather (and those of the next
+  // pass before this pass's LDS accumulation), so their latency overlaps it (element-wise
+  // form, unrolled body, FP64 D: measured 2% faster there and 1.7% slower with FP32 D)
   constexpr bool PRE = MODE == 0 && VARIANT == DOGIP_VARIANT_UNROLLED && sizeof(T) == 8;
   typename E::V pre[E::NPRE];
-  if constexpr (PRE) {
-    if (e < a.nel) {
-      const int64_t w0 = t * (a.te >> 6) + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-      E::preload(reinterpret_cast<const typename E::V*>(a.D) + (w0 * a.nch) * 64 + (threadIdx.x & 63), pre);
+  auto preload = [&](int c) {
+    if constexpr (PRE) {
+      if (cell_of(c) < a.nel)
+        E::preload(reinterpret_cast<const typename E::V*>(a.D) + (wave_of(c) * a.nch) * 64 + (threadIdx.x & 63), pre);
     }
-  }
-  if (one) {
-    gather_batch<T>(td, nd, threadIdx.x, uin, us, ys, ent);
-  } else {
-    for (int64_t j0 = threadIdx.x; j0 < nd; j0 += int64_t(GB) * blockDim.x) gather_batch<T>(td, nd, j0, uin, us, ys, ent);
-  }
+  };
+  preload(0);
+  for (int64_t j0 = threadIdx.x; j0 < nd; j0 += int64_t(GB) * blockDim.x) gather_batch<T>(td, nd, j0, uin, us, ys, ent);
   __syncthreads();
-  double yacc[VT];
-  int sl[VT];
-  if (e < a.nel) {
-    const int lane = threadIdx.x & 63;
-    const int64_t w = t * (a.te >> 6) + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    int li[VT];
-    load_lidx<VT>(a.lidx, w, a.nlc, lane, li);
-    T ue[VT], ye[VT];
-    sfor<VT>([&](auto L) { ue[L] = us[li[L]]; });
-    if constexpr (MODE == 1) {
-      ElemG<D, K, T, VARIANT>::run(static_cast<const T*>(a.D) + a.gw_woff[e >> 6], a.gw_mask[e], ue, ye);
-    } else if constexpr (MODE == 2) {
-      ElemQ<D, K, KIND, T>::run(a, w, lane, ue, ye);
-    } else {
-      const typename E::V* dp = reinterpret_cast<const typename E::V*>(a.D) + (w * a.nch) * 64 + lane;
-      E::template run<PRE>(dp, ue, ye, pre);
+  for (int c = 0; c < a.cpl; ++c) {
+    const int64_t e = cell_of(c);
+    double yacc[VT];
+    int sl[VT];
+    if (e < a.nel) {
+      const int lane = threadIdx.x & 63;
+      const int64_t w = wave_of(c);
+      int li[VT];
+      load_lidx<VT>(a.lidx, w, a.nlc, lane, li);
+      T ue[VT], ye[VT];
+      sfor<VT>([&](auto L) { ue[L] = us[li[L]]; });
+      if constexpr (MODE == 1) {
+        ElemG<D, K, T, VARIANT>::run(static_cast<const T*>(a.D) + a.gw_woff[e >> 6], a.gw_mask[e], ue, ye);
+      } else if constexpr (MODE == 2) {
+        ElemQ<D, K, KIND, T>::run(a, w, lane, ue, ye);
+      } else {
+        const typename E::V* dp = reinterpret_cast<const typename E::V*>(a.D) + (w * a.nch) * 64 + lane;
+        E::template run<PRE>(dp, ue, ye, pre);
+      }
+      sfor<VT>([&](auto L) { yacc[L] = double(ye[L]); sl[L] = li[L]; });
     }
-    sfor<VT>([&](auto L) { yacc[L] = double(ye[L]); sl[L] = li[L]; });
-  }
-  // LDS accumulation one wave after the other, so the sums are bitwise reproducible
-  const int nw = (a.te + 63) >> 6, me = int(threadIdx.x >> 6);
-  for (int wv = 0; wv < nw; ++wv) {
-    if (me == wv && e < a.nel) sfor<VT>([&](auto L) { atomicAdd(&ys[sl[L]], yacc[L]); });
-    __syncthreads();
+    if (c + 1 < a.cpl) preload(c + 1);
+    // LDS accumulation one wave after the other (passes in order), so the sums are
+    // bitwise reproducible
+    for (int wv = 0; wv < nw; ++wv) {
+      if (me == wv && e < a.nel) sfor<VT>([&](auto L) { atomicAdd(&ys[sl[L]], yacc[L]); });
+      __syncthreads();
+    }
   }
   double* stage = a.stage + a.stage_off[t];
   double en = 0.0;
-  if (one) {
-    flush_batch<ENERGY>(ent, nd, threadIdx.x, ys, us, stage, yout, en);
-  } else {
-    for (int64_t j0 = threadIdx.x; j0 < nd; j0 += int64_t(GB) * blockDim.x) {
+  for (int64_t j0 = threadIdx.x; j0 < nd; j0 += int64_t(GB) * blockDim.x) {
 #pragma unroll
-      for (int g = 0; g < GB; ++g) {
-        const int64_t j = j0 + int64_t(g) * blockDim.x;
-        ent[g] = j < nd ? td[j] : TD_BND;
-      }
-      flush_batch<ENERGY>(ent, nd, j0, ys, us, stage, yout, en);
+    for (int g = 0; g < GB; ++g) {
+      const int64_t j = j0 + int64_t(g) * blockDim.x;
+      ent[g] = j < nd ? td[j] : TD_BND;
     }
+    flush_batch<ENERGY>(ent, nd, j0, ys, us, stage, yout, en);
   }
   if constexpr (ENERGY) {
     __shared__ double red[8];
@@ -168,7 +173,7 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
 
 // One workgroup per tile; workgroup -> tile mapping keeps each XCD on a contiguous range.
 template <int D, int K, int KIND, typename T, int VARIANT, bool ENERGY, int PF, bool V32 = false>
-__global__ __launch_bounds__(512, DOGIP_WPE) void k_apply(ApplyLaunch a) {
+__global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 768, DOGIP_WPE) void k_apply(ApplyLaunch a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t t = a.tile_base + xcd_tile(blockIdx.x, gridDim.x);
   tile_body<D, K, KIND, T, VARIANT, ENERGY, PF, 0, V32>(a, t, smem, ENERGY ? a.energy + t : nullptr);
@@ -183,12 +188,11 @@ __global__ __launch_bounds__(512, DOGIP_WPE) void k_apply_g(ApplyLaunch a) {
 
 template <int D, int K, typename T, int VARIANT>
 void launch_apply_g_p(bool energy, const ApplyLaunch& a, hipStream_t st) {
-  const dim3 grid(unsigned(a.ntiles)), block(unsigned(a.te));
   const size_t lds = size_t(a.lds_slots) * (sizeof(double) + sizeof(T));
   if (energy)
-    hipLaunchKernelGGL((k_apply_g<D, K, T, VARIANT, true>), grid, block, lds, st, a);
+    launch_tiles((k_apply_g<D, K, T, VARIANT, true>), a, lds, st);
   else
-    hipLaunchKernelGGL((k_apply_g<D, K, T, VARIANT, false>), grid, block, lds, st, a);
+    launch_tiles((k_apply_g<D, K, T, VARIANT, false>), a, lds, st);
 }
 
 template <int D, int K, int VARIANT>
@@ -202,24 +206,23 @@ bool launch_apply_g_t(int prec, bool energy, const ApplyLaunch& a, hipStream_t s
 
 template <int D, int K, int KIND, int VARIANT>
 bool launch_apply_t(int prec, bool energy, const ApplyLaunch& a, hipStream_t st) {
-  const dim3 grid(unsigned(a.ntiles)), block(unsigned(a.te));
   constexpr int P64 = VARIANT == DOGIP_VARIANT_UNROLLED ? DOGIP_PF64 : 0;
   constexpr int P32 = VARIANT == DOGIP_VARIANT_UNROLLED ? DOGIP_PF32 : 0;
   if (prec == DOGIP_F64) {
     const size_t lds = size_t(a.lds_slots) * (sizeof(double) + sizeof(double));
     if (energy)
-      hipLaunchKernelGGL((k_apply<D, K, KIND, double, VARIANT, true, P64>), grid, block, lds, st, a);
+      launch_tiles((k_apply<D, K, KIND, double, VARIANT, true, P64>), a, lds, st);
     else
-      hipLaunchKernelGGL((k_apply<D, K, KIND, double, VARIANT, false, P64>), grid, block, lds, st, a);
+      launch_tiles((k_apply<D, K, KIND, double, VARIANT, false, P64>), a, lds, st);
   } else {
     const size_t lds = size_t(a.lds_slots) * (sizeof(double) + sizeof(float));
     if (a.u32) {
       if (!energy) return false;  // FP32 vectors: the CG iteration only
-      hipLaunchKernelGGL((k_apply<D, K, KIND, float, VARIANT, true, P32, true>), grid, block, lds, st, a);
+      launch_tiles((k_apply<D, K, KIND, float, VARIANT, true, P32, true>), a, lds, st);
     } else if (energy) {
-      hipLaunchKernelGGL((k_apply<D, K, KIND, float, VARIANT, true, P32>), grid, block, lds, st, a);
+      launch_tiles((k_apply<D, K, KIND, float, VARIANT, true, P32>), a, lds, st);
     } else {
-      hipLaunchKernelGGL((k_apply<D, K, KIND, float, VARIANT, false, P32>), grid, block, lds, st, a);
+      launch_tiles((k_apply<D, K, KIND, float, VARIANT, false, P32>), a, lds, st);
     }
   }
   return true;

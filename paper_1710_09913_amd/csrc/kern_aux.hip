@@ -260,7 +260,8 @@ __global__ __launch_bounds__(512) void k_diag(DiagLaunch a) {
   const int64_t o0 = a.tile_off[t], nd = a.tile_off[t + 1] - o0;
   for (int64_t j = threadIdx.x; j < nd; j += blockDim.x) ys[j] = 0.0;
   __syncthreads();
-  const int64_t e = t * a.te + threadIdx.x;
+  for (int c = 0; c < a.cpl; ++c) {
+  const int64_t e = tile_cell(a, t, c);
   int li[VT];
   double ye[VT];
   if (e < a.nel) {
@@ -287,7 +288,9 @@ __global__ __launch_bounds__(512) void k_diag(DiagLaunch a) {
       });
     }
   }
-  diag_flush<VT>(a, t, e, li, ye, ys, a.out);
+  diag_accumulate<VT>(a, e, li, ye, ys);
+  }
+  diag_store(a, t, ys, a.out);
 }
 
 // ---- Jacobi diagonal of the global projection form: diag_l = sum_j B_jl^2 D_j, each
@@ -302,7 +305,8 @@ __global__ __launch_bounds__(512) void k_diag_g(DiagLaunch a) {
   const int64_t o0 = a.tile_off[t], nd = a.tile_off[t + 1] - o0;
   for (int64_t j = threadIdx.x; j < nd; j += blockDim.x) ys[j] = 0.0;
   __syncthreads();
-  const int64_t e = t * a.te + threadIdx.x;
+  for (int c = 0; c < a.cpl; ++c) {
+  const int64_t e = tile_cell(a, t, c);
   int li[VT];
   double ye[VT];
   if (e < a.nel) {
@@ -329,7 +333,9 @@ __global__ __launch_bounds__(512) void k_diag_g(DiagLaunch a) {
       }
     });
   }
-  diag_flush<VT>(a, t, e, li, ye, ys, a.out);
+  diag_accumulate<VT>(a, e, li, ye, ys);
+  }
+  diag_store(a, t, ys, a.out);
 }
 
 // ---- adjoint contraction: g_T = -(B^ lam_T) . D_T (B^ u_T), boundary entries zero ----
@@ -349,8 +355,9 @@ __global__ __launch_bounds__(512) void k_grad(GradLaunch a) {
     ls[j] = b ? 0.0 : a.lam[td & TD_MASK];
   }
   __syncthreads();
-  const int64_t e = t * a.te + threadIdx.x;
-  if (e >= a.nel) return;
+  for (int c = 0; c < a.cpl; ++c) {
+  const int64_t e = tile_cell(a, t, c);
+  if (e >= a.nel) break;
   const int lane = threadIdx.x & 63;
   const int64_t w = e >> 6;
   int li[VT];
@@ -385,17 +392,16 @@ __global__ __launch_bounds__(512) void k_grad(GradLaunch a) {
     sfor<NB>([&](auto R) { en = fma_t(gl[R], h[R], en); });
   }
   a.g[a.perm[e]] = -en;
+  }
 }
 
 template <int D, int K, int KIND>
 void diag_t(const DiagLaunch& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_diag<D, K, KIND>), dim3(unsigned(a.ntiles)), dim3(unsigned(a.te)),
-                     size_t(a.lds_slots) * sizeof(double), st, a);
+  launch_tiles((k_diag<D, K, KIND>), a, size_t(a.lds_slots) * sizeof(double), st);
 }
 template <int D, int K, int KIND>
 void grad_t(const GradLaunch& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_grad<D, K, KIND>), dim3(unsigned(a.ntiles)), dim3(unsigned(a.te)),
-                     size_t(2) * a.lds_slots * sizeof(double), st, a);
+  launch_tiles((k_grad<D, K, KIND>), a, size_t(2) * a.lds_slots * sizeof(double), st);
 }
 
 }  // namespace dev
@@ -420,21 +426,20 @@ void launch_build_dg(const BuildDLaunch& a, const int64_t* inc_ptr, const int64_
 }
 
 void launch_diag_global(int dim, int k, const DiagLaunch& a, hipStream_t st) {
-  const dim3 grid(unsigned(a.ntiles)), block(unsigned(a.te));
   const size_t lds = size_t(a.lds_slots) * sizeof(double);
   switch (dim * 16 + k) {
-    case 32 + 1: hipLaunchKernelGGL((dev::k_diag_g<2, 1>), grid, block, lds, st, a); break;
-    case 32 + 2: hipLaunchKernelGGL((dev::k_diag_g<2, 2>), grid, block, lds, st, a); break;
-    case 32 + 3: hipLaunchKernelGGL((dev::k_diag_g<2, 3>), grid, block, lds, st, a); break;
-    case 32 + 4: hipLaunchKernelGGL((dev::k_diag_g<2, 4>), grid, block, lds, st, a); break;
-    case 32 + 5: hipLaunchKernelGGL((dev::k_diag_g<2, 5>), grid, block, lds, st, a); break;
-    case 32 + 6: hipLaunchKernelGGL((dev::k_diag_g<2, 6>), grid, block, lds, st, a); break;
-    case 32 + 7: hipLaunchKernelGGL((dev::k_diag_g<2, 7>), grid, block, lds, st, a); break;
-    case 32 + 8: hipLaunchKernelGGL((dev::k_diag_g<2, 8>), grid, block, lds, st, a); break;
-    case 48 + 1: hipLaunchKernelGGL((dev::k_diag_g<3, 1>), grid, block, lds, st, a); break;
-    case 48 + 2: hipLaunchKernelGGL((dev::k_diag_g<3, 2>), grid, block, lds, st, a); break;
-    case 48 + 3: hipLaunchKernelGGL((dev::k_diag_g<3, 3>), grid, block, lds, st, a); break;
-    case 48 + 4: hipLaunchKernelGGL((dev::k_diag_g<3, 4>), grid, block, lds, st, a); break;
+    case 32 + 1: launch_tiles((dev::k_diag_g<2, 1>), a, lds, st); break;
+    case 32 + 2: launch_tiles((dev::k_diag_g<2, 2>), a, lds, st); break;
+    case 32 + 3: launch_tiles((dev::k_diag_g<2, 3>), a, lds, st); break;
+    case 32 + 4: launch_tiles((dev::k_diag_g<2, 4>), a, lds, st); break;
+    case 32 + 5: launch_tiles((dev::k_diag_g<2, 5>), a, lds, st); break;
+    case 32 + 6: launch_tiles((dev::k_diag_g<2, 6>), a, lds, st); break;
+    case 32 + 7: launch_tiles((dev::k_diag_g<2, 7>), a, lds, st); break;
+    case 32 + 8: launch_tiles((dev::k_diag_g<2, 8>), a, lds, st); break;
+    case 48 + 1: launch_tiles((dev::k_diag_g<3, 1>), a, lds, st); break;
+    case 48 + 2: launch_tiles((dev::k_diag_g<3, 2>), a, lds, st); break;
+    case 48 + 3: launch_tiles((dev::k_diag_g<3, 3>), a, lds, st); break;
+    case 48 + 4: launch_tiles((dev::k_diag_g<3, 4>), a, lds, st); break;
     default: throw Error(DOGIP_E_RANGE, "no kernel for this (dim, k)");
   }
 }

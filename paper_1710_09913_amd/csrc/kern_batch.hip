@@ -44,6 +44,7 @@ __global__ __launch_bounds__(256) void k_batch_apply(BatchLaunch bl) {
     a.nch = bl.prec == DOGIP_F64 ? d.nch64 : d.nch32;
     a.nlc = d.nlc;
     a.te = d.te;
+    a.cpl = 1;
     a.lds_slots = d.lds_slots;
     double* eo = ENERGY ? bl.energy + d.tile_base + t : nullptr;
     constexpr int V = DOGIP_VARIANT_UNROLLED;

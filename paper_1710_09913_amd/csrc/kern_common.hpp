@@ -379,18 +379,54 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
-// Last step of a Jacobi-diagonal tile: the cells' terms ye are added into the tile's LDS
-// slots one wave after the other; then the tile writes its own dofs, 1 on Dirichlet rows,
-// and its partial sums of shared dofs into the apply's staging buffer, which the finish
-// kernel adds in a fixed order.  The diagonal is the same bit for bit from run to run.
+}  // namespace dev
+
+// Launch with `lds` bytes of dynamic LDS; above 64 KB the kernel's limit is raised first
+// (a gfx950 workgroup may hold up to 160 KB).
+template <typename Kern, typename... Args>
+void launch_lds(Kern k, dim3 grid, dim3 block, size_t lds, hipStream_t st, Args... args) {
+  if (lds > 65536)
+    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+  hipLaunchKernelGGL(k, grid, block, lds, st, args...);
+}
+
+// Launch a tile kernel (one workgroup per tile) whose launch record L carries te and cpl
+// (cells per lane; 0: the lanes of tile_lanes); extra arguments follow the record.
+template <typename Kern, typename L, typename... Args>
+void launch_tiles(Kern k, const L& a0, size_t lds, hipStream_t st, Args... args) {
+  L a = a0;
+  a.cpl = a.te / tile_lanes(reinterpret_cast<const void*>(k), a.te, lds, a.cpl > 0 ? a.te / a.cpl : 0);
+  launch_lds(k, dim3(unsigned(a.ntiles)), dim3(unsigned(a.te / a.cpl)), lds, st, a, args...);
+}
+
+namespace dev {
+
+// Cell of tile t that lane threadIdx.x takes in pass c: a tile of a.te cells runs on
+// a.te / a.cpl lanes in a.cpl passes, pass c holding tile cells [c * lanes, (c + 1) * lanes).
+// Lanes beyond a smaller tile (batched launches) get a.nel (no cell).
+template <typename L>
+__device__ __forceinline__ int64_t tile_cell(const L& a, int64_t t, int c) {
+  const int lanes = a.te / a.cpl;
+  return int(threadIdx.x) < lanes ? t * a.te + int64_t(c) * lanes + threadIdx.x : a.nel;
+}
+
+// Add one pass's per-cell contributions ye into the tile's LDS sums, one wave after the
+// other (passes in order), so that the sums are bitwise reproducible.
 template <int VT, typename L>
-__device__ __forceinline__ void diag_flush(const L& a, int64_t t, int64_t e, const int (&li)[VT],
-                                           const double (&ye)[VT], double* ys, double* __restrict__ out) {
-  const int nw = (a.te + 63) >> 6, me = int(threadIdx.x >> 6);
+__device__ __forceinline__ void diag_accumulate(const L& a, int64_t e, const int (&li)[VT], const double (&ye)[VT],
+                                                double* ys) {
+  const int nw = (a.te / a.cpl + 63) >> 6, me = int(threadIdx.x >> 6);
   for (int wv = 0; wv < nw; ++wv) {
     if (me == wv && e < a.nel) sfor<VT>([&](auto J) { atomicAdd(&ys[li[J]], ye[J]); });
     __syncthreads();
   }
+}
+
+// Store a tile's sums: exclusive dofs to out, Dirichlet rows 1, shared dofs to the
+// staging buffer for the second pass, which adds them in a fixed order.  The diagonal is
+// the same bit for bit from run to run.
+template <typename L>
+__device__ __forceinline__ void diag_store(const L& a, int64_t t, const double* ys, double* __restrict__ out) {
   const int64_t o0 = a.tile_off[t], nd = a.tile_off[t + 1] - o0;
   double* stage = a.stage + a.stage_off[t];
   for (int64_t j = threadIdx.x; j < nd; j += blockDim.x) {

@@ -73,19 +73,18 @@ __global__ __launch_bounds__(512, DOGIP_WPE) void k_apply_q(ApplyLaunch a) {
 
 template <int D, int K, int KIND>
 bool launch_apply_q_t(int prec, bool energy, const ApplyLaunch& a, hipStream_t st) {
-  const dim3 grid(unsigned(a.ntiles)), block(unsigned(a.te));
   if (prec == DOGIP_F64) {
     const size_t lds = size_t(a.lds_slots) * (sizeof(double) + sizeof(double));
     if (energy)
-      hipLaunchKernelGGL((k_apply_q<D, K, KIND, double, true>), grid, block, lds, st, a);
+      launch_tiles((k_apply_q<D, K, KIND, double, true>), a, lds, st);
     else
-      hipLaunchKernelGGL((k_apply_q<D, K, KIND, double, false>), grid, block, lds, st, a);
+      launch_tiles((k_apply_q<D, K, KIND, double, false>), a, lds, st);
   } else {
     const size_t lds = size_t(a.lds_slots) * (sizeof(double) + sizeof(float));
     if (energy)
-      hipLaunchKernelGGL((k_apply_q<D, K, KIND, float, true>), grid, block, lds, st, a);
+      launch_tiles((k_apply_q<D, K, KIND, float, true>), a, lds, st);
     else
-      hipLaunchKernelGGL((k_apply_q<D, K, KIND, float, false>), grid, block, lds, st, a);
+      launch_tiles((k_apply_q<D, K, KIND, float, false>), a, lds, st);
   }
   return true;
 }
@@ -100,7 +99,8 @@ __global__ __launch_bounds__(512) void k_diag_q(ApplyLaunch a, double* __restric
   const int64_t o0 = a.tile_off[t], nd = a.tile_off[t + 1] - o0;
   for (int64_t j = threadIdx.x; j < nd; j += blockDim.x) ys[j] = 0.0;
   __syncthreads();
-  const int64_t e = t * a.te + threadIdx.x;
+  for (int c = 0; c < a.cpl; ++c) {
+  const int64_t e = tile_cell(a, t, c);
   int li[VT];
   double ye[VT];
   if (e < a.nel) {
@@ -131,13 +131,14 @@ __global__ __launch_bounds__(512) void k_diag_q(ApplyLaunch a, double* __restric
       });
     }
   }
-  diag_flush<VT>(a, t, e, li, ye, ys, out);
+  diag_accumulate<VT>(a, e, li, ye, ys);
+  }
+  diag_store(a, t, ys, out);
 }
 
 template <int D, int K, int KIND>
 void diag_q_t(const ApplyLaunch& a, double* out, hipStream_t st) {
-  hipLaunchKernelGGL((k_diag_q<D, K, KIND>), dim3(unsigned(a.ntiles)), dim3(unsigned(a.te)),
-                     size_t(a.lds_slots) * sizeof(double), st, a, out);
+  launch_tiles((k_diag_q<D, K, KIND>), a, size_t(a.lds_slots) * sizeof(double), st, out);
 }
 
 }  // namespace dev

@@ -3,6 +3,9 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "internal.hpp"
 #include "reftab.hpp"
@@ -84,12 +87,68 @@ static void set_invdiag(Op& op, const double* diag, hipStream_t st) {
   }
 }
 
-// Default tile size (waves of 64 cells): 8 for 3D orders >= 3, where the larger tile
-// shares fewer dofs (3D 64^3 P3: apply 4% faster than 4 waves); 4 elsewhere, where
-// 8 waves measured equal or slower.
-// 8-wave tiles in 3D from P2 on (3D 64^3 P2: FP32 apply 0.0995 against 0.1025 ms with 4 waves),
-// else 4
-static int default_tile_waves(const Space& s) { return (s.dim == 3 && s.k >= 2) ? 8 : 4; }
+// Default tile size in waves of 64 cells.  Element-wise operators take large tiles where
+// that measured faster, run in passes by fewer lanes: the per-tile gather, accumulation
+// and flush are paid once per tile and fewer partial sums are staged (3D 64^3 P3, 1536-cell
+// tiles against 512: FP64 apply 0.51 -> 0.46 ms, FP32 0.30 -> 0.29 ms; 3D 64^3 P2, 3072
+// against 512: 0.159 -> 0.149 and 0.105 -> 0.094 ms; 2D 512^2 P3, 1024 against 256: 0.061 ->
+// 0.054 and 0.0435 -> 0.041 ms).  On the unit-cube meshes 1536 and 3072 cells are aligned
+// 8 x 8 x 4 and 8 x 8 x 8 blocks of cubes.  Large tiles are reduced while the mesh would
+// give fewer than two tiles per compute unit (2D 256^2 P3: 1024-cell tiles 25% slower
+// than 256).  The matrix-core variant and the global form keep at most 8 waves, 3D P4
+// 8, other orders 4 (2D 512^2 P5: 8 waves equal to 4 within noise).
+static int default_tile_waves(const Space& s, int variant, bool global_w) {
+  if (variant == DOGIP_VARIANT_MFMA || global_w) return (s.dim == 3 && s.k >= 2) ? 8 : 4;
+  int tw = 4;
+  if (s.dim == 3 && s.k == 2) tw = 48;
+  if (s.dim == 3 && s.k == 3) tw = 24;
+  if (s.dim == 3 && s.k >= 4) tw = 8;
+  if (s.dim == 2 && s.k == 3) tw = 16;
+  const int64_t min_tiles = 512;  // two per compute unit
+  while (tw > 4 && (s.nc + 64 * tw - 1) / (64 * tw) < min_tiles) tw = tw > 8 ? tw / 2 : 4;
+  return tw;
+}
+
+// The next smaller tile (in waves) tried when a tile's LDS arrays exceed the budget.
+static int smaller_tile(int w) {
+  static const int sizes[] = {48, 32, 24, 16, 12, 8, 6, 4, 3, 2, 1};
+  for (int x : sizes)
+    if (x < w) return x;
+  return 1;
+}
+
+int tile_lanes(const void* kernel, int te, size_t lds, int requested) {
+  static std::mutex mu;
+  static std::map<std::tuple<const void*, int, size_t>, std::pair<int, int>> cache;  // (auto lanes, max lanes)
+  const auto key = std::make_tuple(kernel, te, lds);
+  std::pair<int, int> c{0, 0};
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) c = it->second;
+  }
+  if (c.first == 0) {
+    hipFuncAttributes fa{};
+    HIPCHK(hipFuncGetAttributes(&fa, kernel));
+    if (lds > 65536) HIPCHK(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+    int best = 0, best_waves = 0;
+    for (int lanes = 64; lanes <= te && lanes <= fa.maxThreadsPerBlock; lanes += 64) {
+      if (te % lanes) continue;
+      int blocks = 0;
+      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernel, lanes, lds));
+      const int waves = blocks * (lanes / 64);
+      if (waves > best_waves) best = lanes, best_waves = waves;  // ties keep the fewer lanes
+    }
+    DOGIP_CHECK(best > 0, DOGIP_E_RANGE, "no workgroup shape fits the tile's LDS arrays");
+    c = {best, fa.maxThreadsPerBlock};
+    std::lock_guard<std::mutex> g(mu);
+    cache[key] = c;
+  }
+  if (requested <= 0) return c.first;
+  DOGIP_CHECK(requested % 64 == 0 && te % requested == 0 && requested <= c.second, DOGIP_E_RANGE,
+              "requested lanes do not fit this tile kernel");
+  return requested;
+}
 
 static void check_coef(const Space& s, int coef_kind) {
   DOGIP_CHECK(coef_kind >= DOGIP_COEF_SCALAR && coef_kind <= DOGIP_COEF_RAW_D, DOGIP_E_RANGE, "unknown coefficient form");
@@ -147,7 +206,7 @@ std::unique_ptr<Op> make_op(std::shared_ptr<const Space> sp, int coef_kind, cons
   const Space& s = *sp;
   check_coef(s, coef_kind);
   DOGIP_CHECK(coef != nullptr, DOGIP_E_NULL, "null coefficient pointer");
-  DOGIP_CHECK(tile_waves >= 0 && tile_waves <= 8, DOGIP_E_RANGE, "tile_waves must be 0..8");
+  DOGIP_CHECK(tile_waves >= 0 && tile_waves <= 48, DOGIP_E_RANGE, "tile_waves must be 0..48");
   DOGIP_CHECK(variant >= DOGIP_VARIANT_AUTO && variant <= DOGIP_VARIANT_MFMA, DOGIP_E_RANGE, "unknown variant");
   DOGIP_CHECK((flags & ~(DOGIP_OP_FP32 | DOGIP_OP_GLOBAL_W)) == 0, DOGIP_E_RANGE, "unknown operator flag");
   auto op = std::make_unique<Op>();
@@ -164,19 +223,20 @@ std::unique_ptr<Op> make_op(std::shared_ptr<const Space> sp, int coef_kind, cons
   DOGIP_CHECK(variant != DOGIP_VARIANT_MFMA || !op->global_w, DOGIP_E_RANGE,
               "the matrix-core apply needs the element-wise D");
   op->variant = variant;
-  // tile size: requested (default 4 waves), halved until the LDS arrays fit in 64 KB
-  // (FP64 tiles hold 16 bytes per dof; the matrix-core FP32 kernel 12 bytes per dof and its
-  // 19 KB of B^ operand tables)
-  auto lds = [&](int64_t slots) {
-    return std::max<int64_t>(16 * slots, variant == DOGIP_VARIANT_MFMA ? mfma_lds_tables() + 12 * slots : 0);
-  };
-  int te = 64 * (tile_waves ? tile_waves : default_tile_waves(s));
+  // tile size: requested or the default, stepped down until the LDS arrays fit (FP64 tiles
+  // hold 16 bytes per dof; the matrix-core FP32 kernel, one cell per lane, 12 bytes per dof
+  // and its 19 KB of B^ operand tables within 64 KB)
+  const bool mfma = variant == DOGIP_VARIANT_MFMA;
+  auto lds = [&](int64_t slots) { return mfma ? std::max<int64_t>(16 * slots, mfma_lds_tables() + 12 * slots) : 16 * slots; };
+  const int64_t budget = mfma ? 65536 : LDS_TILE_MAX;
+  int tw = tile_waves ? tile_waves : default_tile_waves(s, variant, op->global_w);
   for (;;) {
-    op->plan = make_tiles(s, te);
-    if (lds(op->plan.max_tile_dofs) <= 65536 || te == 64) break;
-    te /= 2;
+    op->plan = make_tiles(s, 64 * tw);
+    if (lds(op->plan.max_tile_dofs) <= budget || tw == 1) break;
+    tw = smaller_tile(tw);
   }
-  DOGIP_CHECK(lds(op->plan.max_tile_dofs) <= 65536, DOGIP_E_RANGE, "tile dofs exceed the LDS budget");
+  DOGIP_CHECK(lds(op->plan.max_tile_dofs) <= budget, DOGIP_E_RANGE, "tile dofs exceed the LDS budget");
+  DOGIP_CHECK(!mfma || op->plan.te <= 512, DOGIP_E_RANGE, "the matrix-core apply takes tiles of at most 8 waves");
   if (op->global_w) op->gplan = make_global_plan(s, op->plan);
   const TilePlan& p = op->plan;
   op->nch64 = d_chunks(s.wt, s.nsym, 2);
@@ -400,6 +460,8 @@ static ApplyLaunch apply_args(const Op& op, int prec) {
   a.nch = prec == DOGIP_F64 ? op.nch64 : op.nch32;
   a.nlc = op.plan.nlc;
   a.te = op.plan.te;
+  const int lanes = prec == DOGIP_F64 ? op.plan.lanes64 : op.plan.lanes32;
+  a.cpl = lanes ? op.plan.te / lanes : 0;
   a.lds_slots = int(op.plan.max_tile_dofs);
   a.tile_base = 0;
   a.stage_off = op.stage_off.as<int64_t>();
@@ -507,6 +569,7 @@ void op_diag(Op& op, double* diag, hipStream_t st) {
   a.nch = op.nch64;
   a.nlc = op.plan.nlc;
   a.te = op.plan.te;
+  a.cpl = 0;
   a.lds_slots = int(op.plan.max_tile_dofs);
   a.stage = op.stage.as<double>();
   a.stage_off = op.stage_off.as<int64_t>();
@@ -520,6 +583,17 @@ void op_diag(Op& op, double* diag, hipStream_t st) {
   }
   HIPCHK(hipGetLastError());
   finish();
+}
+
+void op_set_tile_lanes(Op& op, int lanes64, int lanes32) {
+  const int te = op.plan.te;
+  for (int l : {lanes64, lanes32})
+    DOGIP_CHECK(l == 0 || (l > 0 && l <= 1024 && l % 64 == 0 && te % l == 0), DOGIP_E_RANGE,
+                "lanes must be 0 or a multiple of 64 up to 1024 dividing the tile's cells");
+  DOGIP_CHECK(op.variant != DOGIP_VARIANT_MFMA || lanes32 == 0 || lanes32 == te, DOGIP_E_RANGE,
+              "the matrix-core apply takes one cell per lane");
+  op.plan.lanes64 = lanes64;
+  op.plan.lanes32 = lanes32;
 }
 
 void op_grad(Op& op, const double* u, const double* lam, double* g, hipStream_t st) {
@@ -540,6 +614,7 @@ void op_grad(Op& op, const double* u, const double* lam, double* g, hipStream_t 
   a.nch = op.nch64;
   a.nlc = op.plan.nlc;
   a.te = op.plan.te;
+  a.cpl = 0;
   a.lds_slots = int(op.plan.max_tile_dofs);
   launch_grad(s.dim, s.k, s.kind, a, st);
   HIPCHK(hipGetLastError());

@@ -208,6 +208,11 @@ class Operator:
         check(lib().dogip_op_set_coef(self.h, COEF[coef_kind], _dev_ptr(coef), stream_ptr(stream)))
         torch.cuda.current_stream().synchronize()
 
+    def set_tile_lanes(self, lanes64: int = 0, lanes32: int = 0):
+        """Lanes of the workgroup that takes one tile of the FP64 / FP32 apply (0: chosen for
+        occupancy); the results do not depend on it."""
+        check(lib().dogip_op_set_tile_lanes(self.h, int(lanes64), int(lanes32)))
+
     def apply(self, u, y=None, prec: str = "f64", stream=None):
         import torch
 

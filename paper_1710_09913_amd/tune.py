@@ -1,6 +1,7 @@
-"""Autotuner for the apply kernels: picks the tile size (cells per workgroup) and the
-element-kernel variant per (dim, k, kind, precision) by timing candidates on a
-representative structured mesh, and caches the choice as JSON.
+"""Autotuner for the apply kernels: picks the tile size (cells per tile, taken by one
+workgroup in passes when larger than its lanes) and the element-kernel variant per
+(dim, k, kind, precision) by timing candidates on a representative structured mesh, and
+caches the choice as JSON.
 
     python -m paper_1710_09913_amd.tune --dim 2 --kind se --k 1 2 3 4 --prec f64 f32
 
@@ -17,7 +18,7 @@ import os
 
 from . import capi
 
-TILE_WAVES = (1, 2, 4, 8)
+TILE_WAVES = (1, 2, 4, 8, 12, 16, 24, 48)  # cells per tile / 64; tiles above 8 waves run in passes
 
 
 def cache_path() -> str:
@@ -59,7 +60,7 @@ def _mesh_size(dim, k, cells_target):
 
 
 def tune(dim, k, kind, prec="f64", cells_target=400_000, reps=20, tile_waves=TILE_WAVES, variants=None,
-         max_tile_cells=512, verbose=False, tag="") -> dict:
+         max_tile_cells=3072, verbose=False, tag="") -> dict:
     """Time every candidate on a unit mesh of about cells_target cells; store and return the
     best under the key of (dim, k, kind, prec, tag)."""
     import torch
@@ -79,7 +80,7 @@ def tune(dim, k, kind, prec="f64", cells_target=400_000, reps=20, tile_waves=TIL
     rows = []
     for var in variants:
         for tw in tile_waves:
-            if 64 * tw > max_tile_cells:
+            if 64 * tw > max_tile_cells or (var == capi.DOGIP_VARIANT_MFMA and tw > 8):
                 continue
             op = Operator(space, coef, "scalar", fp32=(prec == "f32"), tile_waves=tw, variant=var)
             if op.info["tile_cells"] != 64 * tw:  # shrunk to fit the LDS budget: duplicate candidate
@@ -115,7 +116,7 @@ def main(argv=None):
     ap.add_argument("--k", type=int, nargs="+", default=[1, 2, 3, 4])
     ap.add_argument("--prec", nargs="+", default=["f64", "f32"])
     ap.add_argument("--cells", type=int, default=400_000)
-    ap.add_argument("--max-tile-cells", type=int, default=512)
+    ap.add_argument("--max-tile-cells", type=int, default=3072)
     a = ap.parse_args(argv)
     for k in a.k:
         for prec in a.prec:
