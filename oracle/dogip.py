@@ -20,6 +20,9 @@ Pinned by the identity B^^T D B^ = A against ``fem`` (tests/test_oracle_dogip.py
 tests/test_oracle_apply_abs.py: it equals the assembled operator where nothing is
 negative, lies between sum_T |A_T||u_T| and |A u| by the triangle inequality, is the
 absolute textbook P1 stiffness on the reference simplex, and keeps Dirichlet rows.
+``apply_abs_factored`` is the same scale for an apply that forms B^ u_T through the
+factors of ``reference.bhat_factors`` (the gradient at the P_{k-1} nodes, then P_{k-1}
+interpolation to the W nodes); pinned in tests/test_oracle_factored.py.
 """
 
 from __future__ import annotations
@@ -31,7 +34,7 @@ import numpy as np
 from . import fem
 from . import reference as ref
 
-__all__ = ["build_d", "apply", "apply_dirichlet", "apply_abs", "diagonal", "energy_contraction"]
+__all__ = ["build_d", "apply", "apply_dirichlet", "apply_abs", "apply_abs_factored", "diagonal", "energy_contraction"]
 
 
 def build_d(space: fem.Space, coef, kind: str, nquad: int | None = None) -> np.ndarray:
@@ -110,6 +113,29 @@ def apply_abs(space: fem.Space, D: np.ndarray, u: np.ndarray, kind: str, dirichl
     for s in range(0, cd.shape[0], 65536):
         c = cd[s:s + 65536]
         yT = _element_products(B, np.abs(D[s:s + 65536]), ua[c], kind)
+        y += np.bincount(c.reshape(-1), weights=yT.reshape(-1), minlength=space.ndofs)
+    if dirichlet:
+        y[space.boundary] = np.abs(u[space.boundary])
+    return y
+
+
+def apply_abs_factored(space: fem.Space, D: np.ndarray, u: np.ndarray, dirichlet: bool) -> np.ndarray:
+    """|B1|^T (I (x) |B2|)^T |D| (I (x) |B2|) |B1| |u| per cell, summed (elliptic problem):
+    the rounding scale of an apply through the factors B^_r = B2 B1_r."""
+    B1, B2 = ref.bhat_factors(space.d, space.k)
+    B1, B2 = np.abs(B1), np.abs(B2)
+    ua = np.abs(u).copy()
+    if dirichlet:
+        ua[space.boundary] = 0.0
+    cd = space.cell_dofs
+    y = np.zeros(space.ndofs)
+    for s in range(0, cd.shape[0], 65536):
+        c = cd[s:s + 65536]
+        G = np.einsum("rjv,ev->erj", B1, ua[c])                 # |B1| |u_T|, per component and P_{k-1} node
+        g = np.einsum("ij,erj->eir", B2, G)                     # |B2| (.) at the W nodes
+        h = np.einsum("eirs,eis->eir", np.abs(D[s:s + 65536]), g)
+        H = np.einsum("ij,eir->erj", B2, h)                     # |B2|^T (.)
+        yT = np.einsum("rjv,erj->ev", B1, H)                    # |B1|^T (.)
         y += np.bincount(c.reshape(-1), weights=yT.reshape(-1), minlength=space.ndofs)
     if dirichlet:
         y[space.boundary] = np.abs(u[space.boundary])

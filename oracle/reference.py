@@ -21,6 +21,11 @@ and converted to float64 once at the end.
   sum_i x_i^alpha w_i = (1/|T^|) int_T^ x^alpha for all |alpha| <= q,
   with int_T^ x^alpha = prod_r alpha_r! / (|alpha| + d)!.
 
+* Factored elliptic B^ (Section 4's outlook: a cheaper interpolation-projection operator):
+  the gradient of a P_k function is a vector field of degree k-1, so it is fixed by its
+  values at the P_{k-1} lattice and reproduced at the W nodes by P_{k-1} interpolation:
+  B^_r = B2 B1_r with B1_rjl = d phi^_l / d x^_r (x^_{k-1, j}) and B2_ij = phi^{k-1}_j(x^_W^i).
+
 Pins (tests/test_oracle_reference.py): nnz B^ and the count of entries equal to
 +-1 for every row of Tables 1-4; closed Newton-Cotes weights of the P2 triangle
 and tetrahedron; sum of weights; partition of unity; the collapsed Gauss rule
@@ -44,6 +49,8 @@ __all__ = [
     "basis_coefficients",
     "bhat_exact",
     "bhat",
+    "bhat_factors_exact",
+    "bhat_factors",
     "what_exact",
     "what",
     "nnz_counts",
@@ -175,6 +182,42 @@ def bhat(d: int, k: int, kind: str) -> np.ndarray:
     b = bhat_exact(d, k, kind)
     return np.array([[[float(v) for v in row] for row in blk] for blk in b]) if kind == "se" \
         else np.array([[float(v) for v in row] for row in b])
+
+
+@lru_cache(maxsize=None)
+def bhat_factors_exact(d: int, k: int):
+    """Exact factors of the elliptic B^: (B1 [d][P_{k-1} nodes][V_T], B2 [W_T][P_{k-1} nodes]).
+    The gradient of phi^_l at the P_{k-1} lattice, and the P_{k-1} nodal basis at the W
+    nodes (P_{2k-2} lattice); for k = 1 both lattices are the centroid and B2 = [[1]]."""
+    p = k - 1
+    jnodes = lattice(d, p)
+    alphas = multi_indices(d, k)
+    c = basis_coefficients(d, k)
+    vt = len(alphas)
+    b1 = []
+    for r in range(d):
+        rows = []
+        for x in jnodes:
+            mg = [_mono_grad(x, a, r) for a in alphas]
+            rows.append(tuple(sum((mg[m] * c[m][l] for m in range(vt)), Fraction(0)) for l in range(vt)))
+        b1.append(tuple(rows))
+    wnodes = lattice(d, 2 * k - 2)
+    if p == 0:
+        b2 = tuple((Fraction(1),) for _ in wnodes)
+    else:
+        pa = multi_indices(d, p)
+        pc = basis_coefficients(d, p)
+        nj = len(pa)
+        b2 = tuple(tuple(sum((_mono(x, pa[m]) * pc[m][j] for m in range(nj)), Fraction(0)) for j in range(nj))
+                   for x in wnodes)
+    return tuple(b1), b2
+
+
+def bhat_factors(d: int, k: int):
+    """The factors of bhat_factors_exact as float64 arrays (d, NJ, V_T) and (W_T, NJ)."""
+    b1, b2 = bhat_factors_exact(d, k)
+    return (np.array([[[float(v) for v in row] for row in blk] for blk in b1]),
+            np.array([[float(v) for v in row] for row in b2]))
 
 
 def _flatten(b):
