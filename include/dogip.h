@@ -148,6 +148,12 @@ extern "C" {
  * accumulation rounds, as in the vector kernel.  The FP32 copy of D is held in this
  * variant's own layout.  Not accepted by dogip_batch_create. */
 #define DOGIP_VARIANT_MFMA 3
+/* Elliptic problem, k >= 2 (2D k <= 5, 3D k <= 3): B^ applied in factored form
+ * (Section 4's cheaper interpolation-projection operator): grad u_T in P_{k-1} is formed
+ * at the P_{k-1} lattice nodes (B1), then interpolated to the W nodes (B2, exact since W
+ * holds degree 2k-2 >= k-1), and the transpose likewise; B^ = (I_d x B2) B1 exactly, with
+ * 534 instead of 1014 multiply-adds per product at 3D P3.  Same D, same layout. */
+#define DOGIP_VARIANT_FACTORED 4
 
 typedef struct dogip_mesh_s* dogip_mesh;
 typedef struct dogip_space_s* dogip_space;
@@ -246,6 +252,11 @@ int dogip_space_boundary(dogip_space s, int32_t* bnd);
 /* host copies of B^ ([nb][wt][vt], Theorems 2/4) and of w^ ([wt], w^_i =
  * int_T^ phi^W_i / |T^|); either pointer may be NULL. */
 int dogip_space_bhat(dogip_space s, double* bhat, double* what);
+/* host copies of the factors of the elliptic B^ that DOGIP_VARIANT_FACTORED applies:
+ * b1 [dim][n1][vt], the gradient of the P_k basis at the n1 = dim P_{k-1} lattice nodes,
+ * and b2 [wt][n1], the P_{k-1} basis at the W nodes (B^_r = b2 b1_r); either pointer may
+ * be NULL.  DOGIP_E_RANGE where the variant does not exist (projection, k = 1, 3D k = 4). */
+int dogip_space_bhat_factors(dogip_space s, double* b1, double* b2);
 void dogip_space_destroy(dogip_space s);
 
 /* ---- operator: D in device memory, tiles, Jacobi diagonal ---- */

@@ -46,6 +46,7 @@ DOGIP_VARIANT_AUTO = 0
 DOGIP_VARIANT_UNROLLED = 1
 DOGIP_VARIANT_LOOPED = 2
 DOGIP_VARIANT_MFMA = 3
+DOGIP_VARIANT_FACTORED = 4
 DOGIP_NOALLOC_MAX_STAGE = 1 << 22
 
 
@@ -96,6 +97,7 @@ SIGNATURES = {
     "dogip_space_cell_dofs": (C.c_int, [H, P]),
     "dogip_space_boundary": (C.c_int, [H, P]),
     "dogip_space_bhat": (C.c_int, [H, P, P]),
+    "dogip_space_bhat_factors": (C.c_int, [H, P, P]),
     "dogip_space_destroy": (None, [H]),
     "dogip_op_create": (C.c_int, [H, C.c_int, P, C.c_uint, C.c_int, C.c_int, P, PH]),
     "dogip_quadrature": (C.c_int, [C.c_int, C.c_int, P, P]),

@@ -211,6 +211,16 @@ int dogip_space_bhat(dogip_space s, double* bhat, double* what) {
   });
 }
 
+int dogip_space_bhat_factors(dogip_space s, double* b1, double* b2) {
+  return guard([&] {
+    need(s);
+    const auto& sp = *s->s;
+    DOGIP_CHECK(dogip::has_factored(sp.dim, sp.k, sp.kind), DOGIP_E_RANGE, "no factored B^ for this space");
+    dogip::factored_tables(sp.dim, sp.k, b1, b2);
+    return DOGIP_OK;
+  });
+}
+
 void dogip_space_destroy(dogip_space s) { delete s; }
 
 // ---- operator ----

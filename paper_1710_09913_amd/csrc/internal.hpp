@@ -301,6 +301,9 @@ int64_t mfma_lds_tables();  // bytes of LDS the matrix-core kernel adds to a til
 bool has_mfma(int dim, int k, int kind);
 bool launch_apply_global(int dim, int k, int prec, int variant, const ApplyLaunch& a, hipStream_t st);
 bool has_unrolled(int dim, int k, int kind);
+bool has_factored(int dim, int k, int kind);
+// host copies of the factored elliptic B^ tables (DOGIP_VARIANT_FACTORED); false if none
+bool factored_tables(int dim, int k, double* b1, double* b2);
 
 struct DiagLaunch {
   const double* D;

@@ -113,8 +113,11 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
   };
   // the first D chunks of each cell are requested before the gather (and those of the next
   // pass before this pass's LDS accumulation), so their latency overlaps it (element-wise
-  // form, unrolled body, FP64 D: measured 2% faster there and 1.7% slower with FP32 D)
-  constexpr bool PRE = MODE == 0 && VARIANT == DOGIP_VARIANT_UNROLLED && sizeof(T) == 8;
+  // form, compile-time B^).  FP64 D: 2% faster with one pass per tile.  FP32 D: 1.7% slower
+  // with one pass (a wave per SIMD lost to the registers), 2.4% faster at 3D P3, whose
+  // 1536-cell tiles run 12 waves per compute unit, within the 168 VGPRs of 3 waves per SIMD.
+  constexpr bool PRE = MODE == 0 && (VARIANT == DOGIP_VARIANT_UNROLLED || VARIANT == DOGIP_VARIANT_FACTORED) &&
+                       (sizeof(T) == 8 || (D == 3 && K == 3));
   typename E::V pre[E::NPRE];
   auto preload = [&](int c) {
     if constexpr (PRE) {
@@ -206,8 +209,9 @@ bool launch_apply_g_t(int prec, bool energy, const ApplyLaunch& a, hipStream_t s
 
 template <int D, int K, int KIND, int VARIANT>
 bool launch_apply_t(int prec, bool energy, const ApplyLaunch& a, hipStream_t st) {
-  constexpr int P64 = VARIANT == DOGIP_VARIANT_UNROLLED ? DOGIP_PF64 : 0;
-  constexpr int P32 = VARIANT == DOGIP_VARIANT_UNROLLED ? DOGIP_PF32 : 0;
+  constexpr bool UNR = VARIANT == DOGIP_VARIANT_UNROLLED || VARIANT == DOGIP_VARIANT_FACTORED;
+  constexpr int P64 = UNR ? DOGIP_PF64 : 0;
+  constexpr int P32 = UNR ? DOGIP_PF32 : 0;
   if (prec == DOGIP_F64) {
     const size_t lds = size_t(a.lds_slots) * (sizeof(double) + sizeof(double));
     if (energy)

@@ -88,6 +88,11 @@ struct CT {
   static constexpr ref::BTable<D, K, KIND> t{};
 };
 
+template <int D, int K>
+struct CF {
+  static constexpr ref::FTable<D, K> t{};
+};
+
 // The same table in device constant memory, in the compute precision, for the
 // looped element body (wave-uniform index -> scalar loads).
 template <int D, int K, int KIND, typename T>
@@ -136,7 +141,81 @@ struct Elem {
                                           const V* pre = nullptr) {
     T en = T(0);
     sfor<VT>([&](auto L) { ye[L] = T(-0.0); });
-    if constexpr (VARIANT == DOGIP_VARIANT_UNROLLED) {
+    if constexpr (VARIANT == DOGIP_VARIANT_FACTORED) {
+      // B^ = (I (x) B2) B1: G = B1 u_T (the gradient at the P_{k-1} nodes), per W node
+      // g = B2_i G, h = D_i g, H += B2_i^T h, and y_T = B1^T H at the end
+      using FT = ref::FTable<D, K>;
+      constexpr int NJ = FT::NJ;
+      T G[NB][NJ], H[NB][NJ];
+      sfor<NB>([&](auto R) {
+        sfor<NJ>([&](auto J) {
+          T acc = T(-0.0);
+          sfor<VT>([&](auto L) {
+            constexpr double b = CF<D, K>::t.b1[R][J][L];
+            if constexpr (b == 1.0)
+              acc = acc + ue[L];
+            else if constexpr (b == -1.0)
+              acc = acc - ue[L];
+            else if constexpr (b != 0.0)
+              acc = fma_t(T(b), ue[L], acc);
+          });
+          G[R][J] = acc;
+          H[R][J] = T(-0.0);
+        });
+      });
+      V ch[NCH];
+      sfor<WT>([&](auto I) {
+        if constexpr (PRE && I == 0)
+          sfor<NPRE>([&](auto J) { ch[J] = pre[J]; });
+        else
+          sfor_range<first_chunk(I), (I + 1 < WT ? first_chunk(I + 1) : NCH)>(
+              [&](auto J) { ch[J] = ld_stream(dp + J * 64); });
+        T g[NB];
+        sfor<NB>([&](auto R) {
+          T acc = T(-0.0);
+          sfor<NJ>([&](auto J) {
+            constexpr double b = CF<D, K>::t.b2[I][J];
+            if constexpr (b == 1.0)
+              acc = acc + G[R][J];
+            else if constexpr (b != 0.0)
+              acc = fma_t(T(b), G[R][J], acc);
+          });
+          g[R] = acc;
+        });
+        T dv[S];
+        sfor<S>([&](auto C) {
+          constexpr int f = I * S + C;
+          dv[C] = T(ch[f / VEC][f % VEC]);
+        });
+        T h[NB];
+        dmul<NB, S>(dv, g, h);
+        if constexpr (ENERGY) sfor<NB>([&](auto R) { en = fma_t(g[R], h[R], en); });
+        sfor<NB>([&](auto R) {
+          sfor<NJ>([&](auto J) {
+            constexpr double b = CF<D, K>::t.b2[I][J];
+            if constexpr (b == 1.0)
+              H[R][J] = H[R][J] + h[R];
+            else if constexpr (b != 0.0)
+              H[R][J] = fma_t(T(b), h[R], H[R][J]);
+          });
+        });
+      });
+      sfor<VT>([&](auto L) {
+        T acc = T(-0.0);
+        sfor<NB>([&](auto R) {
+          sfor<NJ>([&](auto J) {
+            constexpr double b = CF<D, K>::t.b1[R][J][L];
+            if constexpr (b == 1.0)
+              acc = acc + H[R][J];
+            else if constexpr (b == -1.0)
+              acc = acc - H[R][J];
+            else if constexpr (b != 0.0)
+              acc = fma_t(T(b), H[R][J], acc);
+          });
+        });
+        ye[L] = acc;
+      });
+    } else if constexpr (VARIANT == DOGIP_VARIANT_UNROLLED) {
       V ch[NCH];
       sfor<WT>([&](auto I) {
         if constexpr (PRE && I == 0)

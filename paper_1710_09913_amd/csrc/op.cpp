@@ -47,6 +47,7 @@ struct OpTimer {
 
 bool launch_apply_unrolled_2d(int k, int kind, int prec, bool energy, const ApplyLaunch& a, hipStream_t st);
 bool launch_apply_unrolled_3d(int k, int kind, int prec, bool energy, const ApplyLaunch& a, hipStream_t st);
+bool launch_apply_factored(int dim, int k, int prec, bool energy, const ApplyLaunch& a, hipStream_t st);
 bool launch_apply_looped_2d(int k, int kind, int prec, bool energy, const ApplyLaunch& a, hipStream_t st);
 bool launch_apply_looped_3d(int k, int kind, int prec, bool energy, const ApplyLaunch& a, hipStream_t st);
 
@@ -57,12 +58,15 @@ bool has_unrolled(int dim, int k, int kind) {
 
 bool has_mfma(int dim, int k, int kind) { return dim == 3 && k == 3 && kind == KIND_SE; }
 
+bool has_factored(int dim, int k, int kind) { return kind == KIND_SE && k >= 2 && k <= (dim == 2 ? 5 : 3); }
+
 bool launch_apply(int dim, int k, int kind, int prec, int variant, const ApplyLaunch& a, hipStream_t st) {
   const bool en = a.energy != nullptr;
   if (variant == DOGIP_VARIANT_MFMA) {
     if (prec == DOGIP_F32) return launch_apply_mfma(en, a, st);
     variant = DOGIP_VARIANT_UNROLLED;  // FP64 applies take the unrolled vector kernel
   }
+  if (variant == DOGIP_VARIANT_FACTORED) return launch_apply_factored(dim, k, prec, en, a, st);
   if (variant == DOGIP_VARIANT_UNROLLED)
     return dim == 2 ? launch_apply_unrolled_2d(k, kind, prec, en, a, st)
                     : launch_apply_unrolled_3d(k, kind, prec, en, a, st);
@@ -207,7 +211,7 @@ std::unique_ptr<Op> make_op(std::shared_ptr<const Space> sp, int coef_kind, cons
   check_coef(s, coef_kind);
   DOGIP_CHECK(coef != nullptr, DOGIP_E_NULL, "null coefficient pointer");
   DOGIP_CHECK(tile_waves >= 0 && tile_waves <= 48, DOGIP_E_RANGE, "tile_waves must be 0..48");
-  DOGIP_CHECK(variant >= DOGIP_VARIANT_AUTO && variant <= DOGIP_VARIANT_MFMA, DOGIP_E_RANGE, "unknown variant");
+  DOGIP_CHECK(variant >= DOGIP_VARIANT_AUTO && variant <= DOGIP_VARIANT_FACTORED, DOGIP_E_RANGE, "unknown variant");
   DOGIP_CHECK((flags & ~(DOGIP_OP_FP32 | DOGIP_OP_GLOBAL_W)) == 0, DOGIP_E_RANGE, "unknown operator flag");
   auto op = std::make_unique<Op>();
   op->space = sp;
@@ -222,6 +226,8 @@ std::unique_ptr<Op> make_op(std::shared_ptr<const Space> sp, int coef_kind, cons
               "the matrix-core apply covers the 3D P3 elliptic operator only");
   DOGIP_CHECK(variant != DOGIP_VARIANT_MFMA || !op->global_w, DOGIP_E_RANGE,
               "the matrix-core apply needs the element-wise D");
+  DOGIP_CHECK(variant != DOGIP_VARIANT_FACTORED || has_factored(s.dim, s.k, s.kind), DOGIP_E_RANGE,
+              "the factored B^ covers the elliptic problem with 2 <= k <= 5 (2D), 3 (3D)");
   op->variant = variant;
   // tile size: requested or the default, stepped down until the LDS arrays fit (FP64 tiles
   // hold 16 bytes per dof; the matrix-core FP32 kernel, one cell per lane, 12 bytes per dof

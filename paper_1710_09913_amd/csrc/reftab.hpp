@@ -295,5 +295,36 @@ struct BTable {
   }
 };
 
+// Factored elliptic B^ (k >= 2): the gradient of u in P_k is a vector field in P_{k-1},
+// so B^ = (I_d (x) B2) B1 exactly, with
+//   B1[r][j][l] = d phi^V_l / d x^_r at node j of the P_{k-1} lattice, and
+//   B2[i][j]    = phi^{k-1}_j (x^W_i), the P_{k-1} Lagrange basis at the W nodes (P_{2k-2}).
+// W nodes that are P_{k-1} nodes give unit rows of B2.  At 3D P3 the two factors have 216
+// + 3 x 106 nonzeros (against 1014 in B^), at 2D P5 436 + 2 x 255 (against 1516).
+template <int D, int K>
+struct FTable {
+  static constexpr int VT = dim_p(D, K);
+  static constexpr int NJ = dim_p(D, K - 1);
+  static constexpr int WT = dim_p(D, 2 * K - 2);
+  double b1[D][NJ][VT] = {};
+  double b2[WT][NJ] = {};
+  constexpr FTable() {
+    static_assert(K >= 2, "the factored form needs k >= 2");
+    for (int j = 0; j < NJ; ++j) {
+      Q lam[4];
+      int b[4] = {0, 0, 0, 0};
+      bary_index(D, K - 1, j, b);
+      for (int t = 0; t <= D; ++t) lam[t] = Q(b[t], K - 1);
+      for (int l = 0; l < VT; ++l)
+        for (int r = 0; r < D; ++r) b1[r][j][l] = to_double(basis_grad(D, K, l, r, lam));
+    }
+    for (int i = 0; i < WT; ++i) {
+      Q lam[4];
+      w_node_bary(D, 2 * K - 2, i, lam);
+      for (int j = 0; j < NJ; ++j) b2[i][j] = to_double(basis_value(D, K - 1, j, lam));
+    }
+  }
+};
+
 }  // namespace ref
 }  // namespace dogip

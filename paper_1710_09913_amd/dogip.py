@@ -5,6 +5,7 @@ step of the method runs in the library's HIP kernels.
 from __future__ import annotations
 
 import ctypes as C
+import math
 
 import numpy as np
 
@@ -127,6 +128,17 @@ class Space:
         w = np.empty(i["wt"])
         check(lib().dogip_space_bhat(self.h, b.ctypes.data_as(C.c_void_p), w.ctypes.data_as(C.c_void_p)))
         return b, w
+
+    def bhat_factors(self):
+        """The factors of the elliptic B^ applied by DOGIP_VARIANT_FACTORED: b1 [dim][n1][vt]
+        (gradient of the basis at the P_{k-1} lattice), b2 [wt][n1] (P_{k-1} basis at the W
+        nodes)."""
+        i = self.info
+        n1 = math.comb(i["k"] - 1 + i["dim"], i["dim"])
+        b1 = np.empty((i["dim"], n1, i["vt"]))
+        b2 = np.empty((i["wt"], n1))
+        check(lib().dogip_space_bhat_factors(self.h, b1.ctypes.data_as(C.c_void_p), b2.ctypes.data_as(C.c_void_p)))
+        return b1, b2
 
     def __del__(self):
         if getattr(self, "h", None) and capi._lib is not None:

@@ -77,6 +77,8 @@ def tune(dim, k, kind, prec="f64", cells_target=400_000, reps=20, tile_waves=TIL
         variants = (capi.DOGIP_VARIANT_UNROLLED, capi.DOGIP_VARIANT_LOOPED) if has_unrolled else (capi.DOGIP_VARIANT_LOOPED,)
         if dim == 3 and k == 3 and kind == "se" and prec == "f32":  # the matrix-core FP32 apply
             variants = variants + (capi.DOGIP_VARIANT_MFMA,)
+        if kind == "se" and 2 <= k <= (5 if dim == 2 else 3):  # the factored B^
+            variants = variants + (capi.DOGIP_VARIANT_FACTORED,)
     rows = []
     for var in variants:
         for tw in tile_waves:

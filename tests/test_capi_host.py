@@ -55,6 +55,24 @@ def test_bhat_what_match_oracle(d, k, kind):
     assert (s.info["nnz_bhat"], s.info["nnz_pm1_bhat"]) == (nnz, pm1)
 
 
+@pytest.mark.parametrize("d,k", [(2, 2), (2, 3), (2, 4), (2, 5), (3, 2), (3, 3)])
+def test_bhat_factors_match_oracle(d, k):
+    """The factor tables DOGIP_VARIANT_FACTORED is compiled with (barycentric product form,
+    constexpr) equal the oracle's (Vandermonde inverse, rationals) after rounding, and
+    spaces without the variant are refused."""
+    from paper_1710_09913_amd import Mesh, Space
+    from paper_1710_09913_amd.capi import DogipError
+
+    s = Space(Mesh.unit(d, 1), k, "se", "none")
+    b1, b2 = s.bhat_factors()
+    o1, o2 = ref.bhat_factors(d, k)
+    np.testing.assert_array_equal(b1, o1)
+    np.testing.assert_array_equal(b2, o2)
+    for bad in ((d, 1, "se"), (d, 2, "wp")):
+        with pytest.raises(DogipError):
+            Space(Mesh.unit(bad[0], 1), bad[1], bad[2], "none").bhat_factors()
+
+
 @pytest.mark.parametrize("d,n", [(2, 5), (3, 3)])
 def test_unit_mesh_matches_generator(d, n):
     from paper_1710_09913_amd import Mesh
