@@ -53,6 +53,16 @@ __device__ __forceinline__ void gather_batch(const uint32_t* __restrict__ td, in
   }
 }
 
+// Tile entries j0 + g * blockDim.x of one batch (TD_BND past the end).
+__device__ __forceinline__ void load_entries(const uint32_t* __restrict__ td, int64_t nd, int64_t j0,
+                                             uint32_t (&e)[GB]) {
+#pragma unroll
+  for (int g = 0; g < GB; ++g) {
+    const int64_t j = j0 + int64_t(g) * blockDim.x;
+    e[g] = j < nd ? td[j] : TD_BND;
+  }
+}
+
 // Flush of one batch: shared entries -> staging (second pass sums them), exclusive
 // entries -> y; Dirichlet entries are written by the second pass.
 template <bool ENERGY, typename T, typename VY, typename A>
@@ -75,13 +85,15 @@ __device__ __forceinline__ void flush_batch(const uint32_t (&e)[GB], int64_t nd,
 // stored in T); the per-tile accumulation in LDS is always FP64 (ds_add_f64; FP32
 // accumulation, which would halve the LDS arrays, measured 10-45% slower).  The
 // flush reads the tile's entries again rather than holding them in registers through
-// the element passes (the FP32 kernel then needs 128 VGPRs, 4 waves per SIMD, instead
-// of 133).  energy_out: where the
+// the element passes (which took the FP32 kernel from 128 to 133 VGPRs).  energy_out: where the
 // tile's sum_T u_T^T A_T u_T goes (ENERGY only).  MODE 1: global projection form, D
 // holds one value per W dof in the per-wave layout of GlobalPlan; MODE 2: the
 // conventional quadrature-point apply (ElemQ).
-// V32: FP32 input and output vectors (a.u32, a.y32).
-template <int D, int K, int KIND, typename T, int VARIANT, bool ENERGY, int PF, int MODE = 0, bool V32 = false>
+// V32: FP32 input and output vectors (a.u32, a.y32).  MP: tiles in passes (a.cpl); without it
+// one pass (cpl 1), which lets the compiler keep fewer values live (2D P5 FP64: 165 VGPRs,
+// 3 waves per SIMD, against 243 with the pass loop).
+template <int D, int K, int KIND, typename T, int VARIANT, bool ENERGY, int PF, int MODE = 0, bool V32 = false,
+          bool MP = true>
 __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsigned char* smem, double* energy_out) {
   using E = Elem<D, K, KIND, T, T, VARIANT, false, PF>;
   constexpr int VT = dim_p(D, K);
@@ -104,7 +116,7 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
   }();
   // the tile's cells are taken in cpl passes of `lanes` cells, one per lane; pass c holds
   // tile cells [c * lanes, (c + 1) * lanes), i.e. global waves t * te / 64 + c * lanes / 64 + wave
-  const int lanes = a.te / a.cpl, me = int(threadIdx.x >> 6), nw = (lanes + 63) >> 6;
+  const int cpl = MP ? a.cpl : 1, lanes = a.te / cpl, me = int(threadIdx.x >> 6), nw = (lanes + 63) >> 6;
   auto cell_of = [&](int c) -> int64_t {
     return int(threadIdx.x) < lanes ? t * a.te + int64_t(c) * lanes + threadIdx.x : a.nel;
   };
@@ -117,7 +129,11 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
   // with one pass (a wave per SIMD lost to the registers), 2.4% faster at 3D P3, whose
   // 1536-cell tiles run 12 waves per compute unit, within the 168 VGPRs of 3 waves per SIMD.
   constexpr bool PRE = MODE == 0 && (VARIANT == DOGIP_VARIANT_UNROLLED || VARIANT == DOGIP_VARIANT_FACTORED) &&
-                       (sizeof(T) == 8 || (D == 3 && K == 3));
+                       (sizeof(T) == 8 || (D == 3 && K == 3 && VARIANT == DOGIP_VARIANT_UNROLLED));
+  // the flush's first entries are requested before the last accumulation, except by the
+  // factored kernels in passes, whose G and H arrays leave no registers for them (3D P3
+  // FP64 256 VGPRs and scratch)
+  constexpr bool EARLY_ENTRIES = !MP || VARIANT != DOGIP_VARIANT_FACTORED;
   typename E::V pre[E::NPRE];
   auto preload = [&](int c) {
     if constexpr (PRE) {
@@ -128,7 +144,7 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
   preload(0);
   for (int64_t j0 = threadIdx.x; j0 < nd; j0 += int64_t(GB) * blockDim.x) gather_batch<T>(td, nd, j0, uin, us, ys, ent);
   __syncthreads();
-  for (int c = 0; c < a.cpl; ++c) {
+  for (int c = 0;; ++c) {
     const int64_t e = cell_of(c);
     double yacc[VT];
     int sl[VT];
@@ -149,22 +165,29 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
       }
       sfor<VT>([&](auto L) { yacc[L] = double(ye[L]); sl[L] = li[L]; });
     }
-    if (c + 1 < a.cpl) preload(c + 1);
     // LDS accumulation one wave after the other (passes in order), so the sums are
     // bitwise reproducible
-    for (int wv = 0; wv < nw; ++wv) {
-      if (me == wv && e < a.nel) sfor<VT>([&](auto L) { atomicAdd(&ys[sl[L]], yacc[L]); });
-      __syncthreads();
+    auto accumulate = [&] {
+      for (int wv = 0; wv < nw; ++wv) {
+        if (me == wv && e < a.nel) sfor<VT>([&](auto L) { atomicAdd(&ys[sl[L]], yacc[L]); });
+        __syncthreads();
+      }
+    };
+    if (c + 1 < cpl) {
+      preload(c + 1);
+      accumulate();
+      continue;
     }
+    // last pass: the flush's first entries are requested before the accumulation, so their
+    // latency overlaps it (they are live only from here, not through the element passes)
+    if constexpr (EARLY_ENTRIES) load_entries(td, nd, threadIdx.x, ent);
+    accumulate();
+    break;
   }
   double* stage = a.stage + a.stage_off[t];
   double en = 0.0;
   for (int64_t j0 = threadIdx.x; j0 < nd; j0 += int64_t(GB) * blockDim.x) {
-#pragma unroll
-    for (int g = 0; g < GB; ++g) {
-      const int64_t j = j0 + int64_t(g) * blockDim.x;
-      ent[g] = j < nd ? td[j] : TD_BND;
-    }
+    if (!EARLY_ENTRIES || j0 != threadIdx.x) load_entries(td, nd, j0, ent);
     flush_batch<ENERGY>(ent, nd, j0, ys, us, stage, yout, en);
   }
   if constexpr (ENERGY) {
@@ -175,11 +198,29 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
 }
 
 // One workgroup per tile; workgroup -> tile mapping keeps each XCD on a contiguous range.
-template <int D, int K, int KIND, typename T, int VARIANT, bool ENERGY, int PF, bool V32 = false>
+template <int D, int K, int KIND, typename T, int VARIANT, bool ENERGY, int PF, bool V32, bool MP>
 __global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 768, DOGIP_WPE) void k_apply(ApplyLaunch a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t t = a.tile_base + xcd_tile(blockIdx.x, gridDim.x);
-  tile_body<D, K, KIND, T, VARIANT, ENERGY, PF, 0, V32>(a, t, smem, ENERGY ? a.energy + t : nullptr);
+  tile_body<D, K, KIND, T, VARIANT, ENERGY, PF, 0, V32, MP>(a, t, smem, ENERGY ? a.energy + t : nullptr);
+}
+
+// One pass (the kernel without the pass loop) when the tile fits the workgroup: the lanes
+// asked for equal the tile, or none were asked for and the tile is within the launch bound.
+// The factored kernels always take the pass loop (2D P5 FP64: 0.133 ms with it, 0.175 ms
+// without, where the straight-line body takes 254 VGPRs).
+template <int D, int K, int KIND, typename T, int VARIANT, bool ENERGY, int PF, bool V32>
+void launch_k_apply(const ApplyLaunch& a, size_t lds, hipStream_t st) {
+  const int bound = sizeof(T) == 8 ? 512 : 768;
+  if constexpr (VARIANT != DOGIP_VARIANT_FACTORED) {
+    if (a.cpl == 1 || (a.cpl <= 0 && a.te <= bound)) {
+      ApplyLaunch b = a;
+      b.cpl = 1;
+      launch_tiles((k_apply<D, K, KIND, T, VARIANT, ENERGY, PF, V32, false>), b, lds, st);
+      return;
+    }
+  }
+  launch_tiles((k_apply<D, K, KIND, T, VARIANT, ENERGY, PF, V32, true>), a, lds, st);
 }
 
 template <int D, int K, typename T, int VARIANT, bool ENERGY>
@@ -215,18 +256,18 @@ bool launch_apply_t(int prec, bool energy, const ApplyLaunch& a, hipStream_t st)
   if (prec == DOGIP_F64) {
     const size_t lds = size_t(a.lds_slots) * (sizeof(double) + sizeof(double));
     if (energy)
-      launch_tiles((k_apply<D, K, KIND, double, VARIANT, true, P64>), a, lds, st);
+      launch_k_apply<D, K, KIND, double, VARIANT, true, P64, false>(a, lds, st);
     else
-      launch_tiles((k_apply<D, K, KIND, double, VARIANT, false, P64>), a, lds, st);
+      launch_k_apply<D, K, KIND, double, VARIANT, false, P64, false>(a, lds, st);
   } else {
     const size_t lds = size_t(a.lds_slots) * (sizeof(double) + sizeof(float));
     if (a.u32) {
       if (!energy) return false;  // FP32 vectors: the CG iteration only
-      launch_tiles((k_apply<D, K, KIND, float, VARIANT, true, P32, true>), a, lds, st);
+      launch_k_apply<D, K, KIND, float, VARIANT, true, P32, true>(a, lds, st);
     } else if (energy) {
-      launch_tiles((k_apply<D, K, KIND, float, VARIANT, true, P32>), a, lds, st);
+      launch_k_apply<D, K, KIND, float, VARIANT, true, P32, false>(a, lds, st);
     } else {
-      launch_tiles((k_apply<D, K, KIND, float, VARIANT, false, P32>), a, lds, st);
+      launch_k_apply<D, K, KIND, float, VARIANT, false, P32, false>(a, lds, st);
     }
   }
   return true;

@@ -50,10 +50,10 @@ __global__ __launch_bounds__(256) void k_batch_apply(BatchLaunch bl) {
     constexpr int V = DOGIP_VARIANT_UNROLLED;
     constexpr int PF = sizeof(T) == 8 ? DOGIP_PF64 : DOGIP_PF32;
     switch (d.k) {
-      case 1: tile_body<D, 1, KIND, T, V, ENERGY, PF, 0, V32>(a, t, smem, eo); break;
-      case 2: tile_body<D, 2, KIND, T, V, ENERGY, PF, 0, V32>(a, t, smem, eo); break;
-      case 3: tile_body<D, 3, KIND, T, V, ENERGY, PF, 0, V32>(a, t, smem, eo); break;
-      default: tile_body<D, 4, KIND, T, V, ENERGY, PF, 0, V32>(a, t, smem, eo); break;
+      case 1: tile_body<D, 1, KIND, T, V, ENERGY, PF, 0, V32, false>(a, t, smem, eo); break;
+      case 2: tile_body<D, 2, KIND, T, V, ENERGY, PF, 0, V32, false>(a, t, smem, eo); break;
+      case 3: tile_body<D, 3, KIND, T, V, ENERGY, PF, 0, V32, false>(a, t, smem, eo); break;
+      default: tile_body<D, 4, KIND, T, V, ENERGY, PF, 0, V32, false>(a, t, smem, eo); break;
     }
     __syncthreads();
   }

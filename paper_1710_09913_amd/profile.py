@@ -45,7 +45,8 @@ def run(argv=None):
     ap.add_argument("--kind", default="se")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--copies", type=int, default=3)
-    ap.add_argument("--variant", type=int, default=0, help="element-kernel variant (3: matrix-core FP32 apply)")
+    ap.add_argument("--variant", type=int, default=0,
+                    help="element-kernel variant (3: matrix-core FP32 apply, 4: factored B^)")
     a = ap.parse_args(argv)
 
     import torch
