@@ -130,10 +130,10 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
   // 1536-cell tiles run 12 waves per compute unit, within the 168 VGPRs of 3 waves per SIMD.
   constexpr bool PRE = MODE == 0 && (VARIANT == DOGIP_VARIANT_UNROLLED || VARIANT == DOGIP_VARIANT_FACTORED) &&
                        (sizeof(T) == 8 || (D == 3 && K == 3 && VARIANT == DOGIP_VARIANT_UNROLLED));
-  // the flush's first entries are requested before the last accumulation, except by the
-  // factored kernels in passes, whose G and H arrays leave no registers for them (3D P3
-  // FP64 256 VGPRs and scratch)
-  constexpr bool EARLY_ENTRIES = !MP || VARIANT != DOGIP_VARIANT_FACTORED;
+  // the flush's first entries are requested before the last accumulation in one-pass tiles;
+  // in passes that cost more than it saved (3D 64^3 P2 FP64 Jacobi-PCG 0.056 -> 0.068 s,
+  // factored 3D P3: 256 VGPRs and scratch)
+  constexpr bool EARLY_ENTRIES = !MP;
   typename E::V pre[E::NPRE];
   auto preload = [&](int c) {
     if constexpr (PRE) {
