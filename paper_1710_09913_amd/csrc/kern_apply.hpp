@@ -141,6 +141,8 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
         E::preload(reinterpret_cast<const typename E::V*>(a.D) + (wave_of(c) * a.nch) * 64 + (threadIdx.x & 63), pre);
     }
   };
+  __shared__ int turn;  // the wave whose cells are added next (pass c, wave w: turn c * nw + w)
+  if (threadIdx.x == 0) turn = 0;
   preload(0);
   for (int64_t j0 = threadIdx.x; j0 < nd; j0 += int64_t(GB) * blockDim.x) gather_batch<T>(td, nd, j0, uin, us, ys, ent);
   __syncthreads();
@@ -165,12 +167,13 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
       }
       sfor<VT>([&](auto L) { yacc[L] = double(ye[L]); sl[L] = li[L]; });
     }
-    // LDS accumulation one wave after the other (passes in order), so the sums are
-    // bitwise reproducible
+    // LDS accumulation one wave after the other (passes in order, wave turns instead of a
+    // barrier per wave), so the sums are bitwise reproducible
     auto accumulate = [&] {
-      for (int wv = 0; wv < nw; ++wv) {
-        if (me == wv && e < a.nel) sfor<VT>([&](auto L) { atomicAdd(&ys[sl[L]], yacc[L]); });
-        __syncthreads();
+      if (me < nw) {
+        wait_turn(&turn, c * nw + me);
+        if (e < a.nel) sfor<VT>([&](auto L) { atomicAdd(&ys[sl[L]], yacc[L]); });
+        pass_turn(&turn);
       }
     };
     if (c + 1 < cpl) {
@@ -184,6 +187,7 @@ __device__ __forceinline__ void tile_body(const ApplyLaunch& a, int64_t t, unsig
     accumulate();
     break;
   }
+  __syncthreads();  // every wave's sums are in before the flush reads them
   double* stage = a.stage + a.stage_off[t];
   double en = 0.0;
   for (int64_t j0 = threadIdx.x; j0 < nd; j0 += int64_t(GB) * blockDim.x) {

@@ -480,6 +480,23 @@ void launch_tiles(Kern k, const L& a0, size_t lds, hipStream_t st, Args... args)
 
 namespace dev {
 
+// Ordered accumulation without workgroup barriers: the waves of a tile add their cells'
+// sums into LDS in a fixed order of turns 0, 1, 2, ... counted in LDS.  A wave polls (with
+// s_sleep) until the counter reaches its turn, adds, and passes the turn on with a release,
+// so every slot receives its terms in the same order as with a barrier after each wave, and
+// waves that are not adding go on with their next pass.  The wait is bounded (about 0.1 s
+// of polling, then the wave goes on unordered), so a broken turn sequence cannot hang.
+__device__ __forceinline__ void wait_turn(const int* turn, int my) {
+  for (int it = 0; __hip_atomic_load(turn, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != my; ++it) {
+    if (it > (1 << 22)) break;
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+__device__ __forceinline__ void pass_turn(int* turn) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  if ((threadIdx.x & 63) == 0) __hip_atomic_fetch_add(turn, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // Cell of tile t that lane threadIdx.x takes in pass c: a tile of a.te cells runs on
 // a.te / a.cpl lanes in a.cpl passes, pass c holding tile cells [c * lanes, (c + 1) * lanes).
 // Lanes beyond a smaller tile (batched launches) get a.nel (no cell).
