@@ -115,24 +115,33 @@ __device__ __forceinline__ void finish_entries(int64_t i0, const double* __restr
                                                const V* __restrict__ u, V* __restrict__ y, double& eb) {
   constexpr int E = FINISH_PER_THREAD;
   vec_t<uint32_t, 2> pr[E];
+  uint32_t m0[E], m1[E];
   int32_t dst[E];
   double p0[E], p1[E];
+  // step 1: indices (the range of further slots is requested with the pair, so a dof with more
+  // than two partials waits for one dependent load less)
 #pragma unroll
   for (int c = 0; c < E; ++c) {
     const int64_t i = i0 + int64_t(c) * FINISH_THREADS;
+    m0[c] = m1[c] = 0;
     if (i < nshared) {
       pr[c] = reinterpret_cast<const vec_t<uint32_t, 2>*>(pair)[i];
       dst[c] = shared[i];
+      m0[c] = more_off[i];
+      m1[c] = more_off[i + 1];
     } else if (i < nshared + nbnd) {
       dst[c] = bnd[i - nshared];
     }
   }
+  // step 2: the first two partials (or u on Dirichlet rows) and the first further slot
+  uint32_t s2[E];
 #pragma unroll
   for (int c = 0; c < E; ++c) {
     const int64_t i = i0 + int64_t(c) * FINISH_THREADS;
     if (i < nshared) {
       p0[c] = stage[pr[c][0]];
       p1[c] = stage[pr[c][1] & 0x7fffffffu];
+      if (m1[c] > m0[c]) s2[c] = more[m0[c]];
     } else if (i < nshared + nbnd) {
       p0[c] = double(u[dst[c]]);
     }
@@ -144,8 +153,10 @@ __device__ __forceinline__ void finish_entries(int64_t i0, const double* __restr
       double sum = 0.0;
       sum += p0[c];
       sum += p1[c];
-      if (pr[c][1] >> 31)
-        for (uint32_t j = more_off[i]; j < more_off[i + 1]; ++j) sum += stage[more[j]];
+      if (m1[c] > m0[c]) {
+        sum += stage[s2[c]];
+        for (uint32_t j = m0[c] + 1; j < m1[c]; ++j) sum += stage[more[j]];
+      }
       y[dst[c]] = V(sum);
     } else if (i < nshared + nbnd) {
       y[dst[c]] = V(p0[c]);
