@@ -81,19 +81,43 @@ void copy(double* dst, const double* src, int64_t n, hipStream_t st) {
 // the prolongation's CSR (fine rows) and its transpose (coarse rows), uploaded to level C
 void set_transfer(PmgLevel& C, int64_t nfine, int64_t ncoarse, const std::vector<int64_t>& prow,
                   const std::vector<int32_t>& pcol, const std::vector<double>& pval) {
-  // transpose, entries of a coarse row in ascending fine row
+  // transpose, entries of a coarse row in ascending fine row: the fine rows are cut into nr
+  // ranges, each range counts its entries per coarse row, the counts become offsets (coarse
+  // row major, range minor) and each range fills its entries in order, on host threads
+  const int64_t nr = 8, fchunk = (nfine + nr - 1) / nr;
+  std::vector<std::vector<int64_t>> cnt(size_t(nr), std::vector<int64_t>(size_t(ncoarse), 0));
+  parallel_tasks(nr, [&](int64_t t) {
+    auto& k = cnt[size_t(t)];
+    for (int64_t f = t * fchunk; f < std::min(nfine, (t + 1) * fchunk); ++f)
+      for (int64_t j = prow[f]; j < prow[f + 1]; ++j) k[size_t(pcol[j])]++;
+  });
   std::vector<int64_t> rrow(ncoarse + 1, 0);
-  for (int32_t c : pcol) rrow[c + 1]++;
+  parallel_for(ncoarse, [&](int64_t c) {
+    int64_t tot = 0;
+    for (int64_t t = 0; t < nr; ++t) tot += cnt[size_t(t)][size_t(c)];
+    rrow[c + 1] = tot;
+  });
   for (int64_t i = 0; i < ncoarse; ++i) rrow[i + 1] += rrow[i];
+  parallel_for(ncoarse, [&](int64_t c) {
+    int64_t at = rrow[c];
+    for (int64_t t = 0; t < nr; ++t) {
+      const int64_t n = cnt[size_t(t)][size_t(c)];
+      cnt[size_t(t)][size_t(c)] = at;
+      at += n;
+    }
+  });
   std::vector<int32_t> rcol(pcol.size());
   std::vector<double> rval(pcol.size());
-  std::vector<int64_t> fill(rrow.begin(), rrow.end() - 1);
-  for (int64_t f = 0; f < nfine; ++f)
-    for (int64_t j = prow[f]; j < prow[f + 1]; ++j) {
-      const int64_t at = fill[pcol[j]]++;
-      rcol[at] = int32_t(f);
-      rval[at] = pval[j];
-    }
+  parallel_tasks(nr, [&](int64_t t) {
+    auto& fill = cnt[size_t(t)];
+    for (int64_t f = t * fchunk; f < std::min(nfine, (t + 1) * fchunk); ++f)
+      for (int64_t j = prow[f]; j < prow[f + 1]; ++j) {
+        const int64_t at = fill[size_t(pcol[j])]++;
+        rcol[size_t(at)] = int32_t(f);
+        rval[size_t(at)] = pval[size_t(j)];
+      }
+  });
+  cnt.clear();
   auto up = [](DevBuf& b, const auto& v) {
     using T = typename std::decay_t<decltype(v)>::value_type;
     b.alloc(std::max<size_t>(v.size(), 1) * sizeof(T));
