@@ -375,7 +375,11 @@ int dogip_grad_logcoef(dogip_op op, const double* u, const double* lam, double* 
  * finish kernel, and after the finish.  dogip_op_timer_read synchronizes on the
  * last event and returns the summed milliseconds of the tile kernels and of
  * the finish kernels and the number of applies recorded, then resets.  Any
- * output pointer may be NULL. */
+ * output pointer may be NULL.  The events only time (created with
+ * hipEventDisableSystemFence, so that recording them does not write back and
+ * invalidate the caches inside the timed applies): waiting on them does not
+ * make the applies' outputs visible to the host; synchronize the stream for
+ * that. */
 int dogip_op_timer_enable(dogip_op op, int enable);
 int dogip_op_timer_read(dogip_op op, double* tile_ms_sum, double* finish_ms_sum, int64_t* count);
 void dogip_op_destroy(dogip_op op);

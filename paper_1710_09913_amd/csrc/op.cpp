@@ -34,15 +34,27 @@ void DevBuf::free() {
 }
 
 // Events before the tile kernel, between it and the finish kernel, and after the finish.
+// Per-apply launch timer: events before the tile kernel, between it and the second pass
+// and after it.  The events only time: they are made without the system-scope fence of a
+// default event (a writeback and invalidation of the caches at each record, which on
+// MI355X lengthened a timed apply by about 10 us), and are kept for reuse.
 struct OpTimer {
   bool on = false;
-  std::vector<std::array<hipEvent_t, 3>> ev;
-  void clear() {
+  std::vector<std::array<hipEvent_t, 3>> ev;  // ev[0, used) hold recorded applies
+  size_t used = 0;
+  std::array<hipEvent_t, 3>& next() {
+    if (used == ev.size()) {
+      std::array<hipEvent_t, 3> e{};
+      for (auto& x : e) HIPCHK(hipEventCreateWithFlags(&x, hipEventDisableSystemFence));
+      ev.push_back(e);
+    }
+    return ev[used++];
+  }
+  void clear() { used = 0; }
+  ~OpTimer() {
     for (auto& e : ev)
       for (auto x : e) (void)hipEventDestroy(x);
-    ev.clear();
   }
-  ~OpTimer() { clear(); }
 };
 
 bool launch_apply_unrolled_2d(int k, int kind, int prec, bool energy, const ApplyLaunch& a, hipStream_t st);
@@ -503,8 +515,7 @@ static void apply_impl(Op& op, const double* u, double* y, int prec, hipStream_t
   const bool timed = op.timer->on && stage == op.stage.as<double>();
   std::array<hipEvent_t, 3> ev{};
   if (timed) {
-    for (auto& x : ev) HIPCHK(hipEventCreate(&x));
-    op.timer->ev.push_back(ev);
+    ev = op.timer->next();
     HIPCHK(hipEventRecord(ev[0], st));
   }
   const bool ok = op.nq > 0     ? launch_apply_qp(s.dim, s.k, s.kind, prec, a, st)
@@ -672,7 +683,8 @@ void op_timer_enable(Op& op, bool on) { op.timer->on = on; }
 
 void op_timer_read(Op& op, double* tile_ms, double* finish_ms, int64_t* count) {
   double st = 0.0, sf = 0.0;
-  for (auto& e : op.timer->ev) {
+  for (size_t i = 0; i < op.timer->used; ++i) {
+    const auto& e = op.timer->ev[i];
     HIPCHK(hipEventSynchronize(e[2]));
     float t0 = 0.f, t1 = 0.f;
     HIPCHK(hipEventElapsedTime(&t0, e[0], e[1]));
@@ -682,7 +694,7 @@ void op_timer_read(Op& op, double* tile_ms, double* finish_ms, int64_t* count) {
   }
   if (tile_ms) *tile_ms = st;
   if (finish_ms) *finish_ms = sf;
-  if (count) *count = int64_t(op.timer->ev.size());
+  if (count) *count = int64_t(op.timer->used);
   op.timer->clear();
 }
 
