@@ -54,6 +54,41 @@ def tuned(dim, k, kind, prec="f64", tag=""):
     return (e["tile_waves"], e["variant"]) if e else (0, 0)
 
 
+BATCH_COPIES = 4  # operators in the batch that times a candidate for batched launches
+
+
+def _op_ms(op, u, y, prec, reps):
+    """Mean time of one apply (tile kernel + second pass, the operator's HIP-event timer)."""
+    import torch
+
+    for _ in range(3):
+        op.apply(u, y, prec=prec)
+    torch.cuda.synchronize()
+    op.timer_enable(True)
+    op.timer_read()
+    for _ in range(reps):
+        op.apply(u, y, prec=prec)
+    t, fin, cnt = op.timer_read()
+    op.timer_enable(False)
+    return (t + fin) / cnt
+
+
+def _batch_ms(bt, u, y, prec, reps):
+    """Mean time of one batched apply (HIP events on the current stream around reps applies)."""
+    import torch
+
+    for _ in range(3):
+        bt.apply(u, y, prec=prec)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        bt.apply(u, y, prec=prec)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
 def _mesh_size(dim, k, cells_target):
     per = 2 if dim == 2 else 6
     return max(2, int(round((cells_target / per) ** (1.0 / dim))))
@@ -62,15 +97,18 @@ def _mesh_size(dim, k, cells_target):
 def tune(dim, k, kind, prec="f64", cells_target=400_000, reps=20, tile_waves=TILE_WAVES, variants=None,
          max_tile_cells=3072, verbose=False, tag="") -> dict:
     """Time every candidate on a unit mesh of about cells_target cells; store and return the
-    best under the key of (dim, k, kind, prec, tag)."""
+    best under the key of (dim, k, kind, prec, tag).  With tag "batch" a candidate is timed
+    as the batched kernel runs it: BATCH_COPIES operators of the mesh in one batch, one
+    persistent launch per apply (the batched kernel weighs a tile's fixed costs differently
+    from the single-operator kernel, so the single-operator timing would mislead it)."""
     import torch
 
-    from .dogip import Mesh, Operator, Space
+    from .dogip import Batch, Mesh, Operator, Space
 
-    n = _mesh_size(dim, k, cells_target)
+    n = _mesh_size(dim, k, cells_target // BATCH_COPIES if tag == "batch" else cells_target)
     space = Space(Mesh.unit(dim, n), k, kind, "dirichlet" if kind == "se" else "none")
     coef = torch.ones(space.ncells, dtype=torch.float64)
-    u = torch.ones(space.ndofs, dtype=torch.float64, device="cuda")
+    u = torch.ones(space.ndofs * (BATCH_COPIES if tag == "batch" else 1), dtype=torch.float64, device="cuda")
     y = torch.empty_like(u)
     has_unrolled = (dim == 2 and k <= 5) or (dim == 3 and (k <= 3 if kind == "se" else k <= 2))
     if variants is None:
@@ -88,19 +126,16 @@ def tune(dim, k, kind, prec="f64", cells_target=400_000, reps=20, tile_waves=TIL
             if op.info["tile_cells"] != 64 * tw:  # shrunk to fit the LDS budget: duplicate candidate
                 del op
                 continue
-            for _ in range(3):
-                op.apply(u, y, prec=prec)
-            torch.cuda.synchronize()
-            op.timer_enable(True)
-            op.timer_read()
-            for _ in range(reps):
-                op.apply(u, y, prec=prec)
-            ms, fin, cnt = op.timer_read()
-            ms += fin
-            op.timer_enable(False)
-            rows.append({"tile_waves": tw, "variant": var, "ms": ms / cnt})
+            if tag == "batch":
+                ops = [op] + [Operator(space, coef, "scalar", fp32=(prec == "f32"), tile_waves=tw, variant=var)
+                              for _ in range(BATCH_COPIES - 1)]
+                ms = _batch_ms(Batch(ops), u, y, prec, reps)
+                del ops
+            else:
+                ms = _op_ms(op, u, y, prec, reps)
+            rows.append({"tile_waves": tw, "variant": var, "ms": ms})
             if verbose:
-                print(f"  {_key(dim, k, kind, prec)} tw={tw} var={var}: {ms / cnt:.4f} ms", flush=True)
+                print(f"  {_key(dim, k, kind, prec, tag)} tw={tw} var={var}: {ms:.4f} ms", flush=True)
             del op
     best = min(rows, key=lambda r: r["ms"])
     entry = {"tile_waves": best["tile_waves"], "variant": best["variant"], "ms": best["ms"],

@@ -1,6 +1,7 @@
 """The autotuner's choice against the library default on the tuning mesh: the tuned
 (tile_waves, variant) is never slower than the default configuration (to timing noise),
-and the default is among the candidates it timed."""
+and the default is among the candidates it timed.  For batched launches both are timed
+as the tuner times them, in batches of copies of the operator."""
 
 import statistics
 
@@ -36,6 +37,17 @@ def _ms_pair(a, b, u, y, prec, reps=20, rounds=7):
     return statistics.median(ta), statistics.median(tb)
 
 
+def _batch_ms_pair(a, b, u, y, prec, reps=20, rounds=7):
+    """The same for two batches (one persistent launch per apply, HIP events around reps)."""
+    from paper_1710_09913_amd import tune
+
+    ta, tb = [], []
+    for _ in range(rounds):
+        ta.append(tune._batch_ms(a, u, y, prec, reps))
+        tb.append(tune._batch_ms(b, u, y, prec, reps))
+    return statistics.median(ta), statistics.median(tb)
+
+
 @pytest.mark.parametrize("dim,k,prec,tag,max_cells,variants", [
     (2, 3, "f32", "", 512, None),
     (2, 2, "f32", "batch", 256, (1,)),
@@ -58,9 +70,21 @@ def test_tuned_not_slower_than_default(tmp_path, monkeypatch, dim, k, prec, tag,
     if (e["tile_waves"], e["variant"]) == dflt:
         return  # the tuner chose the default configuration: nothing to compare
     tuned = Operator(space, coef, "scalar", fp32=prec == "f32", tile_waves=e["tile_waves"], variant=e["variant"])
-    u = torch.ones(space.ndofs, dtype=torch.float64, device="cuda")
-    y = torch.empty_like(u)
-    t_def, t_tun = _ms_pair(default, tuned, u, y, prec)
+    if tag == "batch":  # compared as the tuner timed them: in batches of copies of the operator
+        from paper_1710_09913_amd import Batch
+
+        def copies(tw, var):
+            return [Operator(space, coef, "scalar", fp32=prec == "f32", tile_waves=tw, variant=var)
+                    for _ in range(tune.BATCH_COPIES)]
+
+        bd, bt = Batch(copies(*dflt)), Batch(copies(e["tile_waves"], e["variant"]))
+        u = torch.ones(bd.ndofs, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(u)
+        t_def, t_tun = _batch_ms_pair(bd, bt, u, y, prec)
+    else:
+        u = torch.ones(space.ndofs, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(u)
+        t_def, t_tun = _ms_pair(default, tuned, u, y, prec)
     print(f"[tune] default {dflt}: {t_def:.4f} ms, tuned {(e['tile_waves'], e['variant'])}: {t_tun:.4f} ms",
           flush=True)
     if default.info["tile_cells"] <= max_cells and (variants is None or dflt[1] in variants):
