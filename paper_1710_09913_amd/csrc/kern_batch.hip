@@ -193,7 +193,9 @@ __global__ __launch_bounds__(256) void k_b_xr(const int* __restrict__ act, const
   const double alpha = s.sc[p_of(act)].alpha;
   double v[2] = {0.0, 0.0};
   PROBLEM_RANGE(p, lo, hi) {
-    x[i] = fma(alpha, double(pv[i]), x[i]);
+    // the iterate is read and written once per iteration: non-temporal, so that the
+    // memory-side cache keeps the index arrays and directions of the next apply
+    __builtin_nontemporal_store(fma(alpha, double(pv[i]), __builtin_nontemporal_load(x + i)), x + i);
     const V ri = V(fma(-alpha, double(q[i]), double(r[i])));
     r[i] = ri;
     v[0] += double(ri) * (double(invd[i]) * double(ri));

@@ -8,6 +8,14 @@
 namespace dogip {
 namespace dev {
 
+// x += a p for the iterate of CG, which an iteration reads and writes once and does not
+// touch again before the next one: non-temporal accesses keep it out of the memory-side
+// cache, which then keeps the operator's index arrays and the direction that the next
+// apply reads (3D 64^3 P3 Jacobi-PCG to 1e-8: FP64 0.899 -> 0.858 s, mixed 0.507 -> 0.478 s).
+__device__ __forceinline__ void update_iterate(double* x, int64_t i, double a, double p) {
+  __builtin_nontemporal_store(fma(a, p, __builtin_nontemporal_load(x + i)), x + i);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
@@ -103,7 +111,7 @@ __global__ __launch_bounds__(256) void k_pcg_xr(double* __restrict__ x, double* 
   const double alpha = s->alpha;
   double v[2] = {0.0, 0.0};
   GRID_STRIDE(i, n) {
-    x[i] = fma(alpha, p[i], x[i]);
+    update_iterate(x, i, alpha, p[i]);
     const double ri = fma(-alpha, q[i], r[i]);
     r[i] = ri;
     v[0] += ri * (invd[i] * ri);
@@ -392,7 +400,7 @@ __global__ __launch_bounds__(256) void k_pcg_xr32(double* __restrict__ x, float*
   const double alpha = s->alpha;
   double v[2] = {0.0, 0.0};
   GRID_STRIDE(i, n) {
-    x[i] = fma(alpha, double(p[i]), x[i]);
+    update_iterate(x, i, alpha, double(p[i]));
     const float ri = float(fma(-alpha, double(q[i]), double(r[i])));
     r[i] = ri;
     v[0] += double(ri) * (double(invd[i]) * double(ri));
