@@ -11,7 +11,9 @@ namespace dev {
 // x += a p for the iterate of CG, which an iteration reads and writes once and does not
 // touch again before the next one: non-temporal accesses keep it out of the memory-side
 // cache, which then keeps the operator's index arrays and the direction that the next
-// apply reads (3D 64^3 P3 Jacobi-PCG to 1e-8: FP64 0.899 -> 0.858 s, mixed 0.507 -> 0.478 s).
+// apply reads (3D 64^3 P3 Jacobi-PCG to 1e-8: FP64 0.899 -> 0.856 s, mixed 0.507 -> 0.478 s).
+// With FP64 vectors A p and the inverse diagonal are read non-temporally as well (FP64
+// 0.856 -> 0.833 s); with FP32 vectors, which the cache holds more easily, that cost 0.5%.
 __device__ __forceinline__ void update_iterate(double* x, int64_t i, double a, double p) {
   __builtin_nontemporal_store(fma(a, p, __builtin_nontemporal_load(x + i)), x + i);
 }
@@ -112,9 +114,9 @@ __global__ __launch_bounds__(256) void k_pcg_xr(double* __restrict__ x, double* 
   double v[2] = {0.0, 0.0};
   GRID_STRIDE(i, n) {
     update_iterate(x, i, alpha, p[i]);
-    const double ri = fma(-alpha, q[i], r[i]);
+    const double ri = fma(-alpha, __builtin_nontemporal_load(q + i), r[i]);
     r[i] = ri;
-    v[0] += ri * (invd[i] * ri);
+    v[0] += ri * (__builtin_nontemporal_load(invd + i) * ri);
     v[1] += ri * ri;
   }
   block_partials(v, 2, part);
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(256) void k_pcg_p(double* __restrict__ p, const dou
                                                const double* __restrict__ invd, const PcgScalars* __restrict__ s,
                                                int64_t n) {
   const double beta = s->beta;
-  GRID_STRIDE(i, n) p[i] = fma(beta, p[i], invd[i] * r[i]);
+  GRID_STRIDE(i, n) p[i] = fma(beta, p[i], __builtin_nontemporal_load(invd + i) * r[i]);
 }
 
 // r = b - y; partial r.r
