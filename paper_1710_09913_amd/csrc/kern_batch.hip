@@ -183,6 +183,15 @@ __global__ __launch_bounds__(256) void k_b_fin_pq(const int* __restrict__ act, c
   }
 }
 
+// a vector element read once per iteration: non-temporal for FP64 vectors
+template <typename V>
+__device__ __forceinline__ V streamed(const V* a) {
+  if constexpr (sizeof(V) == 8)
+    return __builtin_nontemporal_load(a);
+  else
+    return *a;
+}
+
 template <typename V>
 __global__ __launch_bounds__(256) void k_b_xr(const int* __restrict__ act, const int64_t* __restrict__ voff,
                                               double* __restrict__ x, V* __restrict__ r,
@@ -194,11 +203,13 @@ __global__ __launch_bounds__(256) void k_b_xr(const int* __restrict__ act, const
   double v[2] = {0.0, 0.0};
   PROBLEM_RANGE(p, lo, hi) {
     // the iterate is read and written once per iteration: non-temporal, so that the
-    // memory-side cache keeps the index arrays and directions of the next apply
+    // memory-side cache keeps the index arrays and directions of the next apply; with FP64
+    // vectors A p and the inverse diagonal too (batched FP64 PCG 0.8% faster; with FP32
+    // vectors, which the cache holds more easily, they stay cached)
     __builtin_nontemporal_store(fma(alpha, double(pv[i]), __builtin_nontemporal_load(x + i)), x + i);
-    const V ri = V(fma(-alpha, double(q[i]), double(r[i])));
+    const V ri = V(fma(-alpha, double(streamed<V>(q + i)), double(r[i])));
     r[i] = ri;
-    v[0] += double(ri) * (double(invd[i]) * double(ri));
+    v[0] += double(ri) * (double(streamed<V>(invd + i)) * double(ri));
     v[1] += double(ri) * double(ri);
   }
   bpartials(v, 2, part, p_of(act));
@@ -237,7 +248,7 @@ __global__ __launch_bounds__(256) void k_b_p(const int* __restrict__ act, const 
                                              const V* __restrict__ invd, BatchPcgState s) {
   if (!s.active[p_of(act)]) return;
   const double beta = s.sc[p_of(act)].beta;
-  PROBLEM_RANGE(p, lo, hi) pv[i] = V(fma(beta, double(pv[i]), double(invd[i]) * double(r[i])));
+  PROBLEM_RANGE(p, lo, hi) pv[i] = V(fma(beta, double(pv[i]), double(streamed<V>(invd + i)) * double(r[i])));
 }
 
 // residual replacement for problems with need[p]: r = b - A64 x (the true r.r from the
