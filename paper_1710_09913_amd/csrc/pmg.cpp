@@ -36,6 +36,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <set>
 #include <utility>
 
@@ -56,6 +57,30 @@ constexpr double CHEB_RANGE_H = 20.0;
 // dense inverse (Cholesky on the host at set-up), a larger one by Jacobi-PCG
 constexpr int64_t DENSE_TARGET = 400;
 constexpr int64_t DENSE_MAX = 1000;
+
+// Host arrays of the transfers that are written in full after allocation: default-initialised
+// elements (no zeroing).  Zeroing the ~1.2 GB of them at 3D 64^3 P3 on one thread, only to
+// overwrite every element from host threads, took about a fifth of the set-up.
+template <class T>
+struct NoInit : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = NoInit<U>;
+  };
+  NoInit() = default;
+  template <class U>
+  NoInit(const NoInit<U>&) noexcept {}
+  template <class U>
+  void construct(U* p) noexcept {
+    ::new (static_cast<void*>(p)) U;
+  }
+  template <class U, class... A>
+  void construct(U* p, A&&... a) {
+    ::new (static_cast<void*>(p)) U(std::forward<A>(a)...);
+  }
+};
+template <class T>
+using RawVec = std::vector<T, NoInit<T>>;
 constexpr double COARSE_TOL = 0.1;
 constexpr int COARSE_MAXIT = 400;
 constexpr int POWER_ITERS = 15;
@@ -79,15 +104,18 @@ void copy(double* dst, const double* src, int64_t n, hipStream_t st) {
 }
 
 // the prolongation's CSR (fine rows) and its transpose (coarse rows), uploaded to level C
-void set_transfer(PmgLevel& C, int64_t nfine, int64_t ncoarse, const std::vector<int64_t>& prow,
-                  const std::vector<int32_t>& pcol, const std::vector<double>& pval) {
+template <class RowV, class ColV, class ValV>
+void set_transfer(PmgLevel& C, int64_t nfine, int64_t ncoarse, const RowV& prow, const ColV& pcol,
+                  const ValV& pval) {
   // transpose, entries of a coarse row in ascending fine row: the fine rows are cut into nr
   // ranges, each range counts its entries per coarse row, the counts become offsets (coarse
   // row major, range minor) and each range fills its entries in order, on host threads
   const int64_t nr = 8, fchunk = (nfine + nr - 1) / nr;
-  std::vector<std::vector<int64_t>> cnt(size_t(nr), std::vector<int64_t>(size_t(ncoarse), 0));
+  std::vector<RawVec<int64_t>> cnt(static_cast<size_t>(nr));
   parallel_tasks(nr, [&](int64_t t) {
     auto& k = cnt[size_t(t)];
+    k.resize(size_t(ncoarse));
+    std::fill(k.begin(), k.end(), int64_t(0));
     for (int64_t f = t * fchunk; f < std::min(nfine, (t + 1) * fchunk); ++f)
       for (int64_t j = prow[f]; j < prow[f + 1]; ++j) k[size_t(pcol[j])]++;
   });
@@ -106,8 +134,8 @@ void set_transfer(PmgLevel& C, int64_t nfine, int64_t ncoarse, const std::vector
       at += n;
     }
   });
-  std::vector<int32_t> rcol(pcol.size());
-  std::vector<double> rval(pcol.size());
+  RawVec<int32_t> rcol(pcol.size());
+  RawVec<double> rval(pcol.size());
   parallel_tasks(nr, [&](int64_t t) {
     auto& fill = cnt[size_t(t)];
     for (int64_t f = t * fchunk; f < std::min(nfine, (t + 1) * fchunk); ++f)
@@ -150,8 +178,8 @@ void set_transfer(PmgLevel& C, int64_t nfine, int64_t ncoarse, const std::vector
     const std::vector<uint64_t> keys(seen.begin(), seen.end());
     std::vector<double> tab(256, 0.0);
     for (size_t c = 0; c < keys.size(); ++c) std::memcpy(&tab[c], &keys[c], sizeof(double));
-    auto pack = [&](const std::vector<int32_t>& col, const std::vector<double>& val) {
-      std::vector<uint32_t> e(col.size());
+    auto pack = [&](const auto& col, const auto& val) {
+      RawVec<uint32_t> e(col.size());
       parallel_for(int64_t(col.size()), [&](int64_t j) {
         const auto at = std::lower_bound(keys.begin(), keys.end(), bits(val[size_t(j)])) - keys.begin();
         e[size_t(j)] = uint32_t(col[size_t(j)]) | (uint32_t(at) << 24);
@@ -178,8 +206,8 @@ void build_transfer(const Space& F, const Space& Cs, PmgLevel& C) {
   coarse_basis_at_nodes(d, F.k, tab);
   // each fine dof's row comes from its first cell node in cell order (the smallest
   // c * vf + l holding it); cells are scanned in parallel with an atomic minimum
-  std::vector<std::atomic<int64_t>> first(size_t(F.ndofs));
-  for (auto& a : first) a.store(INT64_MAX, std::memory_order_relaxed);
+  std::unique_ptr<std::atomic<int64_t>[]> first(new std::atomic<int64_t>[size_t(F.ndofs)]);
+  parallel_for(F.ndofs, [&](int64_t f) { first[size_t(f)].store(INT64_MAX, std::memory_order_relaxed); });
   parallel_for(F.nc, [&](int64_t c) {
     for (int l = 0; l < vf; ++l) {
       const int64_t v = c * vf + l;
@@ -192,15 +220,16 @@ void build_transfer(const Space& F, const Space& Cs, PmgLevel& C) {
   std::vector<int> nnz_l(size_t(vf), 0);
   for (int l = 0; l < vf; ++l)
     for (int cc = 0; cc < vc; ++cc) nnz_l[size_t(l)] += tab[size_t(l) * vc + cc] != 0.0 ? 1 : 0;
-  std::vector<int64_t> prow(F.ndofs + 1, 0);
+  RawVec<int64_t> prow(size_t(F.ndofs) + 1);
+  prow[0] = 0;
   for (int64_t f = 0; f < F.ndofs; ++f) {
     const int64_t v = first[size_t(f)].load(std::memory_order_relaxed);
     DOGIP_CHECK(v != INT64_MAX, DOGIP_E_INVALID, "dof held by no cell");
     prow[f + 1] = prow[f] + nnz_l[size_t(v % vf)];
   }
   const size_t nnz = static_cast<size_t>(prow[F.ndofs]);
-  std::vector<int32_t> pcol(nnz);
-  std::vector<double> pval(nnz);
+  RawVec<int32_t> pcol(nnz);
+  RawVec<double> pval(nnz);
   parallel_for(F.ndofs, [&](int64_t f) {
     const int64_t v = first[size_t(f)].load(std::memory_order_relaxed);
     const int64_t c = v / vf;
