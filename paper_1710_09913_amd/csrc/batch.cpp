@@ -236,6 +236,11 @@ int batch_pcg(Batch& b, const double* rhs, double* x, const dogip_solve_opts& o,
   v.p = w.p.as<double>();
   // mixed: r, p and A p in FP32 (x and the inner products FP64)
   v.v32 = mixed;
+  {
+    int64_t idx = 0;
+    for (const auto& op : b.ops) idx += int64_t(op->lidx.bytes + op->tile_dofs.bytes);
+    v.stream = stream_vectors(b.offsets.back(), mixed ? 24 : 40, idx);
+  }
   v.invd32 = b.invd32.as<float>();
   v.r32 = w.r32.as<float>();
   v.p32 = w.p32.as<float>();

@@ -61,6 +61,7 @@ struct BatchVecArgs {
   double* r;
   double* p;
   bool v32;             // mixed CG: r, p (and A p) stored in FP32
+  bool stream;          // vectors used once per iteration read and written non-temporally (stream_vectors)
   const float* invd32;
   float* r32;
   float* p32;

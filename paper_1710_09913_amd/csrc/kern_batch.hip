@@ -183,16 +183,17 @@ __global__ __launch_bounds__(256) void k_b_fin_pq(const int* __restrict__ act, c
   }
 }
 
-// a vector element read once per iteration: non-temporal for FP64 vectors
-template <typename V>
+// a vector element that an iteration reads once: non-temporal for FP64 vectors when S
+// (the host's stream_vectors over the whole batch)
+template <bool S, typename V>
 __device__ __forceinline__ V streamed(const V* a) {
-  if constexpr (sizeof(V) == 8)
+  if constexpr (S && sizeof(V) == 8)
     return __builtin_nontemporal_load(a);
   else
     return *a;
 }
 
-template <typename V>
+template <typename V, bool S>
 __global__ __launch_bounds__(256) void k_b_xr(const int* __restrict__ act, const int64_t* __restrict__ voff,
                                               double* __restrict__ x, V* __restrict__ r,
                                               const V* __restrict__ pv, const V* __restrict__ q,
@@ -202,14 +203,17 @@ __global__ __launch_bounds__(256) void k_b_xr(const int* __restrict__ act, const
   const double alpha = s.sc[p_of(act)].alpha;
   double v[2] = {0.0, 0.0};
   PROBLEM_RANGE(p, lo, hi) {
-    // the iterate is read and written once per iteration: non-temporal, so that the
+    // with S the iterate, read and written once per iteration, is non-temporal, so that the
     // memory-side cache keeps the index arrays and directions of the next apply; with FP64
     // vectors A p and the inverse diagonal too (batched FP64 PCG 0.8% faster; with FP32
     // vectors, which the cache holds more easily, they stay cached)
-    __builtin_nontemporal_store(fma(alpha, double(pv[i]), __builtin_nontemporal_load(x + i)), x + i);
-    const V ri = V(fma(-alpha, double(streamed<V>(q + i)), double(r[i])));
+    if constexpr (S)
+      __builtin_nontemporal_store(fma(alpha, double(pv[i]), __builtin_nontemporal_load(x + i)), x + i);
+    else
+      x[i] = fma(alpha, double(pv[i]), x[i]);
+    const V ri = V(fma(-alpha, double(streamed<S>(q + i)), double(r[i])));
     r[i] = ri;
-    v[0] += double(ri) * (double(streamed<V>(invd + i)) * double(ri));
+    v[0] += double(ri) * (double(streamed<S>(invd + i)) * double(ri));
     v[1] += double(ri) * double(ri);
   }
   bpartials(v, 2, part, p_of(act));
@@ -242,13 +246,13 @@ __global__ __launch_bounds__(256) void k_b_fin_rz(const int* __restrict__ act, c
   }
 }
 
-template <typename V>
+template <typename V, bool S>
 __global__ __launch_bounds__(256) void k_b_p(const int* __restrict__ act, const int64_t* __restrict__ voff,
                                              V* __restrict__ pv, const V* __restrict__ r,
                                              const V* __restrict__ invd, BatchPcgState s) {
   if (!s.active[p_of(act)]) return;
   const double beta = s.sc[p_of(act)].beta;
-  PROBLEM_RANGE(p, lo, hi) pv[i] = V(fma(beta, double(pv[i]), double(streamed<V>(invd + i)) * double(r[i])));
+  PROBLEM_RANGE(p, lo, hi) pv[i] = V(fma(beta, double(pv[i]), double(streamed<S>(invd + i)) * double(r[i])));
 }
 
 // residual replacement for problems with need[p]: r = b - A64 x (the true r.r from the
@@ -435,22 +439,33 @@ void bk_fin_pq(const BatchVecArgs& v, const double* energy, const int64_t* tile_
                        v.p, v.s);
 }
 void bk_xr(const BatchVecArgs& v, double* x, const void* q, hipStream_t st) {
-  if (v.v32)
-    hipLaunchKernelGGL(dev::k_b_xr<float>, dim3(v.gx, v.nact), dim3(256), 0, st, v.act, v.voff, x, v.r32, v.p32,
-                       static_cast<const float*>(q), v.invd32, v.s, v.part);
+  const dim3 g(v.gx, v.nact);
+  const auto* q32 = static_cast<const float*>(q);
+  const auto* q64 = static_cast<const double*>(q);
+  if (v.v32 && v.stream)
+    hipLaunchKernelGGL((dev::k_b_xr<float, true>), g, dim3(256), 0, st, v.act, v.voff, x, v.r32, v.p32, q32, v.invd32,
+                       v.s, v.part);
+  else if (v.v32)
+    hipLaunchKernelGGL((dev::k_b_xr<float, false>), g, dim3(256), 0, st, v.act, v.voff, x, v.r32, v.p32, q32, v.invd32,
+                       v.s, v.part);
+  else if (v.stream)
+    hipLaunchKernelGGL((dev::k_b_xr<double, true>), g, dim3(256), 0, st, v.act, v.voff, x, v.r, v.p, q64, v.invd, v.s,
+                       v.part);
   else
-    hipLaunchKernelGGL(dev::k_b_xr<double>, dim3(v.gx, v.nact), dim3(256), 0, st, v.act, v.voff, x, v.r, v.p,
-                       static_cast<const double*>(q), v.invd, v.s, v.part);
+    hipLaunchKernelGGL((dev::k_b_xr<double, false>), g, dim3(256), 0, st, v.act, v.voff, x, v.r, v.p, q64, v.invd,
+                       v.s, v.part);
 }
 void bk_fin_rz(const BatchVecArgs& v, double delta, int mixed, hipStream_t st) {
   hipLaunchKernelGGL(dev::k_b_fin_rz, dim3(v.nact), dim3(256), 0, st, v.act, v.part, v.gx, v.s, v.tol, delta, mixed);
 }
 void bk_p(const BatchVecArgs& v, hipStream_t st) {
-  if (v.v32)
-    hipLaunchKernelGGL(dev::k_b_p<float>, dim3(v.gx, v.nact), dim3(256), 0, st, v.act, v.voff, v.p32, v.r32, v.invd32,
-                       v.s);
+  const dim3 g(v.gx, v.nact);
+  if (v.v32)  // FP32 vectors: every load cached (streamed<S> is a plain load for them)
+    hipLaunchKernelGGL((dev::k_b_p<float, false>), g, dim3(256), 0, st, v.act, v.voff, v.p32, v.r32, v.invd32, v.s);
+  else if (v.stream)
+    hipLaunchKernelGGL((dev::k_b_p<double, true>), g, dim3(256), 0, st, v.act, v.voff, v.p, v.r, v.invd, v.s);
   else
-    hipLaunchKernelGGL(dev::k_b_p<double>, dim3(v.gx, v.nact), dim3(256), 0, st, v.act, v.voff, v.p, v.r, v.invd, v.s);
+    hipLaunchKernelGGL((dev::k_b_p<double, false>), g, dim3(256), 0, st, v.act, v.voff, v.p, v.r, v.invd, v.s);
 }
 void bk_replace(const BatchVecArgs& v, const double* b, const double* y, int mixed, hipStream_t st) {
   if (v.v32)

@@ -8,15 +8,26 @@
 namespace dogip {
 namespace dev {
 
-// x += a p for the iterate of CG, which an iteration reads and writes once and does not
-// touch again before the next one: non-temporal accesses keep it out of the memory-side
-// cache, which then keeps the operator's index arrays and the direction that the next
-// apply reads (3D 64^3 P3 Jacobi-PCG to 1e-8: FP64 0.899 -> 0.856 s, mixed 0.507 -> 0.478 s).
-// With FP64 vectors A p and the inverse diagonal are read non-temporally as well (FP64
-// 0.856 -> 0.833 s); with FP32 vectors, which the cache holds more easily, that cost 0.5%.
-// The multigrid's Chebyshev steps treat their iterate the same way (its solve 1-2% faster).
+// Accesses to vectors that a CG iteration (or smoother step) uses once: non-temporal when
+// S (the host's stream_vectors: the iteration's vectors and the operator's index arrays
+// exceed the memory-side cache), so that the cache keeps the index arrays and the
+// direction that the next apply reads; cached otherwise.  At 3D 64^3 P3, Jacobi-PCG to
+// 1e-8 with a non-temporal iterate: FP64 0.899 -> 0.856 s, mixed 0.507 -> 0.478 s; with
+// A p and the inverse diagonal too (FP64 vectors) 0.856 -> 0.833 s; the multigrid's
+// Chebyshev steps 1-2%.  Below the cache size the same accesses cost 2-4% (2D 512^2 P2-P4).
+template <bool S>
+__device__ __forceinline__ double load_once(const double* a) {
+  if constexpr (S)
+    return __builtin_nontemporal_load(a);
+  else
+    return *a;
+}
+template <bool S>
 __device__ __forceinline__ void update_iterate(double* x, int64_t i, double a, double p) {
-  __builtin_nontemporal_store(fma(a, p, __builtin_nontemporal_load(x + i)), x + i);
+  if constexpr (S)
+    __builtin_nontemporal_store(fma(a, p, __builtin_nontemporal_load(x + i)), x + i);
+  else
+    x[i] = fma(a, p, x[i]);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -107,6 +118,7 @@ __global__ __launch_bounds__(1024) void k_fin_pq(const double* __restrict__ ener
 }
 
 // x += alpha p, r -= alpha q, z = invd r; partials (r.z, r.r)
+template <bool S>
 __global__ __launch_bounds__(256) void k_pcg_xr(double* __restrict__ x, double* __restrict__ r,
                                                 const double* __restrict__ p, const double* __restrict__ q,
                                                 const double* __restrict__ invd, const PcgScalars* __restrict__ s,
@@ -114,10 +126,10 @@ __global__ __launch_bounds__(256) void k_pcg_xr(double* __restrict__ x, double* 
   const double alpha = s->alpha;
   double v[2] = {0.0, 0.0};
   GRID_STRIDE(i, n) {
-    update_iterate(x, i, alpha, p[i]);
-    const double ri = fma(-alpha, __builtin_nontemporal_load(q + i), r[i]);
+    update_iterate<S>(x, i, alpha, p[i]);
+    const double ri = fma(-alpha, load_once<S>(q + i), r[i]);
     r[i] = ri;
-    v[0] += ri * (__builtin_nontemporal_load(invd + i) * ri);
+    v[0] += ri * (load_once<S>(invd + i) * ri);
     v[1] += ri * ri;
   }
   block_partials(v, 2, part);
@@ -137,11 +149,12 @@ __global__ __launch_bounds__(1024) void k_fin_rz(const double* __restrict__ part
 }
 
 // p = invd r + beta p
+template <bool S>
 __global__ __launch_bounds__(256) void k_pcg_p(double* __restrict__ p, const double* __restrict__ r,
                                                const double* __restrict__ invd, const PcgScalars* __restrict__ s,
                                                int64_t n) {
   const double beta = s->beta;
-  GRID_STRIDE(i, n) p[i] = fma(beta, p[i], __builtin_nontemporal_load(invd + i) * r[i]);
+  GRID_STRIDE(i, n) p[i] = fma(beta, p[i], load_once<S>(invd + i) * r[i]);
 }
 
 // r = b - y; partial r.r
@@ -287,12 +300,13 @@ __global__ __launch_bounds__(256) void k_cheb_init(const double* __restrict__ r,
 }
 
 // one Chebyshev step after t = A d: x += d, r -= t, d = c1 d + c2 D^-1 r
+template <bool S>
 __global__ __launch_bounds__(256) void k_cheb_step(double* __restrict__ x, double* __restrict__ r,
                                                    double* __restrict__ d, const double* __restrict__ t,
                                                    const double* __restrict__ invd, double c1, double c2, int64_t n) {
   GRID_STRIDE(i, n) {
     const double di = d[i];
-    __builtin_nontemporal_store(__builtin_nontemporal_load(x + i) + di, x + i);  // as update_iterate
+    update_iterate<S>(x, i, 1.0, di);
     const double ri = r[i] - t[i];
     r[i] = ri;
     d[i] = fma(c1, di, c2 * invd[i] * ri);
@@ -353,13 +367,14 @@ __global__ __launch_bounds__(256) void k_cheb_init32(const float* __restrict__ r
                                                      float* __restrict__ d, double s, int64_t n) {
   GRID_STRIDE(i, n) d[i] = float(s * invd[i] * double(r[i]));
 }
+template <bool S>
 __global__ __launch_bounds__(256) void k_cheb_step32(double* __restrict__ x, float* __restrict__ r,
                                                      float* __restrict__ d, const float* __restrict__ t,
                                                      const double* __restrict__ invd, double c1, double c2,
                                                      int64_t n) {
   GRID_STRIDE(i, n) {
     const double di = double(d[i]);
-    __builtin_nontemporal_store(__builtin_nontemporal_load(x + i) + di, x + i);  // as update_iterate
+    update_iterate<S>(x, i, 1.0, di);
     const double ri = double(r[i]) - double(t[i]);
     r[i] = float(ri);
     d[i] = float(fma(c1, di, c2 * invd[i] * ri));
@@ -396,6 +411,7 @@ __global__ __launch_bounds__(256) void k_pcg_init32(const double* __restrict__ b
 }
 
 // x += alpha p, r -= alpha q, z = invd r; partials (r.z, r.r)
+template <bool S>
 __global__ __launch_bounds__(256) void k_pcg_xr32(double* __restrict__ x, float* __restrict__ r,
                                                   const float* __restrict__ p, const float* __restrict__ q,
                                                   const float* __restrict__ invd, const PcgScalars* __restrict__ s,
@@ -403,7 +419,7 @@ __global__ __launch_bounds__(256) void k_pcg_xr32(double* __restrict__ x, float*
   const double alpha = s->alpha;
   double v[2] = {0.0, 0.0};
   GRID_STRIDE(i, n) {
-    update_iterate(x, i, alpha, double(p[i]));
+    update_iterate<S>(x, i, alpha, double(p[i]));
     const float ri = float(fma(-alpha, double(q[i]), double(r[i])));
     r[i] = ri;
     v[0] += double(ri) * (double(invd[i]) * double(ri));
@@ -457,14 +473,21 @@ void vk_fin_pq(const double* energy, int64_t ntiles, PcgScalars* s, hipStream_t 
   hipLaunchKernelGGL(dev::k_fin_pq, dim3(1), dim3(1024), 0, st, energy, ntiles, s);
 }
 void vk_pcg_xr(double* x, double* r, const double* p, const double* q, const double* invd, const PcgScalars* s,
-               int64_t n, double* part, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_pcg_xr, dim3(RED_BLOCKS), dim3(256), 0, st, x, r, p, q, invd, s, n, part);
+               int64_t n, double* part, bool stream, hipStream_t st) {
+  if (stream)
+    hipLaunchKernelGGL(dev::k_pcg_xr<true>, dim3(RED_BLOCKS), dim3(256), 0, st, x, r, p, q, invd, s, n, part);
+  else
+    hipLaunchKernelGGL(dev::k_pcg_xr<false>, dim3(RED_BLOCKS), dim3(256), 0, st, x, r, p, q, invd, s, n, part);
 }
 void vk_fin_rz(const double* part, PcgScalars* s, double* hist, int it, hipStream_t st) {
   hipLaunchKernelGGL(dev::k_fin_rz, dim3(1), dim3(1024), 0, st, part, RED_BLOCKS, s, hist, it);
 }
-void vk_pcg_p(double* p, const double* r, const double* invd, const PcgScalars* s, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_pcg_p, dim3(red_grid(n) * 4), dim3(256), 0, st, p, r, invd, s, n);
+void vk_pcg_p(double* p, const double* r, const double* invd, const PcgScalars* s, int64_t n, bool stream,
+              hipStream_t st) {
+  if (stream)
+    hipLaunchKernelGGL(dev::k_pcg_p<true>, dim3(red_grid(n) * 4), dim3(256), 0, st, p, r, invd, s, n);
+  else
+    hipLaunchKernelGGL(dev::k_pcg_p<false>, dim3(red_grid(n) * 4), dim3(256), 0, st, p, r, invd, s, n);
 }
 void vk_resid(const double* b, const double* y, double* r, int64_t n, double* part, double* out, hipStream_t st) {
   hipLaunchKernelGGL(dev::k_resid, dim3(RED_BLOCKS), dim3(256), 0, st, b, y, r, n, part);
@@ -489,8 +512,11 @@ void vk_pcg_init32(const double* b, const double* y, const float* invd, float* r
 }
 
 void vk_pcg_xr32(double* x, float* r, const float* p, const float* q, const float* invd, const PcgScalars* s,
-                 int64_t n, double* part, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_pcg_xr32, dim3(RED_BLOCKS), dim3(256), 0, st, x, r, p, q, invd, s, n, part);
+                 int64_t n, double* part, bool stream, hipStream_t st) {
+  if (stream)
+    hipLaunchKernelGGL(dev::k_pcg_xr32<true>, dim3(RED_BLOCKS), dim3(256), 0, st, x, r, p, q, invd, s, n, part);
+  else
+    hipLaunchKernelGGL(dev::k_pcg_xr32<false>, dim3(RED_BLOCKS), dim3(256), 0, st, x, r, p, q, invd, s, n, part);
 }
 
 void vk_pcg_p32(float* p, const float* r, const float* invd, const PcgScalars* s, int64_t n, hipStream_t st) {
@@ -578,8 +604,11 @@ void vk_cheb_init(const double* r, const double* invd, double* d, double s, int6
   hipLaunchKernelGGL(dev::k_cheb_init, dim3(red_grid(n) * 4), dim3(256), 0, st, r, invd, d, s, n);
 }
 void vk_cheb_step(double* x, double* r, double* d, const double* t, const double* invd, double c1, double c2, int64_t n,
-                  hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_cheb_step, dim3(red_grid(n) * 4), dim3(256), 0, st, x, r, d, t, invd, c1, c2, n);
+                  bool stream, hipStream_t st) {
+  if (stream)
+    hipLaunchKernelGGL(dev::k_cheb_step<true>, dim3(red_grid(n) * 4), dim3(256), 0, st, x, r, d, t, invd, c1, c2, n);
+  else
+    hipLaunchKernelGGL(dev::k_cheb_step<false>, dim3(red_grid(n) * 4), dim3(256), 0, st, x, r, d, t, invd, c1, c2, n);
 }
 void vk_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(dev::k_axpby, dim3(red_grid(n) * 4), dim3(256), 0, st, a, x, b, y, n);
@@ -594,8 +623,12 @@ void vk_cheb_init32(const float* r, const double* invd, float* d, double s, int6
   hipLaunchKernelGGL(dev::k_cheb_init32, dim3(red_grid(n) * 4), dim3(256), 0, st, r, invd, d, s, n);
 }
 void vk_cheb_step32(double* x, float* r, float* d, const float* t, const double* invd, double c1, double c2,
-                    int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(dev::k_cheb_step32, dim3(red_grid(n) * 4), dim3(256), 0, st, x, r, d, t, invd, c1, c2, n);
+                    int64_t n, bool stream, hipStream_t st) {
+  if (stream)
+    hipLaunchKernelGGL(dev::k_cheb_step32<true>, dim3(red_grid(n) * 4), dim3(256), 0, st, x, r, d, t, invd, c1, c2, n);
+  else
+    hipLaunchKernelGGL(dev::k_cheb_step32<false>, dim3(red_grid(n) * 4), dim3(256), 0, st, x, r, d, t, invd, c1, c2,
+                       n);
 }
 void vk_dense_solve(const double* M, const int32_t* idx, int64_t m, const double* b, double* x, hipStream_t st) {
   if (m <= 0) return;

@@ -666,6 +666,7 @@ void smooth(PmgLevel& L, double* x, const double* b, int prec, bool first, hipSt
   const int64_t n = L.n;
   double *r = L.r.as<double>(), *d = L.d.as<double>(), *t = L.t.as<double>();
   const double* invd = A.invdiag.as<double>();
+  const bool stream = stream_vectors(n, 40, int64_t(A.lidx.bytes + A.tile_dofs.bytes));  // x, r, d, t, D^-1
   const double hi = 1.1 * L.lmax, lo = L.lmax / L.range;
   const int degree = L.hlevel ? CHEB_DEGREE_H : CHEB_DEGREE;
   const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
@@ -681,7 +682,7 @@ void smooth(PmgLevel& L, double* x, const double* b, int prec, bool first, hipSt
   for (int i = 0; i < degree; ++i) {
     op_apply(A, d, t, prec, st);
     const double rn = 1.0 / (2.0 * sigma - rho);
-    vk_cheb_step(x, r, d, t, invd, rn * rho, 2.0 * rn / delta, n, st);
+    vk_cheb_step(x, r, d, t, invd, rn * rho, 2.0 * rn / delta, n, stream, st);
     rho = rn;
   }
 }
@@ -695,6 +696,7 @@ void smooth32(PmgLevel& L, double* x, const double* b, bool first, double* energ
   const int64_t n = L.n;
   float *r = L.r.as<float>(), *d = L.d.as<float>(), *t = L.t.as<float>();
   const double* invd = A.invdiag.as<double>();
+  const bool stream = stream_vectors(n, 28, int64_t(A.lidx.bytes + A.tile_dofs.bytes));  // x, D^-1 FP64; r, d, t
   const double hi = 1.1 * L.lmax, lo = L.lmax / L.range;
   const int degree = L.hlevel ? CHEB_DEGREE_H : CHEB_DEGREE;
   const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
@@ -711,7 +713,7 @@ void smooth32(PmgLevel& L, double* x, const double* b, bool first, double* energ
   for (int i = 0; i < degree; ++i) {
     op_apply_v32(A, d, t, st, energy);
     const double rn = 1.0 / (2.0 * sigma - rho);
-    vk_cheb_step32(x, r, d, t, invd, rn * rho, 2.0 * rn / delta, n, st);
+    vk_cheb_step32(x, r, d, t, invd, rn * rho, 2.0 * rn / delta, n, stream, st);
     rho = rn;
   }
 }

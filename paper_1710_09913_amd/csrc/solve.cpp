@@ -83,6 +83,8 @@ static CgResult cg_run(Op& op, const double* b, double* x, bool x0_given, const 
   float* p32 = w.p32.as<float>();
   float* q32 = w.q32.as<float>();
   const float* invd32 = op.invdiag32.as<float>();
+  // per dof: x, r, p, A p and the inverse diagonal (FP64, or r, p, A p, inverse diagonal FP32)
+  const bool stream = stream_vectors(n, v32 ? 24 : 40, int64_t(op.lidx.bytes + op.tile_dofs.bytes));
   if (x0_given) {
     op_apply(op, x, q, DOGIP_F64, st);
     if (v32)
@@ -124,15 +126,15 @@ static CgResult cg_run(Op& op, const double* b, double* x, bool x0_given, const 
       if (v32) {
         op_apply_v32(op, p32, q32, st, w.energy.as<double>());
         vk_fin_pq(w.energy.as<double>(), op.plan.ntiles + op_finish_energy_count(op), sc, st);
-        vk_pcg_xr32(x, r32, p32, q32, invd32, sc, n, part, st);
+        vk_pcg_xr32(x, r32, p32, q32, invd32, sc, n, part, stream, st);
         vk_fin_rz(part, sc, hist, it + j + 1, st);
         vk_pcg_p32(p32, r32, invd32, sc, n, st);
       } else {
         op_apply(op, p, q, cp.prec, st, w.energy.as<double>());
         vk_fin_pq(w.energy.as<double>(), op.plan.ntiles + op_finish_energy_count(op), sc, st);
-        vk_pcg_xr(x, r, p, q, invd, sc, n, part, st);
+        vk_pcg_xr(x, r, p, q, invd, sc, n, part, stream, st);
         vk_fin_rz(part, sc, hist, it + j + 1, st);
-        vk_pcg_p(p, r, invd, sc, n, st);
+        vk_pcg_p(p, r, invd, sc, n, stream, st);
       }
     }
     HIPCHK(hipMemcpyAsync(w.hhist + it + 1, hist + it + 1, sizeof(double) * todo, hipMemcpyDeviceToHost, st));

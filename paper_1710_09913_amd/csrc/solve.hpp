@@ -41,13 +41,24 @@ struct PcgWork {
   }
 };
 
+// Vector kernels whose iteration touches more bytes than the memory-side cache holds
+// (256 MB on MI355X) read and write the vectors that an iteration uses once (the iterate;
+// with FP64 vectors also A p and the inverse diagonal) non-temporally, so that the cache
+// keeps the operator's index arrays and the direction for the next apply; smaller ones
+// keep every vector cached.  bytes_per_dof: the vectors' bytes per dof; index_bytes: the
+// operator's index arrays.
+inline bool stream_vectors(int64_t n, int bytes_per_dof, int64_t index_bytes) {
+  return double(n) * bytes_per_dof + double(index_bytes) > 256.0 * 1024 * 1024;
+}
+
 void vk_pcg_init(const double* b, const double* y, const double* invd, double* r, double* p, int64_t n, double* part,
                  PcgScalars* s, double* hist, hipStream_t st);
 void vk_fin_pq(const double* energy, int64_t ntiles, PcgScalars* s, hipStream_t st);
 void vk_pcg_xr(double* x, double* r, const double* p, const double* q, const double* invd, const PcgScalars* s,
-               int64_t n, double* part, hipStream_t st);
+               int64_t n, double* part, bool stream, hipStream_t st);
 void vk_fin_rz(const double* part, PcgScalars* s, double* hist, int it, hipStream_t st);
-void vk_pcg_p(double* p, const double* r, const double* invd, const PcgScalars* s, int64_t n, hipStream_t st);
+void vk_pcg_p(double* p, const double* r, const double* invd, const PcgScalars* s, int64_t n, bool stream,
+              hipStream_t st);
 void vk_resid(const double* b, const double* y, double* r, int64_t n, double* part, double* out, hipStream_t st);
 // r = b - y, and when p is given also p = invd r (restart); rho and rr refreshed
 void vk_replace(const double* b, const double* y, const double* invd, double* r, double* p, int64_t n, double* part,
@@ -75,7 +86,7 @@ void vk_csr_pk_x32(const int64_t* rowptr, const uint32_t* ent, const double* tab
                    int64_t nrows, int64_t nnz, hipStream_t st);
 void vk_cheb_init(const double* r, const double* invd, double* d, double s, int64_t n, hipStream_t st);
 void vk_cheb_step(double* x, double* r, double* d, const double* t, const double* invd, double c1, double c2, int64_t n,
-                  hipStream_t st);
+                  bool stream, hipStream_t st);
 void vk_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t st);
 void vk_sub(const double* b, const double* t, double* r, int64_t n, hipStream_t st);
 // FP32-storage forms of the smoother steps: r = float(b - t); d = float(s D^-1 r);
@@ -83,7 +94,7 @@ void vk_sub(const double* b, const double* t, double* r, int64_t n, hipStream_t 
 void vk_sub_to32(const double* b, const double* t, float* r, int64_t n, hipStream_t st);
 void vk_cheb_init32(const float* r, const double* invd, float* d, double s, int64_t n, hipStream_t st);
 void vk_cheb_step32(double* x, float* r, float* d, const float* t, const double* invd, double c1, double c2,
-                    int64_t n, hipStream_t st);
+                    int64_t n, bool stream, hipStream_t st);
 void vk_hash_fill(double* v, int64_t n, hipStream_t st);
 // flexible CG on device scalars s[8] (r.z, p.Ap, alpha, r.r, new r.z, old r.z, beta, flag):
 // alpha = r.z / p.Ap (flag 1 if p.Ap <= 0, 2 if not finite); beta = (new - old) / r.z,
@@ -101,7 +112,7 @@ void vk_dense_solve(const double* M, const int32_t* idx, int64_t m, const double
 void vk_pcg_init32(const double* b, const double* y, const float* invd, float* r, float* p, int64_t n, double* part,
                    PcgScalars* s, double* hist, hipStream_t st);
 void vk_pcg_xr32(double* x, float* r, const float* p, const float* q, const float* invd, const PcgScalars* s,
-                 int64_t n, double* part, hipStream_t st);
+                 int64_t n, double* part, bool stream, hipStream_t st);
 void vk_pcg_p32(float* p, const float* r, const float* invd, const PcgScalars* s, int64_t n, hipStream_t st);
 void vk_replace32(const double* b, const double* y, const float* invd, float* r, float* p, int64_t n, double* part,
                   PcgScalars* s, hipStream_t st);
